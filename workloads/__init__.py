@@ -1,0 +1,120 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and assembles integral arrays from
+them; it contains none of the eigensolver or sigma arithmetic, so both the
+CPU oracle and the HIP path can consume the same inputs without sharing
+method code.
+
+Integral recipe (the paper's molecular instances need an integral engine,
+which is absent; these seeded integrals stand in for them with the same
+orbital counts and the same 8-fold symmetric structure):
+
+  1. rng = numpy.random.default_rng(seed)        (PCG64)
+  2. h[p, p] = -1.0 + 0.25 * p                    (0-based p)
+  3. u ~ N(0,1), N(N-1)/2 draws in triu_indices(N, 1) order:
+         h[p, q] = h[q, p] = 0.05 * u
+  4. for k in 1..K: v ~ N(0,1), N(N+1)/2 draws in triu_indices(N) order:
+         L_k[p, q] = L_k[q, p] = 0.1 * v * exp(-|p - q| / 4)
+  5. (pq|rs) = sum_k L_k[p, q] * L_k[r, s]        (PSD as an N^2 x N^2 matrix)
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Integrals",
+    "make_integrals",
+    "start_noise",
+    "sigma_inputs",
+    "batch_instances",
+    "CONFIGS",
+]
+
+
+@dataclass(frozen=True)
+class Integrals:
+    norb: int
+    rank: int
+    seed: int
+    h1: np.ndarray   # [norb, norb] float64, symmetric
+    eri: np.ndarray  # [norb, norb, norb, norb] float64, chemists' (pq|rs)
+
+    def digest(self) -> str:
+        m = hashlib.sha256()
+        m.update(np.ascontiguousarray(self.h1).tobytes())
+        m.update(np.ascontiguousarray(self.eri).tobytes())
+        return m.hexdigest()
+
+
+def _draw(norb: int, rank: int, rng: np.random.Generator):
+    n = norb
+    h = np.zeros((n, n))
+    h[np.arange(n), np.arange(n)] = -1.0 + 0.25 * np.arange(n)
+    iu = np.triu_indices(n, 1)
+    u = rng.standard_normal(len(iu[0]))
+    h[iu] = 0.05 * u
+    h[(iu[1], iu[0])] = 0.05 * u
+    it = np.triu_indices(n)
+    damp = np.exp(-np.abs(it[0] - it[1]) / 4.0)
+    L = np.zeros((rank, n, n))
+    for k in range(rank):
+        v = rng.standard_normal(len(it[0]))
+        L[k][it] = 0.1 * v * damp
+        L[k][(it[1], it[0])] = 0.1 * v * damp
+    Lm = L.reshape(rank, n * n)
+    eri = (Lm.T @ Lm).reshape(n, n, n, n)
+    return h, eri
+
+
+def make_integrals(norb: int, rank: int, seed: int) -> Integrals:
+    """Seeded integrals G(norb, rank, seed) following the recipe above."""
+    rng = np.random.default_rng(seed)
+    h, eri = _draw(norb, rank, rng)
+    return Integrals(norb, rank, seed, h, eri)
+
+
+def start_noise(norb: int, rank: int, seed: int, ndet: int) -> np.ndarray:
+    """Gaussian noise for the 'lowest determinant + 1e-3 noise' start vector.
+
+    Drawn from the same generator as the integrals, after the integral draws,
+    so the start vector is a pure function of (norb, rank, seed).
+    Returns xi (unscaled, N(0,1)); the caller forms e_0 + 1e-3 * xi.
+    """
+    rng = np.random.default_rng(seed)
+    _draw(norb, rank, rng)
+    return rng.standard_normal(ndet)
+
+
+def sigma_inputs(seed: int, nvec: int, ndet: int, dtype=np.float64) -> np.ndarray:
+    """Dense normalised random vectors [nvec, ndet] for sigma throughput and parity."""
+    rng = np.random.default_rng(seed + 7)
+    c = rng.standard_normal((nvec, ndet))
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    return c.astype(dtype)
+
+
+def batch_instances(count: int = 512, master_seed: int = 2603):
+    """Instance list for the batching workload: (norb, nelec_per_spin, nroots, seed).
+
+    norb uniform in 6..10, n_alpha = n_beta = floor(norb / 2), 1..3 roots,
+    integrals G(norb, 2 * norb, seed=i).
+    """
+    rng = np.random.default_rng(master_seed)
+    out = []
+    for i in range(count):
+        norb = int(rng.integers(6, 11))
+        nroots = int(rng.integers(1, 4))
+        out.append((norb, norb // 2, nroots, i))
+    return out
+
+
+# The five workloads: (name, norb, n_alpha, n_beta, eri rank, seed, nroots)
+CONFIGS = {
+    "cas6": dict(norb=6, na=3, nb=3, rank=12, seed=0, nroots=1),
+    "cas10": dict(norb=10, na=5, nb=5, rank=20, seed=0, nroots=3),
+    "cas14": dict(norb=14, na=7, nb=7, rank=28, seed=0, nroots=5),
+    "cas16": dict(norb=16, na=8, nb=8, rank=32, seed=0, nroots=1),
+}
