@@ -1,0 +1,172 @@
+/*
+ * sbci.h -- C ABI of libsbci.so: the FCI sigma build and the SBCI1 solver of
+ * "Quantum chemistry based on classical mechanics inspired by simulated
+ * bifurcation" (Aiga & Goto), on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Results, "SBCI1 algorithm"): the lowest n eigenpairs of the
+ * electronic Hamiltonian H in the Slater-determinant basis of norb spatial
+ * orbitals with n_alpha / n_beta electrons:
+ *   H = sum_pq h_pq E_pq + 1/2 sum_pqrs (pq|rs) (E_pq E_rs - delta_qr E_ps),
+ *   E_pq = sum over spins of a+_p a_q.
+ * Determinants are pairs of occupation strings (Ia, Ib); a string is an
+ * m-subset of orbitals, strings are ordered by ascending bit mask and the
+ * determinant index is Ia * N_beta + Ib (CI vectors are row-major [Ia][Ib]).
+ * Energies are electronic (no constant term).
+ *
+ * Conventions for every function:
+ *   - return value: SBCI_OK (0) or a negative sbci_status; the message of
+ *     the last failure on the calling thread is sbci_last_error();
+ *   - "dev" pointers are device (HIP) memory on the context's device,
+ *     "host" pointers are host memory; the caller owns every pointer it passes;
+ *   - the context owns everything it allocates and frees it in sbci_destroy;
+ *   - one context is driven by one host thread at a time; all GPU work is
+ *     enqueued on the context's stream (sbci_set_stream), sbci_sigma is
+ *     asynchronous, the solvers return after synchronising that stream;
+ *   - on error the outputs are unspecified and the context stays usable.
+ */
+#ifndef SBCI_H
+#define SBCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sbci_status {
+  SBCI_OK = 0,
+  SBCI_EINVAL = -1,   /* bad argument: sizes, null pointers, aliasing, unknown dtype */
+  SBCI_ENOMEM = -2,   /* device allocation failed */
+  SBCI_EDEVICE = -3,  /* a HIP call or kernel launch failed */
+  SBCI_ENOCONV = -4,  /* step cap reached; outputs hold the last iterate */
+  SBCI_ENUMERIC = -5  /* NaN/Inf in a reduction or an unrecoverable subspace */
+} sbci_status;
+
+typedef enum sbci_dtype {
+  SBCI_F64 = 0,   /* FP64 vectors, FP64 sigma (reference form)                     */
+  SBCI_F32 = 1,   /* FP32 vectors, FP32 sigma (FP32 MFMA for the opposite-spin part) */
+  SBCI_BF16 = 2   /* FP32 vectors; opposite-spin part on BF16 MFMA with FP32
+                     accumulation, one-electron and same-spin parts in FP32         */
+} sbci_dtype;
+
+typedef struct sbci_ctx sbci_ctx;
+
+/* Thresholds and policies.  Defaults (sbci_default_opts) are the paper's
+ * values: eps0 = 1e-10 Eh, r0 = 1e-5 (Sections S1.2/S1.3, frozen core = No),
+ * b_th = 1e-2, eps1 = 1e-7, x_th1 = 0.1, x_th2 = 1.2, r1 = 1, max_cycle = 20
+ * (Section S1.5). */
+typedef struct sbci_opts {
+  double eps0, r0;            /* convergence: dE < eps0 and |z'| < r0 (Eqs. S30, S61) */
+  double b_th, eps1;          /* restart S62a: alpha > 0, |b| < b_th, dE < eps1        */
+  double x_th1, x_th2;        /* restart S62b: |x| < x_th1 or |x| > x_th2              */
+  double r1;                  /* restart S62c: |z'| > r1 and t > 0                     */
+  int max_cycle;              /* steps per segment before a forced restart             */
+  int max_steps;              /* sigma builds per root before SBCI_ENOCONV             */
+  int precision;              /* sbci_dtype of the low-precision phase (SBCI_F64: none) */
+  double mix_eps0, mix_r0;    /* low-precision phase ends at dE < mix_eps0 and |z'| < mix_r0 */
+  int mix_stall;              /* ... or after this many steps without an energy decrease */
+  double precond_floor;       /* |D - E0| is floored at this value (default 1e-8)      */
+  double lindep;              /* Gram-Schmidt radicand / Ritz coefficient guard (1e-14) */
+  int max_space;              /* Davidson subspace cap (default 12 + nroots if <= 0)    */
+  const double *x0;           /* host [ndet] start vector for root 0, or NULL for the
+                                 Section S1.1 start from the lowest diagonal elements */
+} sbci_opts;
+
+typedef struct sbci_report {
+  int nroots_converged;
+  int nsteps;                 /* SBCI steps (or Davidson iterations) over all roots    */
+  int nrestarts;
+  int64_t nsigma_f64;         /* sigma vector applications in FP64                     */
+  int64_t nsigma_low;         /* ... in the low-precision form                          */
+  double seconds;             /* wall time of the solve, seconds                        */
+  double t_converged[16];     /* seconds from solve start until root i converged        */
+  double resid[16];           /* final |z'| (SBCI) or |r| (Davidson) of root i          */
+  int64_t peak_vector_bytes;  /* device bytes of solver vectors at the peak             */
+} sbci_report;
+
+/* One record per SBCI step (filled when tracing is on, sbci_set_trace). */
+typedef struct sbci_step_info {
+  int root, segment, t;
+  int precision;              /* sbci_dtype of the sigma used in this step             */
+  double E, dE, dz, b, c, k, xnorm;
+  double seconds;             /* since the solve started                                */
+  int reason;                 /* 0 none, 1 converged, 2 S62a, 3 S62b, 4 S62c,
+                                 5 max_cycle, 6 rank guard, 7 coefficient guard,
+                                 8 switch to FP64 refinement                           */
+} sbci_step_info;
+
+void sbci_default_opts(sbci_opts *opt);
+const char *sbci_last_error(void);
+
+/* Build a context: validates the integrals, uploads them and builds on the
+ * device the alpha/beta strings, single-excitation tables, same-spin
+ * Hamiltonian lists, pair-scatter tables and the diagonal D.
+ *   norb in [1, 63]; 0 <= nalpha, nbeta <= norb;
+ *   h1  host [norb][norb] row-major, symmetric to 1e-12 * max|h|;
+ *   eri host [norb]^4 chemists' (pq|rs), 8-fold symmetric to 1e-12 * max|eri|.
+ * Errors: SBCI_EINVAL (sizes, symmetry, NULL), SBCI_ENOMEM, SBCI_EDEVICE. */
+int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                sbci_ctx **out);
+int sbci_destroy(sbci_ctx *ctx);
+
+/* Use this HIP stream (hipStream_t passed as void*) for all later work; NULL
+ * selects the null (legacy default) stream.  A new context uses a
+ * non-blocking stream of its own until this is called. */
+int sbci_set_stream(sbci_ctx *ctx, void *hip_stream);
+
+/* Sizes: N_det = C(norb, nalpha) * C(norb, nbeta) and the string counts. */
+int64_t sbci_ndet(const sbci_ctx *ctx);
+int64_t sbci_nstrings(const sbci_ctx *ctx, int spin /* 0 alpha, 1 beta */);
+
+/* Copy a device table into dev_out (which = 0/1: alpha/beta strings as
+ * uint64 masks [N_s]; 2/3: alpha/beta single-excitation tables as 8-byte
+ * records {int32 J; uint8 p; uint8 q; int8 sign; uint8 0} [N_s][s] with
+ * s = m (norb - m + 1): E_pq |I> = sign |J>; per string the m diagonal
+ * entries (p = q ascending) come first, then q occupied ascending x p empty
+ * ascending).  *bytes receives the size; dev_out may be NULL to query it. */
+int sbci_tables(sbci_ctx *ctx, int which, void *dev_out, int64_t *bytes);
+
+/* D[Ia, Ib] = <Ia Ib|H|Ia Ib> into dev_out [N_det] FP64 (the diagonal used by
+ * the preconditioner (D - E0 I)^-1 of Eq. 7). */
+int sbci_hdiag(sbci_ctx *ctx, double *dev_out);
+
+/* sigma = H c for nvec vectors (the matrix-vector product every SBCI step
+ * needs once, Eq. S32).  dev_c, dev_sigma: [nvec][N_det] contiguous, element
+ * type double (SBCI_F64) or float (SBCI_F32, SBCI_BF16); they must not
+ * overlap.  Asynchronous on the context stream. */
+int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype);
+
+/* SBCI1 (Algorithm 1 with Sections S1.1-S1.5) for the lowest nroots states.
+ * tol > 0 overrides opt: eps0 = tol, r0 = sqrt(tol) (the paper's two pairs,
+ * 1e-10/1e-5 and 1e-8/1e-4, both have r0 = sqrt(eps0)); tol <= 0 keeps opt.
+ * opt may be NULL (defaults).  energies: host [nroots]; dev_vecs: device
+ * [nroots][N_det] FP64 normalised eigenvectors, or NULL; rep may be NULL.
+ * Returns SBCI_ENOCONV if a root hits max_steps (outputs hold the last
+ * iterates). */
+int sbci_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
+               double *energies, double *dev_vecs, sbci_report *rep);
+
+/* Step-level interface to the same solver: sbci_begin prepares root 0,
+ * each sbci_step performs one SBCI step (one sigma build) and fills *info;
+ * *done becomes 1 once all roots have converged.  sbci_finish copies the
+ * results like sbci_solve. */
+int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt);
+int sbci_step(sbci_ctx *ctx, sbci_step_info *info, int *done);
+int sbci_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report *rep);
+
+/* Per-step trace of the last solve (tracing on by default): copies up to
+ * max records into out (host) and returns the number copied (>= 0). */
+int sbci_set_trace(sbci_ctx *ctx, int on);
+int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max);
+
+/* Block Davidson-Liu on the same sigma (the paper's baseline method):
+ * block = nroots, preconditioner (D - theta_k)^-1, subspace cap max_space
+ * (12 + nroots by default), collapse to the Ritz vectors.  Same outputs and
+ * thresholds as sbci_solve; always FP64. */
+int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
+                  double *energies, double *dev_vecs, sbci_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBCI_H */

@@ -1,0 +1,284 @@
+"""Python binding of libsbci.so (argument marshalling only).
+
+Every step of the sigma build and of the SBCI1 / Davidson solvers runs in the
+HIP library; this module only converts arguments.  PyTorch supplies device
+memory (tensors on ``cuda``) and the stream.  There is no CPU fallback: if
+the library is missing the import of any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsbci.so")
+
+SBCI_OK, SBCI_EINVAL, SBCI_ENOMEM, SBCI_EDEVICE, SBCI_ENOCONV, SBCI_ENUMERIC = 0, -1, -2, -3, -4, -5
+F64, F32, BF16 = 0, 1, 2
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
+           7: "coef", 8: "refine"}
+
+
+class SbciError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sbci error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("eps0", ctypes.c_double), ("r0", ctypes.c_double),
+        ("b_th", ctypes.c_double), ("eps1", ctypes.c_double),
+        ("x_th1", ctypes.c_double), ("x_th2", ctypes.c_double),
+        ("r1", ctypes.c_double),
+        ("max_cycle", ctypes.c_int), ("max_steps", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("mix_eps0", ctypes.c_double), ("mix_r0", ctypes.c_double),
+        ("mix_stall", ctypes.c_int),
+        ("precond_floor", ctypes.c_double), ("lindep", ctypes.c_double),
+        ("max_space", ctypes.c_int),
+        ("x0", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("nroots_converged", ctypes.c_int), ("nsteps", ctypes.c_int), ("nrestarts", ctypes.c_int),
+        ("nsigma_f64", ctypes.c_int64), ("nsigma_low", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("t_converged", ctypes.c_double * 16), ("resid", ctypes.c_double * 16),
+        ("peak_vector_bytes", ctypes.c_int64),
+    ]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [
+        ("root", ctypes.c_int), ("segment", ctypes.c_int), ("t", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("E", ctypes.c_double), ("dE", ctypes.c_double), ("dz", ctypes.c_double),
+        ("b", ctypes.c_double), ("c", ctypes.c_double), ("k", ctypes.c_double),
+        ("xnorm", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("reason", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["reason"] = REASONS.get(self.reason, str(self.reason))
+        return d
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point declared in include/sbci.h
+_P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+SIGNATURES = [
+    ("sbci_default_opts", None, [ctypes.POINTER(Opts)]),
+    ("sbci_last_error", ctypes.c_char_p, []),
+    ("sbci_create", _I, [_I, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    ("sbci_destroy", _I, [_P]),
+    ("sbci_set_stream", _I, [_P, _P]),
+    ("sbci_ndet", _I64, [_P]),
+    ("sbci_nstrings", _I64, [_P, _I]),
+    ("sbci_tables", _I, [_P, _I, _P, ctypes.POINTER(_I64)]),
+    ("sbci_hdiag", _I, [_P, _P]),
+    ("sbci_sigma", _I, [_P, _P, _P, _I, _I]),
+    ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
+    ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
+    ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
+    ("sbci_finish", _I, [_P, _P, _P, ctypes.POINTER(Report)]),
+    ("sbci_set_trace", _I, [_P, _I]),
+    ("sbci_trace", _I, [_P, ctypes.POINTER(StepInfo), _I]),
+    ("sbci_davidson", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
+]
+
+
+def lib():
+    """Load libsbci.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2603_06101_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != SBCI_OK and rc not in allow:
+        raise SbciError(rc, lib().sbci_last_error().decode())
+    return rc
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().sbci_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = DTYPES[v]
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class SolveResult:
+    energies: np.ndarray
+    vectors: object          # torch tensor [nroots, ndet] float64 on cuda, or None
+    report: dict
+    trace: list
+    status: int
+
+
+class Context:
+    """One FCI problem (norb, nalpha, nbeta, h1, eri) resident on the GPU."""
+
+    def __init__(self, norb, nalpha, nbeta, h1, eri, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsbci needs a HIP device")
+        self.norb, self.na, self.nb = norb, nalpha, nbeta
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        self._keep = (h1, eri)
+        h = _P()
+        _check(lib().sbci_create(norb, nalpha, nbeta, h1.ctypes.data, eri.ctypes.data,
+                                 ctypes.byref(h)))
+        self.h = h
+        self.ndet = lib().sbci_ndet(h)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().sbci_set_stream(h, ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sbci_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nstrings(self, spin):
+        return lib().sbci_nstrings(self.h, spin)
+
+    def tables(self, which):
+        """which: 0/1 alpha/beta strings (uint64 as int64), 2/3 excitation tables (raw bytes)."""
+        torch = _torch()
+        nb = _I64()
+        _check(lib().sbci_tables(self.h, which, None, ctypes.byref(nb)))
+        if which in (0, 1):
+            out = torch.empty(nb.value // 8, dtype=torch.int64, device="cuda")
+        else:
+            out = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        if nb.value:
+            _check(lib().sbci_tables(self.h, which, ctypes.c_void_p(out.data_ptr()), None))
+        return out
+
+    def hdiag(self):
+        torch = _torch()
+        out = torch.empty(self.ndet, dtype=torch.float64, device="cuda")
+        _check(lib().sbci_hdiag(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sigma(self, c, dtype="f64", out=None):
+        """sigma = H c for c [nvec, ndet] (or [ndet]) on cuda; float64 for f64, float32 otherwise."""
+        torch = _torch()
+        code = DTYPES[dtype] if isinstance(dtype, str) else dtype
+        want = torch.float64 if code == F64 else torch.float32
+        if c.dtype != want or not c.is_cuda or not c.is_contiguous():
+            raise ValueError(f"c must be a contiguous cuda {want} tensor")
+        nvec = 1 if c.dim() == 1 else c.shape[0]
+        if c.numel() != nvec * self.ndet:
+            raise ValueError("c has the wrong size")
+        if out is None:
+            out = torch.empty_like(c)
+        _check(lib().sbci_sigma(self.h, ctypes.c_void_p(c.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), nvec, code))
+        return out
+
+    def _run(self, fn, nroots, tol, opts, want_vectors):
+        torch = _torch()
+        o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
+        e = np.zeros(nroots)
+        vec = torch.empty((nroots, self.ndet), dtype=torch.float64, device="cuda") \
+            if want_vectors else None
+        rep = Report()
+        rc = fn(self.h, nroots, tol, ctypes.byref(o), e.ctypes.data,
+                ctypes.c_void_p(vec.data_ptr()) if vec is not None else None, ctypes.byref(rep))
+        _check(rc, allow=(SBCI_ENOCONV,))
+        return SolveResult(e, vec, _report_dict(rep, nroots), self.trace(), rc)
+
+    def solve(self, nroots, tol=1e-10, opts=None, want_vectors=True, x0=None):
+        """SBCI1 for the lowest nroots states; x0: optional host start vector (numpy)."""
+        o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
+        if x0 is not None:
+            x0 = np.ascontiguousarray(x0, dtype=np.float64)
+            o.x0 = x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return self._run(lib().sbci_solve, nroots, tol, o, want_vectors)
+
+    def davidson(self, nroots, tol=1e-10, opts=None, want_vectors=True):
+        return self._run(lib().sbci_davidson, nroots, tol, opts, want_vectors)
+
+    def begin(self, nroots, tol=1e-10, opts=None, x0=None):
+        o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
+        if x0 is not None:
+            self._x0 = np.ascontiguousarray(x0, dtype=np.float64)
+            o.x0 = self._x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._opts = o
+        _check(lib().sbci_begin(self.h, nroots, tol, ctypes.byref(o)))
+        self._nroots = nroots
+
+    def step(self):
+        info = StepInfo()
+        done = _I(0)
+        _check(lib().sbci_step(self.h, ctypes.byref(info), ctypes.byref(done)))
+        return info.as_dict(), bool(done.value)
+
+    def finish(self, want_vectors=True):
+        torch = _torch()
+        e = np.zeros(self._nroots)
+        vec = torch.empty((self._nroots, self.ndet), dtype=torch.float64, device="cuda") \
+            if want_vectors else None
+        rep = Report()
+        rc = lib().sbci_finish(self.h, e.ctypes.data,
+                               ctypes.c_void_p(vec.data_ptr()) if vec is not None else None,
+                               ctypes.byref(rep))
+        _check(rc, allow=(SBCI_ENOCONV,))
+        return SolveResult(e, vec, _report_dict(rep, self._nroots), self.trace(), rc)
+
+    def trace(self):
+        n = lib().sbci_trace(self.h, None, 0)
+        if n <= 0:
+            return []
+        buf = (StepInfo * n)()
+        m = lib().sbci_trace(self.h, buf, n)
+        return [buf[i].as_dict() for i in range(m)]
+
+
+def _report_dict(rep: Report, nroots: int) -> dict:
+    k = min(nroots, 16)
+    return dict(nroots_converged=rep.nroots_converged, nsteps=rep.nsteps, nrestarts=rep.nrestarts,
+                nsigma_f64=rep.nsigma_f64, nsigma_low=rep.nsigma_low, seconds=rep.seconds,
+                t_converged=list(rep.t_converged[:k]), resid=list(rep.resid[:k]),
+                peak_vector_bytes=rep.peak_vector_bytes)
+
+
+def decode_table(raw, nstr, s):
+    """Split the raw 8-byte excitation records into (J, p, q, sign) numpy arrays [nstr, s]."""
+    a = np.asarray(raw.cpu().numpy() if hasattr(raw, "cpu") else raw, dtype=np.uint8)
+    rec = a.view(np.dtype([("J", "<i4"), ("p", "u1"), ("q", "u1"), ("sign", "i1"), ("pad", "u1")]))
+    rec = rec.reshape(nstr, s) if s else rec.reshape(nstr, 0)
+    return rec

@@ -1,0 +1,138 @@
+// Internal declarations of libsbci: context layout, launch helpers, kernels'
+// host-side launchers.  Not part of the public ABI (include/sbci.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbci.h"
+
+namespace sbci {
+
+// 8-byte single-excitation record: E_pq |I> = sign |J>.
+struct Ent {
+  int32_t J;
+  uint8_t p, q;
+  int8_t sign;
+  uint8_t pad;
+};
+static_assert(sizeof(Ent) == 8, "Ent must be 8 bytes");
+
+// Scatter code of the pair tables: target string with the sign folded in.
+// code >= 0: +1 * string code; code < 0 and != kInvalid: -1 * string ~code.
+constexpr int32_t kInvalid = INT32_MIN;
+
+struct SpinTables {
+  int m = 0;                // electrons of this spin
+  int64_t ns = 0;           // number of strings C(norb, m)
+  int s = 0;                // single excitations per string, m (norb - m + 1)
+  int nf = 0;               // same-spin list length 1 + m(N-m) + C(m,2)C(N-m,2)
+  uint64_t *str = nullptr;  // [ns]
+  Ent *tab = nullptr;       // [ns][s]
+  int32_t *pair = nullptr;  // [npair][ns] scatter codes
+  int32_t *fcol = nullptr;  // [ns][nf] same-spin list columns
+  double *fval64 = nullptr; // [ns][nf] FP64 values
+  float *fval32 = nullptr;  // [ns][nf] FP32 values
+  double *fdiag = nullptr;  // [ns] same-spin diagonal energy of each string
+  bool shared = false;      // aliases the alpha tables (n_alpha == n_beta)
+};
+
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Solver;  // SBCI1 driver state (solver.hip)
+
+}  // namespace sbci
+
+struct sbci_ctx {
+  int norb = 0, na = 0, nb = 0;
+  int npair = 0;
+  int64_t ndet = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  sbci::SpinTables A, B;
+  int64_t *binom = nullptr;       // device [65][65]
+  double *h1 = nullptr;           // device [N][N]
+  double *eri = nullptr;          // device [N^4]
+  double *W64 = nullptr;          // device [npair][npair] (kl|k'l')
+  float *W32 = nullptr;
+  __hip_bfloat16 *Wbf = nullptr;
+  double *hdiag = nullptr;        // device [ndet]
+  float *hdiag32 = nullptr;       // device [ndet]
+  sbci::Workspace ws_t, ws_s;     // transposed input / output scratch of sigma
+  sbci::Workspace ws_red;         // reduction partials + results
+  sbci::Solver *solver = nullptr;
+  bool trace_on = true;
+  std::vector<sbci_step_info> trace;
+};
+
+namespace sbci {
+
+// ---- error handling (capi.hip) ----
+int set_error(int code, const std::string &msg);
+#define SBCI_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::sbci::set_error(e_ == hipErrorOutOfMemory ? SBCI_ENOMEM : SBCI_EDEVICE, \
+                               std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define SBCI_CHECK_LAUNCH()                                                       \
+  do {                                                                            \
+    hipError_t e_ = hipGetLastError();                                            \
+    if (e_ != hipSuccess)                                                         \
+      return ::sbci::set_error(SBCI_EDEVICE, std::string("kernel launch: ") +    \
+                                                 hipGetErrorString(e_));          \
+  } while (0)
+#define SBCI_TRY(expr)          \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != SBCI_OK) return r_; \
+  } while (0)
+
+int ensure(Workspace &w, size_t bytes);
+
+// ---- tables.hip ----
+int build_tables(sbci_ctx *ctx, const double *h1_host, const double *eri_host);
+void free_tables(sbci_ctx *ctx);
+
+// ---- sigma.hip ----
+// sigma = H c for nvec vectors of element type T (double or float).
+// mode: SBCI_F64 (T = double), SBCI_F32 or SBCI_BF16 (T = float).
+int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
+
+// ---- vec.hip: vector kernels with FP64 reductions ----
+// Reductions write `nq` doubles to `out` (device); deterministic order.
+template <typename T>
+int dots(sbci_ctx *ctx, int64_t n, const T *a, const T *const *bs, int nb, double *out);
+template <typename T>
+int lincomb(sbci_ctx *ctx, int64_t n, T *out, const T *const *xs, const double *coef, int nx,
+            double beta);
+template <typename Td, typename Ts>
+int convert(sbci_ctx *ctx, int64_t n, Td *dst, const Ts *src, double scale);
+
+// Fused SBCI update pass (see vec.hip for the full contract).
+struct UpdateArgs {
+  double b, c, E, inv_norm, E0, floor, sx;
+  int sy;          // 0: y_t treated as zero (segment start)
+  int read_z;      // 0: z/Z not read (segment start, b = c = 0)
+  int nconv;       // number of converged roots to project against (dots only)
+  int want_zdots;  // 1: also reduce x.w, y.w, w.w (no deflation follows)
+};
+template <typename T>
+int update(sbci_ctx *ctx, int64_t n, T *x, T *X, T *y, T *Y, const T *z, const T *Z, T *w,
+           const T *D, const T *const *xc, const UpdateArgs &a, double *out);
+template <typename T>
+int deflate(sbci_ctx *ctx, int64_t n, T *w, const T *x, const T *y, const T *const *xc, int nconv,
+            const double *d_coef, double *out);
+template <typename T>
+int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const T *Z, double *out);
+
+}  // namespace sbci

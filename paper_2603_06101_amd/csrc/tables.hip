@@ -1,0 +1,364 @@
+// Strings, lexical addressing, single-excitation tables, same-spin
+// Hamiltonian lists, pair-scatter tables and the diagonal D (one-time set-up
+// of a context, all built on the device).
+//
+// Determinant basis of the paper's problem statement (Results, "SBCI1
+// algorithm"); the determinant count C(N, n_alpha) * C(N, n_beta) is the one
+// printed for every instance in Section S3.1.
+//
+// * strings: m-subsets of {0..N-1} as uint64 masks in ascending order; the
+//   rank of a mask is sum_k C(o_k, k) over its occupied o_1 < ... < o_m
+//   (combinatorial number system), so rank and order agree;
+// * E_pq |I> = sign |I - q + p>, sign = (-1)^(occupied strictly between p, q);
+// * same-spin list of string I: every J with a non-zero same-spin matrix
+//   element <J| sum h_pq E_pq + 1/2 sum (pq|rs)(E_pq E_rs - d_qr E_ps) |I>
+//   (within one spin), from the Slater-Condon rules: J = I (diagonal), the
+//   m(N-m) singles and the C(m,2) C(N-m,2) doubles;
+// * pair table: for string J and unordered orbital pair {k >= l}, the string
+//   I' and sign with <I'| E_kl or E_lk |J> != 0 (at most one orientation is
+//   non-zero), used to scatter the opposite-spin contraction.
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace sbci {
+
+namespace {
+
+__device__ __forceinline__ int64_t rank_of(uint64_t mask, const int64_t *__restrict__ binom) {
+  int64_t r = 0;
+  int k = 1;
+  while (mask) {
+    int o = __builtin_ctzll(mask);
+    r += binom[o * 65 + k];
+    ++k;
+    mask &= mask - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ int parity_between(uint64_t mask, int a, int b) {
+  int lo = a < b ? a : b, hi = a < b ? b : a;
+  if (hi - lo < 2) return 0;
+  uint64_t m = ((1ull << hi) - 1) & ~((1ull << (lo + 1)) - 1);
+  return __popcll(mask & m) & 1;
+}
+
+__global__ void k_strings(int norb, int m, int64_t ns, const int64_t *__restrict__ binom,
+                          uint64_t *__restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  int64_t r = i;
+  uint64_t mask = 0;
+  int o = norb - 1;
+  for (int k = m; k >= 1; --k) {
+    while (binom[o * 65 + k] > r) --o;
+    mask |= 1ull << o;
+    r -= binom[o * 65 + k];
+    --o;
+  }
+  out[i] = mask;
+}
+
+__global__ void k_exc_table(int norb, int m, int64_t ns, int s, const uint64_t *__restrict__ str,
+                            const int64_t *__restrict__ binom, Ent *__restrict__ tab) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const uint64_t mask = str[i];
+  Ent *row = tab + i * s;
+  int e = 0;
+  for (int o = 0; o < norb; ++o) {
+    if ((mask >> o) & 1) {
+      Ent t;
+      t.J = (int32_t)i;
+      t.p = (uint8_t)o;
+      t.q = (uint8_t)o;
+      t.sign = 1;
+      t.pad = 0;
+      row[e++] = t;
+    }
+  }
+  for (int q = 0; q < norb; ++q) {
+    if (!((mask >> q) & 1)) continue;
+    for (int p = 0; p < norb; ++p) {
+      if ((mask >> p) & 1) continue;
+      uint64_t nm = (mask & ~(1ull << q)) | (1ull << p);
+      Ent t;
+      t.J = (int32_t)rank_of(nm, binom);
+      t.p = (uint8_t)p;
+      t.q = (uint8_t)q;
+      t.sign = parity_between(mask, p, q) ? -1 : 1;
+      t.pad = 0;
+      row[e++] = t;
+    }
+  }
+}
+
+__global__ void k_pair_table(int norb, int64_t ns, int npair, const uint64_t *__restrict__ str,
+                             const int64_t *__restrict__ binom, int32_t *__restrict__ pair) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int kl = blockIdx.y;
+  if (j >= ns || kl >= npair) return;
+  int k = 0;
+  while ((k + 1) * (k + 2) / 2 <= kl) ++k;
+  int l = kl - k * (k + 1) / 2;
+  const uint64_t mask = str[j];
+  const int bk = (mask >> k) & 1, bl = (mask >> l) & 1;
+  int32_t code = kInvalid;
+  if (k == l) {
+    if (bk) code = (int32_t)j;
+  } else if (bk != bl) {
+    // the occupied one of {k, l} moves to the empty one
+    uint64_t nm = mask ^ (1ull << k) ^ (1ull << l);
+    int32_t tgt = (int32_t)rank_of(nm, binom);
+    int neg = parity_between(mask, k, l);
+    code = neg ? ~tgt : tgt;
+  }
+  pair[(int64_t)kl * ns + j] = code;
+}
+
+__device__ __forceinline__ double G4(const double *__restrict__ g, int n, int p, int q, int r, int s) {
+  return g[((p * n + q) * n + r) * n + s];
+}
+
+__global__ void k_flist(int norb, int m, int64_t ns, int nf, const uint64_t *__restrict__ str,
+                        const int64_t *__restrict__ binom, const double *__restrict__ h,
+                        const double *__restrict__ g, int32_t *__restrict__ fcol,
+                        double *__restrict__ f64, float *__restrict__ f32,
+                        double *__restrict__ fdiag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int n = norb;
+  const uint64_t mask = str[i];
+  int32_t *col = fcol + i * nf;
+  double *val = f64 + i * nf;
+  float *val32 = f32 + i * nf;
+  int e = 0;
+  // diagonal: sum_p h_pp + 1/2 sum_{p,q in I} [(pp|qq) - (pq|qp)]
+  double d = 0.0;
+  for (int p = 0; p < n; ++p) {
+    if (!((mask >> p) & 1)) continue;
+    d += h[p * n + p];
+    for (int q = 0; q < n; ++q)
+      if ((mask >> q) & 1) d += 0.5 * (G4(g, n, p, p, q, q) - G4(g, n, p, q, q, p));
+  }
+  fdiag[i] = d;
+  col[e] = (int32_t)i;
+  val[e] = d;
+  val32[e] = (float)d;
+  ++e;
+  // singles q -> p: sign * [h_pq + sum_{r in I, r != q} ((pq|rr) - (pr|rq))]
+  for (int q = 0; q < n; ++q) {
+    if (!((mask >> q) & 1)) continue;
+    for (int p = 0; p < n; ++p) {
+      if ((mask >> p) & 1) continue;
+      double v = h[p * n + q];
+      for (int r = 0; r < n; ++r)
+        if (r != q && ((mask >> r) & 1)) v += G4(g, n, p, q, r, r) - G4(g, n, p, r, r, q);
+      if (parity_between(mask, p, q)) v = -v;
+      uint64_t nm = (mask & ~(1ull << q)) | (1ull << p);
+      col[e] = (int32_t)rank_of(nm, binom);
+      val[e] = v;
+      val32[e] = (float)v;
+      ++e;
+    }
+  }
+  // doubles (q1 < q2) -> (p1 < p2): sign * [(p1 q1|p2 q2) - (p1 q2|p2 q1)]
+  for (int q1 = 0; q1 < n; ++q1) {
+    if (!((mask >> q1) & 1)) continue;
+    for (int q2 = q1 + 1; q2 < n; ++q2) {
+      if (!((mask >> q2) & 1)) continue;
+      for (int p1 = 0; p1 < n; ++p1) {
+        if ((mask >> p1) & 1) continue;
+        for (int p2 = p1 + 1; p2 < n; ++p2) {
+          if ((mask >> p2) & 1) continue;
+          double v = G4(g, n, p1, q1, p2, q2) - G4(g, n, p1, q2, p2, q1);
+          uint64_t m1 = (mask & ~(1ull << q2)) | (1ull << p2);
+          int neg = parity_between(mask, p2, q2) ^ parity_between(m1, p1, q1);
+          uint64_t m2 = (m1 & ~(1ull << q1)) | (1ull << p1);
+          col[e] = (int32_t)rank_of(m2, binom);
+          val[e] = neg ? -v : v;
+          val32[e] = (float)val[e];
+          ++e;
+        }
+      }
+    }
+  }
+}
+
+// D[Ia, Ib] = fdiag_a[Ia] + fdiag_b[Ib] + sum_{p in Ia, q in Ib} (pp|qq)
+__global__ void k_hdiag(int norb, int64_t nsa, int64_t nsb, const uint64_t *__restrict__ sa,
+                        const uint64_t *__restrict__ sb, const double *__restrict__ fa,
+                        const double *__restrict__ fb, const double *__restrict__ g,
+                        double *__restrict__ D, float *__restrict__ D32) {
+  __shared__ double J[64 * 64];
+  const int n = norb;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int p = t / n, q = t % n;
+    J[t] = G4(g, n, p, p, q, q);
+  }
+  __syncthreads();
+  const int64_t ndet = nsa * nsb;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ndet;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ia = i / nsb, ib = i - ia * nsb;
+    uint64_t ma = sa[ia];
+    const uint64_t mb = sb[ib];
+    double e = fa[ia] + fb[ib];
+    while (ma) {
+      int p = __builtin_ctzll(ma);
+      ma &= ma - 1;
+      uint64_t mm = mb;
+      while (mm) {
+        int q = __builtin_ctzll(mm);
+        mm &= mm - 1;
+        e += J[p * n + q];
+      }
+    }
+    D[i] = e;
+    D32[i] = (float)e;
+  }
+}
+
+int64_t choose_host(int n, int k) {
+  static int64_t t[65][65];
+  static bool ready = false;
+  if (!ready) {
+    for (int i = 0; i <= 64; ++i) {
+      t[i][0] = 1;
+      for (int j = 1; j <= 64; ++j) t[i][j] = i == 0 ? 0 : t[i - 1][j - 1] + t[i - 1][j];
+    }
+    ready = true;
+  }
+  if (n < 0 || k < 0 || k > n || n > 64) return 0;
+  return t[n][k];
+}
+
+int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
+  const int n = ctx->norb;
+  T.m = m;
+  T.ns = choose_host(n, m);
+  T.s = m * (n - m + 1);
+  const int64_t nd = choose_host(m, 2) * choose_host(n - m, 2);
+  T.nf = (int)(1 + (int64_t)m * (n - m) + nd);
+  if (T.ns > INT32_MAX / 2) return set_error(SBCI_EINVAL, "string count exceeds int32 addressing");
+  hipStream_t st = ctx->stream;
+  SBCI_HIP(hipMalloc(&T.str, sizeof(uint64_t) * T.ns));
+  SBCI_HIP(hipMalloc(&T.tab, sizeof(Ent) * T.ns * (T.s > 0 ? T.s : 1)));
+  SBCI_HIP(hipMalloc(&T.pair, sizeof(int32_t) * T.ns * ctx->npair));
+  SBCI_HIP(hipMalloc(&T.fcol, sizeof(int32_t) * T.ns * T.nf));
+  SBCI_HIP(hipMalloc(&T.fval64, sizeof(double) * T.ns * T.nf));
+  SBCI_HIP(hipMalloc(&T.fval32, sizeof(float) * T.ns * T.nf));
+  SBCI_HIP(hipMalloc(&T.fdiag, sizeof(double) * T.ns));
+  const int bs = 128;
+  const unsigned gx = (unsigned)((T.ns + bs - 1) / bs);
+  k_strings<<<gx, bs, 0, st>>>(n, m, T.ns, ctx->binom, T.str);
+  SBCI_CHECK_LAUNCH();
+  if (T.s > 0) {
+    k_exc_table<<<gx, bs, 0, st>>>(n, m, T.ns, T.s, T.str, ctx->binom, T.tab);
+    SBCI_CHECK_LAUNCH();
+  }
+  k_pair_table<<<dim3(gx, ctx->npair), bs, 0, st>>>(n, T.ns, ctx->npair, T.str, ctx->binom, T.pair);
+  SBCI_CHECK_LAUNCH();
+  const int fbs = 64;  // heavy per-thread loops: small blocks
+  k_flist<<<(unsigned)((T.ns + fbs - 1) / fbs), fbs, 0, st>>>(n, m, T.ns, T.nf, T.str, ctx->binom,
+                                                              ctx->h1, ctx->eri, T.fcol, T.fval64,
+                                                              T.fval32, T.fdiag);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+void free_spin(SpinTables &T) {
+  if (T.shared) {
+    T = SpinTables();
+    return;
+  }
+  hipFree(T.str);
+  hipFree(T.tab);
+  hipFree(T.pair);
+  hipFree(T.fcol);
+  hipFree(T.fval64);
+  hipFree(T.fval32);
+  hipFree(T.fdiag);
+  T = SpinTables();
+}
+
+}  // namespace
+
+int build_tables(sbci_ctx *ctx, const double *h1, const double *eri) {
+  const int n = ctx->norb;
+  ctx->npair = n * (n + 1) / 2;
+  hipStream_t st = ctx->stream;
+  // binomial table [65][65]
+  std::vector<int64_t> binom(65 * 65);
+  for (int i = 0; i <= 64; ++i)
+    for (int k = 0; k <= 64; ++k) binom[i * 65 + k] = choose_host(i, k);
+  SBCI_HIP(hipMalloc(&ctx->binom, sizeof(int64_t) * 65 * 65));
+  SBCI_HIP(hipMemcpyAsync(ctx->binom, binom.data(), sizeof(int64_t) * 65 * 65,
+                          hipMemcpyHostToDevice, st));
+  const size_t n4 = (size_t)n * n * n * n;
+  SBCI_HIP(hipMalloc(&ctx->h1, sizeof(double) * n * n));
+  SBCI_HIP(hipMalloc(&ctx->eri, sizeof(double) * n4));
+  SBCI_HIP(hipMemcpyAsync(ctx->h1, h1, sizeof(double) * n * n, hipMemcpyHostToDevice, st));
+  SBCI_HIP(hipMemcpyAsync(ctx->eri, eri, sizeof(double) * n4, hipMemcpyHostToDevice, st));
+  // packed-pair ERI matrix W[kl][k'l'] = (kl|k'l'), k >= l
+  const int np = ctx->npair;
+  std::vector<double> W((size_t)np * np);
+  std::vector<float> W32((size_t)np * np);
+  std::vector<__hip_bfloat16> Wbf((size_t)np * np);
+  std::vector<int> pk(np), pl(np);
+  for (int k = 0, kl = 0; k < n; ++k)
+    for (int l = 0; l <= k; ++l, ++kl) pk[kl] = k, pl[kl] = l;
+  for (int a = 0; a < np; ++a)
+    for (int b = 0; b < np; ++b) {
+      double v = eri[((size_t)(pk[a] * n + pl[a]) * n + pk[b]) * n + pl[b]];
+      W[(size_t)a * np + b] = v;
+      W32[(size_t)a * np + b] = (float)v;
+      Wbf[(size_t)a * np + b] = __float2bfloat16((float)v);
+    }
+  SBCI_HIP(hipMalloc(&ctx->W64, sizeof(double) * np * np));
+  SBCI_HIP(hipMalloc(&ctx->W32, sizeof(float) * np * np));
+  SBCI_HIP(hipMalloc(&ctx->Wbf, sizeof(__hip_bfloat16) * np * np));
+  SBCI_HIP(hipMemcpyAsync(ctx->W64, W.data(), sizeof(double) * np * np, hipMemcpyHostToDevice, st));
+  SBCI_HIP(hipMemcpyAsync(ctx->W32, W32.data(), sizeof(float) * np * np, hipMemcpyHostToDevice, st));
+  SBCI_HIP(hipMemcpyAsync(ctx->Wbf, Wbf.data(), sizeof(__hip_bfloat16) * np * np,
+                          hipMemcpyHostToDevice, st));
+  SBCI_TRY(build_spin(ctx, ctx->A, ctx->na));
+  if (ctx->nb == ctx->na) {
+    ctx->B = ctx->A;
+    ctx->B.shared = true;
+  } else {
+    SBCI_TRY(build_spin(ctx, ctx->B, ctx->nb));
+  }
+  ctx->ndet = ctx->A.ns * ctx->B.ns;
+  SBCI_HIP(hipMalloc(&ctx->hdiag, sizeof(double) * ctx->ndet));
+  SBCI_HIP(hipMalloc(&ctx->hdiag32, sizeof(float) * ctx->ndet));
+  int64_t blocks = (ctx->ndet + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_hdiag<<<(unsigned)blocks, 256, 0, st>>>(n, ctx->A.ns, ctx->B.ns, ctx->A.str, ctx->B.str,
+                                            ctx->A.fdiag, ctx->B.fdiag, ctx->eri, ctx->hdiag,
+                                            ctx->hdiag32);
+  SBCI_CHECK_LAUNCH();
+  SBCI_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
+  return SBCI_OK;
+}
+
+void free_tables(sbci_ctx *ctx) {
+  free_spin(ctx->B);
+  free_spin(ctx->A);
+  hipFree(ctx->binom);
+  hipFree(ctx->h1);
+  hipFree(ctx->eri);
+  hipFree(ctx->W64);
+  hipFree(ctx->W32);
+  hipFree(ctx->Wbf);
+  hipFree(ctx->hdiag);
+  hipFree(ctx->hdiag32);
+  ctx->binom = nullptr;
+  ctx->h1 = ctx->eri = ctx->W64 = ctx->hdiag = nullptr;
+  ctx->W32 = ctx->hdiag32 = nullptr;
+  ctx->Wbf = nullptr;
+}
+
+}  // namespace sbci

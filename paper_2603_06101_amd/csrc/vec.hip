@@ -1,0 +1,317 @@
+// Vector passes of the SBCI step with FP64 reductions (HBM-bound kernels).
+//
+// k_update is the fused symplectic-Euler pass of one SBCI1 step:
+//   y <- sy*y - c*z,  Y <- sy*Y - c*Z            (Eqs. S25-S26 / S56-S57)
+//   x <- sx*x + b*y,  X <- sx*X + b*Y            (Eqs. S27-S28 / S58-S59)
+//   z' = (X - E x) * inv_norm                     (Eq. S60, Algorithm 1 line 12)
+//   w  = z' / (D - E0)                            (Eq. S31 before the projection)
+// and reduces, in FP64, every inner product the next step's Ritz problem
+// needs except those involving Z = H z (which exists only after the next
+// sigma): |z'|^2, x.x, x.y, y.y, x.X, x.Y, y.Y, optionally x.w, y.w, w.w, and
+// the projections x_c^i . w on the converged roots.  sx rescales x, X at the
+// start of a segment (a restart normalises x without a separate pass) and
+// sy = 0 drops y, Y (y_0 = 0 at a segment start).
+//
+// Reductions are deterministic: each block writes its partial sums, and the
+// last block to finish (an atomic ticket) adds the partials in block order.
+#include "internal.h"
+
+namespace sbci {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int MAXQ = 32;
+constexpr int MAXV = 16;
+
+struct Ptrs {
+  const void *p[MAXV];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Reduce v[0..nq) over the block; the last block of the grid writes out[q].
+template <int NQ>
+__device__ void grid_reduce(double (&v)[NQ], int nq, double *__restrict__ part,
+                            unsigned *__restrict__ ticket, double *__restrict__ out) {
+  __shared__ double sh[BS / 64][NQ];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q >= nq) break;
+    double s = wave_sum(v[q]);
+    if (lane == 0) sh[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    double s = 0;
+    for (int w = 0; w < BS / 64; ++w) s += sh[w][threadIdx.x];
+    part[(size_t)blockIdx.x * MAXQ + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x < nq) {
+      double s = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b)
+        s += __builtin_nontemporal_load(&part[(size_t)b * MAXQ + threadIdx.x]);
+      out[threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dots(int64_t n, const T *__restrict__ a, Ptrs bs, int nb,
+                                             double *part, unsigned *ticket, double *out) {
+  double v[MAXV];
+#pragma unroll
+  for (int q = 0; q < MAXV; ++q) v[q] = 0;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double ai = (double)a[i];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q)
+      if (q < nb) v[q] += ai * (double)static_cast<const T *>(bs.p[q])[i];
+  }
+  grid_reduce<MAXV>(v, nb, part, ticket, out);
+}
+
+struct Coefs {
+  double c[MAXV];
+};
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_lincomb(int64_t n, T *__restrict__ out, Ptrs xs, Coefs cf,
+                                                int nx, double beta) {
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double s = beta == 0.0 ? 0.0 : beta * (double)out[i];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q)
+      if (q < nx) s += cf.c[q] * (double)static_cast<const T *>(xs.p[q])[i];
+    out[i] = (T)s;
+  }
+}
+
+template <typename Td, typename Ts>
+__global__ __launch_bounds__(BS) void k_convert(int64_t n, Td *__restrict__ dst,
+                                                const Ts *__restrict__ src, double scale) {
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    dst[i] = (Td)(scale * (double)src[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_update(int64_t n, T *__restrict__ x, T *__restrict__ X,
+                                               T *__restrict__ y, T *__restrict__ Y,
+                                               const T *__restrict__ z, const T *__restrict__ Z,
+                                               T *__restrict__ w, const T *__restrict__ D, Ptrs xc,
+                                               UpdateArgs a, double *part, unsigned *ticket,
+                                               double *out) {
+  // slots: 0 |z'|^2, 1 xx, 2 xy, 3 yy, 4 xX, 5 xY, 6 yY, 7 xw, 8 yw, 9 ww, 10+j xc_j.w
+  double v[10 + MAXV];
+#pragma unroll
+  for (int q = 0; q < 10 + MAXV; ++q) v[q] = 0;
+  const double b = a.b, c = a.c, E = a.E, inv = a.inv_norm, E0 = a.E0, fl = a.floor, sx = a.sx;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double zi = 0, Zi = 0, yi = 0, Yi = 0;
+    if (a.read_z) {
+      zi = (double)z[i];
+      Zi = (double)Z[i];
+    }
+    if (a.sy) {
+      yi = (double)y[i];
+      Yi = (double)Y[i];
+    }
+    const double yn = yi - c * zi, Yn = Yi - c * Zi;
+    const double xn = sx * (double)x[i] + b * yn, Xn = sx * (double)X[i] + b * Yn;
+    const double r = (Xn - E * xn) * inv;
+    double den = (double)D[i] - E0;
+    if (fabs(den) < fl) den = fl;
+    const double wi = r / den;
+    x[i] = (T)xn;
+    X[i] = (T)Xn;
+    y[i] = (T)yn;
+    Y[i] = (T)Yn;
+    w[i] = (T)wi;
+    // reduce what was stored (the next step sees the rounded vectors)
+    const double xs = (double)(T)xn, ys = (double)(T)yn, Xs = (double)(T)Xn, Ys = (double)(T)Yn;
+    const double ws = (double)(T)wi;
+    v[0] += r * r;
+    v[1] += xs * xs;
+    v[2] += xs * ys;
+    v[3] += ys * ys;
+    v[4] += xs * Xs;
+    v[5] += xs * Ys;
+    v[6] += ys * Ys;
+    if (a.want_zdots) {
+      v[7] += xs * ws;
+      v[8] += ys * ws;
+      v[9] += ws * ws;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < a.nconv) v[10 + j] += ws * (double)static_cast<const T *>(xc.p[j])[i];
+  }
+  grid_reduce<10 + MAXV>(v, 10 + a.nconv, part, ticket, out);
+}
+
+// z = w - sum_j d_j xc_j (in place); reduces x.z, y.z, z.z
+template <typename T>
+__global__ __launch_bounds__(BS) void k_deflate(int64_t n, T *__restrict__ w, const T *__restrict__ x,
+                                                const T *__restrict__ y, Ptrs xc, int nconv,
+                                                const double *__restrict__ d, double *part,
+                                                unsigned *ticket, double *out) {
+  double dj[MAXV];
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) dj[j] = j < nconv ? d[j] : 0.0;
+  double v[3] = {0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double zi = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nconv) zi -= dj[j] * (double)static_cast<const T *>(xc.p[j])[i];
+    const T zt = (T)zi;
+    w[i] = zt;
+    const double zs = (double)zt;
+    v[0] += (double)x[i] * zs;
+    v[1] += (double)y[i] * zs;
+    v[2] += zs * zs;
+  }
+  grid_reduce<3>(v, 3, part, ticket, out);
+}
+
+// x.Z, y.Z, z.Z (H acting on the right-hand vector)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dots_xyz(int64_t n, const T *__restrict__ x,
+                                                 const T *__restrict__ y, const T *__restrict__ z,
+                                                 const T *__restrict__ Z, double *part,
+                                                 unsigned *ticket, double *out) {
+  double v[3] = {0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double Zi = (double)Z[i];
+    v[0] += (double)x[i] * Zi;
+    v[1] += (double)y[i] * Zi;
+    v[2] += (double)z[i] * Zi;
+  }
+  grid_reduce<3>(v, 3, part, ticket, out);
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + BS - 1) / BS;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+struct RedBuf {
+  double *part;
+  unsigned *ticket;
+};
+
+int red_buf(sbci_ctx *ctx, RedBuf &r) {
+  const size_t part_b = sizeof(double) * 2048 * MAXQ;
+  if (!ctx->ws_red.ptr) {
+    SBCI_TRY(ensure(ctx->ws_red, part_b + 256));
+    SBCI_HIP(hipMemsetAsync(ctx->ws_red.ptr, 0, part_b + 256, ctx->stream));
+  }
+  r.part = static_cast<double *>(ctx->ws_red.ptr);
+  r.ticket = reinterpret_cast<unsigned *>(static_cast<char *>(ctx->ws_red.ptr) + part_b);
+  return SBCI_OK;
+}
+
+}  // namespace
+
+template <typename T>
+int dots(sbci_ctx *ctx, int64_t n, const T *a, const T *const *bs, int nb, double *out) {
+  if (nb < 1 || nb > MAXV) return set_error(SBCI_EINVAL, "dots: 1..16 vectors");
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  Ptrs p{};
+  for (int i = 0; i < nb; ++i) p.p[i] = bs[i];
+  k_dots<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, a, p, nb, r.part, r.ticket, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename T>
+int lincomb(sbci_ctx *ctx, int64_t n, T *out, const T *const *xs, const double *coef, int nx,
+            double beta) {
+  if (nx < 0 || nx > MAXV) return set_error(SBCI_EINVAL, "lincomb: 0..16 vectors");
+  Ptrs p{};
+  Coefs cf{};
+  for (int i = 0; i < nx; ++i) {
+    p.p[i] = xs[i];
+    cf.c[i] = coef[i];
+  }
+  k_lincomb<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, out, p, cf, nx, beta);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename Td, typename Ts>
+int convert(sbci_ctx *ctx, int64_t n, Td *dst, const Ts *src, double scale) {
+  k_convert<Td, Ts><<<grid_for(n), BS, 0, ctx->stream>>>(n, dst, src, scale);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename T>
+int update(sbci_ctx *ctx, int64_t n, T *x, T *X, T *y, T *Y, const T *z, const T *Z, T *w,
+           const T *D, const T *const *xc, const UpdateArgs &a, double *out) {
+  if (a.nconv < 0 || a.nconv > MAXV) return set_error(SBCI_EINVAL, "update: too many roots");
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  Ptrs p{};
+  for (int i = 0; i < a.nconv; ++i) p.p[i] = xc[i];
+  k_update<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, y, Y, z, Z, w, D, p, a, r.part,
+                                                   r.ticket, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename T>
+int deflate(sbci_ctx *ctx, int64_t n, T *w, const T *x, const T *y, const T *const *xc, int nconv,
+            const double *d_coef, double *out) {
+  if (nconv < 0 || nconv > MAXV) return set_error(SBCI_EINVAL, "deflate: too many roots");
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  Ptrs p{};
+  for (int i = 0; i < nconv; ++i) p.p[i] = xc[i];
+  k_deflate<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, w, x, y, p, nconv, d_coef, r.part, r.ticket,
+                                                    out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename T>
+int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const T *Z, double *out) {
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  k_dots_xyz<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, y, z, Z, r.part, r.ticket, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+#define INST(T)                                                                                   \
+  template int dots<T>(sbci_ctx *, int64_t, const T *, const T *const *, int, double *);         \
+  template int lincomb<T>(sbci_ctx *, int64_t, T *, const T *const *, const double *, int, double); \
+  template int update<T>(sbci_ctx *, int64_t, T *, T *, T *, T *, const T *, const T *, T *,      \
+                         const T *, const T *const *, const UpdateArgs &, double *);              \
+  template int deflate<T>(sbci_ctx *, int64_t, T *, const T *, const T *, const T *const *, int,  \
+                          const double *, double *);                                              \
+  template int dots_xyz<T>(sbci_ctx *, int64_t, const T *, const T *, const T *, const T *, double *);
+INST(double)
+INST(float)
+#undef INST
+template int convert<double, float>(sbci_ctx *, int64_t, double *, const float *, double);
+template int convert<float, double>(sbci_ctx *, int64_t, float *, const double *, double);
+template int convert<double, double>(sbci_ctx *, int64_t, double *, const double *, double);
+template int convert<float, float>(sbci_ctx *, int64_t, float *, const float *, double);
+
+}  // namespace sbci

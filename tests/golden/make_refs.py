@@ -1,0 +1,62 @@
+"""Write tests/golden/refs.json: reference energies computed by the oracle only.
+
+Run:  python tests/golden/make_refs.py
+Contents (all FP64, electronic energies, Eh):
+  cas6   seed 0, rank 12: dense Slater-Condon eigh (lowest 6) and the oracle
+         SBCI1 energy from the start e_0 + 1e-3 * noise (one root);
+  cas10  seeds 0..9, rank 20: Lanczos eigsh on the oracle sigma (lowest 6,
+         tol 1e-14), oracle SBCI1 (3 roots, Section S1.1 start) and oracle
+         Davidson (3 roots).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from scipy.sparse.linalg import LinearOperator, eigsh  # noqa: E402
+
+from oracle import hamiltonian as H  # noqa: E402
+from oracle import sbci  # noqa: E402
+from oracle import sigma as S  # noqa: E402
+from workloads import make_integrals, start_noise  # noqa: E402
+
+
+def main():
+    out = {"generator": "tests/golden/make_refs.py", "cas6": {}, "cas10": {}}
+    n, na, nb, K = 6, 3, 3, 12
+    I = make_integrals(n, K, 0)
+    Hs = H.dense_h_slater_condon(n, na, nb, I.h1, I.eri)
+    w = np.linalg.eigvalsh(Hs)
+    op = S.Operator(n, na, nb, I.h1, I.eri)
+    x0 = np.zeros(op.ndet)
+    x0[0] = 1.0
+    x0 = x0 + 1e-3 * start_noise(n, K, 0, op.ndet)
+    r = sbci.sbci1(op, op.diag(), 1, x0=x0)
+    out["cas6"] = {"seed": 0, "rank": K, "eigh": w[:6].tolist(), "sbci1": r.energies.tolist(),
+                   "sbci1_nsigma": r.nsigma, "digest": I.digest()}
+    for seed in range(10):
+        t = time.time()
+        n, na, nb, K = 10, 5, 5, 20
+        I = make_integrals(n, K, seed)
+        op = S.Operator(n, na, nb, I.h1, I.eri)
+        L = LinearOperator((op.ndet, op.ndet), matvec=lambda v: S.sigma(n, na, nb, I.h1, I.eri, v),
+                           dtype=np.float64)
+        ev = np.sort(eigsh(L, k=6, which="SA", tol=1e-14)[0])
+        d = op.diag()
+        rs = sbci.sbci1(op, d, 3)
+        rd = sbci.davidson(op, d, 3)
+        out["cas10"][str(seed)] = {"rank": K, "eigsh": ev.tolist(), "sbci1": rs.energies.tolist(),
+                                   "sbci1_nsigma": rs.nsigma, "davidson": rd.energies.tolist(),
+                                   "davidson_nsigma": rd.nsigma, "digest": I.digest()}
+        print(seed, ev[:3], rs.energies, rd.energies, f"{time.time() - t:.1f}s", flush=True)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "refs.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,124 @@
+"""GPU parity of tables, diagonal and sigma against the CPU oracle (through the C ABI)."""
+from math import comb
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sigma as OS  # noqa: E402
+from oracle import strings as OST  # noqa: E402
+from workloads import make_integrals, sigma_inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(n, na, nb, rank=None, seed=0):
+    import paper_2603_06101_amd as sb
+    I = make_integrals(n, rank or 2 * n, seed)
+    return sb.Context(n, na, nb, I.h1, I.eri), I
+
+
+TABLE_CASES = [(1, 0, 1), (4, 0, 2), (4, 2, 2), (5, 5, 2), (6, 3, 3), (7, 4, 2), (8, 4, 4),
+               (10, 5, 5), (12, 3, 6), (14, 7, 7), (16, 8, 8)]
+
+
+@pytest.mark.parametrize("n,na,nb", TABLE_CASES)
+def test_tables_bit_exact(n, na, nb):
+    import paper_2603_06101_amd as sb
+    ctx, _ = _ctx(n, na, nb)
+    for spin, m in ((0, na), (1, nb)):
+        strs = ctx.tables(spin).cpu().numpy().view(np.uint64)
+        assert np.array_equal(strs, OST.strings(n, m))
+        raw = ctx.tables(2 + spin)
+        s = m * (n - m + 1)
+        got = sb.decode_table(raw, comb(n, m), s)
+        want = OST.packed_table(n, m)
+        assert got.tobytes() == want.tobytes()
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,na,nb", [(4, 2, 2), (6, 3, 3), (7, 4, 2), (10, 5, 5), (14, 7, 7)])
+def test_hdiag(n, na, nb):
+    ctx, I = _ctx(n, na, nb)
+    d = ctx.hdiag().cpu().numpy()
+    want = OS.hdiag(n, na, nb, I.h1, I.eri, ctx.ndet)
+    assert np.abs(d - want).max() <= 1e-14 * np.abs(want).max()
+    ctx.close()
+
+
+SIGMA_CASES = [(1, 1, 0), (2, 1, 1), (4, 0, 2), (4, 2, 2), (5, 5, 5), (5, 2, 3), (6, 3, 3),
+               (7, 4, 2), (8, 4, 4), (9, 4, 5), (10, 5, 5), (11, 3, 4), (12, 6, 6)]
+
+
+@pytest.mark.parametrize("n,na,nb", SIGMA_CASES)
+def test_sigma_f64_parity(n, na, nb):
+    ctx, I = _ctx(n, na, nb, seed=1)
+    nvec = 2
+    c = sigma_inputs(3, nvec, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,na,nb", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (9, 4, 5)])
+def test_sigma_low_precision_error(n, na, nb, dtype, tol):
+    ctx, I = _ctx(n, na, nb, seed=2)
+    c = sigma_inputs(4, 1, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    got = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype=dtype).cpu().numpy()
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < tol, rel
+    ctx.close()
+
+
+def test_sigma_invariants_full_size_cas14():
+    """cas14 (11.8 M determinants): sampled rows against the oracle, symmetry, linearity."""
+    n, na, nb, K = 14, 7, 7, 28
+    ctx, I = _ctx(n, na, nb, rank=K)
+    c = sigma_inputs(0, 2, ctx.ndet)
+    ct = torch.from_numpy(c).cuda()
+    s = ctx.sigma(ct)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([[0, ctx.ndet - 1], rng.integers(0, ctx.ndet, 300)]))
+    want = OS.sigma_rows(n, na, nb, I.h1, I.eri, c[0], rows)
+    got = s[0].cpu().numpy()[rows]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # u^T H v = v^T H u and linearity
+    u, v = ct[0], ct[1]
+    a = float(u @ s[1])
+    b = float(v @ s[0])
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0) * 10
+    lin = ctx.sigma((0.5 * ct[0] - 2.0 * ct[1]).contiguous())
+    assert float((lin - (0.5 * s[0] - 2.0 * s[1])).abs().max()) <= 1e-12 * float(s.abs().max())
+    # transpose symmetry (n_alpha = n_beta): sigma(C^T) = sigma(C)^T
+    ns = comb(n, na)
+    tt = ctx.sigma(ct[0].view(ns, ns).t().contiguous().view(-1))
+    assert float((tt.view(ns, ns) - s[0].view(ns, ns).t()).abs().max()) <= 1e-12 * float(s.abs().max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_sigma_full_size_cas16_sampled(dtype):
+    """cas16 (165.6 M determinants), nvec = 1: sampled rows against the oracle."""
+    n, na, nb, K = 16, 8, 8, 32
+    ctx, I = _ctx(n, na, nb, rank=K)
+    c = sigma_inputs(0, 1, ctx.ndet)[0]
+    if dtype == "f64":
+        ct = torch.from_numpy(c).cuda()
+    else:
+        ct = torch.from_numpy(c.astype(np.float32)).cuda()
+    s = ctx.sigma(ct, dtype=dtype)
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([[0, ctx.ndet - 1], rng.integers(0, ctx.ndet, 200)]))
+    want = OS.sigma_rows(n, na, nb, I.h1, I.eri, c, rows)
+    got = s.cpu().numpy()[rows].astype(np.float64)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-2}[dtype]
+    assert err <= tol, err
+    del s, ct
+    ctx.close()
+    torch.cuda.empty_cache()

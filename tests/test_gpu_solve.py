@@ -1,0 +1,145 @@
+"""GPU SBCI1 / Davidson solves against the oracle (through the C ABI)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import hamiltonian as H  # noqa: E402
+from oracle import sbci as OSB  # noqa: E402
+from oracle import sigma as OS  # noqa: E402
+from workloads import make_integrals, start_noise  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REFS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "refs.json")))
+
+
+def _ctx(n, na, nb, rank, seed):
+    import paper_2603_06101_amd as sb
+    I = make_integrals(n, rank, seed)
+    return sb.Context(n, na, nb, I.h1, I.eri), I
+
+
+def _cas6_start(ndet):
+    x0 = np.zeros(ndet)
+    x0[0] = 1.0
+    return x0 + 1e-3 * start_noise(6, 12, 0, ndet)
+
+
+def test_cas6_noise_start_matches_oracle():
+    ctx, I = _ctx(6, 3, 3, 12, 0)
+    assert REFS["cas6"]["digest"] == I.digest()
+    r = ctx.solve(1, tol=1e-10, x0=_cas6_start(ctx.ndet))
+    assert r.status == 0
+    E = r.energies[0]
+    assert abs(E - REFS["cas6"]["sbci1"][0]) < 1e-8
+    w = np.array(REFS["cas6"]["eigh"])
+    assert np.min(np.abs(w - E)) < 1e-8
+    x = r.vectors[0].cpu().numpy()
+    Hs = H.dense_h_slater_condon(6, 3, 3, I.h1, I.eri)
+    assert np.linalg.norm(Hs @ x - E * x) < 1e-5
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+    ctx.close()
+
+
+def test_cas6_step_trajectory_matches_oracle():
+    """Per-step energies, b, c and |x| of the GPU solver follow the oracle's steps."""
+    ctx, I = _ctx(6, 3, 3, 12, 0)
+    x0 = _cas6_start(ctx.ndet)
+    op = OS.Operator(6, 3, 3, I.h1, I.eri)
+    ref = OSB.sbci1(op, op.diag(), 1, x0=x0)
+    ctx.begin(1, tol=1e-10, x0=x0)
+    steps = []
+    done = False
+    while not done:
+        info, done = ctx.step()
+        steps.append(info)
+    res = ctx.finish()
+    assert len(steps) == len(ref.steps)
+    for g, o in zip(steps, ref.steps):
+        assert (g["root"], g["segment"], g["t"]) == (o.root, o.segment, o.t)
+        assert abs(g["E"] - o.E) < 1e-10
+        assert abs(g["b"] - o.b) < 1e-7 * max(1, abs(o.b))
+        assert abs(g["c"] - o.c) < 1e-7 * max(1, abs(o.c))
+        assert abs(g["xnorm"] - o.xnorm) < 1e-9
+        assert g["reason"] == (o.reason or "")
+    assert abs(res.energies[0] - ref.energies[0]) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_cas10_sbci_and_davidson(seed):
+    ref = REFS["cas10"][str(seed)]
+    ctx, I = _ctx(10, 5, 5, 20, seed)
+    assert ref["digest"] == I.digest()
+    r = ctx.solve(3, tol=1e-10)
+    assert r.status == 0
+    # same algorithm, same start: the oracle's SBCI1 energies, root by root
+    assert np.abs(r.energies - np.array(ref["sbci1"])).max() < 1e-8
+    ev = np.array(ref["eigsh"])
+    for E in r.energies:
+        assert np.min(np.abs(ev - E)) < 1e-8 or E > ev[-1]
+    X = r.vectors
+    G = (X @ X.T).cpu().numpy()
+    assert np.abs(G - np.eye(3)).max() < 1e-8
+    d = ctx.davidson(3, tol=1e-10)
+    assert d.status == 0
+    assert np.abs(d.energies - ev[:3]).max() < 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_cas10_mixed_precision_reaches_fp64(prec):
+    ref = REFS["cas10"]["0"]
+    ctx, _ = _ctx(10, 5, 5, 20, 0)
+    r = ctx.solve(3, tol=1e-10, opts=dict(precision=prec))
+    assert r.status == 0
+    assert np.abs(r.energies - np.array(ref["sbci1"])).max() < 1e-8
+    assert r.report["nsigma_low"] > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,na,nb,nroots,seed", [(7, 4, 3, 2, 0), (6, 2, 3, 2, 1), (8, 4, 4, 3, 3)])
+def test_small_cases_match_oracle(n, na, nb, nroots, seed):
+    ctx, I = _ctx(n, na, nb, 2 * n, seed)
+    op = OS.Operator(n, na, nb, I.h1, I.eri)
+    ref = OSB.sbci1(op, op.diag(), nroots)
+    r = ctx.solve(nroots, tol=1e-10)
+    assert np.abs(r.energies - ref.energies).max() < 1e-8
+    d = ctx.davidson(nroots, tol=1e-10)
+    rd = OSB.davidson(op, op.diag(), nroots)
+    assert np.abs(d.energies - rd.energies).max() < 1e-8
+    ctx.close()
+
+
+def test_single_determinant_space():
+    ctx, I = _ctx(5, 5, 5, 10, 0)
+    assert ctx.ndet == 1
+    r = ctx.solve(1, tol=1e-10)
+    want = H.dense_h_slater_condon(5, 5, 5, I.h1, I.eri)[0, 0]
+    assert abs(r.energies[0] - want) < 1e-12
+    ctx.close()
+
+
+def test_solve_rejects_bad_arguments():
+    import paper_2603_06101_amd as sb
+    ctx, _ = _ctx(4, 2, 2, 8, 0)
+    with pytest.raises(sb.SbciError):
+        ctx.solve(0)
+    with pytest.raises(sb.SbciError):
+        ctx.solve(37)
+    with pytest.raises(sb.SbciError):
+        ctx.solve(1, opts=dict(precision=7))
+    ctx.close()
+
+
+def test_step_cap_reports_noconv():
+    import paper_2603_06101_amd as sb
+    ctx, _ = _ctx(8, 4, 4, 16, 0)
+    r = ctx.solve(1, tol=1e-10, opts=dict(max_steps=3))
+    assert r.status == sb.SBCI_ENOCONV
+    assert np.isfinite(r.energies[0])
+    ctx.close()
