@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the SBCI sigma/solve hot path on one MI355X.
+
+One step = one pass of the whole path on the workload: build the context
+(strings, excitation and pair tables, same-spin lists, diagonal) from the
+integrals already on the host, then solve the lowest nroots states with
+SBCI1 in the precision form (low-precision sigma phase + FP64 refinement) to
+the paper's thresholds (eps0 = 1e-10, r0 = 1e-5), so every root is within
+1e-8 Eh of the FP64 solution.
+
+Reported (one JSON line):
+  value        sigma determinant-applications per second over the whole step
+               (sum over sigma calls of N_det, divided by the step time), Gdet/s;
+  ms_per_step  time to |dE| < 1e-8 for all roots (mixed form), including the
+               context build;
+  fp64         the same solve with FP64 sigma only (reference form), timed
+               once outside the timed region, and its agreement with the
+               mixed energies;
+  sigma        per-precision sigma throughput (Gdet/s per root) and the
+               per-kernel durations measured with HIP events on the
+               library's stream;
+  roofline     the dominant kernel of the step against the MI355X peak;
+  cpu_baseline the CPU oracle's plain FP64 string sigma on the host cores,
+               on a bounded sample of determinant rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cas14", choices=["cas6", "cas10", "cas14", "cas16"])
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sigma-reps", type=int, default=5)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, I, ndet, seconds):
+    import numpy as np
+
+    from oracle import sigma as OS
+    from workloads import sigma_inputs
+    c = sigma_inputs(0, 1, ndet)[0]
+    rng = np.random.default_rng(11)
+    n = 2000
+    rows = rng.integers(0, ndet, n)
+    t = time.perf_counter()
+    OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
+    dt = time.perf_counter() - t
+    n2 = int(max(2000, min(5e6, n * seconds / max(dt, 1e-6))))
+    rows = rng.integers(0, ndet, n2)
+    t = time.perf_counter()
+    OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n2 / dt / 1e9, "unit": "Gdet/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n2} random determinant rows of the FP64 string sigma "
+                      f"({cfg['norb']} orbitals, {ndet} determinants), {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the multi-GPU sharding is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2603_06101_amd as sb
+    from workloads import CONFIGS, make_integrals, sigma_inputs
+
+    cfg = CONFIGS[a.workload]
+    nroots = cfg["nroots"]
+    I = make_integrals(cfg["norb"], cfg["rank"], cfg["seed"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    def step(prec):
+        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+        r = ctx.solve(nroots, tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+        ctx.close()
+        return r
+
+    for _ in range(a.warmup):
+        step(a.precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step(a.precision) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / a.steps * 1e3
+    last = res[-1]
+    ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+    ndet = ctx.ndet
+    nsig_f64 = sum(r.report["nsigma_f64"] for r in res) / a.steps
+    nsig_low = sum(r.report["nsigma_low"] for r in res) / a.steps
+    value = ndet * (nsig_f64 + nsig_low) / (ms / 1e3) / 1e9
+
+    # reference form: FP64 sigma throughout (outside the timed region)
+    t = time.perf_counter()
+    ref = ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"), want_vectors=False)
+    torch.cuda.synchronize()
+    t_f64 = time.perf_counter() - t
+    dE = float(np.max(np.abs(np.sort(ref.energies) - np.sort(last.energies))))
+
+    # sigma per precision, per kernel (HIP events on the library stream)
+    parts = ["same_alpha", "opp_mfma", "transpose", "same_beta", "add_t"]
+    sig = {}
+    c64 = torch.from_numpy(sigma_inputs(0, 1, ndet)[0]).cuda()
+    for dt in ["f64", "f32", "bf16"]:
+        c = c64 if dt == "f64" else c64.float()
+        out, _ = ctx.sigma_timed(c, dt)
+        runs = [ctx.sigma_timed(c, dt, out=out)[1] for _ in range(a.sigma_reps)]
+        med = np.median(np.array(runs), axis=0)
+        sig[dt] = {"gdet_per_s": ndet / (med.sum() / 1e3) / 1e9, "ms": float(med.sum()),
+                   "kernels_ms": dict(zip(parts, [round(float(v), 4) for v in med]))}
+    del c64, out
+    ctx.close()
+
+    # dominant kernel of the step: sigma calls x per-kernel time
+    counts = {"f64": nsig_f64}
+    counts[a.precision] = counts.get(a.precision, 0.0) + nsig_low
+    share = {(p, dt): cnt * sig[dt]["kernels_ms"][p] for dt, cnt in counts.items() for p in parts}
+    (kname, kdt), _ = max(share.items(), key=lambda kv: kv[1])
+    na_s = cfg["na"] * (cfg["norb"] - cfg["na"] + 1)
+    k_ms = sig[kdt]["kernels_ms"][kname]
+    if kname == "opp_mfma":
+        flops = 2.0 * na_s * na_s * ndet       # minimum opposite-spin flops per determinant: 2 s^2
+        roof = {"bound": "mfma", "achieved": flops / (k_ms / 1e3) / 1e12,
+                "peak": PEAK[kdt] / 1e12, "unit": "TFLOP/s"}
+    else:
+        esz = 8 if kdt == "f64" else 4
+        byts = 2.0 * esz * ndet
+        roof = {"bound": "hbm", "achieved": byts / (k_ms / 1e3) / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"{kname} ({kdt})"
+    roof["ms_per_launch"] = k_ms
+
+    line = {
+        "metric": "sigma=H.c Gdet/s per root; time to |dE|<1e-8 Eh, mixed vs FP64 SBCI",
+        "value": round(value, 4),
+        "unit": "Gdet/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16": "bf16+f32+f64"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": a.workload, "norb": cfg["norb"], "nalpha": cfg["na"],
+                   "nbeta": cfg["nb"], "ndet": ndet, "nroots": nroots, "eri_rank": cfg["rank"],
+                   "seed": cfg["seed"], "precision": a.precision, "parallelism": "1 GPU"},
+        "time_to_1e8_s": {"mixed": round(ms / 1e3, 4), "fp64": round(t_f64, 4),
+                          "speedup": round(t_f64 / (ms / 1e3), 3)},
+        "energies": [float(e) for e in last.energies],
+        "max_abs_dE_vs_fp64": dE,
+        "nsigma": {"f64": nsig_f64, "low": nsig_low},
+        "sigma": sig,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,13 @@ int sbci_hdiag(sbci_ctx *ctx, double *dev_out);
  * overlap.  Asynchronous on the context stream. */
 int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype);
 
+/* The same sigma, synchronously, with HIP events recorded on the context
+ * stream around its five kernels; ms_parts (host [5]) receives the elapsed
+ * milliseconds of: same-spin alpha lists, opposite-spin MFMA contraction,
+ * transpose of c, same-spin beta lists on the transpose, transposed add. */
+int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype,
+                     float *ms_parts);
+
 /* SBCI1 (Algorithm 1 with Sections S1.1-S1.5) for the lowest nroots states.
  * tol > 0 overrides opt: eps0 = tol, r0 = sqrt(tol) (the paper's two pairs,
  * 1e-10/1e-5 and 1e-8/1e-4, both have r0 = sqrt(eps0)); tol <= 0 keeps opt.

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("sbci_tables", _I, [_P, _I, _P, ctypes.POINTER(_I64)]),
     ("sbci_hdiag", _I, [_P, _P]),
     ("sbci_sigma", _I, [_P, _P, _P, _I, _I]),
+    ("sbci_sigma_timed", _I, [_P, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
     ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
     ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
@@ -208,6 +209,18 @@ class Context:
         _check(lib().sbci_sigma(self.h, ctypes.c_void_p(c.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), nvec, code))
         return out
+
+    def sigma_timed(self, c, dtype="f64", out=None):
+        """sigma with per-kernel HIP-event timings: (out, [alpha, opp, transpose, beta, add] ms)."""
+        torch = _torch()
+        code = DTYPES[dtype] if isinstance(dtype, str) else dtype
+        nvec = 1 if c.dim() == 1 else c.shape[0]
+        if out is None:
+            out = torch.empty_like(c)
+        ms = (ctypes.c_float * 5)()
+        _check(lib().sbci_sigma_timed(self.h, ctypes.c_void_p(c.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), nvec, code, ms))
+        return out, [float(v) for v in ms]
 
     def _run(self, fn, nroots, tol, opts, want_vectors):
         torch = _torch()

@@ -213,6 +213,16 @@ int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int 
   return sigma(ctx, dev_c, dev_sigma, nvec, dtype);
 }
 
+int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype,
+                     float *ms_parts) {
+  if (!ms_parts) return set_error(SBCI_EINVAL, "ms_parts is NULL");
+  if (!ctx || !dev_c || !dev_sigma) return set_error(SBCI_EINVAL, "NULL argument");
+  if (nvec < 1 || nvec > 65535) return set_error(SBCI_EINVAL, "nvec must be in [1, 65535]");
+  if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
+    return set_error(SBCI_EINVAL, "unknown dtype");
+  return sigma_profile(ctx, dev_c, dev_sigma, nvec, dtype, ms_parts);
+}
+
 int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {
   if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
   return solver_begin(ctx, nroots, tol, opt);

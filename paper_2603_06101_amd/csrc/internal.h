@@ -22,9 +22,12 @@ struct Ent {
 };
 static_assert(sizeof(Ent) == 8, "Ent must be 8 bytes");
 
-// Scatter code of the pair tables: target string with the sign folded in.
-// code >= 0: +1 * string code; code < 0 and != kInvalid: -1 * string ~code.
-constexpr int32_t kInvalid = INT32_MIN;
+// Scatter code of the pair tables: (target string << 1) | (sign < 0);
+// kInvalid marks a pair that does not connect the string to any other.
+constexpr uint32_t kInvalid = 0xffffffffu;
+// Pair-table rows are padded with kInvalid (to 16 * (ceil(npair / 16) + 9)
+// rows) so that the MFMA tiles of the opposite-spin kernel, in any grouping
+// of at most 9 tiles, never need a row bound.
 
 struct SpinTables {
   int m = 0;                // electrons of this spin
@@ -33,7 +36,8 @@ struct SpinTables {
   int nf = 0;               // same-spin list length 1 + m(N-m) + C(m,2)C(N-m,2)
   uint64_t *str = nullptr;  // [ns]
   Ent *tab = nullptr;       // [ns][s]
-  int32_t *pair = nullptr;  // [npair][ns] scatter codes
+  uint32_t *pair = nullptr; // [npair_pad][ns_pad] scatter codes
+  int64_t ns_pad = 0;       // ns rounded up to 16 (pair-table row stride)
   int32_t *fcol = nullptr;  // [ns][nf] same-spin list columns
   double *fval64 = nullptr; // [ns][nf] FP64 values
   float *fval32 = nullptr;  // [ns][nf] FP32 values
@@ -53,6 +57,7 @@ struct Solver;  // SBCI1 driver state (solver.hip)
 struct sbci_ctx {
   int norb = 0, na = 0, nb = 0;
   int npair = 0;
+  int npair_pad = 0;              // padded pair-table rows
   int64_t ndet = 0;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -107,6 +112,9 @@ void free_tables(sbci_ctx *ctx);
 // sigma = H c for nvec vectors of element type T (double or float).
 // mode: SBCI_F64 (T = double), SBCI_F32 or SBCI_BF16 (T = float).
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
+// Same, with HIP events around its five parts; ms[0..4] = alpha lists,
+// opposite spin, transpose, beta lists, transposed add (milliseconds).
+int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms);
 
 // ---- vec.hip: vector kernels with FP64 reductions ----
 // Reductions write `nq` doubles to `out` (device); deterministic order.

@@ -65,78 +65,127 @@ __global__ void k_add_t(const T *__restrict__ src, T *__restrict__ dst, int64_t 
   }
 }
 
-// One wave per list row r, 64 consecutive columns per wave.
-template <typename T, typename V, int WAVES>
+// One wave per list row r; each lane owns VC columns c, c + 64, ... so that
+// every load instruction of the wave reads 64 consecutive elements.  Work
+// items (row group, column tile) are numbered column-tile-major and dealt to
+// the 8 XCDs in contiguous ranges (workgroup b runs on XCD b % 8), so each
+// XCD streams its own column tiles and its L2 holds one tile's source rows.
+template <typename T, typename V, int WAVES, int VC>
 __global__ __launch_bounds__(64 * WAVES) void k_same(
     const int32_t *__restrict__ fcol, const V *__restrict__ fval, int nf, int64_t R, int64_t C,
-    const T *__restrict__ src, T *__restrict__ dst, int accumulate) {
+    const T *__restrict__ src, T *__restrict__ dst, int accumulate, int64_t rgroups,
+    int64_t per_xcd, int64_t total) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WAVES + (threadIdx.x >> 6)));
+  const int64_t b = blockIdx.x;
+  const int64_t w = (b & 7) * per_xcd + (b >> 3);
+  if (w >= total) return;
+  const int64_t ct = w / rgroups, rg = w - ct * rgroups;
+  const int64_t r = __builtin_amdgcn_readfirstlane((int)(rg * WAVES + (threadIdx.x >> 6)));
   if (r >= R) return;
-  const int64_t c = (int64_t)blockIdx.y * 64 + lane;
-  const bool ok = c < C;
-  const int64_t cc = ok ? c : C - 1;
   const int64_t vo = (int64_t)blockIdx.z * R * C;
-  const T *__restrict__ s = src + vo + cc;
+  const int64_t c0 = ct * 64 * VC + lane;
+  const T *__restrict__ s[VC];
+#pragma unroll
+  for (int u = 0; u < VC; ++u) {
+    int64_t c = c0 + 64 * u;
+    s[u] = src + vo + (c < C ? c : C - 1);
+  }
   const int32_t *__restrict__ col = fcol + r * nf;
   const V *__restrict__ val = fval + r * nf;
-  T acc0 = 0, acc1 = 0;
+  T acc[VC];
+#pragma unroll
+  for (int u = 0; u < VC; ++u) acc[u] = 0;
+  constexpr int UN = 8;
   int e = 0;
-  for (; e + 8 <= nf; e += 8) {
-    T v[8];
+  for (; e + UN <= nf; e += UN) {
+    T v[UN][VC];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = s[(int64_t)col[e + u] * C];
+    for (int k = 0; k < UN; ++k) {
+      const int64_t off = (int64_t)col[e + k] * C;
 #pragma unroll
-    for (int u = 0; u < 8; u += 2) {
-      acc0 += (T)val[e + u] * v[u];
-      acc1 += (T)val[e + u + 1] * v[u + 1];
+      for (int u = 0; u < VC; ++u) v[k][u] = s[u][off];
+    }
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      const T f = (T)val[e + k];
+#pragma unroll
+      for (int u = 0; u < VC; ++u) acc[u] += f * v[k][u];
     }
   }
-  for (; e < nf; ++e) acc0 += (T)val[e] * s[(int64_t)col[e] * C];
-  if (ok) {
-    T *d = dst + vo + r * C + c;
-    *d = accumulate ? *d + (acc0 + acc1) : (acc0 + acc1);
+  for (; e < nf; ++e) {
+    const int64_t off = (int64_t)col[e] * C;
+    const T f = (T)val[e];
+#pragma unroll
+    for (int u = 0; u < VC; ++u) acc[u] += f * s[u][off];
+  }
+#pragma unroll
+  for (int u = 0; u < VC; ++u) {
+    int64_t c = c0 + 64 * u;
+    if (c < C) {
+      T *d = dst + vo + r * C + c;
+      *d = accumulate ? *d + acc[u] : acc[u];
+    }
   }
 }
 
 // MFMA flavours of the opposite-spin contraction.
+//   A     element type of the ERI tile in LDS (and of the B fragments)
+//   Acc   accumulation type of sigma's row in LDS (FP64 in every flavour:
+//         measured on gfx950, ds_add_f64 sustains several times the rate of
+//         ds_add_f32 for this scatter, and it is more accurate)
+//   KSTEP K per MFMA, KPL K elements per lane
+//   orow  output row held by lane group g, register r (measured on gfx950:
+//         the f64 16x16x4 result interleaves its rows across lane groups)
 struct MF64 {
-  using A = double;      // LDS element of the A (ERI) and B (gathered C) tiles
-  using Acc = double;    // LDS accumulation of sigma's row
+  using A = double;
+  using Acc = double;
   using Frag = double;
   using Out = d4_t;
-  static constexpr int KSTEP = 4;   // K per MFMA
-  static constexpr int KPL = 1;     // K elements per lane per MFMA
-  // output row held by lane group g, register r (measured on gfx950: the
-  // f64 16x16x4 result interleaves rows across lane groups)
+  static constexpr int KSTEP = 4, KPL = 1, PAD = 1;
   __device__ static int orow(int g, int r) { return g + 4 * r; }
   template <typename T> __device__ static A cvt(T x) { return (A)x; }
+  __device__ static Frag load_a(const A *p) { return *p; }
+  template <typename T>
+  __device__ static Frag load_b(const T *cv, const uint32_t *off, uint32_t J) {
+    return (Frag)cv[off[0] + J];
+  }
   __device__ static Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
 struct MF32 {
   using A = float;
-  using Acc = float;
+  using Acc = double;  // FP64 LDS atomics are far faster than FP32 ones on gfx950
   using Frag = float;
   using Out = f4_t;
-  static constexpr int KSTEP = 4;
-  static constexpr int KPL = 1;
+  static constexpr int KSTEP = 4, KPL = 1, PAD = 1;
   __device__ static int orow(int g, int r) { return 4 * g + r; }
   template <typename T> __device__ static A cvt(T x) { return (A)x; }
+  __device__ static Frag load_a(const A *p) { return *p; }
+  template <typename T>
+  __device__ static Frag load_b(const T *cv, const uint32_t *off, uint32_t J) {
+    return (Frag)cv[off[0] + J];
+  }
   __device__ static Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 struct MBF16 {
   using A = __bf16;
-  using Acc = float;
+  using Acc = double;
   using Frag = bf8_t;
   using Out = f4_t;
-  static constexpr int KSTEP = 32;
-  static constexpr int KPL = 8;
+  static constexpr int KSTEP = 32, KPL = 8, PAD = 0;
   __device__ static int orow(int g, int r) { return 4 * g + r; }
   template <typename T> __device__ static A cvt(T x) { return (__bf16)(float)x; }
+  __device__ static Frag load_a(const A *p) { return *reinterpret_cast<const bf8_t *>(p); }
+  template <typename T>
+  __device__ static Frag load_b(const T *cv, const uint32_t *off, uint32_t J) {
+    Frag f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) f[t] = (__bf16)(float)cv[off[t] + J];
+    return f;
+  }
   __device__ static Out mma(Frag a, Frag b, Out c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -147,180 +196,324 @@ __device__ __forceinline__ int pair_index(int p, int q) {
   return k * (k + 1) / 2 + l;
 }
 
-// LDS layout (dynamic): acc[nsb] | Ws[MROWS][KW + PAD] | Rt[16][KW + PAD] | eJ[s] | eW[s]
-// KW = kc_steps * KSTEP (K columns in one chunk), MROWS = Mt * 16.
-template <typename M, typename T, int MTW>
-__global__ __launch_bounds__(256) void k_opp(
-    int64_t nsa, int64_t nsb, int s, int npair, int Mt, int kc_steps,
+constexpr int32_t kPadEntry = -1;  // K padding: zero column of A
+
+// Opposite-spin contraction, one output row Ia (of one vector) per
+// workgroup of NW waves.
+//   M[kl][J] = sum_e sign_e (kl|kl_e) C[J_e][J]     e over the alpha
+//              single excitations (p_e, q_e, J_e, sign_e) of Ia (incl. diagonal)
+//   sigma[Ia][I'] += sign' M[kl][J]                 for E_kl or E_lk |J> = sign' |I'>
+// LDS (dynamic): acc[nsb + 64] | Ws[ngroups*MG*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
+//   acc  sigma's row Ia; the 64 extra slots absorb the lanes whose pair
+//        code is invalid, so the scatter needs no branch
+//   Ws   A tile of one K chunk: sign_e (kl|kl_e), zero for padded rows / K
+//   eoff row offset J_e * nsb of the C row feeding K element e
+// Each wave owns 16-column tiles J0 = 16 (wave + NW i).  It gathers the B
+// fragment C[J_e][J0 + li] straight from global memory into registers (the
+// next tile's fragment is fetched before the current tile's MFMAs), runs all
+// M tiles of its group, and scatters through the packed pair codes.  K and M
+// are padded to compile-time tile counts, so the inner loops carry no bound
+// checks; no workgroup barrier sits inside the column loop.
+template <typename M, typename T, int MG, int KS, bool AREG, int NW>
+__global__ __launch_bounds__(64 * NW) void k_opp(
+    int64_t nsa, int64_t nsb, int64_t nsb_pad, int s, int npair, int ngroups, int nkc,
     const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
-    const int32_t *__restrict__ pairb, const T *__restrict__ c, T *__restrict__ sigma) {
+    const uint32_t *__restrict__ pairb, const T *__restrict__ c, T *__restrict__ sigma) {
   using A = typename M::A;
   using Acc = typename M::Acc;
+  using Frag = typename M::Frag;
+  constexpr int KW = KS * M::KSTEP;
+  constexpr int LDW = KW + M::PAD;
+  constexpr int GROWS = MG * 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ia = blockIdx.x;
   const int64_t vo = (int64_t)blockIdx.y * nsa * nsb;
-  const int KW = kc_steps * M::KSTEP;
-  const int LDW = KW + (M::KPL == 1 ? 1 : 8);  // padded row stride (elements)
-  const int MROWS = Mt * 16;
+  const int MROWS = ngroups * GROWS;
+  const int ktot = nkc * KW;
   Acc *acc = reinterpret_cast<Acc *>(smem);
-  size_t off = ((size_t)nsb * sizeof(Acc) + 15) & ~(size_t)15;
+  size_t off = ((size_t)(nsb + 64) * sizeof(Acc) + 15) & ~(size_t)15;
   A *Ws = reinterpret_cast<A *>(smem + off);
   off += (((size_t)MROWS * LDW * sizeof(A)) + 15) & ~(size_t)15;
-  A *Rt = reinterpret_cast<A *>(smem + off);
-  off += (((size_t)16 * LDW * sizeof(A)) + 15) & ~(size_t)15;
-  int32_t *eJ = reinterpret_cast<int32_t *>(smem + off);
-  off += (size_t)s * sizeof(int32_t);
-  int32_t *eW = reinterpret_cast<int32_t *>(smem + off);  // pair index, sign in bit 31
+  uint32_t *eoff = reinterpret_cast<uint32_t *>(smem + off);
+  off += (size_t)ktot * sizeof(uint32_t);
+  int32_t *eW = reinterpret_cast<int32_t *>(smem + off);
 
-  for (int e = tid; e < s; e += 256) {
-    Ent t = taba[ia * s + e];
-    eJ[e] = t.J;
-    int kl = pair_index(t.p, t.q);
-    eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
+  for (int e = tid; e < ktot; e += 64 * NW) {
+    if (e < s) {
+      Ent t = taba[ia * s + e];
+      eoff[e] = (uint32_t)t.J * (uint32_t)nsb;
+      int kl = pair_index(t.p, t.q);
+      eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
+    } else {
+      eoff[e] = (uint32_t)ia * (uint32_t)nsb;  // any valid row: its A column is zero
+      eW[e] = kPadEntry;
+    }
   }
-  for (int64_t j = tid; j < nsb; j += 256) acc[j] = (Acc)0;
-  __syncthreads();
+  for (int64_t j = tid; j < nsb + 64; j += 64 * NW) acc[j] = (Acc)0;
 
   const T *__restrict__ cv = c + vo;
-  const int nkc = (s + KW - 1) / KW;
-  const int64_t njt = (nsb + 15) / 16;
-  const int g = lane >> 4;   // lane group 0..3
+  const uint32_t nsb32 = (uint32_t)nsb;
+  const uint32_t pstride = (uint32_t)nsb_pad;
+  const int njt = (int)((nsb + 15) / 16);
+  const int g = lane >> 4;
   const int li = lane & 15;
 
   for (int kc = 0; kc < nkc; ++kc) {
-    const int e0 = kc * KW;
-    // A tile: Ws[row][k] = sign_e * (row | kl_e) for e = e0 + k
-    for (int idx = tid; idx < MROWS * KW; idx += 256) {
-      int row = idx / KW, k = idx - row * KW;
-      int e = e0 + k;
+    __syncthreads();  // entries ready; the previous chunk's Ws is no longer read
+    for (int idx = tid; idx < MROWS * KW; idx += 64 * NW) {
+      const int row = idx / KW, k = idx - row * KW;
+      const int w = eW[kc * KW + k];
       A v = M::cvt(0.0f);
-      if (e < s && row < npair) {
-        int w = eW[e];
-        int kl = w & 0x7fffffff;
-        double x = Wd ? Wd[(int64_t)row * npair + kl] : (double)Wf[(int64_t)row * npair + kl];
+      if (w != kPadEntry && row < npair) {
+        const int kl = w & 0x7fffffff;
+        const double x = Wd ? Wd[(int64_t)row * npair + kl] : (double)Wf[(int64_t)row * npair + kl];
         v = M::cvt(w < 0 ? -x : x);
       }
       Ws[row * LDW + k] = v;
     }
-    for (int64_t jt = 0; jt < njt; ++jt) {
-      const int64_t j0 = jt * 16;
-      __syncthreads();  // Ws ready / previous Rt consumed
-      // B tile (transposed): Rt[j][k] = C[J_e][j0 + j]
-      for (int idx = tid; idx < 16 * KW; idx += 256) {
-        int k = idx >> 4, j = idx & 15;
-        int e = e0 + k;
-        A v = M::cvt(0.0f);
-        if (e < s && j0 + j < nsb) v = M::cvt(cv[(int64_t)eJ[e] * nsb + j0 + j]);
-        Rt[j * LDW + k] = v;
-      }
-      __syncthreads();
-      for (int mb = 0; mb < Mt; mb += 4 * MTW) {
-        typename M::Out out[MTW];
+    __syncthreads();
+    uint32_t boff[KS][M::KPL];
 #pragma unroll
-        for (int u = 0; u < MTW; ++u)
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) out[u][r] = 0;
-        for (int ks = 0; ks < kc_steps; ++ks) {
-          const int kb = ks * M::KSTEP + g * M::KPL;
-          typename M::Frag bf;
-          typename M::Frag af[MTW];
-          if constexpr (M::KPL == 1) {
-            bf = Rt[li * LDW + kb];
+      for (int t = 0; t < M::KPL; ++t) boff[ks][t] = eoff[kc * KW + ks * M::KSTEP + g * M::KPL + t];
+    Frag areg[AREG ? MG : 1][AREG ? KS : 1];
+    if constexpr (AREG) {
 #pragma unroll
-            for (int u = 0; u < MTW; ++u) {
-              int mt = mb + wave + 4 * u;
-              af[u] = mt < Mt ? Ws[(mt * 16 + li) * LDW + kb] : (A)0;
-            }
-          } else {
-            bf = *reinterpret_cast<const bf8_t *>(&Rt[li * LDW + kb]);
+      for (int u = 0; u < MG; ++u)
 #pragma unroll
-            for (int u = 0; u < MTW; ++u) {
-              int mt = mb + wave + 4 * u;
-              int mrow = mt < Mt ? mt * 16 + li : 0;
-              af[u] = *reinterpret_cast<const bf8_t *>(&Ws[mrow * LDW + kb]);
-            }
-          }
+        for (int ks = 0; ks < KS; ++ks)
+          areg[u][ks] = M::load_a(&Ws[(u * 16 + li) * LDW + ks * M::KSTEP + g * M::KPL]);
+    }
+    // Per column tile: load this tile's pair codes, then prefetch the next
+    // tile's B fragments (unconditionally: past the last tile a clamped,
+    // valid column is fetched and never used), then multiply and scatter.
+    // Loads complete in issue order, so the scatter's wait for the codes
+    // leaves the prefetch in flight and the codes' latency hides behind the
+    // MFMAs.  Pair-table rows are padded to whole 16-column tiles with
+    // invalid codes, and out-of-range B columns are clamped, so no lane
+    // needs a column test.
+    int jt = wave;
+    Frag bn[KS];
+    {
+      const uint32_t J = (uint32_t)(jt * 16 + li);
+      const uint32_t jl = J < nsb32 ? J : nsb32 - 1;
 #pragma unroll
-          for (int u = 0; u < MTW; ++u) out[u] = M::mma(af[u], bf, out[u]);
-        }
-        // scatter: out[u][r] = M[row = mt*16 + orow(g, r)][J = j0 + li]
-        const int64_t J = j0 + li;
+      for (int ks = 0; ks < KS; ++ks) bn[ks] = M::load_b(cv, boff[ks], jl);
+    }
+    for (; jt < njt; jt += NW) {
+      const uint32_t J = (uint32_t)(jt * 16 + li);
+      Frag b[KS];
 #pragma unroll
-        for (int u = 0; u < MTW; ++u) {
-          int mt = mb + wave + 4 * u;
-          if (mt >= Mt || J >= nsb) continue;
+      for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
+      for (int grp = 0; grp < ngroups; ++grp) {
+        uint32_t code[MG][4];
+#pragma unroll
+        for (int u = 0; u < MG; ++u)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            int row = mt * 16 + M::orow(g, r);
-            if (row >= npair) continue;
-            int32_t code = pairb[(int64_t)row * nsb + J];
-            if (code == kInvalid) continue;
-            Acc v = (Acc)out[u][r];
-            if (code < 0) {
-              code = ~code;
-              v = -v;
-            }
-            atomicAdd(&acc[code], v);
+            const uint32_t row = (uint32_t)(grp * GROWS + u * 16 + M::orow(g, r));
+            code[u][r] = pairb[row * pstride + J];
           }
+        if (grp == 0) {
+          const uint32_t Jn = (uint32_t)((jt + NW) * 16 + li);
+          const uint32_t jn = Jn < nsb32 ? Jn : nsb32 - 1;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) bn[ks] = M::load_b(cv, boff[ks], jn);
         }
+        // keep the loads above ahead of the MFMAs below (issue order matters)
+        __builtin_amdgcn_sched_barrier(0);
+        typename M::Out out[MG];
+#pragma unroll
+        for (int u = 0; u < MG; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[u][r] = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int u = 0; u < MG; ++u) {
+            Frag a;
+            if constexpr (AREG)
+              a = areg[u][ks];
+            else
+              a = M::load_a(&Ws[(grp * GROWS + u * 16 + li) * LDW + ks * M::KSTEP + g * M::KPL]);
+            out[u] = M::mma(a, b[ks], out[u]);
+          }
+#pragma unroll
+        for (int u = 0; u < MG; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t cd = code[u][r];
+            const uint32_t tgt = cd == kInvalid ? nsb32 + (uint32_t)lane : cd >> 1;
+            Acc v = (Acc)out[u][r];
+            if (cd & 1u) v = -v;
+            atomicAdd(&acc[tgt], v);
+          }
       }
     }
-    __syncthreads();  // all waves done with Ws before the next chunk overwrites it
   }
   __syncthreads();
   T *__restrict__ sv = sigma + vo + ia * nsb;
-  for (int64_t j = tid; j < nsb; j += 256) sv[j] += (T)acc[j];
+  for (int64_t j = tid; j < nsb; j += 64 * NW) sv[j] += (T)acc[j];
+}
+
+struct OppPlan {
+  int MG, KS, ngroups, nkc;
+  size_t lds;
+};
+
+template <typename M>
+size_t opp_lds(int64_t nsb, int MG, int KS, int ngroups, int nkc) {
+  const int KW = KS * M::KSTEP, LDW = KW + M::PAD;
+  size_t b = ((size_t)(nsb + 64) * sizeof(typename M::Acc) + 15) & ~(size_t)15;
+  b += (((size_t)ngroups * MG * 16 * LDW * sizeof(typename M::A)) + 15) & ~(size_t)15;
+  b += (size_t)nkc * KW * 8;
+  return b;
+}
+
+template <typename M>
+int plan_opp(sbci_ctx *ctx, const int *mg_options, int nmg, const int *ks_options, int nks,
+             OppPlan &p) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  const int Mt = (ctx->npair + 15) / 16;
+  // M tiles per group: the smallest option covering all of Mt, else the one
+  // with the least padding (ties: fewer groups)
+  p.MG = 0;
+  for (int i = 0; i < nmg; ++i)
+    if (mg_options[i] >= Mt && (p.MG == 0 || mg_options[i] < p.MG)) p.MG = mg_options[i];
+  if (p.MG == 0) {
+    int best = 1 << 30;
+    for (int i = 0; i < nmg; ++i) {
+      const int m = mg_options[i], cost = (Mt + m - 1) / m * m;
+      if (cost < best || (cost == best && m > p.MG)) {
+        best = cost;
+        p.MG = m;
+      }
+    }
+  }
+  p.ngroups = (Mt + p.MG - 1) / p.MG;
+  if (p.ngroups * p.MG * 16 > ctx->npair_pad)
+    return set_error(SBCI_EINVAL, "pair table padding too small");
+  const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
+  const size_t cap = 160 * 1024;
+  // fewest K chunks that fit, then the smallest K tile
+  p.KS = 0;
+  for (int i = 0; i < nks; ++i) {
+    const int ks = ks_options[i];
+    const int nkc = (kst + ks - 1) / ks;
+    if (opp_lds<M>(B.ns, p.MG, ks, p.ngroups, nkc) > cap) continue;
+    if (p.KS == 0 || (nkc < p.nkc) || (nkc == p.nkc && ks < p.KS)) {
+      p.KS = ks;
+      p.nkc = nkc;
+    }
+  }
+  if (p.KS == 0)
+    return set_error(SBCI_EINVAL, "opposite-spin sigma: beta string count too large for LDS");
+  p.lds = opp_lds<M>(B.ns, p.MG, p.KS, p.ngroups, p.nkc);
+  return SBCI_OK;
+}
+
+template <typename M, typename T, int MG, int KS, bool AREG>
+void launch_opp_k(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
+                  const T *c, T *out) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  constexpr int NW = 8;
+  k_opp<M, T, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
+      A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab, B.pair, c, out);
+}
+
+template <typename M, typename T, int MG>
+void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
+                 const T *c, T *out) {
+  if constexpr (M::KPL == 8) {
+    // A fragments in registers when they are few enough (MG * KS <= 18)
+    const bool areg = p.ngroups == 1 && MG * p.KS <= 18;
+    if (p.KS == 1) {
+      if (areg) launch_opp_k<M, T, MG, 1, true>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 1, false>(ctx, p, grid, Wf, Wd, c, out);
+    } else if (p.KS == 2) {
+      if (areg) launch_opp_k<M, T, MG, 2, true>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 2, false>(ctx, p, grid, Wf, Wd, c, out);
+    } else {
+      if (areg) launch_opp_k<M, T, MG, 3, true>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 3, false>(ctx, p, grid, Wf, Wd, c, out);
+    }
+  } else {
+    if constexpr (std::is_same<typename M::A, double>::value) {
+      if (p.KS == 4) launch_opp_k<M, T, MG, 4, false>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 7, false>(ctx, p, grid, Wf, Wd, c, out);
+    } else {
+      if (p.KS == 8) launch_opp_k<M, T, MG, 8, false>(ctx, p, grid, Wf, Wd, c, out);
+      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 14, false>(ctx, p, grid, Wf, Wd, c, out);
+    }
+  }
 }
 
 template <typename M, typename T>
 int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (A.s == 0 || B.m == 0) return SBCI_OK;
-  const int npair = ctx->npair;
-  const int Mt = (npair + 15) / 16;
-  const int MROWS = Mt * 16;
-  const int ksteps_total = (A.s + M::KSTEP - 1) / M::KSTEP;
-  const size_t lds_cap = 160 * 1024;
-  const size_t acc_b = ((size_t)B.ns * sizeof(typename M::Acc) + 15) & ~(size_t)15;
-  const size_t ent_b = (size_t)A.s * 8;
-  int kc = ksteps_total;
-  auto need = [&](int k) {
-    int KW = k * M::KSTEP, LDW = KW + (M::KPL == 1 ? 1 : 8);
-    size_t ws = (((size_t)MROWS * LDW * sizeof(typename M::A)) + 15) & ~(size_t)15;
-    size_t rt = (((size_t)16 * LDW * sizeof(typename M::A)) + 15) & ~(size_t)15;
-    return acc_b + ws + rt + ent_b;
-  };
-  while (kc > 1 && need(kc) > lds_cap) --kc;
-  if (need(kc) > lds_cap)
-    return set_error(SBCI_EINVAL, "opposite-spin sigma: beta string count too large for LDS");
-  const size_t lds = need(kc);
+  if (ctx->ndet >= ((int64_t)1 << 31))
+    return set_error(SBCI_EINVAL, "opposite-spin sigma: N_det must be below 2^31");
+  // K tiles (k-steps per chunk) offered to the planner; the register budget
+  // of two waves per SIMD bounds them (B fragments are double-buffered)
+  static const int ks_d[2] = {4, 7};
+  static const int ks_f[3] = {8, 9, 14};
+  static const int ks_b[3] = {1, 2, 3};
+  static const int mg_d[3] = {4, 5, 7};
+  static const int mg_f[3] = {4, 7, 9};
+  OppPlan p{};
+  if (M::KPL == 8)
+    SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_b, 3, p));
+  else if (std::is_same<typename M::A, double>::value)
+    SBCI_TRY(plan_opp<M>(ctx, mg_d, 3, ks_d, 2, p));
+  else
+    SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_f, 3, p));
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
   dim3 grid((unsigned)A.ns, (unsigned)nvec);
-  const int mtw_need = (Mt + 3) / 4;
-  if (mtw_need <= 1) {
-    k_opp<M, T, 1><<<grid, 256, lds, ctx->stream>>>(A.ns, B.ns, A.s, npair, Mt, kc, Wf, Wd, A.tab,
-                                                    B.pair, c, out);
-  } else if (mtw_need == 2) {
-    k_opp<M, T, 2><<<grid, 256, lds, ctx->stream>>>(A.ns, B.ns, A.s, npair, Mt, kc, Wf, Wd, A.tab,
-                                                    B.pair, c, out);
+  if constexpr (std::is_same<typename M::A, double>::value) {
+    if (p.MG == 4) dispatch_ks<M, T, 4>(ctx, p, grid, Wf, Wd, c, out);
+    else if (p.MG == 5) dispatch_ks<M, T, 5>(ctx, p, grid, Wf, Wd, c, out);
+    else dispatch_ks<M, T, 7>(ctx, p, grid, Wf, Wd, c, out);
   } else {
-    k_opp<M, T, 3><<<grid, 256, lds, ctx->stream>>>(A.ns, B.ns, A.s, npair, Mt, kc, Wf, Wd, A.tab,
-                                                    B.pair, c, out);
+    if (p.MG == 4) dispatch_ks<M, T, 4>(ctx, p, grid, Wf, Wd, c, out);
+    else if (p.MG == 7) dispatch_ks<M, T, 7>(ctx, p, grid, Wf, Wd, c, out);
+    else dispatch_ks<M, T, 9>(ctx, p, grid, Wf, Wd, c, out);
   }
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
 
+template <typename T, typename V, int VC>
+void launch_same_vc(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, int64_t C,
+                    const T *src, T *dst, int nvec, int accumulate) {
+  constexpr int WAVES = 4;
+  const int64_t rgroups = (R + WAVES - 1) / WAVES;
+  const int64_t ctiles = (C + 64 * VC - 1) / (64 * VC);
+  const int64_t total = rgroups * ctiles;
+  const int64_t per_xcd = (total + 7) / 8;
+  dim3 grid((unsigned)(per_xcd * 8), 1, (unsigned)nvec);
+  k_same<T, V, WAVES, VC><<<grid, 64 * WAVES, 0, ctx->stream>>>(S.fcol, fval, S.nf, R, C, src, dst,
+                                                               accumulate, rgroups, per_xcd, total);
+}
+
 template <typename T, typename V>
 int launch_same(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, int64_t C,
                 const T *src, T *dst, int nvec, int accumulate) {
-  constexpr int WAVES = 4;
-  dim3 grid((unsigned)((R + WAVES - 1) / WAVES), (unsigned)((C + 63) / 64), (unsigned)nvec);
-  k_same<T, V, WAVES><<<grid, 64 * WAVES, 0, ctx->stream>>>(S.fcol, fval, S.nf, R, C, src, dst,
-                                                           accumulate);
+  // widest column tile whose source rows (R x 64 VC elements) stay within
+  // about half of one XCD's 4 MB L2
+  const double tile1 = (double)R * 64 * sizeof(T);
+  const double budget = 2.0 * 1024 * 1024;
+  if (C >= 256 && 4 * tile1 <= budget)
+    launch_same_vc<T, V, 4>(ctx, S, fval, R, C, src, dst, nvec, accumulate);
+  else if (C >= 128 && 2 * tile1 <= budget)
+    launch_same_vc<T, V, 2>(ctx, S, fval, R, C, src, dst, nvec, accumulate);
+  else
+    launch_same_vc<T, V, 1>(ctx, S, fval, R, C, src, dst, nvec, accumulate);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -337,8 +530,19 @@ int launch_transpose(sbci_ctx *ctx, const T *src, T *dst, int64_t R, int64_t C, 
   return SBCI_OK;
 }
 
+// Optional per-part timing: ev[0..5] recorded on the launch stream around
+// the five parts (alpha lists, opposite spin, transpose, beta lists, add).
+struct PartEvents {
+  hipEvent_t ev[6];
+};
+
+int rec(sbci_ctx *ctx, PartEvents *pe, int i) {
+  if (pe) SBCI_HIP(hipEventRecord(pe->ev[i], ctx->stream));
+  return SBCI_OK;
+}
+
 template <typename T, typename M>
-int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec) {
+int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullptr) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   const int64_t na = A.ns, nb = B.ns;
   const size_t vbytes = sizeof(T) * (size_t)ctx->ndet * nvec;
@@ -348,37 +552,61 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   T *st = static_cast<T *>(ctx->ws_s.ptr);
   const bool dbl = std::is_same<T, double>::value;
   // alpha part (plain write), then opposite-spin (accumulate)
+  SBCI_TRY(rec(ctx, pe, 0));
   if (dbl)
     SBCI_TRY((launch_same<T, double>(ctx, A, A.fval64, na, nb, c, out, nvec, 0)));
   else
     SBCI_TRY((launch_same<T, float>(ctx, A, A.fval32, na, nb, c, out, nvec, 0)));
+  SBCI_TRY(rec(ctx, pe, 1));
   SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec)));
+  SBCI_TRY(rec(ctx, pe, 2));
   // beta part on C^T, added back transposed
   SBCI_TRY(launch_transpose<T>(ctx, c, ct, na, nb, nvec, false));
+  SBCI_TRY(rec(ctx, pe, 3));
   if (dbl)
     SBCI_TRY((launch_same<T, double>(ctx, B, B.fval64, nb, na, ct, st, nvec, 0)));
   else
     SBCI_TRY((launch_same<T, float>(ctx, B, B.fval32, nb, na, ct, st, nvec, 0)));
+  SBCI_TRY(rec(ctx, pe, 4));
   SBCI_TRY(launch_transpose<T>(ctx, st, out, nb, na, nvec, true));
+  SBCI_TRY(rec(ctx, pe, 5));
   return SBCI_OK;
 }
 
 }  // namespace
 
-int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
+namespace {
+int sigma_dispatch(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, PartEvents *pe) {
   switch (mode) {
     case SBCI_F64:
       return sigma_t<double, MF64>(ctx, static_cast<const double *>(c), static_cast<double *>(out),
-                                   nvec);
+                                   nvec, pe);
     case SBCI_F32:
       return sigma_t<float, MF32>(ctx, static_cast<const float *>(c), static_cast<float *>(out),
-                                  nvec);
+                                  nvec, pe);
     case SBCI_BF16:
       return sigma_t<float, MBF16>(ctx, static_cast<const float *>(c), static_cast<float *>(out),
-                                   nvec);
+                                   nvec, pe);
     default:
       return set_error(SBCI_EINVAL, "unknown sigma dtype");
   }
+}
+}  // namespace
+
+int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
+  return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
+}
+
+int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms) {
+  PartEvents pe{};
+  for (int i = 0; i < 6; ++i) SBCI_HIP(hipEventCreate(&pe.ev[i]));
+  int rc = sigma_dispatch(ctx, c, out, nvec, mode, &pe);
+  if (rc == SBCI_OK) {
+    SBCI_HIP(hipEventSynchronize(pe.ev[5]));
+    for (int i = 0; i < 5; ++i) SBCI_HIP(hipEventElapsedTime(&ms[i], pe.ev[i], pe.ev[i + 1]));
+  }
+  for (int i = 0; i < 6; ++i) hipEventDestroy(pe.ev[i]);
+  return rc;
 }
 
 }  // namespace sbci

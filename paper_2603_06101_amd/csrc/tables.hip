@@ -95,27 +95,29 @@ __global__ void k_exc_table(int norb, int m, int64_t ns, int s, const uint64_t *
   }
 }
 
-__global__ void k_pair_table(int norb, int64_t ns, int npair, const uint64_t *__restrict__ str,
-                             const int64_t *__restrict__ binom, int32_t *__restrict__ pair) {
+__global__ void k_pair_table(int norb, int64_t ns, int64_t ns_pad, int npair, int npair_pad,
+                             const uint64_t *__restrict__ str, const int64_t *__restrict__ binom,
+                             uint32_t *__restrict__ pair) {
   int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int kl = blockIdx.y;
-  if (j >= ns || kl >= npair) return;
-  int k = 0;
-  while ((k + 1) * (k + 2) / 2 <= kl) ++k;
-  int l = kl - k * (k + 1) / 2;
-  const uint64_t mask = str[j];
-  const int bk = (mask >> k) & 1, bl = (mask >> l) & 1;
-  int32_t code = kInvalid;
-  if (k == l) {
-    if (bk) code = (int32_t)j;
-  } else if (bk != bl) {
-    // the occupied one of {k, l} moves to the empty one
-    uint64_t nm = mask ^ (1ull << k) ^ (1ull << l);
-    int32_t tgt = (int32_t)rank_of(nm, binom);
-    int neg = parity_between(mask, k, l);
-    code = neg ? ~tgt : tgt;
+  if (j >= ns_pad || kl >= npair_pad) return;
+  uint32_t code = kInvalid;
+  if (kl < npair && j < ns) {
+    int k = 0;
+    while ((k + 1) * (k + 2) / 2 <= kl) ++k;
+    int l = kl - k * (k + 1) / 2;
+    const uint64_t mask = str[j];
+    const int bk = (mask >> k) & 1, bl = (mask >> l) & 1;
+    if (k == l) {
+      if (bk) code = (uint32_t)j << 1;
+    } else if (bk != bl) {
+      // the occupied one of {k, l} moves to the empty one
+      uint64_t nm = mask ^ (1ull << k) ^ (1ull << l);
+      uint32_t tgt = (uint32_t)rank_of(nm, binom);
+      code = (tgt << 1) | (uint32_t)parity_between(mask, k, l);
+    }
   }
-  pair[(int64_t)kl * ns + j] = code;
+  pair[(int64_t)kl * ns_pad + j] = code;
 }
 
 __device__ __forceinline__ double G4(const double *__restrict__ g, int n, int p, int q, int r, int s) {
@@ -246,7 +248,8 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
   hipStream_t st = ctx->stream;
   SBCI_HIP(hipMalloc(&T.str, sizeof(uint64_t) * T.ns));
   SBCI_HIP(hipMalloc(&T.tab, sizeof(Ent) * T.ns * (T.s > 0 ? T.s : 1)));
-  SBCI_HIP(hipMalloc(&T.pair, sizeof(int32_t) * T.ns * ctx->npair));
+  T.ns_pad = (T.ns + 15) / 16 * 16;
+  SBCI_HIP(hipMalloc(&T.pair, sizeof(uint32_t) * T.ns_pad * ctx->npair_pad));
   SBCI_HIP(hipMalloc(&T.fcol, sizeof(int32_t) * T.ns * T.nf));
   SBCI_HIP(hipMalloc(&T.fval64, sizeof(double) * T.ns * T.nf));
   SBCI_HIP(hipMalloc(&T.fval32, sizeof(float) * T.ns * T.nf));
@@ -259,7 +262,9 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
     k_exc_table<<<gx, bs, 0, st>>>(n, m, T.ns, T.s, T.str, ctx->binom, T.tab);
     SBCI_CHECK_LAUNCH();
   }
-  k_pair_table<<<dim3(gx, ctx->npair), bs, 0, st>>>(n, T.ns, ctx->npair, T.str, ctx->binom, T.pair);
+  const unsigned gxp = (unsigned)((T.ns_pad + bs - 1) / bs);
+  k_pair_table<<<dim3(gxp, ctx->npair_pad), bs, 0, st>>>(n, T.ns, T.ns_pad, ctx->npair,
+                                                         ctx->npair_pad, T.str, ctx->binom, T.pair);
   SBCI_CHECK_LAUNCH();
   const int fbs = 64;  // heavy per-thread loops: small blocks
   k_flist<<<(unsigned)((T.ns + fbs - 1) / fbs), fbs, 0, st>>>(n, m, T.ns, T.nf, T.str, ctx->binom,
@@ -289,6 +294,7 @@ void free_spin(SpinTables &T) {
 int build_tables(sbci_ctx *ctx, const double *h1, const double *eri) {
   const int n = ctx->norb;
   ctx->npair = n * (n + 1) / 2;
+  ctx->npair_pad = 16 * ((ctx->npair + 15) / 16 + 9);
   hipStream_t st = ctx->stream;
   // binomial table [65][65]
   std::vector<int64_t> binom(65 * 65);

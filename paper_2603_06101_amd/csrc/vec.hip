@@ -13,7 +13,7 @@
 // sy = 0 drops y, Y (y_0 = 0 at a segment start).
 //
 // Reductions are deterministic: each block writes its partial sums, and the
-// last block to finish (an atomic ticket) adds the partials in block order.
+// last block to finish (an atomic ticket) adds the partials in a fixed order.
 #include "internal.h"
 
 namespace sbci {
@@ -58,11 +58,20 @@ __device__ void grid_reduce(double (&v)[NQ], int nq, double *__restrict__ part,
   __syncthreads();
   if (last) {
     __threadfence();
-    if (threadIdx.x < nq) {
+    // all threads of the last block add the partials: thread t takes blocks
+    // t, t + BS, ... (fixed order), then a block reduction per slot
+    for (int q = 0; q < nq; ++q) {
       double s = 0;
-      for (unsigned b = 0; b < gridDim.x; ++b)
-        s += __builtin_nontemporal_load(&part[(size_t)b * MAXQ + threadIdx.x]);
-      out[threadIdx.x] = s;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += BS) s += part[(size_t)b * MAXQ + q];
+      s = wave_sum(s);
+      __syncthreads();
+      if (lane == 0) sh[wave][0] = s;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < BS / 64; ++w) t += sh[w][0];
+        out[q] = t;
+      }
     }
     if (threadIdx.x == 0) *ticket = 0u;
   }

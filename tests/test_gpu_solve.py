@@ -70,6 +70,24 @@ def test_cas6_step_trajectory_matches_oracle():
     ctx.close()
 
 
+def _check_eigenpairs(n, na, nb, I, r, tol_res=3e-5):
+    """Every converged root is an eigenpair of H: residual from the oracle's sigma."""
+    X = r.vectors.cpu().numpy()
+    S = OS.sigma(n, na, nb, I.h1, I.eri, X)
+    for a, E in enumerate(r.energies):
+        x = X[a]
+        assert abs(np.linalg.norm(x) - 1) < 1e-10
+        assert abs(x @ S[a] - E) < 1e-9
+        assert np.linalg.norm(S[a] - E * x) < tol_res
+    G = X @ X.T
+    assert np.abs(G - np.eye(len(r.energies))).max() < 1e-8
+
+
+# Which excited states sequential SBCI1 reaches from the Section S1.1 / S1.4
+# start vectors depends on rounding when n_alpha = n_beta: the start lies in
+# the spin-flip-symmetric sector and the antisymmetric states enter only as
+# rounding grows.  The oracle and the GPU therefore agree on root 0 and on
+# every root being an eigenpair, not on the order of the excited roots.
 @pytest.mark.parametrize("seed", range(10))
 def test_cas10_sbci_and_davidson(seed):
     ref = REFS["cas10"][str(seed)]
@@ -77,27 +95,22 @@ def test_cas10_sbci_and_davidson(seed):
     assert ref["digest"] == I.digest()
     r = ctx.solve(3, tol=1e-10)
     assert r.status == 0
-    # same algorithm, same start: the oracle's SBCI1 energies, root by root
-    assert np.abs(r.energies - np.array(ref["sbci1"])).max() < 1e-8
-    ev = np.array(ref["eigsh"])
-    for E in r.energies:
-        assert np.min(np.abs(ev - E)) < 1e-8 or E > ev[-1]
-    X = r.vectors
-    G = (X @ X.T).cpu().numpy()
-    assert np.abs(G - np.eye(3)).max() < 1e-8
+    assert abs(r.energies[0] - ref["sbci1"][0]) < 1e-8
+    _check_eigenpairs(10, 5, 5, I, r)
     d = ctx.davidson(3, tol=1e-10)
     assert d.status == 0
-    assert np.abs(d.energies - ev[:3]).max() < 1e-8
+    assert np.abs(d.energies - np.array(ref["eigsh"][:3])).max() < 1e-8
     ctx.close()
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_cas10_mixed_precision_reaches_fp64(prec):
     ref = REFS["cas10"]["0"]
-    ctx, _ = _ctx(10, 5, 5, 20, 0)
+    ctx, I = _ctx(10, 5, 5, 20, 0)
     r = ctx.solve(3, tol=1e-10, opts=dict(precision=prec))
     assert r.status == 0
-    assert np.abs(r.energies - np.array(ref["sbci1"])).max() < 1e-8
+    assert abs(r.energies[0] - ref["sbci1"][0]) < 1e-8
+    _check_eigenpairs(10, 5, 5, I, r)
     assert r.report["nsigma_low"] > 0
     ctx.close()
 
@@ -108,7 +121,11 @@ def test_small_cases_match_oracle(n, na, nb, nroots, seed):
     op = OS.Operator(n, na, nb, I.h1, I.eri)
     ref = OSB.sbci1(op, op.diag(), nroots)
     r = ctx.solve(nroots, tol=1e-10)
-    assert np.abs(r.energies - ref.energies).max() < 1e-8
+    assert abs(r.energies[0] - ref.energies[0]) < 1e-8
+    _check_eigenpairs(n, na, nb, I, r)
+    w = np.linalg.eigvalsh(H.dense_h_slater_condon(n, na, nb, I.h1, I.eri))
+    for E in r.energies:
+        assert np.min(np.abs(w - E)) < 1e-8
     d = ctx.davidson(nroots, tol=1e-10)
     rd = OSB.davidson(op, op.diag(), nroots)
     assert np.abs(d.energies - rd.energies).max() < 1e-8
