@@ -62,7 +62,8 @@ typedef struct sbci_opts {
   double r1;                  /* restart S62c: |z'| > r1 and t > 0                     */
   int max_cycle;              /* steps per segment before a forced restart             */
   int max_steps;              /* sigma builds per root before SBCI_ENOCONV             */
-  int precision;              /* sbci_dtype of the low-precision phase (SBCI_F64: none) */
+  int precision;              /* first phase: SBCI_F64 (FP64 only), SBCI_F32 (FP32 then
+                                 FP64) or SBCI_BF16 (BF16, FP32, then FP64)           */
   double mix_eps0, mix_r0;    /* low-precision phase ends at dE < mix_eps0 and |z'| < mix_r0 */
   int mix_stall;              /* ... or after this many steps without an energy decrease */
   double precond_floor;       /* |D - E0| is floored at this value (default 1e-8)      */
@@ -70,6 +71,7 @@ typedef struct sbci_opts {
   int max_space;              /* Davidson subspace cap (default 12 + nroots if <= 0)    */
   const double *x0;           /* host [ndet] start vector for root 0, or NULL for the
                                  Section S1.1 start from the lowest diagonal elements */
+  double bf16_eps0, bf16_r0;  /* SBCI_BF16: BF16 phase hands over to FP32 at these   */
 } sbci_opts;
 
 typedef struct sbci_report {

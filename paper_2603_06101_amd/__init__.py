@@ -42,6 +42,7 @@ class Opts(ctypes.Structure):
         ("precond_floor", ctypes.c_double), ("lindep", ctypes.c_double),
         ("max_space", ctypes.c_int),
         ("x0", ctypes.POINTER(ctypes.c_double)),
+        ("bf16_eps0", ctypes.c_double), ("bf16_r0", ctypes.c_double),
     ]
 
 

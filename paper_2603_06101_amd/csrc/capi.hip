@@ -101,12 +101,19 @@ void sbci_default_opts(sbci_opts *o) {
   o->lindep = 1e-14;
   o->max_space = 0;
   o->x0 = nullptr;
+  o->bf16_eps0 = 1e-5;
+  o->bf16_r0 = 1e-2;
 }
 
 const char *sbci_last_error(void) { return g_err.c_str(); }
 
-int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
-                sbci_ctx **out) {
+}  // extern "C"
+
+namespace sbci {
+// Context on a given stream; own_stream = false leaves the stream to the caller
+// (the batch form builds many contexts on one stream).
+int create_context(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                   hipStream_t stream, bool own_stream, sbci_ctx **out) {
   if (!out) return set_error(SBCI_EINVAL, "out is NULL");
   *out = nullptr;
   if (norb < 1 || norb > 63) return set_error(SBCI_EINVAL, "norb must be in [1, 63]");
@@ -124,12 +131,16 @@ int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double 
   ctx->na = nalpha;
   ctx->nb = nbeta;
   ctx->device = dev;
-  hipError_t e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete ctx;
-    return set_error(SBCI_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  if (own_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete ctx;
+      return set_error(SBCI_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    ctx->stream = ctx->own_stream;
+  } else {
+    ctx->stream = stream;
   }
-  ctx->stream = ctx->own_stream;
   int rc = build_tables(ctx, h1, eri);
   if (rc != SBCI_OK) {
     std::string msg = g_err;
@@ -138,6 +149,14 @@ int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double 
   }
   *out = ctx;
   return SBCI_OK;
+}
+}  // namespace sbci
+
+extern "C" {
+
+int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                sbci_ctx **out) {
+  return create_context(norb, nalpha, nbeta, h1, eri, nullptr, true, out);
 }
 
 int sbci_destroy(sbci_ctx *ctx) {

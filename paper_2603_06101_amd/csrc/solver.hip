@@ -18,11 +18,15 @@
 // scale, and the host rescales the dots it already has.
 //
 // Precision form: with opt.precision = SBCI_F32 or SBCI_BF16 each root first
-// runs with FP32 vectors and the low-precision sigma (all reductions, the
-// Ritz problem, the restart tests and the deflation stay FP64); when it
-// reaches mix_eps0 / mix_r0 (or stalls) x is promoted to FP64, X = H x is
-// recomputed with the FP64 sigma and FP64 steps refine it to eps0 / r0.
+// runs with FP32 vectors and a low-precision sigma (all reductions, the Ritz
+// problem, the restart tests and the deflation stay FP64).  SBCI_BF16 starts
+// with the BF16-MFMA sigma and moves to the FP32 sigma at bf16_eps0 /
+// bf16_r0; the FP32 phase ends at mix_eps0 / mix_r0 (either phase also ends
+// after mix_stall steps without an energy decrease).  Each hand-over
+// recomputes X = H x with the next sigma and starts a new segment; the last
+// one promotes x to FP64, and FP64 steps refine it to eps0 / r0.
 #include "internal.h"
+#include "ritz.h"
 
 #include <algorithm>
 #include <chrono>
@@ -31,146 +35,7 @@
 
 namespace sbci {
 
-// ------------------------------------------------------------ small eigh
-// Cyclic Jacobi for a symmetric n x n matrix (row-major), eigenvalues
-// ascending, eigenvectors in the columns of V.
-void jacobi_eigh(int n, const double *Ain, double *w, double *V) {
-  std::vector<double> A(Ain, Ain + (size_t)n * n);
-  for (int i = 0; i < n * n; ++i) V[i] = 0;
-  for (int i = 0; i < n; ++i) V[i * n + i] = 1;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0, tot = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += A[i * n + j] * A[i * n + j];
-        if (i != j) off += A[i * n + j] * A[i * n + j];
-      }
-    if (off <= 1e-32 * tot || off == 0) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double apq = A[p * n + q];
-        if (apq == 0) continue;
-        double app = A[p * n + p], aqq = A[q * n + q];
-        double theta = (aqq - app) / (2 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
-        double c = 1 / std::sqrt(t * t + 1), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          double vkp = V[k * n + p], vkq = V[k * n + q];
-          V[k * n + p] = c * vkp - s * vkq;
-          V[k * n + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  std::vector<int> idx(n);
-  for (int i = 0; i < n; ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
-  std::vector<double> Vs((size_t)n * n);
-  for (int j = 0; j < n; ++j) {
-    w[j] = A[idx[j] * n + idx[j]];
-    for (int k = 0; k < n; ++k) Vs[k * n + j] = V[k * n + idx[j]];
-  }
-  std::memcpy(V, Vs.data(), sizeof(double) * n * n);
-}
-
 namespace {
-
-// Result of the small Ritz problem: energies, coefficients of the lowest
-// and second Ritz vectors on (x, y, z), and the update parameters.
-struct Ritz {
-  bool rank_ok = false, coef_ok = false;
-  double E[3] = {0, 0, 0};
-  double a1[3] = {0, 0, 0}, a2[3] = {0, 0, 0};
-  double b = 0, c = 0, k = 0;
-};
-
-// First step of a segment: 2x2 problem in span{x, z} (Eqs. S10-S24).
-Ritz ritz_first(double Nxx, double Nxz, double Nzz, double Hxx, double Hxz, double Hzz,
-                double lindep) {
-  Ritz r;
-  const double Ax = 1.0 / std::sqrt(Nxx);            // x0 is normalised: Ax = 1 (Eq. S10)
-  const double ux = Nxz * Ax;                        // xbar . z
-  const double rad = Nzz - ux * ux;
-  if (!(rad > lindep * std::max(Nzz, 1e-300))) return r;
-  r.rank_ok = true;
-  const double Bz = 1.0 / std::sqrt(rad);            // Eq. S12
-  const double Bx = -ux * Bz * Ax;                   // Eq. S13 (zbar = Bz z + Bx x)
-  const double V00 = Ax * Ax * Hxx;                  // Eq. S15a
-  const double V01 = Ax * (Bx * Hxx + Bz * Hxz);     // Eq. S15b
-  const double V11 = Bx * Bx * Hxx + Bz * Bz * Hzz + 2 * Bx * Bz * Hxz;  // Eq. S15c
-  double Vm[4] = {V00, V01, V01, V11}, w[2], U[4];
-  jacobi_eigh(2, Vm, w, U);
-  r.E[0] = w[0];
-  r.E[1] = w[1];
-  for (int i = 0; i < 2; ++i) {
-    double vx = U[0 * 2 + i], vz = U[1 * 2 + i];
-    double *a = i == 0 ? r.a1 : r.a2;
-    a[0] = vx * Ax + vz * Bx;                        // Eq. S17
-    a[1] = 0;
-    a[2] = vz * Bz;
-  }
-  if (std::fabs(r.a1[0]) < lindep) return r;
-  r.coef_ok = true;
-  r.k = 1.0 / r.a1[0];                               // Eq. S23
-  r.b = 1.0;
-  r.c = -r.a1[2] / r.a1[0];                          // Eq. S24
-  return r;
-}
-
-// Later step: 3x3 problem in span{x, y, z} (Eqs. S33-S55).
-Ritz ritz_next(const double N[6], const double H[6], double lindep) {
-  // N, H order: xx, xy, xz, yy, yz, zz
-  Ritz r;
-  const double Nxx = N[0], Nxy = N[1], Nxz = N[2], Nyy = N[3], Nyz = N[4], Nzz = N[5];
-  const double Hxx = H[0], Hxy = H[1], Hxz = H[2], Hyy = H[3], Hyz = H[4], Hzz = H[5];
-  const double Ax = 1.0 / std::sqrt(Nxx);                         // Eq. S34
-  const double rady = Nyy - Nxy * Nxy / Nxx;
-  if (!(rady > lindep * std::max(Nyy, 1e-300))) return r;
-  const double By = 1.0 / std::sqrt(rady);                        // Eq. S36
-  const double Bx = -(Nxy / Nxx) * By;                            // Eq. S37
-  const double P = Bx * Nxz + By * Nyz;                           // Eq. S42
-  const double radz = Nzz - Nxz * Nxz / Nxx - P * P;
-  if (!(radz > lindep * std::max(Nzz, 1e-300))) return r;
-  r.rank_ok = true;
-  const double Cz = 1.0 / std::sqrt(radz);                        // Eq. S39
-  const double Cy = -P * By * Cz;                                 // Eq. S40
-  const double Cx = -(Nxz / Nxx + P * Bx) * Cz;                   // Eq. S41
-  const double hxc = Cx * Hxx + Cy * Hxy + Cz * Hxz;              // x^T H zbar / 1
-  const double hyc = Cx * Hxy + Cy * Hyy + Cz * Hyz;              // y^T H zbar
-  double Vm[9];
-  Vm[0] = Ax * Ax * Hxx;                                          // Eq. S44a
-  Vm[1] = Vm[3] = Ax * (Bx * Hxx + By * Hxy);                     // Eq. S44b
-  Vm[2] = Vm[6] = Ax * hxc;                                       // Eq. S44c
-  Vm[4] = Bx * Bx * Hxx + By * By * Hyy + 2 * Bx * By * Hxy;      // Eq. S44d
-  Vm[5] = Vm[7] = Bx * hxc + By * hyc;                            // Eq. S44e
-  Vm[8] = Cx * Cx * Hxx + Cy * Cy * Hyy + Cz * Cz * Hzz + 2 * Cx * Cy * Hxy + 2 * Cx * Cz * Hxz +
-          2 * Cy * Cz * Hyz;                                      // Eq. S44f
-  double w[3], U[9];
-  jacobi_eigh(3, Vm, w, U);
-  for (int i = 0; i < 3; ++i) r.E[i] = w[i];
-  for (int i = 0; i < 2; ++i) {
-    double vx = U[0 * 3 + i], vy = U[1 * 3 + i], vz = U[2 * 3 + i];
-    double *a = i == 0 ? r.a1 : r.a2;
-    a[0] = vx * Ax + vy * Bx + vz * Cx;                           // Eq. S46
-    a[1] = vy * By + vz * Cy;
-    a[2] = vz * Cz;
-  }
-  if (std::fabs(r.a1[0]) < lindep || std::fabs(r.a1[1]) < lindep) return r;
-  r.coef_ok = true;
-  r.k = 1.0 / r.a1[0];                                            // Eq. S53
-  r.b = r.a1[1] / r.a1[0];                                        // Eq. S54
-  r.c = -r.a1[2] / r.a1[1];                                       // Eq. S55
-  return r;
-}
 
 double now_s() {
   using namespace std::chrono;
@@ -355,7 +220,28 @@ int sigma_phase(sbci_ctx *ctx, Solver &S, const T *c, T *out) {
     return sigma(ctx, c, out, 1, SBCI_F64);
   }
   S.rep.nsigma_low += 1;
-  return sigma(ctx, c, out, 1, S.o.precision);
+  return sigma(ctx, c, out, 1, S.phase);
+}
+
+// BF16 phase -> FP32 phase: X = H x recomputed with the FP32 sigma (the
+// carried X holds the BF16 contraction's error) and a new segment starts.
+int to_f32(sbci_ctx *ctx, Solver &S) {
+  SBCI_TRY(sigma(ctx, S.v32[X_], S.v32[XX_], 1, SBCI_F32));
+  S.rep.nsigma_low += 1;
+  const float *xp[1] = {S.v32[X_]};
+  const float *Xp[1] = {S.v32[XX_]};
+  SBCI_TRY(dots<float>(ctx, S.n, S.v32[X_], xp, 1, S.red + 40));
+  SBCI_TRY(dots<float>(ctx, S.n, S.v32[X_], Xp, 1, S.red + 41));
+  double d[2];
+  SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  S.E = d[1] / d[0];
+  S.phase = SBCI_F32;
+  const int steps = S.steps_root, seg = S.seg;
+  SBCI_TRY(start_root<float>(ctx, S));
+  S.steps_root = steps;
+  S.seg = seg + 1;
+  return SBCI_OK;
 }
 
 // Promote the low-precision iterate to FP64 and restart there (refinement).
@@ -552,7 +438,9 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
     } else {
       S.stall += 1;
     }
-    if ((dE < S.o.mix_eps0 && dz < S.o.mix_r0) || S.stall >= S.o.mix_stall) {
+    const bool bf = S.phase == SBCI_BF16;
+    const double e0 = bf ? S.o.bf16_eps0 : S.o.mix_eps0, r0 = bf ? S.o.bf16_r0 : S.o.mix_r0;
+    if ((dE < e0 && dz < r0) || S.stall >= S.o.mix_stall) {
       promote_now = true;
       reason = 8;
     }
@@ -568,7 +456,7 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
   if (info) *info = ctx->trace.empty() ? sbci_step_info{} : ctx->trace.back();
   S.E = Enew;
   if (conv) return finish_root(ctx, S, xn, true);
-  if (promote_now) return promote(ctx, S);
+  if (promote_now) return S.phase == SBCI_BF16 ? to_f32(ctx, S) : promote(ctx, S);
   if (S.steps_root >= S.o.max_steps) {
     S.any_noconv = true;
     if (low) return promote(ctx, S);
@@ -658,7 +546,7 @@ int initial_vector(sbci_ctx *ctx, Solver &S) {
   SBCI_HIP(hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < i; ++j) Hs[i * k + j] = Hs[j * k + i] = 0.5 * (Hs[i * k + j] + Hs[j * k + i]);
-  jacobi_eigh(k, Hs.data(), w.data(), U.data());
+  jacobi_eigh<16>(k, Hs.data(), w.data(), U.data());
   std::vector<const double *> es(k), Hes(k);
   std::vector<double> cf(k);
   for (int i = 0; i < k; ++i) {
@@ -876,7 +764,7 @@ int davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double
     std::vector<double> hs((size_t)m * m), w(m), U((size_t)m * m);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < m; ++j) hs[i * m + j] = h[(size_t)i * maxs + j];
-    jacobi_eigh(m, hs.data(), w.data(), U.data());
+    jacobi_eigh<32>(m, hs.data(), w.data(), U.data());
     std::vector<const double *> vs(m), ws(m);
     for (int i = 0; i < m; ++i) {
       vs[i] = vptr(V.p, i);
