@@ -175,6 +175,71 @@ int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max);
 int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
                   double *energies, double *dev_vecs, sbci_report *rep);
 
+
+/* ------------------------------------------------------------------------
+ * Batching form: many independent instances (each its own norb, n_alpha,
+ * n_beta, integrals and number of roots) solved by SBCI1 in one
+ * persistent-kernel launch captured in a hipGraph.  One workgroup runs the
+ * whole SBCI1 state machine of one instance (Algorithm 1 with Sections
+ * S1.1-S1.5: start vectors, steps, restarts, deflation against the lower
+ * roots, the precision hand-overs of sbci_solve); workgroups take instances
+ * from a device queue.  Limits per instance: 1 <= norb <= 11 (at most 512
+ * strings per spin), 1 <= nroots <= min(4, N_det).
+ */
+typedef struct sbci_batch sbci_batch;
+
+/* Launch shape of the persistent kernel (chosen by sbci_batch_tune). */
+typedef struct sbci_batch_config {
+  int threads;    /* workgroup size: 256, 512 or 1024                          */
+  int wg_per_cu;  /* persistent workgroups per compute unit: 1..4              */
+  int order;      /* queue order: 0 = largest estimated work first, 1 = input  */
+  int row_tile;   /* rows / columns of C per same-spin LDS tile: 8 or 16       */
+} sbci_batch_config;
+
+typedef struct sbci_batch_report {
+  double seconds;            /* device time of the graph launch (HIP events)    */
+  int64_t nsigma_f64;        /* sigma applications, summed over instances       */
+  int64_t nsigma_low;
+  int64_t det_sigma;         /* sum over instances of N_det x sigma applications */
+  int64_t nsteps, nrestarts; /* summed over instances                           */
+  int ninst_converged;       /* instances with status SBCI_OK                   */
+  int threads, wg_per_cu, order, row_tile;  /* the launch shape used           */
+} sbci_batch_report;
+
+/* Builds every instance's tables (as sbci_create does for one) on the
+ * current device.  norb, nalpha, nbeta: host [ninst]; h1[i], eri[i]: host
+ * pointers to instance i's integrals in the layout of sbci_create (read
+ * during the call only).  EINVAL for a NULL argument, ninst < 1 or an
+ * instance outside the limits above. */
+int sbci_batch_create(int ninst, const int *norb, const int *nalpha, const int *nbeta,
+                      const double *const *h1, const double *const *eri, sbci_batch **out);
+int sbci_batch_destroy(sbci_batch *b);
+int64_t sbci_batch_ndet(const sbci_batch *b, int inst);   /* -1 for a bad index */
+
+/* Solves every instance: nroots host [ninst]; tol, opt as for sbci_solve
+ * (opt->x0 must be NULL; opt->precision selects the FP64 or mixed form);
+ * cfg NULL = the last tuned shape, else a default shape.  energies: host,
+ * the roots of instance 0, then instance 1, ... (sum of nroots entries; NaN
+ * for a root that was not reached); status: host [ninst] per-instance
+ * sbci_status, or NULL.  Returns SBCI_ENOCONV / SBCI_ENUMERIC if any
+ * instance ended so (the outputs are still written). */
+int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
+                     const sbci_batch_config *cfg, double *energies, int *status,
+                     sbci_batch_report *rep);
+
+/* Autotuner: times full batch solves over a candidate set of launch shapes
+ * (workgroup size x residency, then queue order and tile height around the
+ * best) with HIP events, keeps the fastest for later sbci_batch_solve calls
+ * and writes it to best.  ms, cand: host arrays of capacity *ncand (or
+ * NULL) receive each candidate's time and shape; *ncand returns the number
+ * of candidates tried. */
+int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
+                    sbci_batch_config *best, double *ms, sbci_batch_config *cand, int *ncand);
+
+/* Copies the converged FP64 vectors of instance inst from the last solve to
+ * dev_out ([nconv][N_det], nconv = roots reached). */
+int sbci_batch_vectors(sbci_batch *b, int inst, double *dev_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,26 @@ _lib = None
 
 # (name, restype, argtypes) of every entry point declared in include/sbci.h
 _P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("row_tile", _I)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [
+        ("seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
+        ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
+        ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("row_tile", _I),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 SIGNATURES = [
     ("sbci_default_opts", None, [ctypes.POINTER(Opts)]),
     ("sbci_last_error", ctypes.c_char_p, []),
@@ -95,6 +115,14 @@ SIGNATURES = [
     ("sbci_set_trace", _I, [_P, _I]),
     ("sbci_trace", _I, [_P, ctypes.POINTER(StepInfo), _I]),
     ("sbci_davidson", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
+    ("sbci_batch_create", _I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    ("sbci_batch_destroy", _I, [_P]),
+    ("sbci_batch_ndet", _I64, [_P, _I]),
+    ("sbci_batch_solve", _I, [_P, _P, _D, ctypes.POINTER(Opts), ctypes.POINTER(BatchConfig), _P, _P,
+                              ctypes.POINTER(BatchReport)]),
+    ("sbci_batch_tune", _I, [_P, _P, _D, ctypes.POINTER(Opts), ctypes.POINTER(BatchConfig), _P,
+                             ctypes.POINTER(BatchConfig), ctypes.POINTER(_I)]),
+    ("sbci_batch_vectors", _I, [_P, _I, _P]),
 ]
 
 
@@ -280,6 +308,99 @@ class Context:
         buf = (StepInfo * n)()
         m = lib().sbci_trace(self.h, buf, n)
         return [buf[i].as_dict() for i in range(m)]
+
+
+@dataclass
+class BatchResult:
+    energies: list           # per instance: numpy array of its roots' energies
+    status: np.ndarray       # per-instance sbci_status
+    report: dict
+    rc: int
+
+
+class Batch:
+    """Many independent instances solved by SBCI1 in one persistent-kernel graph launch.
+
+    instances: sequence of (norb, nalpha, nbeta, h1, eri) with host numpy integrals.
+    """
+
+    def __init__(self, instances):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsbci needs a HIP device")
+        n = len(instances)
+        norb = np.array([t[0] for t in instances], dtype=np.int32)
+        na = np.array([t[1] for t in instances], dtype=np.int32)
+        nb = np.array([t[2] for t in instances], dtype=np.int32)
+        self._ints = [(np.ascontiguousarray(t[3], dtype=np.float64),
+                       np.ascontiguousarray(t[4], dtype=np.float64)) for t in instances]
+        hp = (ctypes.c_void_p * n)(*[h.ctypes.data for h, _ in self._ints])
+        ep = (ctypes.c_void_p * n)(*[e.ctypes.data for _, e in self._ints])
+        h = _P()
+        _check(lib().sbci_batch_create(n, norb.ctypes.data, na.ctypes.data, nb.ctypes.data,
+                                       ctypes.cast(hp, _P), ctypes.cast(ep, _P), ctypes.byref(h)))
+        self.h = h
+        self.n = n
+        self.ndet = [lib().sbci_batch_ndet(h, i) for i in range(n)]
+        self._nroots = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sbci_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _roots(nroots, n):
+        r = np.full(n, nroots, dtype=np.int32) if np.isscalar(nroots) else \
+            np.ascontiguousarray(nroots, dtype=np.int32)
+        if r.shape != (n,):
+            raise ValueError("nroots must be a scalar or one entry per instance")
+        return r
+
+    def solve(self, nroots, tol=1e-10, opts=None, config=None):
+        r = self._roots(nroots, self.n)
+        o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
+        e = np.full(int(r.sum()), np.nan)
+        st = np.zeros(self.n, dtype=np.int32)
+        rep = BatchReport()
+        cfg = None
+        if config is not None:
+            cfg = config if isinstance(config, BatchConfig) else BatchConfig(**config)
+        rc = lib().sbci_batch_solve(self.h, r.ctypes.data, tol, ctypes.byref(o),
+                                    ctypes.byref(cfg) if cfg is not None else None,
+                                    e.ctypes.data, st.ctypes.data, ctypes.byref(rep))
+        _check(rc, allow=(SBCI_ENOCONV, SBCI_ENUMERIC))
+        self._nroots = r
+        parts = np.split(e, np.cumsum(r)[:-1])
+        return BatchResult(parts, st, rep.as_dict(), rc)
+
+    def tune(self, nroots, tol=1e-10, opts=None):
+        """Run the autotuner; returns (best config dict, [(config dict, ms), ...])."""
+        r = self._roots(nroots, self.n)
+        o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
+        best = BatchConfig()
+        cap = 32
+        ms = np.zeros(cap)
+        cand = (BatchConfig * cap)()
+        nc = _I(cap)
+        _check(lib().sbci_batch_tune(self.h, r.ctypes.data, tol, ctypes.byref(o), ctypes.byref(best),
+                                     ms.ctypes.data, cand, ctypes.byref(nc)))
+        k = min(nc.value, cap)
+        return best.as_dict(), [(cand[i].as_dict(), float(ms[i])) for i in range(k)]
+
+    def vectors(self, inst):
+        """Converged FP64 vectors of instance inst from the last solve: [nconv, ndet] on cuda."""
+        torch = _torch()
+        k = int(self._nroots[inst])
+        out = torch.full((k, self.ndet[inst]), float("nan"), dtype=torch.float64, device="cuda")
+        _check(lib().sbci_batch_vectors(self.h, inst, ctypes.c_void_p(out.data_ptr())))
+        return out
 
 
 def _report_dict(rep: Report, nroots: int) -> dict:

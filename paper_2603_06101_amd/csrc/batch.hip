@@ -1,0 +1,1588 @@
+// Batching form: many independent CAS instances, each with its own roots,
+// solved by SBCI1 (Algorithm 1 with Supplementary Sections S1.1-S1.5) in ONE
+// persistent-kernel launch captured in a hipGraph.
+//
+// Design
+//   * One workgroup owns one instance for the whole solve: the SBCI state
+//     machine (start vectors, steps, restarts, precision hand-overs, root
+//     sequencing) runs on the device, its scalars in LDS, with the 2x2 / 3x3
+//     Ritz problems of ritz.h solved by one lane.  No host round trip, no
+//     grid-wide barrier: workgroups never wait for each other.
+//   * Workgroups take instances from an atomic queue in longest-first order
+//     (or input order), so uneven sizes balance across the 256 CUs.  Every
+//     workgroup leaves when the queue is exhausted; every instance ends after
+//     at most max_steps steps per root.
+//   * sigma inside a workgroup follows the decomposition of sigma.hip:
+//       same-spin beta part in-row, on row tiles of C staged in LDS,
+//       same-spin alpha part on column tiles of C staged in LDS,
+//       opposite-spin part row by row as an MFMA contraction of the signed
+//       ERI pair tile with s gathered rows of C, scattered through the beta
+//       pair table into an LDS copy of sigma's row (FP64 LDS atomics).
+//     Same-spin lists are stored transposed ([entry][string]) so that the
+//     list loads of a wavefront are coalesced.
+//   * The vector passes (fused update, deflation, dots) are the same
+//     arithmetic as vec.hip with workgroup-level FP64 reductions in a fixed
+//     order.
+//   * Launch shape (workgroup size, workgroups per CU, queue order, tile
+//     height) is chosen by a measured autotuner (sbci_batch_tune).
+#include "internal.h"
+#include "mfma.h"
+#include "ritz.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+struct sbci_batch;
+
+namespace sbci {
+int create_context(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                   hipStream_t stream, bool own_stream, sbci_ctx **out);
+}
+
+namespace sbci {
+namespace {
+
+constexpr int BMAXR = 4;     // roots per instance
+constexpr int BMAX_NS = 512; // strings per spin
+constexpr int BMAX_S = 36;   // single excitations per string
+constexpr int BMAX_NP = 80;  // pair rows, padded to 16
+constexpr int NVW = 7;       // work vectors: x, X, y, Y, za, zb, Z
+enum { SX = 0, SXX = 1, SY = 2, SYY = 3, SZA = 4, SZB = 5, SZ = 6 };
+
+struct BInst {
+  int ns_a, ns_b, s_a, s_b, nf_a, nf_b, npair, nroots;
+  int64_t ndet, ns_pad_b;
+  const Ent *tab_a;
+  const uint32_t *pair_b;
+  const int32_t *fcol_a, *fcol_b;  // transposed lists [nf][ns]
+  const double *fv64_a, *fv64_b;
+  const float *fv32_a, *fv32_b;
+  const double *W64;
+  const float *W32;
+  const __bf16 *Wbf;
+  const double *D64;
+  const float *D32;
+  double *v64;  // [NVW + nroots][ndet]
+  float *v32;   // [NVW + nroots][ndet] (precision form only)
+};
+
+struct BOut {
+  double E[BMAXR];
+  double dz[BMAXR];
+  int status, nconv, nsteps, nrestarts, nsig64, nsiglow, pad0, pad1;
+};
+
+struct BParams {
+  double eps0, r0, b_th, eps1, x_th1, x_th2, r1, mix_eps0, mix_r0, bf16_eps0, bf16_r0, floor,
+      lindep;
+  int max_cycle, max_steps, precision, mix_stall;
+  int rt;  // rows (columns) per same-spin tile: 8 or 16
+};
+
+// ------------------------------------------------------------ reductions
+template <int NT>
+struct Red {
+  double w[NT / 64][16];
+  double out[16];
+};
+
+// Sum v[0..q) over the workgroup; the result lands in r.out (all threads
+// read it after the trailing barrier).  Fixed order: lanes by xor tree,
+// waves in index order.
+template <int NT, int Q>
+__device__ void wg_sum(double (&v)[Q], int q, Red<NT> &r) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (j < q) {
+      double x = v[j];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) r.w[wv][j] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < q) {
+    double s = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += r.w[w][threadIdx.x];
+    r.out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ control state
+// Ritz result as plain data (LDS variables cannot have initialisers).
+struct RitzS {
+  int rank_ok, coef_ok;
+  double E[3], a1[3], a2[3], b, c, k;
+};
+__device__ inline RitzS pod(const Ritz &r) {
+  RitzS o;
+  o.rank_ok = r.rank_ok;
+  o.coef_ok = r.coef_ok;
+  for (int i = 0; i < 3; ++i) {
+    o.E[i] = r.E[i];
+    o.a1[i] = r.a1[i];
+    o.a2[i] = r.a2[i];
+  }
+  o.b = r.b;
+  o.c = r.c;
+  o.k = r.k;
+  return o;
+}
+
+struct Ctl {
+  int alpha, seg, t, steps_root, phase, seg_start, stall, done, any_noconv, nconv, status;
+  int m64[NVW], m32[NVW];  // logical slot -> physical vector
+  int nsteps, nrestarts, nsig64, nsiglow;
+  double E, sx, bestE;
+  double Ec[BMAXR];
+  double h1[16], h2[4], h3[4];
+  RitzS last, r;
+  // scratch of the start (S1.1)
+  int64_t idx[BMAXR];
+  double Hs[BMAXR * BMAXR], w[BMAXR], U[BMAXR * BMAXR];
+  double dzroot;
+  int action;
+};
+
+// ------------------------------------------------------------ WG sigma
+// Same-spin part on one tile: for every output string i of the spin and
+// every tile position r (8 per item): acc = sum_f F[i][f] * L[col(i,f)][r].
+// L holds the staged tile, [nsrc][rt + 1] (padded against bank conflicts).
+template <typename T, typename V, int NT>
+__device__ void same_tile(int nout, int nf, int rt, const int32_t *__restrict__ fcol,
+                          const V *__restrict__ fval, const T *L, V (&acc)[8], int i, int sub) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) acc[v] = 0;
+  const int ld = rt + 1;
+  const T *Lr = L + sub * 8;
+  for (int f = 0; f < nf; ++f) {
+    const int j = fcol[(int64_t)f * nout + i];
+    const V fv = fval[(int64_t)f * nout + i];
+    const T *row = Lr + j * ld;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v] += fv * (V)row[v];
+  }
+}
+
+template <typename T>
+struct ListVals;
+template <>
+struct ListVals<double> {
+  using V = double;
+  __device__ static const double *a(const BInst &I) { return I.fv64_a; }
+  __device__ static const double *b(const BInst &I) { return I.fv64_b; }
+};
+template <>
+struct ListVals<float> {
+  using V = float;
+  __device__ static const float *a(const BInst &I) { return I.fv32_a; }
+  __device__ static const float *b(const BInst &I) { return I.fv32_b; }
+};
+
+template <typename M>
+struct WSel;
+template <>
+struct WSel<MF64> {
+  __device__ static const double *w(const BInst &I) { return I.W64; }
+};
+template <>
+struct WSel<MF32> {
+  __device__ static const float *w(const BInst &I) { return I.W32; }
+};
+template <>
+struct WSel<MBF16> {
+  __device__ static const __bf16 *w(const BInst &I) { return I.Wbf; }
+};
+
+// out = H c for one vector of instance I (T = double: FP64 everywhere;
+// T = float: FP32 same-spin part, MFMA flavour M for the opposite spin).
+template <typename T, typename M, int NT>
+__device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__ c,
+                         T *__restrict__ out, char *lds) {
+  using V = typename ListVals<T>::V;
+  const int tid = threadIdx.x;
+  const int nsa = I.ns_a, nsb = I.ns_b;
+  const int rt = P.rt, ld = rt + 1, nsub = rt / 8;
+  T *L = reinterpret_cast<T *>(lds);
+  V acc[8];
+  // (1) beta same-spin, in-row, rt rows of C per tile
+  for (int r0 = 0; r0 < nsa; r0 += rt) {
+    for (int e = tid; e < rt * nsb; e += NT) {
+      const int r = e / nsb, j = e - r * nsb;
+      L[j * ld + r] = r0 + r < nsa ? c[(int64_t)(r0 + r) * nsb + j] : (T)0;
+    }
+    __syncthreads();
+    for (int it = tid; it < nsb * nsub; it += NT) {
+      const int i = it % nsb, sub = it / nsb;
+      same_tile<T, V, NT>(nsb, I.nf_b, rt, I.fcol_b, ListVals<T>::b(I), L, acc, i, sub);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int r = r0 + sub * 8 + v;
+        if (r < nsa) out[(int64_t)r * nsb + i] = (T)acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  // (2) alpha same-spin, cross-row, rt columns of C per tile
+  for (int c0 = 0; c0 < nsb; c0 += rt) {
+    for (int e = tid; e < rt * nsa; e += NT) {
+      const int j = e / rt, cc = e - j * rt;
+      L[j * ld + cc] = c0 + cc < nsb ? c[(int64_t)j * nsb + c0 + cc] : (T)0;
+    }
+    __syncthreads();
+    for (int it = tid; it < nsa * nsub; it += NT) {
+      const int i = it % nsa, sub = it / nsa;
+      same_tile<T, V, NT>(nsa, I.nf_a, rt, I.fcol_a, ListVals<T>::a(I), L, acc, i, sub);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int cc = c0 + sub * 8 + v;
+        if (cc < nsb) {
+          T *o = out + (int64_t)i * nsb + cc;
+          *o = (T)((V)*o + acc[v]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // (3) opposite spin, one row Ia at a time
+  using A = typename M::A;
+  using Frag = typename M::Frag;
+  using Out = typename M::Out;
+  constexpr int KSMAX = (BMAX_S + M::KSTEP - 1) / M::KSTEP;
+  const int kpad = ((I.s_a + M::KSTEP - 1) / M::KSTEP) * M::KSTEP;
+  const int ks_n = kpad / M::KSTEP;
+  const int ldw = kpad + M::PAD;
+  const int npt = (I.npair + 15) / 16;
+  double *sig = reinterpret_cast<double *>(lds);                    // [nsb]
+  A *Ws = reinterpret_cast<A *>(lds + sizeof(double) * BMAX_NS);     // [npt*16][ldw]
+  uint32_t *eoff = reinterpret_cast<uint32_t *>(lds + sizeof(double) * BMAX_NS +
+                                                sizeof(double) * BMAX_NP * (BMAX_S + 8));
+  const A *W = WSel<M>::w(I);
+  const int lane = tid & 63, wv = tid >> 6, li = lane & 15, g = lane >> 4;
+  const int njt = (nsb + 15) / 16;
+  for (int ia = 0; ia < nsa; ++ia) {
+    for (int j = tid; j < nsb; j += NT) sig[j] = 0;
+    const Ent *te = I.tab_a + (int64_t)ia * I.s_a;
+    for (int e = tid; e < npt * 16 * kpad; e += NT) {
+      const int kl = e / kpad, k = e - kl * kpad;
+      A v = M::cvt(0.0);
+      if (kl < I.npair && k < I.s_a) {
+        const Ent t = te[k];
+        const double wkl = (double)W[kl * I.npair + pair_index(t.p, t.q)];
+        v = M::cvt(t.sign < 0 ? -wkl : wkl);
+      }
+      Ws[kl * ldw + k] = v;
+    }
+    for (int k = tid; k < kpad; k += NT) eoff[k] = k < I.s_a ? (uint32_t)te[k].J * (uint32_t)nsb : 0u;
+    __syncthreads();
+    for (int jt = wv; jt < njt; jt += NT / 64) {
+      const int j = jt * 16 + li;
+      const uint32_t jc = (uint32_t)(j < nsb ? j : nsb - 1);
+      Frag bf[KSMAX];
+#pragma unroll
+      for (int ks = 0; ks < KSMAX; ++ks) {
+        if (ks < ks_n) {
+          uint32_t off[M::KPL];
+#pragma unroll
+          for (int t = 0; t < M::KPL; ++t) off[t] = eoff[ks * M::KSTEP + g * M::KPL + t];
+          bf[ks] = M::load_b(c, off, jc);
+        }
+      }
+      for (int u = 0; u < npt; ++u) {
+        Out o = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks)
+          if (ks < ks_n) o = M::mma(M::load_a(&Ws[(u * 16 + li) * ldw + ks * M::KSTEP + g * M::KPL]), bf[ks], o);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int kl = u * 16 + M::orow(g, r);
+          const uint32_t code = I.pair_b[(int64_t)kl * I.ns_pad_b + j];
+          if (code != kInvalid) {
+            const double val = (double)o[r];
+            atomicAdd(&sig[code >> 1], (code & 1u) ? -val : val);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = tid; j < nsb; j += NT) {
+      T *o = out + (int64_t)ia * nsb + j;
+      *o = (T)((double)*o + sig[j]);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ vector passes
+template <typename T>
+struct Vecs {
+  T *base;
+  int64_t n;
+  const int *map;
+  __device__ T *operator()(int slot) const { return base + (int64_t)map[slot] * n; }
+  __device__ T *xc(int j) const { return base + (int64_t)(NVW + j) * n; }
+};
+
+template <typename T>
+__device__ const T *diag(const BInst &I);
+template <>
+__device__ const double *diag<double>(const BInst &I) { return I.D64; }
+template <>
+__device__ const float *diag<float>(const BInst &I) { return I.D32; }
+
+template <typename T>
+__device__ Vecs<T> vecs(const BInst &I, const Ctl &C);
+template <>
+__device__ Vecs<double> vecs<double>(const BInst &I, const Ctl &C) { return {I.v64, I.ndet, C.m64}; }
+template <>
+__device__ Vecs<float> vecs<float>(const BInst &I, const Ctl &C) { return {I.v32, I.ndet, C.m32}; }
+
+struct Upd {
+  double b, c, E, inv, E0, fl, sx;
+  int sy, read_z, nconv, want_zdots;
+};
+
+// Fused SBCI update (Eqs. S56-S60 with Eq. S31's preconditioner), the same
+// per-element arithmetic as the full-size k_update.  Results in C.h1.
+template <typename T, int NT>
+__device__ void wg_update(const BInst &I, Ctl &C, Red<NT> &R, const Upd &a, int zslot, int wslot) {
+  const Vecs<T> V = vecs<T>(I, C);
+  T *x = V(SX), *X = V(SXX), *y = V(SY), *Y = V(SYY), *w = V(wslot);
+  const T *zz = V(zslot);
+  const T *Z = V(SZ);
+  const T *D = diag<T>(I);
+  double v[10 + BMAXR];
+#pragma unroll
+  for (int q = 0; q < 10 + BMAXR; ++q) v[q] = 0;
+  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+    double zi = 0, Zi = 0, yi = 0, Yi = 0;
+    if (a.read_z) {
+      zi = (double)zz[i];
+      Zi = (double)Z[i];
+    }
+    if (a.sy) {
+      yi = (double)y[i];
+      Yi = (double)Y[i];
+    }
+    const double yn = yi - a.c * zi, Yn = Yi - a.c * Zi;
+    const double xn = a.sx * (double)x[i] + a.b * yn, Xn = a.sx * (double)X[i] + a.b * Yn;
+    const double r = (Xn - a.E * xn) * a.inv;
+    double den = (double)D[i] - a.E0;
+    if (fabs(den) < a.fl) den = a.fl;
+    const double wi = r / den;
+    x[i] = (T)xn;
+    X[i] = (T)Xn;
+    y[i] = (T)yn;
+    Y[i] = (T)Yn;
+    w[i] = (T)wi;
+    const double xs = (double)(T)xn, ys = (double)(T)yn, Xs = (double)(T)Xn, Ys = (double)(T)Yn;
+    const double ws = (double)(T)wi;
+    v[0] += r * r;
+    v[1] += xs * xs;
+    v[2] += xs * ys;
+    v[3] += ys * ys;
+    v[4] += xs * Xs;
+    v[5] += xs * Ys;
+    v[6] += ys * Ys;
+    if (a.want_zdots) {
+      v[7] += xs * ws;
+      v[8] += ys * ws;
+      v[9] += ws * ws;
+    }
+#pragma unroll
+    for (int j = 0; j < BMAXR; ++j)
+      if (j < a.nconv) v[10 + j] += ws * (double)V.xc(j)[i];
+  }
+  wg_sum<NT>(v, 10 + a.nconv, R);
+  if ((int)threadIdx.x < 10 + a.nconv) C.h1[threadIdx.x] = R.out[threadIdx.x];
+  __syncthreads();
+}
+
+// z = w - sum_j d_j xc_j in place (Eq. S31), d_j = C.h1[10 + j]; x.z, y.z, z.z -> C.h2
+template <typename T, int NT>
+__device__ void wg_deflate(const BInst &I, Ctl &C, Red<NT> &R, int wslot) {
+  const Vecs<T> V = vecs<T>(I, C);
+  T *w = V(wslot);
+  const T *x = V(SX), *y = V(SY);
+  double dj[BMAXR];
+#pragma unroll
+  for (int j = 0; j < BMAXR; ++j) dj[j] = j < C.nconv ? C.h1[10 + j] : 0.0;
+  double v[3] = {0, 0, 0};
+  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+    double zi = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < BMAXR; ++j)
+      if (j < C.nconv) zi -= dj[j] * (double)V.xc(j)[i];
+    const T zt = (T)zi;
+    w[i] = zt;
+    const double zs = (double)zt;
+    v[0] += (double)x[i] * zs;
+    v[1] += (double)y[i] * zs;
+    v[2] += zs * zs;
+  }
+  wg_sum<NT>(v, 3, R);
+  if (threadIdx.x < 3) C.h2[threadIdx.x] = R.out[threadIdx.x];
+  __syncthreads();
+}
+
+// x.Z, y.Z, z.Z -> C.h3
+template <typename T, int NT>
+__device__ void wg_dots_xyz(const BInst &I, Ctl &C, Red<NT> &R, int zslot) {
+  const Vecs<T> V = vecs<T>(I, C);
+  const T *x = V(SX), *y = V(SY), *z = V(zslot), *Z = V(SZ);
+  double v[3] = {0, 0, 0};
+  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+    const double Zi = (double)Z[i];
+    v[0] += (double)x[i] * Zi;
+    v[1] += (double)y[i] * Zi;
+    v[2] += (double)z[i] * Zi;
+  }
+  wg_sum<NT>(v, 3, R);
+  if (threadIdx.x < 3) C.h3[threadIdx.x] = R.out[threadIdx.x];
+  __syncthreads();
+}
+
+// Up to BMAXR + 1 vectors with coefficients, passed by value so that the
+// unrolled loops below keep them in registers.
+template <typename T>
+struct Pack {
+  const T *p[BMAXR + 1];
+  double c[BMAXR + 1];
+  int n;
+};
+
+// dot products a . b_j -> R.out[j]
+template <typename T, int NT>
+__device__ void wg_dots(int64_t n, const T *a, const Pack<T> bs, Red<NT> &R) {
+  double v[BMAXR + 1];
+#pragma unroll
+  for (int j = 0; j < BMAXR + 1; ++j) v[j] = 0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const double ai = (double)a[i];
+#pragma unroll
+    for (int j = 0; j < BMAXR + 1; ++j)
+      if (j < bs.n) v[j] += ai * (double)bs.p[j][i];
+  }
+  wg_sum<NT>(v, bs.n, R);
+}
+
+// out = beta * out + sum_q c_q * x_q (elementwise; out may alias one of x_q)
+template <typename T, int NT>
+__device__ void wg_lincomb(int64_t n, T *out, const Pack<T> xs, double beta) {
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    double s = beta == 0.0 ? 0.0 : beta * (double)out[i];
+#pragma unroll
+    for (int q = 0; q < BMAXR + 1; ++q)
+      if (q < xs.n) s += xs.c[q] * (double)xs.p[q][i];
+    out[i] = (T)s;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ Pack<T> pack(int n) {
+  Pack<T> k;
+#pragma unroll
+  for (int j = 0; j < BMAXR + 1; ++j) {
+    k.p[j] = nullptr;
+    k.c[j] = 0;
+  }
+  k.n = n;
+  return k;
+}
+
+template <typename Td, typename Ts, int NT>
+__device__ void wg_convert(int64_t n, Td *dst, const Ts *src, double scale) {
+  for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = (Td)(scale * (double)src[i]);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ the SBCI1 state machine
+template <int NT>
+struct Solve {
+  const BInst &I;
+  const BParams &P;
+  Ctl &C;
+  Red<NT> &R;
+  char *lds;
+
+  __device__ bool lane0() const { return threadIdx.x == 0; }
+
+  template <typename T>
+  __device__ void sigma_phase(const T *c, T *o, int mode) {
+    if constexpr (std::is_same<T, double>::value) {
+      wg_sigma<double, MF64, NT>(I, P, c, o, lds);
+      if (lane0()) C.nsig64 += 1;
+    } else {
+      if (mode == SBCI_BF16)
+        wg_sigma<float, MBF16, NT>(I, P, c, o, lds);
+      else
+        wg_sigma<float, MF32, NT>(I, P, c, o, lds);
+      if (lane0()) C.nsiglow += 1;
+    }
+    __syncthreads();
+  }
+
+  __device__ double shift(double Enew) const { return C.alpha == 0 ? Enew : C.Ec[0]; }
+
+  template <typename T>
+  __device__ void segment_start(double sx) {
+    Upd a{};
+    a.b = 0;
+    a.c = 0;
+    a.E = C.E;
+    a.inv = 1.0;
+    a.E0 = shift(C.E);
+    a.fl = P.floor;
+    a.sx = sx;
+    a.sy = 0;
+    a.read_z = 0;
+    a.nconv = C.nconv;
+    a.want_zdots = C.nconv == 0;
+    // the preconditioned residual goes to the current z slot (za)
+    wg_update<T, NT>(I, C, R, a, SZB, SZA);
+    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, SZA);
+    if (lane0()) {
+      C.sx = 1.0;
+      C.seg_start = 1;
+      C.t = 0;
+    }
+    __syncthreads();
+  }
+
+  // Algorithm 1 line 1 with Eqs. S4-S7; returns false on a vanished vector
+  template <typename T>
+  __device__ bool start_root() {
+    const Vecs<T> V = vecs<T>(I, C);
+    T *x = V(SX), *X = V(SXX);
+    const int nc = C.nconv;
+    if (nc > 0) {
+      Pack<T> px = pack<T>(nc), pX = pack<T>(nc);
+#pragma unroll
+      for (int j = 0; j < BMAXR; ++j) {
+        px.p[j] = pX.p[j] = V.xc(j);
+      }
+      wg_dots<T, NT>(I.ndet, x, px, R);
+#pragma unroll
+      for (int j = 0; j < BMAXR; ++j) {
+        if (j < nc) {
+          px.c[j] = -R.out[j];
+          pX.c[j] = -C.Ec[j] * R.out[j];
+        }
+      }
+      __syncthreads();
+      wg_lincomb<T, NT>(I.ndet, x, px, 1.0);   // Eq. S4
+      wg_lincomb<T, NT>(I.ndet, X, pX, 1.0);   // Eq. S5
+    }
+    Pack<T> p1 = pack<T>(1);
+    p1.p[0] = x;
+    wg_dots<T, NT>(I.ndet, x, p1, R);
+    const double nxx = R.out[0];
+    __syncthreads();
+    if (!(nxx > 0) || !isfinite(nxx)) return false;
+    if (lane0()) {
+      C.seg = 0;
+      C.steps_root = 0;
+      C.stall = 0;
+      C.bestE = C.E;
+    }
+    __syncthreads();
+    segment_start<T>(1.0 / sqrt(nxx));  // Eqs. S6-S7, applied lazily
+    return true;
+  }
+
+  // E = x.X / x.x of the current vectors of precision T
+  template <typename T>
+  __device__ double rayleigh() {
+    const Vecs<T> V = vecs<T>(I, C);
+    Pack<T> bs = pack<T>(2);
+    bs.p[0] = V(SX);
+    bs.p[1] = V(SXX);
+    wg_dots<T, NT>(I.ndet, V(SX), bs, R);
+    const double e = R.out[1] / R.out[0];
+    __syncthreads();
+    return e;
+  }
+
+  __device__ bool to_f32() {
+    const Vecs<float> V = vecs<float>(I, C);
+    sigma_phase<float>(V(SX), V(SXX), SBCI_F32);
+    const double e = rayleigh<float>();
+    const int steps = C.steps_root, seg = C.seg;
+    if (lane0()) {
+      C.E = e;
+      C.phase = SBCI_F32;
+    }
+    __syncthreads();
+    if (!start_root<float>()) return false;
+    if (lane0()) {
+      C.steps_root = steps;
+      C.seg = seg + 1;
+    }
+    __syncthreads();
+    return true;
+  }
+
+  __device__ bool promote() {
+    const Vecs<double> V = vecs<double>(I, C);
+    const Vecs<float> F = vecs<float>(I, C);
+    wg_convert<double, float, NT>(I.ndet, V(SX), F(SX), 1.0);
+    sigma_phase<double>(V(SX), V(SXX), SBCI_F64);
+    const double e = rayleigh<double>();
+    const int steps = C.steps_root, seg = C.seg;
+    if (lane0()) {
+      C.E = e;
+      C.phase = SBCI_F64;
+    }
+    __syncthreads();
+    if (!start_root<double>()) return false;
+    if (lane0()) {
+      C.steps_root = steps;
+      C.seg = seg + 1;
+    }
+    __syncthreads();
+    return true;
+  }
+
+  // Converged root (FP64): store x_c, then the next root's start from the
+  // second Ritz vector of this step (Section S1.4).  Returns false on error.
+  __device__ bool finish_root(double xn, bool second_ok) {
+    const Vecs<double> V = vecs<double>(I, C);
+    const int j = C.nconv;
+    wg_convert<double, double, NT>(I.ndet, V.xc(j), V(SX), 1.0 / xn);
+    if (P.precision != SBCI_F64) {
+      const Vecs<float> F = vecs<float>(I, C);
+      wg_convert<float, double, NT>(I.ndet, F.xc(j), V.xc(j), 1.0);
+    }
+    if (lane0()) {
+      C.Ec[j] = C.E;
+      C.nconv = j + 1;
+      if (C.nconv >= I.nroots) C.done = 1;
+    }
+    __syncthreads();
+    if (C.done) return true;
+    if (!second_ok) {
+      if (lane0()) C.status = SBCI_ENUMERIC;
+      __syncthreads();
+      return false;
+    }
+    const double ax = C.last.a2[0], ay = C.last.a2[1], az = C.last.a2[2];
+    const double b = C.last.b, c = C.last.c;
+    Pack<double> in1 = pack<double>(3), in2 = pack<double>(3);
+    in1.c[0] = in2.c[0] = ax;
+    in1.c[1] = in2.c[1] = ay - ax * b;
+    in1.c[2] = in2.c[2] = ay * c + az;
+    in1.p[0] = V(SX);
+    in1.p[1] = V(SY);
+    in1.p[2] = V(SZA);
+    in2.p[0] = V(SXX);
+    in2.p[1] = V(SYY);
+    in2.p[2] = V(SZ);
+    wg_lincomb<double, NT>(I.ndet, V(SZB), in1, 0.0);
+    wg_lincomb<double, NT>(I.ndet, V(SYY), in2, 0.0);
+    if (lane0()) {
+      int t = C.m64[SX];
+      C.m64[SX] = C.m64[SZB];
+      C.m64[SZB] = t;
+      t = C.m64[SXX];
+      C.m64[SXX] = C.m64[SYY];
+      C.m64[SYY] = t;
+      C.E = C.last.E[1];
+      C.alpha += 1;
+    }
+    __syncthreads();
+    if (P.precision != SBCI_F64) {
+      const Vecs<double> V2 = vecs<double>(I, C);
+      const Vecs<float> F = vecs<float>(I, C);
+      wg_convert<float, double, NT>(I.ndet, F(SX), V2(SX), 1.0);
+      wg_convert<float, double, NT>(I.ndet, F(SXX), V2(SXX), 1.0);
+      if (lane0()) C.phase = P.precision;
+      __syncthreads();
+      return start_root<float>();
+    }
+    if (lane0()) C.phase = SBCI_F64;
+    __syncthreads();
+    return start_root<double>();
+  }
+
+  template <typename T>
+  __device__ bool restart_from_ritz() {
+    const RitzS r = C.r;
+    const Vecs<T> V = vecs<T>(I, C);
+    Pack<T> in1 = pack<T>(3), in2 = pack<T>(3);
+    in1.c[0] = in2.c[0] = r.a1[0] * C.sx;
+    in1.c[1] = in2.c[1] = C.seg_start ? 0.0 : r.a1[1];
+    in1.c[2] = in2.c[2] = r.a1[2];
+    in1.p[0] = V(SX);
+    in1.p[1] = V(SY);
+    in1.p[2] = V(SZA);
+    in2.p[0] = V(SXX);
+    in2.p[1] = V(SYY);
+    in2.p[2] = V(SZ);
+    wg_lincomb<T, NT>(I.ndet, V(SZB), in1, 0.0);
+    wg_lincomb<T, NT>(I.ndet, V(SYY), in2, 0.0);
+    if (lane0()) {
+      int *m = std::is_same<T, double>::value ? C.m64 : C.m32;
+      int t = m[SX];
+      m[SX] = m[SZB];
+      m[SZB] = t;
+      t = m[SXX];
+      m[SXX] = m[SYY];
+      m[SYY] = t;
+      C.E = r.E[0];
+      C.seg += 1;
+      C.nrestarts += 1;
+    }
+    __syncthreads();
+    const Vecs<T> V2 = vecs<T>(I, C);
+    Pack<T> p1 = pack<T>(1);
+    p1.p[0] = V2(SX);
+    wg_dots<T, NT>(I.ndet, V2(SX), p1, R);
+    const double nxx = R.out[0];
+    __syncthreads();
+    segment_start<T>(1.0 / sqrt(nxx));
+    return true;
+  }
+
+  // One SBCI step of the running root in precision T.  Returns false when
+  // the instance stops with an error (C.status set).
+  template <typename T>
+  __device__ bool step() {
+    const Vecs<T> V = vecs<T>(I, C);
+    const int mode = C.phase;
+    sigma_phase<T>(V(SZA), V(SZ), mode);                       // Eq. S32
+    wg_dots_xyz<T, NT>(I, C, R, SZA);
+    if (lane0()) {
+      C.steps_root += 1;
+      C.nsteps += 1;
+      const double sx = C.sx;
+      double N[6], Hm[6];
+      N[0] = sx * sx * C.h1[1];
+      N[1] = sx * C.h1[2];
+      N[3] = C.h1[3];
+      Hm[0] = sx * sx * C.h1[4];
+      Hm[1] = sx * C.h1[5];
+      Hm[3] = C.h1[6];
+      if (C.nconv > 0) {
+        N[2] = sx * C.h2[0];
+        N[4] = C.h2[1];
+        N[5] = C.h2[2];
+      } else {
+        N[2] = sx * C.h1[7];
+        N[4] = C.h1[8];
+        N[5] = C.h1[9];
+      }
+      Hm[2] = sx * C.h3[0];
+      Hm[4] = C.h3[1];
+      Hm[5] = C.h3[2];
+      bool fin = true;
+      for (int i = 0; i < 6; ++i) fin = fin && isfinite(N[i]) && isfinite(Hm[i]);
+      // action: 0 update, 1 error, 2 finish (eigenvector at segment start),
+      // 3 promote, 4 new segment (rank), 5 restart from Ritz
+      if (!fin) {
+        C.action = 1;
+        C.status = SBCI_ENUMERIC;
+      } else {
+        C.r = pod(C.seg_start ? ritz_first(N[0], N[2], N[5], Hm[0], Hm[2], Hm[5], P.lindep)
+                              : ritz_next(N, Hm, P.lindep));
+        if (!C.r.rank_ok) {
+          if (C.seg_start) {
+            const double dz0 = sqrt(C.h1[0]);
+            if (C.phase == SBCI_F64 && dz0 < P.r0) {
+              C.action = 2;
+              C.dzroot = dz0;
+            } else if (C.phase != SBCI_F64) {
+              C.action = 3;
+            } else {
+              C.action = 1;
+              C.status = SBCI_ENUMERIC;
+            }
+          } else {
+            C.action = 4;
+            C.nrestarts += 1;
+            C.seg += 1;
+            C.dzroot = sx / sqrt(N[0]);
+          }
+        } else if (!C.r.coef_ok) {
+          C.action = 5;
+        } else {
+          C.action = 0;
+        }
+      }
+    }
+    __syncthreads();
+    const int act = C.action;
+    if (act == 1) return false;
+    if (act == 2) {
+      if (lane0()) C.h2[3] = C.dzroot;  // residual of the finished root
+      __syncthreads();
+      return finish_root(sqrt(C.h1[1]), false);
+    }
+    if (act == 3) return promote();
+    if (act == 4) {
+      segment_start<T>(C.dzroot);
+      return true;
+    }
+    if (act == 5) return restart_from_ritz<T>();
+    const RitzS r = C.r;
+    const double Enew = r.E[0];
+    Upd a{};
+    a.b = r.b;
+    a.c = r.c;
+    a.E = Enew;
+    a.inv = 1.0 / fabs(r.k);
+    a.E0 = shift(Enew);
+    a.fl = P.floor;
+    a.sx = C.sx;
+    a.sy = C.seg_start ? 0 : 1;
+    a.read_z = 1;
+    a.nconv = C.nconv;
+    a.want_zdots = C.nconv == 0;
+    wg_update<T, NT>(I, C, R, a, SZA, SZB);
+    // decisions (lane 0), then the follow-up passes
+    if (lane0()) {
+      C.last = r;
+      const double dz = sqrt(C.h1[0]);
+      const double xn = sqrt(C.h1[1]);
+      const double dE = fabs(Enew - C.E);
+      C.dzroot = dz;
+      C.h2[3] = xn;
+      int act2 = 0;  // 0 continue, 1 error, 2 converged, 3 hand-over, 4 cap
+      if (!isfinite(dz) || !isfinite(xn) || !isfinite(Enew)) {
+        act2 = 1;
+        C.status = SBCI_ENUMERIC;
+      } else {
+        int reason = 0;
+        bool conv = false, prom = false;
+        const bool low = C.phase != SBCI_F64;
+        if (!low && dE < P.eps0 && dz < P.r0) {
+          conv = true;
+          reason = 1;
+        } else if (low) {
+          if (Enew < C.bestE - 1e-15 * fabs(C.bestE)) {
+            C.bestE = Enew;
+            C.stall = 0;
+          } else {
+            C.stall += 1;
+          }
+          const bool bf = C.phase == SBCI_BF16;
+          const double e0 = bf ? P.bf16_eps0 : P.mix_eps0, r0 = bf ? P.bf16_r0 : P.mix_r0;
+          if ((dE < e0 && dz < r0) || C.stall >= P.mix_stall) {
+            prom = true;
+            reason = 8;
+          }
+        }
+        if (!conv && !prom) {
+          const bool s62a = C.alpha > 0 && fabs(r.b) < P.b_th && dE < P.eps1;
+          const bool s62b = xn < P.x_th1 || xn > P.x_th2;
+          const bool s62c = dz > P.r1 && C.t > 0;
+          const bool cap = C.t + 1 >= P.max_cycle;
+          reason = s62a ? 2 : s62b ? 3 : s62c ? 4 : cap ? 5 : 0;
+        }
+        C.E = Enew;
+        if (conv) {
+          act2 = 2;
+        } else if (prom) {
+          act2 = 3;
+        } else if (C.steps_root >= P.max_steps) {
+          C.any_noconv = 1;
+          act2 = 4;
+        } else {
+          if (reason >= 2) {
+            C.nrestarts += 1;
+            C.seg += 1;
+            C.t = 0;
+            C.seg_start = 1;
+            C.sx = 1.0 / xn;
+          } else {
+            C.t += 1;
+            C.seg_start = 0;
+            C.sx = 1.0;
+          }
+        }
+      }
+      C.action = act2;
+    }
+    __syncthreads();
+    const int act2 = C.action;
+    const double xn = C.h2[3];
+    if (act2 == 1) return false;
+    if (act2 == 2) return finish_root(xn, true);
+    if (act2 == 3) return C.phase == SBCI_BF16 ? to_f32() : promote();
+    if (act2 == 4) {
+      if (C.phase != SBCI_F64) return promote();
+      return finish_root(xn, true);
+    }
+    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, SZB);
+    if (lane0()) {
+      int *m = std::is_same<T, double>::value ? C.m64 : C.m32;
+      const int t = m[SZA];
+      m[SZA] = m[SZB];
+      m[SZB] = t;
+    }
+    __syncthreads();
+    return true;
+  }
+
+  // Section S1.1: the k lowest diagonal determinants (ties: lower index),
+  // sigma on their unit vectors, k x k eigenproblem; x, X from its lowest
+  // eigenvector.  He_i are kept in the y, Y, za, zb slots (k <= 4).
+  __device__ bool initial_vector() {
+    const Vecs<double> V = vecs<double>(I, C);
+    const int k = (int)(I.nroots < I.ndet ? I.nroots : I.ndet);
+    const double *D = I.D64;
+    for (int q = 0; q < k; ++q) {
+      double bv = INFINITY;
+      int64_t bi = INT64_MAX;
+      for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+        bool taken = false;
+        for (int p = 0; p < q; ++p) taken = taken || C.idx[p] == i;
+        const double d = D[i];
+        if (!taken && (d < bv || (d == bv && i < bi))) {
+          bv = d;
+          bi = i;
+        }
+      }
+      // argmin over the workgroup: (value, index) lexicographic
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int64_t oi = __shfl_xor(bi, o, 64);
+        if (ov < bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if ((threadIdx.x & 63) == 0) {
+        R.w[threadIdx.x >> 6][0] = bv;
+        R.w[threadIdx.x >> 6][1] = __longlong_as_double(bi);
+      }
+      __syncthreads();
+      if (lane0()) {
+        double v0 = R.w[0][0];
+        int64_t i0 = __double_as_longlong(R.w[0][1]);
+        for (int w = 1; w < NT / 64; ++w) {
+          const double v1 = R.w[w][0];
+          const int64_t i1 = __double_as_longlong(R.w[w][1]);
+          if (v1 < v0 || (v1 == v0 && i1 < i0)) {
+            v0 = v1;
+            i0 = i1;
+          }
+        }
+        C.idx[q] = i0;
+      }
+      __syncthreads();
+    }
+    const int hs[4] = {SY, SYY, SZA, SZB};
+    double *x = V(SX);
+    for (int q = 0; q < k; ++q) {
+      for (int64_t i = threadIdx.x; i < I.ndet; i += NT) x[i] = i == C.idx[q] ? 1.0 : 0.0;
+      __syncthreads();
+      sigma_phase<double>(x, V(hs[q]), SBCI_F64);              // Eq. S1
+      if ((int)threadIdx.x < k) C.Hs[threadIdx.x * k + q] = V(hs[q])[C.idx[threadIdx.x]];
+      __syncthreads();
+    }
+    if (lane0()) {
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j)
+          C.Hs[i * k + j] = C.Hs[j * k + i] = 0.5 * (C.Hs[i * k + j] + C.Hs[j * k + i]);
+      jacobi_eigh<BMAXR>(k, C.Hs, C.w, C.U);
+      C.E = C.w[0];
+    }
+    __syncthreads();
+    // x = sum_i U[i][0] e_idx_i (Eq. S2), X = sum_i U[i][0] He_i (Eq. S3)
+    for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+      double s = 0;
+      for (int q = 0; q < k; ++q)
+        if (C.idx[q] == i) s += C.U[q * k + 0];
+      x[i] = s;
+    }
+    Pack<double> hp = pack<double>(k);
+#pragma unroll
+    for (int q = 0; q < BMAXR; ++q) {
+      hp.p[q] = V(hs[q]);
+      hp.c[q] = q < k ? C.U[q * k + 0] : 0.0;
+    }
+    wg_lincomb<double, NT>(I.ndet, V(SXX), hp, 0.0);
+    return true;
+  }
+
+  __device__ void run(BOut &out) {
+    if (lane0()) {
+      C.alpha = 0;
+      C.seg = 0;
+      C.t = 0;
+      C.steps_root = 0;
+      C.phase = SBCI_F64;
+      C.seg_start = 1;
+      C.stall = 0;
+      C.done = 0;
+      C.any_noconv = 0;
+      C.nconv = 0;
+      C.status = SBCI_OK;
+      for (int i = 0; i < NVW; ++i) C.m64[i] = C.m32[i] = i;
+      C.nsteps = C.nrestarts = C.nsig64 = C.nsiglow = 0;
+      C.E = 0;
+      C.sx = 1;
+      C.bestE = 0;
+      for (int i = 0; i < BMAXR; ++i) {
+        C.Ec[i] = NAN;
+        C.idx[i] = -1;
+      }
+      C.last = pod(Ritz());
+      C.r = pod(Ritz());
+    }
+    __syncthreads();
+    bool ok = initial_vector();
+    if (ok) {
+      if (P.precision != SBCI_F64) {
+        const Vecs<double> V = vecs<double>(I, C);
+        const Vecs<float> F = vecs<float>(I, C);
+        wg_convert<float, double, NT>(I.ndet, F(SX), V(SX), 1.0);
+        wg_convert<float, double, NT>(I.ndet, F(SXX), V(SXX), 1.0);
+        if (lane0()) C.phase = P.precision;
+        __syncthreads();
+        ok = start_root<float>();
+      } else {
+        ok = start_root<double>();
+      }
+      if (!ok && lane0()) C.status = SBCI_ENUMERIC;
+      __syncthreads();
+    }
+    // hard bound on the number of passes (every pass is a step or a phase change)
+    const int cap = I.nroots * (P.max_steps + 8) + 8;
+    int guard = 0;
+    int last_nconv = 0;
+    while (ok && !C.done && guard < cap) {
+      ++guard;
+      ok = C.phase == SBCI_F64 ? step<double>() : step<float>();
+      if (lane0() && C.nconv > last_nconv) out.dz[C.nconv - 1] = C.dzroot;
+      last_nconv = C.nconv;
+      __syncthreads();
+    }
+    if (lane0()) {
+      for (int i = 0; i < BMAXR; ++i) out.E[i] = C.Ec[i];
+      out.nconv = C.nconv;
+      out.nsteps = C.nsteps;
+      out.nrestarts = C.nrestarts;
+      out.nsig64 = C.nsig64;
+      out.nsiglow = C.nsiglow;
+      int st = C.status;
+      if (st == SBCI_OK && (!C.done || C.any_noconv)) st = SBCI_ENOCONV;
+      out.status = st;
+    }
+    __syncthreads();
+  }
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
+                                              const int *__restrict__ order, int ninst,
+                                              unsigned *queue, BOut *out,
+                                              const BParams *__restrict__ prm) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ Ctl C;
+  __shared__ Red<NT> R;
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int it = item;
+    __syncthreads();
+    if (it >= ninst) break;
+    const int id = order[it];
+    // descriptors and parameters stay in global memory (uniform loads)
+    Solve<NT> S{inst[id], *prm, C, R, lds};
+    S.run(out[id]);
+  }
+}
+
+// Graph-safe reset of the work queue (a kernel, not a memset node).
+__global__ void k_batch_reset(unsigned *queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) queue[0] = 0u;
+}
+
+// Transposed same-spin lists: dst[f][i] = src[i][f].
+template <typename T>
+__global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t ns, int nf) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= ns * nf) return;
+  const int64_t i = e / nf, f = e - i * nf;
+  dst[f * ns + i] = src[e];
+}
+
+size_t lds_bytes(int rt, int nsa, int nsb) {
+  const size_t same = sizeof(double) * (size_t)(rt + 1) * (size_t)std::max(nsa, nsb);
+  const size_t opp = sizeof(double) * BMAX_NS + sizeof(double) * BMAX_NP * (BMAX_S + 8) +
+                     sizeof(uint32_t) * 64;
+  return std::max(same, opp);
+}
+
+}  // namespace
+}  // namespace sbci
+
+// ------------------------------------------------------------ host side
+using namespace sbci;
+
+struct SpinT {
+  int32_t *fcol = nullptr;
+  double *f64 = nullptr;
+  float *f32 = nullptr;
+};
+
+struct sbci_batch {
+  int ninst = 0;
+  int device = 0;
+  int ncu = 0;
+  hipStream_t stream = nullptr;
+  std::vector<sbci_ctx *> ctx;
+  std::vector<SpinT> la, lb;  // transposed lists per instance
+  std::vector<int> nroots;    // of the last solve
+  BInst *d_inst = nullptr;
+  BParams *d_params = nullptr;
+  int *d_order = nullptr;
+  unsigned *d_queue = nullptr;
+  BOut *d_out = nullptr;
+  double *arena64 = nullptr;
+  float *arena32 = nullptr;
+  size_t cap64 = 0, cap32 = 0;
+  std::vector<BInst> h_inst;
+  sbci_batch_config tuned{};
+  bool have_tuned = false;
+  int solved_precision = -1;
+};
+
+namespace {
+
+int batch_error(int code, const std::string &m) { return set_error(code, m); }
+
+int build_lists(sbci_batch *b, int i) {
+  sbci_ctx *c = b->ctx[i];
+  auto mk = [&](const SpinTables &T, SpinT &o) -> int {
+    const int64_t n = T.ns * T.nf;
+    SBCI_HIP(hipMalloc(&o.fcol, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+    SBCI_HIP(hipMalloc(&o.f64, sizeof(double) * std::max<int64_t>(n, 1)));
+    SBCI_HIP(hipMalloc(&o.f32, sizeof(float) * std::max<int64_t>(n, 1)));
+    if (n > 0) {
+      const unsigned g = (unsigned)((n + 255) / 256);
+      k_list_t<int32_t><<<g, 256, 0, b->stream>>>(T.fcol, o.fcol, T.ns, T.nf);
+      k_list_t<double><<<g, 256, 0, b->stream>>>(T.fval64, o.f64, T.ns, T.nf);
+      k_list_t<float><<<g, 256, 0, b->stream>>>(T.fval32, o.f32, T.ns, T.nf);
+      SBCI_CHECK_LAUNCH();
+    }
+    return SBCI_OK;
+  };
+  SBCI_TRY(mk(c->A, b->la[i]));
+  if (c->B.shared) {
+    b->lb[i] = b->la[i];
+  } else {
+    SBCI_TRY(mk(c->B, b->lb[i]));
+  }
+  return SBCI_OK;
+}
+
+template <int NT>
+int instantiate(sbci_batch *b, const sbci_batch_config &cfg, size_t lds, BParams P,
+                hipGraphExec_t *exec_out, hipGraph_t *graph_out) {
+  SBCI_HIP(hipFuncSetAttribute((const void *)k_batch<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  const unsigned grid = (unsigned)std::max(1, std::min(b->ncu * cfg.wg_per_cu, b->ninst));
+  hipGraph_t g = nullptr;
+  SBCI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue);
+  k_batch<NT><<<grid, NT, lds, b->stream>>>(b->d_inst, b->d_order, b->ninst, b->d_queue, b->d_out,
+                                            b->d_params);
+  hipError_t le = hipGetLastError();
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (le != hipSuccess) return batch_error(SBCI_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
+  if (e != hipSuccess) return batch_error(SBCI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return batch_error(SBCI_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  *exec_out = x;
+  *graph_out = g;
+  return SBCI_OK;
+}
+
+int check_config(const sbci_batch_config &c) {
+  if (c.threads != 256 && c.threads != 512 && c.threads != 1024)
+    return batch_error(SBCI_EINVAL, "batch config: threads must be 256, 512 or 1024");
+  if (c.wg_per_cu < 1 || c.wg_per_cu > 4)
+    return batch_error(SBCI_EINVAL, "batch config: wg_per_cu must be in 1..4");
+  if (c.order != 0 && c.order != 1) return batch_error(SBCI_EINVAL, "batch config: order must be 0 or 1");
+  if (c.row_tile != 8 && c.row_tile != 16)
+    return batch_error(SBCI_EINVAL, "batch config: row_tile must be 8 or 16");
+  return SBCI_OK;
+}
+
+int params_from(const sbci_opts *opt, double tol, BParams &P, int &precision) {
+  sbci_opts o;
+  if (opt) o = *opt; else sbci_default_opts(&o);
+  if (tol > 0) {
+    o.eps0 = tol;
+    o.r0 = std::sqrt(tol);
+  }
+  if (!(o.eps0 > 0) || !(o.r0 > 0)) return batch_error(SBCI_EINVAL, "eps0 and r0 must be > 0");
+  if (o.precision != SBCI_F64 && o.precision != SBCI_F32 && o.precision != SBCI_BF16)
+    return batch_error(SBCI_EINVAL, "unknown precision");
+  if (o.max_cycle < 1 || o.max_steps < 1) return batch_error(SBCI_EINVAL, "max_cycle, max_steps >= 1");
+  if (o.x0) return batch_error(SBCI_EINVAL, "batch solve: opts.x0 must be NULL");
+  P.eps0 = o.eps0;
+  P.r0 = o.r0;
+  P.b_th = o.b_th;
+  P.eps1 = o.eps1;
+  P.x_th1 = o.x_th1;
+  P.x_th2 = o.x_th2;
+  P.r1 = o.r1;
+  P.mix_eps0 = o.mix_eps0;
+  P.mix_r0 = o.mix_r0;
+  P.bf16_eps0 = o.bf16_eps0;
+  P.bf16_r0 = o.bf16_r0;
+  P.floor = o.precond_floor;
+  P.lindep = o.lindep;
+  P.max_cycle = o.max_cycle;
+  P.max_steps = o.max_steps;
+  P.precision = o.precision;
+  P.mix_stall = o.mix_stall;
+  precision = o.precision;
+  return SBCI_OK;
+}
+
+// Per-instance vectors and descriptors for this nroots / precision.
+int prepare(sbci_batch *b, const int *nroots, int precision) {
+  size_t need64 = 0, need32 = 0;
+  for (int i = 0; i < b->ninst; ++i) {
+    if (nroots[i] < 1 || nroots[i] > BMAXR || nroots[i] > b->ctx[i]->ndet)
+      return batch_error(SBCI_EINVAL, "batch nroots must be in [1, min(4, N_det)] for every instance");
+    const size_t n = (size_t)b->ctx[i]->ndet * (size_t)(NVW + nroots[i]);
+    need64 += (n + 63) / 64 * 64;
+    if (precision != SBCI_F64) need32 += (n + 63) / 64 * 64;
+  }
+  if (need64 > b->cap64) {
+    hipFree(b->arena64);
+    b->arena64 = nullptr;
+    SBCI_HIP(hipMalloc(&b->arena64, sizeof(double) * need64));
+    b->cap64 = need64;
+  }
+  if (need32 > b->cap32) {
+    hipFree(b->arena32);
+    b->arena32 = nullptr;
+    SBCI_HIP(hipMalloc(&b->arena32, sizeof(float) * need32));
+    b->cap32 = need32;
+  }
+  b->h_inst.resize(b->ninst);
+  size_t o64 = 0, o32 = 0;
+  for (int i = 0; i < b->ninst; ++i) {
+    sbci_ctx *c = b->ctx[i];
+    BInst &I = b->h_inst[i];
+    I.ns_a = (int)c->A.ns;
+    I.ns_b = (int)c->B.ns;
+    I.s_a = c->A.s;
+    I.s_b = c->B.s;
+    I.nf_a = c->A.nf;
+    I.nf_b = c->B.nf;
+    I.npair = c->npair;
+    I.nroots = nroots[i];
+    I.ndet = c->ndet;
+    I.ns_pad_b = c->B.ns_pad;
+    I.tab_a = c->A.tab;
+    I.pair_b = c->B.pair;
+    I.fcol_a = b->la[i].fcol;
+    I.fcol_b = b->lb[i].fcol;
+    I.fv64_a = b->la[i].f64;
+    I.fv64_b = b->lb[i].f64;
+    I.fv32_a = b->la[i].f32;
+    I.fv32_b = b->lb[i].f32;
+    I.W64 = c->W64;
+    I.W32 = c->W32;
+    I.Wbf = reinterpret_cast<const __bf16 *>(c->Wbf);
+    I.D64 = c->hdiag;
+    I.D32 = c->hdiag32;
+    const size_t n = (size_t)c->ndet * (size_t)(NVW + nroots[i]);
+    I.v64 = b->arena64 + o64;
+    o64 += (n + 63) / 64 * 64;
+    if (precision != SBCI_F64) {
+      I.v32 = b->arena32 + o32;
+      o32 += (n + 63) / 64 * 64;
+    } else {
+      I.v32 = nullptr;
+    }
+  }
+  SBCI_HIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(BInst) * b->ninst,
+                          hipMemcpyHostToDevice, b->stream));
+  b->nroots.assign(nroots, nroots + b->ninst);
+  return SBCI_OK;
+}
+
+int set_order(sbci_batch *b, int order) {
+  std::vector<int> ord(b->ninst);
+  for (int i = 0; i < b->ninst; ++i) ord[i] = i;
+  if (order == 0) {
+    // longest first: work ~ N_det * (F list + opposite-spin pair rows) * roots
+    auto work = [&](int i) {
+      const BInst &I = b->h_inst[i];
+      return (double)I.ndet * (double)(I.nf_a + I.nf_b + I.npair * I.s_a / 2 + 24) * I.nroots;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work(x) > work(y); });
+  }
+  SBCI_HIP(hipMemcpyAsync(b->d_order, ord.data(), sizeof(int) * b->ninst, hipMemcpyHostToDevice,
+                          b->stream));
+  return SBCI_OK;
+}
+
+int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, double *ms) {
+  size_t lds = 0;
+  for (auto &I : b->h_inst) lds = std::max(lds, lds_bytes(cfg.row_tile, I.ns_a, I.ns_b));
+  // The solve parameters are baked into the captured launch, so every call
+  // captures a fresh graph (a few microseconds next to the solve).
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  BParams Pc = P;
+  Pc.rt = cfg.row_tile;
+  SBCI_HIP(hipMemcpyAsync(b->d_params, &Pc, sizeof(BParams), hipMemcpyHostToDevice, b->stream));
+  int rc = SBCI_OK;
+  if (cfg.threads == 256)
+    rc = instantiate<256>(b, cfg, lds, Pc, &x, &g);
+  else if (cfg.threads == 512)
+    rc = instantiate<512>(b, cfg, lds, Pc, &x, &g);
+  else
+    rc = instantiate<1024>(b, cfg, lds, Pc, &x, &g);
+  if (rc != SBCI_OK) return rc;
+  hipEvent_t e0, e1;
+  SBCI_HIP(hipEventCreate(&e0));
+  SBCI_HIP(hipEventCreate(&e1));
+  SBCI_HIP(hipEventRecord(e0, b->stream));
+  hipError_t e = hipGraphLaunch(x, b->stream);
+  SBCI_HIP(hipEventRecord(e1, b->stream));
+  hipError_t s = hipStreamSynchronize(b->stream);
+  float t = 0;
+  hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipGraphExecDestroy(x);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return batch_error(SBCI_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  if (s != hipSuccess) return batch_error(SBCI_EDEVICE, std::string("batch solve: ") + hipGetErrorString(s));
+  if (ms) *ms = t;
+  return SBCI_OK;
+}
+
+sbci_batch_config default_config() {
+  sbci_batch_config c{};
+  c.threads = 256;
+  c.wg_per_cu = 2;
+  c.order = 0;
+  c.row_tile = 16;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbci_batch_create(int ninst, const int *norb, const int *nalpha, const int *nbeta,
+                      const double *const *h1, const double *const *eri, sbci_batch **out) {
+  if (!out) return batch_error(SBCI_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ninst < 1) return batch_error(SBCI_EINVAL, "ninst must be >= 1");
+  if (!norb || !nalpha || !nbeta || !h1 || !eri) return batch_error(SBCI_EINVAL, "NULL argument");
+  for (int i = 0; i < ninst; ++i) {
+    if (norb[i] < 1 || norb[i] > 11)
+      return batch_error(SBCI_EINVAL, "batch instances need 1 <= norb <= 11");
+    if (!h1[i] || !eri[i]) return batch_error(SBCI_EINVAL, "NULL integrals");
+  }
+  sbci_batch *b = new sbci_batch();
+  b->ninst = ninst;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return batch_error(SBCI_EDEVICE, std::string("batch device setup: ") + hipGetErrorString(e));
+  }
+  b->ctx.assign(ninst, nullptr);
+  b->la.resize(ninst);
+  b->lb.resize(ninst);
+  for (int i = 0; i < ninst; ++i) {
+    int rc = create_context(norb[i], nalpha[i], nbeta[i], h1[i], eri[i], b->stream, false, &b->ctx[i]);
+    if (rc == SBCI_OK) {
+      sbci_ctx *c = b->ctx[i];
+      if (c->A.ns > BMAX_NS || c->B.ns > BMAX_NS || c->A.s > BMAX_S || c->B.s > BMAX_S ||
+          16 * ((c->npair + 15) / 16) > BMAX_NP)
+        rc = batch_error(SBCI_EINVAL, "batch instance exceeds the workgroup limits");
+    }
+    if (rc == SBCI_OK) rc = build_lists(b, i);
+    if (rc != SBCI_OK) {
+      std::string m = sbci_last_error();
+      sbci_batch_destroy(b);
+      return batch_error(rc, "instance " + std::to_string(i) + ": " + m);
+    }
+  }
+  hipError_t e2 = hipMalloc(&b->d_inst, sizeof(BInst) * ninst);
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_params, sizeof(BParams));
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_order, sizeof(int) * ninst);
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_queue, 256);
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_out, sizeof(BOut) * ninst);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
+  if (e2 != hipSuccess) {
+    sbci_batch_destroy(b);
+    return batch_error(SBCI_EDEVICE, std::string("batch allocation: ") + hipGetErrorString(e2));
+  }
+  *out = b;
+  return SBCI_OK;
+}
+
+int sbci_batch_destroy(sbci_batch *b) {
+  if (!b) return SBCI_OK;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  for (int i = 0; i < (int)b->ctx.size(); ++i) {
+    const bool shared = b->ctx[i] && b->ctx[i]->B.shared;
+    hipFree(b->la[i].fcol);
+    hipFree(b->la[i].f64);
+    hipFree(b->la[i].f32);
+    if (!shared) {
+      hipFree(b->lb[i].fcol);
+      hipFree(b->lb[i].f64);
+      hipFree(b->lb[i].f32);
+    }
+    if (b->ctx[i]) sbci_destroy(b->ctx[i]);
+  }
+  hipFree(b->d_inst);
+  hipFree(b->d_params);
+  hipFree(b->d_order);
+  hipFree(b->d_queue);
+  hipFree(b->d_out);
+  hipFree(b->arena64);
+  hipFree(b->arena32);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+  return SBCI_OK;
+}
+
+int64_t sbci_batch_ndet(const sbci_batch *b, int inst) {
+  if (!b || inst < 0 || inst >= b->ninst) return -1;
+  return b->ctx[inst]->ndet;
+}
+
+int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
+                     const sbci_batch_config *cfg_in, double *energies, int *status,
+                     sbci_batch_report *rep) {
+  if (!b || !nroots) return batch_error(SBCI_EINVAL, "NULL argument");
+  BParams P{};
+  int precision = 0;
+  SBCI_TRY(params_from(opt, tol, P, precision));
+  sbci_batch_config cfg = cfg_in ? *cfg_in : (b->have_tuned ? b->tuned : default_config());
+  SBCI_TRY(check_config(cfg));
+  SBCI_TRY(prepare(b, nroots, precision));
+  SBCI_TRY(set_order(b, cfg.order));
+  double ms = 0;
+  SBCI_TRY(run_graph(b, cfg, P, &ms));
+  b->solved_precision = precision;
+  std::vector<BOut> o(b->ninst);
+  SBCI_HIP(hipMemcpy(o.data(), b->d_out, sizeof(BOut) * b->ninst, hipMemcpyDeviceToHost));
+  sbci_batch_report r{};
+  r.seconds = ms * 1e-3;
+  int64_t off = 0;
+  int worst = SBCI_OK;
+  for (int i = 0; i < b->ninst; ++i) {
+    const BOut &q = o[i];
+    for (int a = 0; a < nroots[i]; ++a) {
+      if (energies) energies[off + a] = a < q.nconv ? q.E[a] : NAN;
+    }
+    off += nroots[i];
+    if (status) status[i] = q.status;
+    if (q.status == SBCI_OK) r.ninst_converged += 1;
+    else if (worst == SBCI_OK || q.status == SBCI_ENUMERIC) worst = q.status;
+    r.nsigma_f64 += q.nsig64;
+    r.nsigma_low += q.nsiglow;
+    r.det_sigma += (int64_t)b->ctx[i]->ndet * (q.nsig64 + q.nsiglow);
+    r.nsteps += q.nsteps;
+    r.nrestarts += q.nrestarts;
+  }
+  r.threads = cfg.threads;
+  r.wg_per_cu = cfg.wg_per_cu;
+  r.order = cfg.order;
+  r.row_tile = cfg.row_tile;
+  if (rep) *rep = r;
+  if (worst != SBCI_OK)
+    return batch_error(worst, worst == SBCI_ENOCONV ? "some batch instances did not converge"
+                                                    : "numerical failure in a batch instance");
+  return SBCI_OK;
+}
+
+int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
+                    sbci_batch_config *best, double *ms_out, sbci_batch_config *cand_out,
+                    int *ncand) {
+  if (!b || !nroots) return batch_error(SBCI_EINVAL, "NULL argument");
+  BParams P{};
+  int precision = 0;
+  SBCI_TRY(params_from(opt, tol, P, precision));
+  SBCI_TRY(prepare(b, nroots, precision));
+  // stage 1: workgroup size x residency (longest-first, tall tiles);
+  // stage 2: queue order and tile height around the winner.
+  std::vector<sbci_batch_config> tried;
+  std::vector<double> times;
+  auto trial = [&](const sbci_batch_config &c) -> int {
+    SBCI_TRY(set_order(b, c.order));
+    double ms = 0;
+    SBCI_TRY(run_graph(b, c, P, &ms));
+    tried.push_back(c);
+    times.push_back(ms);
+    return SBCI_OK;
+  };
+  for (int nt : {256, 512, 1024})
+    for (int w : {1, 2}) {
+      sbci_batch_config c{};
+      c.threads = nt;
+      c.wg_per_cu = w;
+      c.order = 0;
+      c.row_tile = 16;
+      SBCI_TRY(trial(c));
+    }
+  size_t bi = std::min_element(times.begin(), times.end()) - times.begin();
+  sbci_batch_config w = tried[bi];
+  {
+    sbci_batch_config c = w;
+    c.order = 1;
+    SBCI_TRY(trial(c));
+    c = w;
+    c.row_tile = 8;
+    SBCI_TRY(trial(c));
+  }
+  bi = std::min_element(times.begin(), times.end()) - times.begin();
+  b->tuned = tried[bi];
+  b->have_tuned = true;
+  if (best) *best = tried[bi];
+  const int n = (int)tried.size();
+  if (ncand) {
+    const int cap = *ncand;
+    for (int i = 0; i < n && i < cap; ++i) {
+      if (ms_out) ms_out[i] = times[i];
+      if (cand_out) cand_out[i] = tried[i];
+    }
+    *ncand = n;
+  }
+  return SBCI_OK;
+}
+
+int sbci_batch_vectors(sbci_batch *b, int inst, double *dev_out) {
+  if (!b || !dev_out || inst < 0 || inst >= b->ninst) return batch_error(SBCI_EINVAL, "bad argument");
+  if (b->h_inst.empty()) return batch_error(SBCI_EINVAL, "sbci_batch_vectors before a solve");
+  const BInst &I = b->h_inst[inst];
+  BOut o;
+  SBCI_HIP(hipMemcpy(&o, b->d_out + inst, sizeof(BOut), hipMemcpyDeviceToHost));
+  const int nc = std::min(o.nconv, I.nroots);
+  SBCI_HIP(hipMemcpyAsync(dev_out, I.v64 + (int64_t)NVW * I.ndet, sizeof(double) * I.ndet * nc,
+                          hipMemcpyDeviceToDevice, b->stream));
+  SBCI_HIP(hipStreamSynchronize(b->stream));
+  return SBCI_OK;
+}
+
+}  // extern "C"

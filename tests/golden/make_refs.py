@@ -7,6 +7,11 @@ Contents (all FP64, electronic energies, Eh):
   cas10  seeds 0..9, rank 20: Lanczos eigsh on the oracle sigma (lowest 6,
          tol 1e-14), oracle SBCI1 (3 roots, Section S1.1 start) and oracle
          Davidson (3 roots).
+  batch512  every 32nd instance of the 512-instance batching workload
+         (master seed 2603): oracle SBCI1 with that instance's roots and
+         the lowest eigenvalues from Lanczos eigsh on the oracle sigma.
+
+"python tests/golden/make_refs.py batch" recomputes only the batch section.
 """
 import json
 import os
@@ -23,10 +28,38 @@ from scipy.sparse.linalg import LinearOperator, eigsh  # noqa: E402
 from oracle import hamiltonian as H  # noqa: E402
 from oracle import sbci  # noqa: E402
 from oracle import sigma as S  # noqa: E402
-from workloads import make_integrals, start_noise  # noqa: E402
+from workloads import batch_instances, make_integrals, start_noise  # noqa: E402
+
+REFS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "refs.json")
+BATCH_SAMPLE = list(range(0, 512, 32))
+
+
+def batch_section():
+    sec = {}
+    inst = batch_instances(512, 2603)
+    for i in BATCH_SAMPLE:
+        t = time.time()
+        n, m, nroots, seed = inst[i]
+        I = make_integrals(n, 2 * n, seed)
+        op = S.Operator(n, m, m, I.h1, I.eri)
+        L = LinearOperator((op.ndet, op.ndet), matvec=lambda v: S.sigma(n, m, m, I.h1, I.eri, v),
+                           dtype=np.float64)
+        ev = np.sort(eigsh(L, k=min(6, op.ndet - 1), which="SA", tol=1e-14)[0])
+        rs = sbci.sbci1(op, op.diag(), nroots)
+        sec[str(i)] = {"norb": n, "nelec": m, "nroots": nroots, "seed": seed, "rank": 2 * n,
+                       "eigsh": ev.tolist(), "sbci1": rs.energies.tolist(), "digest": I.digest()}
+        print("batch", i, n, nroots, rs.energies, f"{time.time() - t:.1f}s", flush=True)
+    return sec
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "batch":
+        with open(REFS) as f:
+            out = json.load(f)
+        out["batch512"] = batch_section()
+        with open(REFS, "w") as f:
+            json.dump(out, f, indent=1)
+        return
     out = {"generator": "tests/golden/make_refs.py", "cas6": {}, "cas10": {}}
     n, na, nb, K = 6, 3, 3, 12
     I = make_integrals(n, K, 0)
@@ -54,7 +87,8 @@ def main():
                                    "sbci1_nsigma": rs.nsigma, "davidson": rd.energies.tolist(),
                                    "davidson_nsigma": rd.nsigma, "digest": I.digest()}
         print(seed, ev[:3], rs.energies, rd.energies, f"{time.time() - t:.1f}s", flush=True)
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "refs.json"), "w") as f:
+    out["batch512"] = batch_section()
+    with open(REFS, "w") as f:
         json.dump(out, f, indent=1)
 
 
