@@ -20,6 +20,9 @@ Reported (one JSON line):
                per-kernel durations measured with HIP events on the
                library's stream;
   roofline     the dominant kernel of the step against the MI355X peak;
+  batch        the batching form on its own workload (512 instances of
+               CAS(6..10), 1-3 roots each): autotuned persistent-kernel
+               graph launch, makespan FP64 vs mixed, per-instance span;
   cpu_baseline the CPU oracle's plain FP64 string sigma on the host cores,
                on a bounded sample of determinant rows.
 """
@@ -45,12 +48,69 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cas14", choices=["cas6", "cas10", "cas14", "cas16"])
-    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching-form section")
+    ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
+                    help="profiling driver: run --sigma-reps sigma calls of this dtype on the "
+                         "workload and one 1 GiB device copy (the counter scale reference), "
+                         "print their sizes and exit")
     return ap.parse_args()
+
+
+def batch_section(sb, precision):
+    """Batching form: 512 uneven instances, one persistent-kernel graph launch per solve."""
+    import numpy as np
+
+    from workloads import batch_instances, make_integrals
+    inst = batch_instances(512, 2603)
+    ints = []
+    for n, m, _, seed in inst:
+        I = make_integrals(n, 2 * n, seed)
+        ints.append((n, m, m, I.h1, I.eri))
+    t = time.perf_counter()
+    b = sb.Batch(ints)
+    t_create = time.perf_counter() - t
+    nroots = [x[2] for x in inst]
+    out = {"instances": len(inst), "ndet_total": int(sum(b.ndet)),
+           "roots_total": int(sum(nroots)), "create_s": round(t_create, 3)}
+    res = {}
+    for prec in ("f64", precision) if precision != "f64" else ("f64",):
+        best, cands = b.tune(nroots, tol=1e-10, opts=dict(precision=prec))
+        r = b.solve(nroots, tol=1e-10, opts=dict(precision=prec))
+        rd = b.solve(nroots, tol=1e-10, opts=dict(precision=prec),
+                     config=dict(threads=256, wg_per_cu=2, order=0, row_tile=16))
+        spans = np.array([d["t_end"] - d["t_start"] for d in r.instances])
+        crit = int(np.argmax(spans))
+        res[prec] = r
+        out[prec] = {
+            "makespan_s": round(r.report["seconds"], 4),
+            "gdet_per_s": round(r.report["det_sigma"] / r.report["seconds"] / 1e9, 4),
+            "converged": int(r.report["ninst_converged"]),
+            "nsigma": {"f64": r.report["nsigma_f64"], "low": r.report["nsigma_low"]},
+            "steps": r.report["nsteps"],
+            "tuned": best,
+            "tuned_vs_default": round(rd.report["seconds"] / r.report["seconds"], 3),
+            "candidates_ms": [[c["threads"], c["wg_per_cu"], c["order"], c["row_tile"], round(ms, 1)]
+                              for c, ms in cands],
+            "critical_instance": {"id": crit, "norb": inst[crit][0], "nroots": inst[crit][2],
+                                  "span_s": round(float(spans[crit]), 4),
+                                  "steps": r.instances[crit]["nsteps"]},
+            "median_instance_span_s": round(float(np.median(spans)), 5),
+        }
+    if precision != "f64":
+        e64 = np.array([e[0] for e in res["f64"].energies])
+        emx = np.array([e[0] for e in res[precision].energies])
+        d = emx - e64
+        out["root0_mixed_minus_fp64"] = {"max_abs_same_state": float(np.max(np.abs(d[np.abs(d) < 1e-6]))),
+                                         "lower_state_count": int(np.sum(d < -1e-6))}
+        out["speedup_mixed_vs_fp64"] = round(res["f64"].report["seconds"] /
+                                             res[precision].report["seconds"], 3)
+    b.close()
+    return out
 
 
 def cpu_baseline(cfg, I, ndet, seconds):
@@ -93,6 +153,22 @@ def main():
     I = make_integrals(cfg["norb"], cfg["rank"], cfg["seed"])
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.kernel_driver:
+        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+        c = torch.from_numpy(sigma_inputs(0, 1, ctx.ndet)[0]).cuda()
+        if a.kernel_driver != "f64":
+            c = c.float()
+        out = torch.empty_like(c)
+        for _ in range(a.sigma_reps):
+            ctx.sigma(c, a.kernel_driver, out=out)
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"driver": a.kernel_driver, "ndet": ctx.ndet, "sigma_calls": a.sigma_reps,
+                          "copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        ctx.close()
+        return
 
     def step(prec):
         ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
@@ -181,6 +257,8 @@ def main():
         "sigma": sig,
         "roofline": roof,
     }
+    if not a.no_batch:
+        line["batch"] = batch_section(sb, a.precision)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
     print(json.dumps(line))

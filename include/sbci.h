@@ -183,7 +183,7 @@ int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
  * whole SBCI1 state machine of one instance (Algorithm 1 with Sections
  * S1.1-S1.5: start vectors, steps, restarts, deflation against the lower
  * roots, the precision hand-overs of sbci_solve); workgroups take instances
- * from a device queue.  Limits per instance: 1 <= norb <= 11 (at most 512
+ * from a device queue.  Limits per instance: 1 <= norb <= 10 (at most 252
  * strings per spin), 1 <= nroots <= min(4, N_det).
  */
 typedef struct sbci_batch sbci_batch;
@@ -198,6 +198,8 @@ typedef struct sbci_batch_config {
 
 typedef struct sbci_batch_report {
   double seconds;            /* device time of the graph launch (HIP events)    */
+  double span_seconds;       /* first instance start to last instance end,
+                                from the device real-time counter              */
   int64_t nsigma_f64;        /* sigma applications, summed over instances       */
   int64_t nsigma_low;
   int64_t det_sigma;         /* sum over instances of N_det x sigma applications */
@@ -205,6 +207,18 @@ typedef struct sbci_batch_report {
   int ninst_converged;       /* instances with status SBCI_OK                   */
   int threads, wg_per_cu, order, row_tile;  /* the launch shape used           */
 } sbci_batch_report;
+
+/* Per-instance outcome of a batch solve (times from the device real-time
+ * counter, relative to the earliest instance start). */
+typedef struct sbci_batch_inst {
+  int status;                /* sbci_status of this instance                    */
+  int nroots_converged;
+  int nsteps, nrestarts, nsigma_f64, nsigma_low;
+  double t_start, t_end;     /* seconds                                         */
+  double resid[4];           /* |z'| at convergence of each root (NaN if none)   */
+  double t_sigma[3];         /* seconds in sigma: beta same-spin, alpha
+                                same-spin, opposite-spin parts                  */
+} sbci_batch_inst;
 
 /* Builds every instance's tables (as sbci_create does for one) on the
  * current device.  norb, nalpha, nbeta: host [ninst]; h1[i], eri[i]: host
@@ -220,11 +234,11 @@ int64_t sbci_batch_ndet(const sbci_batch *b, int inst);   /* -1 for a bad index 
  * (opt->x0 must be NULL; opt->precision selects the FP64 or mixed form);
  * cfg NULL = the last tuned shape, else a default shape.  energies: host,
  * the roots of instance 0, then instance 1, ... (sum of nroots entries; NaN
- * for a root that was not reached); status: host [ninst] per-instance
- * sbci_status, or NULL.  Returns SBCI_ENOCONV / SBCI_ENUMERIC if any
+ * for a root that was not reached); info: host [ninst] per-instance
+ * outcome, or NULL.  Returns SBCI_ENOCONV / SBCI_ENUMERIC if any
  * instance ended so (the outputs are still written). */
 int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
-                     const sbci_batch_config *cfg, double *energies, int *status,
+                     const sbci_batch_config *cfg, double *energies, sbci_batch_inst *info,
                      sbci_batch_report *rep);
 
 /* Autotuner: times full batch solves over a candidate set of launch shapes

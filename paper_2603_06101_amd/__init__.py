@@ -85,9 +85,17 @@ class BatchConfig(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchInst(ctypes.Structure):
+    _fields_ = [
+        ("status", _I), ("nroots_converged", _I), ("nsteps", _I), ("nrestarts", _I),
+        ("nsigma_f64", _I), ("nsigma_low", _I), ("t_start", _D), ("t_end", _D),
+        ("resid", _D * 4), ("t_sigma", _D * 3),
+    ]
+
+
 class BatchReport(ctypes.Structure):
     _fields_ = [
-        ("seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
+        ("seconds", _D), ("span_seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
         ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
         ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("row_tile", _I),
     ]
@@ -118,8 +126,8 @@ SIGNATURES = [
     ("sbci_batch_create", _I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     ("sbci_batch_destroy", _I, [_P]),
     ("sbci_batch_ndet", _I64, [_P, _I]),
-    ("sbci_batch_solve", _I, [_P, _P, _D, ctypes.POINTER(Opts), ctypes.POINTER(BatchConfig), _P, _P,
-                              ctypes.POINTER(BatchReport)]),
+    ("sbci_batch_solve", _I, [_P, _P, _D, ctypes.POINTER(Opts), ctypes.POINTER(BatchConfig), _P,
+                              ctypes.POINTER(BatchInst), ctypes.POINTER(BatchReport)]),
     ("sbci_batch_tune", _I, [_P, _P, _D, ctypes.POINTER(Opts), ctypes.POINTER(BatchConfig), _P,
                              ctypes.POINTER(BatchConfig), ctypes.POINTER(_I)]),
     ("sbci_batch_vectors", _I, [_P, _I, _P]),
@@ -316,6 +324,7 @@ class BatchResult:
     status: np.ndarray       # per-instance sbci_status
     report: dict
     rc: int
+    instances: list          # per-instance dicts: nsteps, times, residuals, ...
 
 
 class Batch:
@@ -367,18 +376,26 @@ class Batch:
         r = self._roots(nroots, self.n)
         o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
         e = np.full(int(r.sum()), np.nan)
-        st = np.zeros(self.n, dtype=np.int32)
+        info = (BatchInst * self.n)()
         rep = BatchReport()
         cfg = None
         if config is not None:
             cfg = config if isinstance(config, BatchConfig) else BatchConfig(**config)
         rc = lib().sbci_batch_solve(self.h, r.ctypes.data, tol, ctypes.byref(o),
                                     ctypes.byref(cfg) if cfg is not None else None,
-                                    e.ctypes.data, st.ctypes.data, ctypes.byref(rep))
+                                    e.ctypes.data, info, ctypes.byref(rep))
         _check(rc, allow=(SBCI_ENOCONV, SBCI_ENUMERIC))
         self._nroots = r
         parts = np.split(e, np.cumsum(r)[:-1])
-        return BatchResult(parts, st, rep.as_dict(), rc)
+        inst = []
+        for i in range(self.n):
+            q = info[i]
+            d = {f: getattr(q, f) for f, _ in BatchInst._fields_ if f not in ("resid", "t_sigma")}
+            d["resid"] = list(q.resid[:int(r[i])])
+            d["t_sigma"] = list(q.t_sigma)
+            inst.append(d)
+        st = np.array([d["status"] for d in inst], dtype=np.int32)
+        return BatchResult(parts, st, rep.as_dict(), rc, inst)
 
     def tune(self, nroots, tol=1e-10, opts=None):
         """Run the autotuner; returns (best config dict, [(config dict, ms), ...])."""

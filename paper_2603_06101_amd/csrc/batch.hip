@@ -44,9 +44,10 @@ namespace sbci {
 namespace {
 
 constexpr int BMAXR = 4;     // roots per instance
-constexpr int BMAX_NS = 512; // strings per spin
-constexpr int BMAX_S = 36;   // single excitations per string
-constexpr int BMAX_NP = 80;  // pair rows, padded to 16
+constexpr int BMAX_NORB = 10;
+constexpr int BMAX_NS = 252; // strings per spin, C(10, 5)
+constexpr int BMAX_S = 30;   // single excitations per string, 5 * 6
+constexpr int BMAX_NP = 64;  // pair rows (55 for norb = 10), padded to 16
 constexpr int NVW = 7;       // work vectors: x, X, y, Y, za, zb, Z
 enum { SX = 0, SXX = 1, SY = 2, SYY = 3, SZA = 4, SZB = 5, SZ = 6 };
 
@@ -70,6 +71,8 @@ struct BInst {
 struct BOut {
   double E[BMAXR];
   double dz[BMAXR];
+  uint64_t t0, t1;  // device real-time counter at the instance's start and end
+  uint64_t tsig[3]; // counter ticks in the sigma parts: beta same-spin, alpha same-spin, opposite
   int status, nconv, nsteps, nrestarts, nsig64, nsiglow, pad0, pad1;
 };
 
@@ -137,6 +140,7 @@ struct Ctl {
   int alpha, seg, t, steps_root, phase, seg_start, stall, done, any_noconv, nconv, status;
   int m64[NVW], m32[NVW];  // logical slot -> physical vector
   int nsteps, nrestarts, nsig64, nsiglow;
+  uint64_t tsig[3];
   double E, sx, bestE;
   double Ec[BMAXR];
   double h1[16], h2[4], h3[4];
@@ -149,22 +153,41 @@ struct Ctl {
 };
 
 // ------------------------------------------------------------ WG sigma
-// Same-spin part on one tile: for every output string i of the spin and
-// every tile position r (8 per item): acc = sum_f F[i][f] * L[col(i,f)][r].
-// L holds the staged tile, [nsrc][rt + 1] (padded against bank conflicts).
-template <typename T, typename V, int NT>
-__device__ void same_tile(int nout, int nf, int rt, const int32_t *__restrict__ fcol,
-                          const V *__restrict__ fval, const T *L, V (&acc)[8], int i, int sub) {
+constexpr int SV = 4;  // tile positions per same-spin work item
+constexpr int FU = 4;  // list entries fetched ahead per work item
+
+// Same-spin part on one staged tile: acc[v] = sum_f F[i][f] * L[col(i,f)][sub*SV + v]
+// for output string i.  L is [nsrc][ld] in LDS; the lists are transposed
+// ([entry][string]) so that a wavefront's list loads are coalesced, and FU
+// entries are fetched before they are used so that their latencies overlap.
+template <typename T, typename V>
+__device__ void same_item(int nout, int nf, int ld, const int32_t *__restrict__ fcol,
+                          const V *__restrict__ fval, const T *L, V (&acc)[SV], int i, int sub) {
 #pragma unroll
-  for (int v = 0; v < 8; ++v) acc[v] = 0;
-  const int ld = rt + 1;
-  const T *Lr = L + sub * 8;
-  for (int f = 0; f < nf; ++f) {
+  for (int v = 0; v < SV; ++v) acc[v] = 0;
+  const T *Lr = L + sub * SV;
+  int f = 0;
+  for (; f + FU <= nf; f += FU) {
+    int j[FU];
+    V w[FU];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      j[u] = fcol[(int64_t)(f + u) * nout + i];
+      w[u] = fval[(int64_t)(f + u) * nout + i];
+    }
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const T *row = Lr + j[u] * ld;
+#pragma unroll
+      for (int v = 0; v < SV; ++v) acc[v] += w[u] * (V)row[v];
+    }
+  }
+  for (; f < nf; ++f) {
     const int j = fcol[(int64_t)f * nout + i];
-    const V fv = fval[(int64_t)f * nout + i];
+    const V w = fval[(int64_t)f * nout + i];
     const T *row = Lr + j * ld;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) acc[v] += fv * (V)row[v];
+    for (int v = 0; v < SV; ++v) acc[v] += w * (V)row[v];
   }
 }
 
@@ -198,17 +221,20 @@ struct WSel<MBF16> {
   __device__ static const __bf16 *w(const BInst &I) { return I.Wbf; }
 };
 
+constexpr size_t kWBytes = sizeof(double) * BMAX_NP * BMAX_NP;  // LDS copy of the pair ERI matrix
+
 // out = H c for one vector of instance I (T = double: FP64 everywhere;
 // T = float: FP32 same-spin part, MFMA flavour M for the opposite spin).
 template <typename T, typename M, int NT>
 __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__ c,
-                         T *__restrict__ out, char *lds) {
+                         T *__restrict__ out, char *lds, uint64_t *tick) {
+  uint64_t tk = __builtin_amdgcn_s_memrealtime();
   using V = typename ListVals<T>::V;
   const int tid = threadIdx.x;
   const int nsa = I.ns_a, nsb = I.ns_b;
-  const int rt = P.rt, ld = rt + 1, nsub = rt / 8;
+  const int rt = P.rt, ld = rt + 1, nsub = rt / SV;
   T *L = reinterpret_cast<T *>(lds);
-  V acc[8];
+  V acc[SV];
   // (1) beta same-spin, in-row, rt rows of C per tile
   for (int r0 = 0; r0 < nsa; r0 += rt) {
     for (int e = tid; e < rt * nsb; e += NT) {
@@ -218,14 +244,19 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
     __syncthreads();
     for (int it = tid; it < nsb * nsub; it += NT) {
       const int i = it % nsb, sub = it / nsb;
-      same_tile<T, V, NT>(nsb, I.nf_b, rt, I.fcol_b, ListVals<T>::b(I), L, acc, i, sub);
+      same_item<T, V>(nsb, I.nf_b, ld, I.fcol_b, ListVals<T>::b(I), L, acc, i, sub);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int r = r0 + sub * 8 + v;
+      for (int v = 0; v < SV; ++v) {
+        const int r = r0 + sub * SV + v;
         if (r < nsa) out[(int64_t)r * nsb + i] = (T)acc[v];
       }
     }
     __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t t = __builtin_amdgcn_s_memrealtime();
+    tick[0] += t - tk;
+    tk = t;
   }
   // (2) alpha same-spin, cross-row, rt columns of C per tile
   for (int c0 = 0; c0 < nsb; c0 += rt) {
@@ -236,10 +267,10 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
     __syncthreads();
     for (int it = tid; it < nsa * nsub; it += NT) {
       const int i = it % nsa, sub = it / nsa;
-      same_tile<T, V, NT>(nsa, I.nf_a, rt, I.fcol_a, ListVals<T>::a(I), L, acc, i, sub);
+      same_item<T, V>(nsa, I.nf_a, ld, I.fcol_a, ListVals<T>::a(I), L, acc, i, sub);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int cc = c0 + sub * 8 + v;
+      for (int v = 0; v < SV; ++v) {
+        const int cc = c0 + sub * SV + v;
         if (cc < nsb) {
           T *o = out + (int64_t)i * nsb + cc;
           *o = (T)((V)*o + acc[v]);
@@ -248,73 +279,93 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
     }
     __syncthreads();
   }
-  // (3) opposite spin, one row Ia at a time
+  if (threadIdx.x == 0) {
+    const uint64_t t = __builtin_amdgcn_s_memrealtime();
+    tick[1] += t - tk;
+    tk = t;
+  }
+  // (3) opposite spin.  Each wavefront owns the rows Ia = wave, wave + NW, ...:
+  // the signed ERI tile of the row's s alpha excitations sits in its
+  // registers (A fragments, built from an LDS copy of the pair matrix), the
+  // s gathered rows of C stream in as B fragments 16 columns at a time, and
+  // every M[kl][J] is scattered through the beta pair table into the wave's
+  // own LDS copy of sigma's row.  No workgroup barrier inside the phase.
   using A = typename M::A;
   using Frag = typename M::Frag;
   using Out = typename M::Out;
+  constexpr int NW = NT / 64;
   constexpr int KSMAX = (BMAX_S + M::KSTEP - 1) / M::KSTEP;
-  const int kpad = ((I.s_a + M::KSTEP - 1) / M::KSTEP) * M::KSTEP;
-  const int ks_n = kpad / M::KSTEP;
-  const int ldw = kpad + M::PAD;
-  const int npt = (I.npair + 15) / 16;
-  double *sig = reinterpret_cast<double *>(lds);                    // [nsb]
-  A *Ws = reinterpret_cast<A *>(lds + sizeof(double) * BMAX_NS);     // [npt*16][ldw]
-  uint32_t *eoff = reinterpret_cast<uint32_t *>(lds + sizeof(double) * BMAX_NS +
-                                                sizeof(double) * BMAX_NP * (BMAX_S + 8));
-  const A *W = WSel<M>::w(I);
+  constexpr int NPT = BMAX_NP / 16;
+  const int np = I.npair;
+  A *Wl = reinterpret_cast<A *>(lds);
+  double *rows = reinterpret_cast<double *>(lds + kWBytes);
+  {
+    const A *W = WSel<M>::w(I);
+    for (int e = tid; e < np * np; e += NT) Wl[e] = W[e];
+  }
+  __syncthreads();
   const int lane = tid & 63, wv = tid >> 6, li = lane & 15, g = lane >> 4;
+  double *sigw = rows + wv * BMAX_NS;
   const int njt = (nsb + 15) / 16;
-  for (int ia = 0; ia < nsa; ++ia) {
-    for (int j = tid; j < nsb; j += NT) sig[j] = 0;
-    const Ent *te = I.tab_a + (int64_t)ia * I.s_a;
-    for (int e = tid; e < npt * 16 * kpad; e += NT) {
-      const int kl = e / kpad, k = e - kl * kpad;
-      A v = M::cvt(0.0);
-      if (kl < I.npair && k < I.s_a) {
-        const Ent t = te[k];
-        const double wkl = (double)W[kl * I.npair + pair_index(t.p, t.q)];
-        v = M::cvt(t.sign < 0 ? -wkl : wkl);
+  const int sa = I.s_a;
+  // The K and pair-tile loops run at the largest shape (the norb = 10
+  // instances that bound the makespan use all of it): padded K slots carry
+  // zero ERI fragments and padded pair rows carry invalid scatter codes.
+  for (int ia = wv; ia < nsa && sa > 0; ia += NW) {
+    const Ent *te = I.tab_a + (int64_t)ia * sa;
+    uint32_t boff[KSMAX][M::KPL];
+    Frag af[NPT][KSMAX];
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+#pragma unroll
+      for (int t = 0; t < M::KPL; ++t) {
+        const int e = ks * M::KSTEP + g * M::KPL + t;
+        const Ent en = te[e < sa ? e : sa - 1];
+        const bool ok = e < sa;
+        boff[ks][t] = ok ? (uint32_t)en.J * (uint32_t)nsb : 0u;
+        const int pk = pair_index(en.p, en.q);
+        const double sg = !ok ? 0.0 : en.sign < 0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+          const int kl = u * 16 + li;
+          const double w = kl < np ? sg * (double)Wl[kl * np + pk] : 0.0;
+          if constexpr (M::KPL == 1)
+            af[u][ks] = M::cvt(w);
+          else
+            af[u][ks][t] = M::cvt(w);
+        }
       }
-      Ws[kl * ldw + k] = v;
     }
-    for (int k = tid; k < kpad; k += NT) eoff[k] = k < I.s_a ? (uint32_t)te[k].J * (uint32_t)nsb : 0u;
-    __syncthreads();
-    for (int jt = wv; jt < njt; jt += NT / 64) {
+    for (int j = lane; j < nsb; j += 64) sigw[j] = 0;
+    for (int jt = 0; jt < njt; ++jt) {
       const int j = jt * 16 + li;
       const uint32_t jc = (uint32_t)(j < nsb ? j : nsb - 1);
       Frag bf[KSMAX];
 #pragma unroll
-      for (int ks = 0; ks < KSMAX; ++ks) {
-        if (ks < ks_n) {
-          uint32_t off[M::KPL];
+      for (int ks = 0; ks < KSMAX; ++ks) bf[ks] = M::load_b(c, boff[ks], jc);
 #pragma unroll
-          for (int t = 0; t < M::KPL; ++t) off[t] = eoff[ks * M::KSTEP + g * M::KPL + t];
-          bf[ks] = M::load_b(c, off, jc);
-        }
-      }
-      for (int u = 0; u < npt; ++u) {
+      for (int u = 0; u < NPT; ++u) {
         Out o = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < KSMAX; ++ks)
-          if (ks < ks_n) o = M::mma(M::load_a(&Ws[(u * 16 + li) * ldw + ks * M::KSTEP + g * M::KPL]), bf[ks], o);
+        for (int ks = 0; ks < KSMAX; ++ks) o = M::mma(af[u][ks], bf[ks], o);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int kl = u * 16 + M::orow(g, r);
           const uint32_t code = I.pair_b[(int64_t)kl * I.ns_pad_b + j];
           if (code != kInvalid) {
             const double val = (double)o[r];
-            atomicAdd(&sig[code >> 1], (code & 1u) ? -val : val);
+            atomicAdd(&sigw[code >> 1], (code & 1u) ? -val : val);
           }
         }
       }
     }
-    __syncthreads();
-    for (int j = tid; j < nsb; j += NT) {
+    for (int j = lane; j < nsb; j += 64) {
       T *o = out + (int64_t)ia * nsb + j;
-      *o = (T)((double)*o + sig[j]);
+      *o = (T)((double)*o + sigw[j]);
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (threadIdx.x == 0) tick[2] += __builtin_amdgcn_s_memrealtime() - tk;
 }
 
 // ------------------------------------------------------------ vector passes
@@ -515,13 +566,13 @@ struct Solve {
   template <typename T>
   __device__ void sigma_phase(const T *c, T *o, int mode) {
     if constexpr (std::is_same<T, double>::value) {
-      wg_sigma<double, MF64, NT>(I, P, c, o, lds);
+      wg_sigma<double, MF64, NT>(I, P, c, o, lds, C.tsig);
       if (lane0()) C.nsig64 += 1;
     } else {
       if (mode == SBCI_BF16)
-        wg_sigma<float, MBF16, NT>(I, P, c, o, lds);
+        wg_sigma<float, MBF16, NT>(I, P, c, o, lds, C.tsig);
       else
-        wg_sigma<float, MF32, NT>(I, P, c, o, lds);
+        wg_sigma<float, MF32, NT>(I, P, c, o, lds, C.tsig);
       if (lane0()) C.nsiglow += 1;
     }
     __syncthreads();
@@ -1026,6 +1077,7 @@ struct Solve {
       C.status = SBCI_OK;
       for (int i = 0; i < NVW; ++i) C.m64[i] = C.m32[i] = i;
       C.nsteps = C.nrestarts = C.nsig64 = C.nsiglow = 0;
+      C.tsig[0] = C.tsig[1] = C.tsig[2] = 0;
       C.E = 0;
       C.sx = 1;
       C.bestE = 0;
@@ -1071,6 +1123,7 @@ struct Solve {
       out.nrestarts = C.nrestarts;
       out.nsig64 = C.nsig64;
       out.nsiglow = C.nsiglow;
+      for (int q = 0; q < 3; ++q) out.tsig[q] = C.tsig[q];
       int st = C.status;
       if (st == SBCI_OK && (!C.done || C.any_noconv)) st = SBCI_ENOCONV;
       out.status = st;
@@ -1097,7 +1150,12 @@ __global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
     const int id = order[it];
     // descriptors and parameters stay in global memory (uniform loads)
     Solve<NT> S{inst[id], *prm, C, R, lds};
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     S.run(out[id]);
+    if (threadIdx.x == 0) {
+      out[id].t0 = t0;
+      out[id].t1 = __builtin_amdgcn_s_memrealtime();
+    }
   }
 }
 
@@ -1115,10 +1173,9 @@ __global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t
   dst[f * ns + i] = src[e];
 }
 
-size_t lds_bytes(int rt, int nsa, int nsb) {
+size_t lds_bytes(int rt, int nsa, int nsb, int threads) {
   const size_t same = sizeof(double) * (size_t)(rt + 1) * (size_t)std::max(nsa, nsb);
-  const size_t opp = sizeof(double) * BMAX_NS + sizeof(double) * BMAX_NP * (BMAX_S + 8) +
-                     sizeof(uint32_t) * 64;
+  const size_t opp = kWBytes + sizeof(double) * BMAX_NS * (size_t)(threads / 64);
   return std::max(same, opp);
 }
 
@@ -1159,6 +1216,8 @@ struct sbci_batch {
 namespace {
 
 int batch_error(int code, const std::string &m) { return set_error(code, m); }
+
+constexpr double kRealtimeHz = 100e6;  // s_memrealtime counter frequency
 
 int build_lists(sbci_batch *b, int i) {
   sbci_ctx *c = b->ctx[i];
@@ -1339,7 +1398,7 @@ int set_order(sbci_batch *b, int order) {
 
 int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, double *ms) {
   size_t lds = 0;
-  for (auto &I : b->h_inst) lds = std::max(lds, lds_bytes(cfg.row_tile, I.ns_a, I.ns_b));
+  for (auto &I : b->h_inst) lds = std::max(lds, lds_bytes(cfg.row_tile, I.ns_a, I.ns_b, cfg.threads));
   // The solve parameters are baked into the captured launch, so every call
   // captures a fresh graph (a few microseconds next to the solve).
   hipGraph_t g = nullptr;
@@ -1394,8 +1453,8 @@ int sbci_batch_create(int ninst, const int *norb, const int *nalpha, const int *
   if (ninst < 1) return batch_error(SBCI_EINVAL, "ninst must be >= 1");
   if (!norb || !nalpha || !nbeta || !h1 || !eri) return batch_error(SBCI_EINVAL, "NULL argument");
   for (int i = 0; i < ninst; ++i) {
-    if (norb[i] < 1 || norb[i] > 11)
-      return batch_error(SBCI_EINVAL, "batch instances need 1 <= norb <= 11");
+    if (norb[i] < 1 || norb[i] > BMAX_NORB)
+      return batch_error(SBCI_EINVAL, "batch instances need 1 <= norb <= 10");
     if (!h1[i] || !eri[i]) return batch_error(SBCI_EINVAL, "NULL integrals");
   }
   sbci_batch *b = new sbci_batch();
@@ -1472,7 +1531,7 @@ int64_t sbci_batch_ndet(const sbci_batch *b, int inst) {
 }
 
 int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_opts *opt,
-                     const sbci_batch_config *cfg_in, double *energies, int *status,
+                     const sbci_batch_config *cfg_in, double *energies, sbci_batch_inst *info,
                      sbci_batch_report *rep) {
   if (!b || !nroots) return batch_error(SBCI_EINVAL, "NULL argument");
   BParams P{};
@@ -1489,6 +1548,11 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   SBCI_HIP(hipMemcpy(o.data(), b->d_out, sizeof(BOut) * b->ninst, hipMemcpyDeviceToHost));
   sbci_batch_report r{};
   r.seconds = ms * 1e-3;
+  uint64_t tmin = ~0ull, tmax = 0;
+  for (const BOut &q : o) {
+    tmin = std::min(tmin, q.t0);
+    tmax = std::max(tmax, q.t1);
+  }
   int64_t off = 0;
   int worst = SBCI_OK;
   for (int i = 0; i < b->ninst; ++i) {
@@ -1497,7 +1561,19 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
       if (energies) energies[off + a] = a < q.nconv ? q.E[a] : NAN;
     }
     off += nroots[i];
-    if (status) status[i] = q.status;
+    if (info) {
+      sbci_batch_inst &f = info[i];
+      f.status = q.status;
+      f.nroots_converged = q.nconv;
+      f.nsteps = q.nsteps;
+      f.nrestarts = q.nrestarts;
+      f.nsigma_f64 = q.nsig64;
+      f.nsigma_low = q.nsiglow;
+      f.t_start = (double)(q.t0 - tmin) / kRealtimeHz;
+      f.t_end = (double)(q.t1 - tmin) / kRealtimeHz;
+      for (int a = 0; a < 4; ++a) f.resid[a] = a < q.nconv ? q.dz[a] : NAN;
+      for (int a = 0; a < 3; ++a) f.t_sigma[a] = (double)q.tsig[a] / kRealtimeHz;
+    }
     if (q.status == SBCI_OK) r.ninst_converged += 1;
     else if (worst == SBCI_OK || q.status == SBCI_ENUMERIC) worst = q.status;
     r.nsigma_f64 += q.nsig64;
@@ -1506,6 +1582,7 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
     r.nsteps += q.nsteps;
     r.nrestarts += q.nrestarts;
   }
+  r.span_seconds = tmax > tmin ? (double)(tmax - tmin) / kRealtimeHz : 0.0;
   r.threads = cfg.threads;
   r.wg_per_cu = cfg.wg_per_cu;
   r.order = cfg.order;

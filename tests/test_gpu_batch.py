@@ -63,6 +63,9 @@ def test_small_batch_fp64_matches_oracle(small_batch):
     assert (r.status == 0).all()
     assert r.report["ninst_converged"] == len(SMALL)
     assert r.report["nsigma_low"] == 0
+    for d in r.instances:
+        assert d["t_end"] >= d["t_start"] >= 0
+        assert all(x < 1e-5 for x in d["resid"])
     for i, (n, na, nb, k, seed) in enumerate(SMALL):
         I = make_integrals(n, 2 * n, seed)
         op = OS.Operator(n, na, nb, I.h1, I.eri)
