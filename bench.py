@@ -82,7 +82,7 @@ def batch_section(sb, precision):
         best, cands = b.tune(nroots, tol=1e-10, opts=dict(precision=prec))
         r = b.solve(nroots, tol=1e-10, opts=dict(precision=prec))
         rd = b.solve(nroots, tol=1e-10, opts=dict(precision=prec),
-                     config=dict(threads=256, wg_per_cu=2, order=0, row_tile=16))
+                     config=dict(threads=256, wg_per_cu=2, order=0, k_panel=16))
         spans = np.array([d["t_end"] - d["t_start"] for d in r.instances])
         crit = int(np.argmax(spans))
         res[prec] = r
@@ -94,7 +94,7 @@ def batch_section(sb, precision):
             "steps": r.report["nsteps"],
             "tuned": best,
             "tuned_vs_default": round(rd.report["seconds"] / r.report["seconds"], 3),
-            "candidates_ms": [[c["threads"], c["wg_per_cu"], c["order"], c["row_tile"], round(ms, 1)]
+            "candidates_ms": [[c["threads"], c["wg_per_cu"], c["order"], c["k_panel"], round(ms, 1)]
                               for c, ms in cands],
             "critical_instance": {"id": crit, "norb": inst[crit][0], "nroots": inst[crit][2],
                                   "span_s": round(float(spans[crit]), 4),

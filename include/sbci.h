@@ -193,7 +193,7 @@ typedef struct sbci_batch_config {
   int threads;    /* workgroup size: 256, 512 or 1024                          */
   int wg_per_cu;  /* persistent workgroups per compute unit: 1..4              */
   int order;      /* queue order: 0 = largest estimated work first, 1 = input  */
-  int row_tile;   /* rows / columns of C per same-spin LDS tile: 8 or 16       */
+  int k_panel;    /* K panel of the same-spin MFMA products in LDS: 8 or 16    */
 } sbci_batch_config;
 
 typedef struct sbci_batch_report {
@@ -205,7 +205,7 @@ typedef struct sbci_batch_report {
   int64_t det_sigma;         /* sum over instances of N_det x sigma applications */
   int64_t nsteps, nrestarts; /* summed over instances                           */
   int ninst_converged;       /* instances with status SBCI_OK                   */
-  int threads, wg_per_cu, order, row_tile;  /* the launch shape used           */
+  int threads, wg_per_cu, order, k_panel;   /* the launch shape used           */
 } sbci_batch_report;
 
 /* Per-instance outcome of a batch solve (times from the device real-time
@@ -216,8 +216,8 @@ typedef struct sbci_batch_inst {
   int nsteps, nrestarts, nsigma_f64, nsigma_low;
   double t_start, t_end;     /* seconds                                         */
   double resid[4];           /* |z'| at convergence of each root (NaN if none)   */
-  double t_sigma[3];         /* seconds in sigma: beta same-spin, alpha
-                                same-spin, opposite-spin parts                  */
+  double t_same, t_opp;      /* seconds in sigma: one-electron + same-spin part,
+                                opposite-spin part                              */
 } sbci_batch_inst;
 
 /* Builds every instance's tables (as sbci_create does for one) on the
@@ -242,7 +242,7 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
                      sbci_batch_report *rep);
 
 /* Autotuner: times full batch solves over a candidate set of launch shapes
- * (workgroup size x residency, then queue order and tile height around the
+ * (workgroup size x residency, then queue order and K panel around the
  * best) with HIP events, keeps the fastest for later sbci_batch_solve calls
  * and writes it to best.  ms, cand: host arrays of capacity *ncand (or
  * NULL) receive each candidate's time and shape; *ncand returns the number

@@ -79,7 +79,7 @@ _P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int6
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("row_tile", _I)]
+    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,7 +89,7 @@ class BatchInst(ctypes.Structure):
     _fields_ = [
         ("status", _I), ("nroots_converged", _I), ("nsteps", _I), ("nrestarts", _I),
         ("nsigma_f64", _I), ("nsigma_low", _I), ("t_start", _D), ("t_end", _D),
-        ("resid", _D * 4), ("t_sigma", _D * 3),
+        ("resid", _D * 4), ("t_same", _D), ("t_opp", _D),
     ]
 
 
@@ -97,7 +97,7 @@ class BatchReport(ctypes.Structure):
     _fields_ = [
         ("seconds", _D), ("span_seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
         ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
-        ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("row_tile", _I),
+        ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I),
     ]
 
     def as_dict(self):
@@ -390,9 +390,8 @@ class Batch:
         inst = []
         for i in range(self.n):
             q = info[i]
-            d = {f: getattr(q, f) for f, _ in BatchInst._fields_ if f not in ("resid", "t_sigma")}
+            d = {f: getattr(q, f) for f, _ in BatchInst._fields_ if f != "resid"}
             d["resid"] = list(q.resid[:int(r[i])])
-            d["t_sigma"] = list(q.t_sigma)
             inst.append(d)
         st = np.array([d["status"] for d in inst], dtype=np.int32)
         return BatchResult(parts, st, rep.as_dict(), rc, inst)

@@ -12,19 +12,19 @@
 //     (or input order), so uneven sizes balance across the 256 CUs.  Every
 //     workgroup leaves when the queue is exhausted; every instance ends after
 //     at most max_steps steps per root.
-//   * sigma inside a workgroup follows the decomposition of sigma.hip:
-//       same-spin beta part in-row, on row tiles of C staged in LDS,
-//       same-spin alpha part on column tiles of C staged in LDS,
-//       opposite-spin part row by row as an MFMA contraction of the signed
-//       ERI pair tile with s gathered rows of C, scattered through the beta
-//       pair table into an LDS copy of sigma's row (FP64 LDS atomics).
-//     Same-spin lists are stored transposed ([entry][string]) so that the
-//     list loads of a wavefront are coalesced.
+//   * sigma inside a workgroup: the one-electron and same-spin parts as two
+//     dense MFMA products C * H_beta + H_alpha * C (for norb <= 10 these
+//     operators are 50-95 % dense) with LDS-staged K panels; the
+//     opposite-spin part per wavefront and row as an MFMA contraction of the
+//     signed ERI pair tile (in registers) with s gathered rows of C,
+//     scattered through the beta pair table into the wave's LDS copy of
+//     sigma's row (FP64 LDS atomics).
 //   * The vector passes (fused update, deflation, dots) are the same
 //     arithmetic as vec.hip with workgroup-level FP64 reductions in a fixed
 //     order.
-//   * Launch shape (workgroup size, workgroups per CU, queue order, tile
-//     height) is chosen by a measured autotuner (sbci_batch_tune).
+//   * Launch shape (workgroup size, workgroups per CU, queue order, K panel
+//     of the same-spin products) is chosen by a measured autotuner
+//     (sbci_batch_tune).
 #include "internal.h"
 #include "mfma.h"
 #include "ritz.h"
@@ -56,9 +56,8 @@ struct BInst {
   int64_t ndet, ns_pad_b;
   const Ent *tab_a;
   const uint32_t *pair_b;
-  const int32_t *fcol_a, *fcol_b;  // transposed lists [nf][ns]
-  const double *fv64_a, *fv64_b;
-  const float *fv32_a, *fv32_b;
+  const double *H64_a, *H64_b;  // dense same-spin operators [ns][ns] (symmetric)
+  const float *H32_a, *H32_b;
   const double *W64;
   const float *W32;
   const __bf16 *Wbf;
@@ -72,7 +71,7 @@ struct BOut {
   double E[BMAXR];
   double dz[BMAXR];
   uint64_t t0, t1;  // device real-time counter at the instance's start and end
-  uint64_t tsig[3]; // counter ticks in the sigma parts: beta same-spin, alpha same-spin, opposite
+  uint64_t tsig[2]; // counter ticks in the sigma parts: same-spin, opposite-spin
   int status, nconv, nsteps, nrestarts, nsig64, nsiglow, pad0, pad1;
 };
 
@@ -80,7 +79,7 @@ struct BParams {
   double eps0, r0, b_th, eps1, x_th1, x_th2, r1, mix_eps0, mix_r0, bf16_eps0, bf16_r0, floor,
       lindep;
   int max_cycle, max_steps, precision, mix_stall;
-  int rt;  // rows (columns) per same-spin tile: 8 or 16
+  int kp;  // K panel of the same-spin GEMMs: 8 or 16
 };
 
 // ------------------------------------------------------------ reductions
@@ -140,7 +139,7 @@ struct Ctl {
   int alpha, seg, t, steps_root, phase, seg_start, stall, done, any_noconv, nconv, status;
   int m64[NVW], m32[NVW];  // logical slot -> physical vector
   int nsteps, nrestarts, nsig64, nsiglow;
-  uint64_t tsig[3];
+  uint64_t tsig[2];
   double E, sx, bestE;
   double Ec[BMAXR];
   double h1[16], h2[4], h3[4];
@@ -153,58 +152,104 @@ struct Ctl {
 };
 
 // ------------------------------------------------------------ WG sigma
-constexpr int SV = 4;  // tile positions per same-spin work item
-constexpr int FU = 4;  // list entries fetched ahead per work item
-
-// Same-spin part on one staged tile: acc[v] = sum_f F[i][f] * L[col(i,f)][sub*SV + v]
-// for output string i.  L is [nsrc][ld] in LDS; the lists are transposed
-// ([entry][string]) so that a wavefront's list loads are coalesced, and FU
-// entries are fetched before they are used so that their latencies overlap.
-template <typename T, typename V>
-__device__ void same_item(int nout, int nf, int ld, const int32_t *__restrict__ fcol,
-                          const V *__restrict__ fval, const T *L, V (&acc)[SV], int i, int sub) {
-#pragma unroll
-  for (int v = 0; v < SV; ++v) acc[v] = 0;
-  const T *Lr = L + sub * SV;
-  int f = 0;
-  for (; f + FU <= nf; f += FU) {
-    int j[FU];
-    V w[FU];
-#pragma unroll
-    for (int u = 0; u < FU; ++u) {
-      j[u] = fcol[(int64_t)(f + u) * nout + i];
-      w[u] = fval[(int64_t)(f + u) * nout + i];
-    }
-#pragma unroll
-    for (int u = 0; u < FU; ++u) {
-      const T *row = Lr + j[u] * ld;
-#pragma unroll
-      for (int v = 0; v < SV; ++v) acc[v] += w[u] * (V)row[v];
-    }
-  }
-  for (; f < nf; ++f) {
-    const int j = fcol[(int64_t)f * nout + i];
-    const V w = fval[(int64_t)f * nout + i];
-    const T *row = Lr + j * ld;
-#pragma unroll
-    for (int v = 0; v < SV; ++v) acc[v] += w * (V)row[v];
-  }
-}
-
 template <typename T>
-struct ListVals;
+struct DenseH;
 template <>
-struct ListVals<double> {
-  using V = double;
-  __device__ static const double *a(const BInst &I) { return I.fv64_a; }
-  __device__ static const double *b(const BInst &I) { return I.fv64_b; }
+struct DenseH<double> {
+  __device__ static const double *a(const BInst &I) { return I.H64_a; }
+  __device__ static const double *b(const BInst &I) { return I.H64_b; }
 };
 template <>
-struct ListVals<float> {
-  using V = float;
-  __device__ static const float *a(const BInst &I) { return I.fv32_a; }
-  __device__ static const float *b(const BInst &I) { return I.fv32_b; }
+struct DenseH<float> {
+  __device__ static const float *a(const BInst &I) { return I.H32_a; }
+  __device__ static const float *b(const BInst &I) { return I.H32_b; }
 };
+
+// One-electron and same-spin part as two dense products on MFMA:
+//   out = C * H_beta + H_alpha * C       (C is [ns_a][ns_b]; H_s symmetric)
+// For norb <= 10 the same-spin operators are 50-95 % dense, so the dense
+// form does little extra work and runs at matrix-core rate.  K panels of
+// both operands are staged in LDS; each wavefront owns whole 16-row tile
+// rows and a block of CB column tiles per pass.
+template <typename T, typename M, int NT>
+__device__ void wg_same_dense(const BInst &I, const T *__restrict__ c, T *__restrict__ out,
+                              int kp, char *lds) {
+  static_assert(M::KPL == 1 && M::KSTEP == 4, "dense same-spin GEMM uses 16x16x4 MFMA");
+  using Frag = typename M::Frag;
+  using Out = typename M::Out;
+  constexpr int NW = NT / 64;
+  constexpr int TMMAX = (BMAX_NS + 15) / 16;
+  constexpr int RW = (TMMAX + NW - 1) / NW;          // tile rows per wave
+  constexpr int CB = RW >= 8 ? 1 : 8 / RW;           // column tiles per wave and pass
+  const int nsa = I.ns_a, nsb = I.ns_b;
+  const int tm = (nsa + 15) / 16, tn = (nsb + 15) / 16;
+  const int mp = tm * 16;
+  const int lda = kp + 1, ldb = CB * 16 + 1;
+  T *Ap = reinterpret_cast<T *>(lds);                 // [mp][lda]
+  T *Bp = Ap + (size_t)(TMMAX * 16) * lda;            // [kp][ldb]
+  const T *Ha = DenseH<T>::a(I), *Hb = DenseH<T>::b(I);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, g = lane >> 4;
+  for (int n0 = 0; n0 < tn; n0 += CB) {
+    Out acc[RW][CB];
+#pragma unroll
+    for (int u = 0; u < RW; ++u)
+#pragma unroll
+      for (int v = 0; v < CB; ++v) acc[u][v] = Out{0, 0, 0, 0};
+    // product 0: C * H_beta (K = ns_b); product 1: H_alpha * C (K = ns_a)
+    for (int prod = 0; prod < 2; ++prod) {
+      const int K = prod == 0 ? nsb : nsa;
+      for (int k0 = 0; k0 < K; k0 += kp) {
+        // A panel: rows of C (prod 0) or H_alpha (prod 1), columns k0..k0+kp
+        for (int e = tid; e < mp * kp; e += NT) {
+          const int r = e / kp, k = e - r * kp, kk = k0 + k;
+          T v = (T)0;
+          if (r < nsa && kk < K) v = prod == 0 ? c[(int64_t)r * nsb + kk] : Ha[(int64_t)r * nsa + kk];
+          Ap[r * lda + k] = v;
+        }
+        // B panel: rows k0..k0+kp of H_beta (prod 0) or C (prod 1), CB column tiles
+        for (int e = tid; e < kp * CB * 16; e += NT) {
+          const int k = e / (CB * 16), j = e - k * (CB * 16), kk = k0 + k, col = n0 * 16 + j;
+          T v = (T)0;
+          if (kk < K && col < nsb)
+            v = prod == 0 ? Hb[(int64_t)kk * nsb + col] : c[(int64_t)kk * nsb + col];
+          Bp[k * ldb + j] = v;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kp / 4; ++ks) {
+          Frag b[CB];
+#pragma unroll
+          for (int v = 0; v < CB; ++v) b[v] = Bp[(ks * 4 + g) * ldb + v * 16 + li];
+#pragma unroll
+          for (int u = 0; u < RW; ++u) {
+            const int tr = wv + u * NW;
+            if (tr < tm) {
+              const Frag a = Ap[(tr * 16 + li) * lda + ks * 4 + g];
+#pragma unroll
+              for (int v = 0; v < CB; ++v) acc[u][v] = M::mma(a, b[v], acc[u][v]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const int tr = wv + u * NW;
+      if (tr < tm) {
+#pragma unroll
+        for (int v = 0; v < CB; ++v) {
+          const int col = (n0 + v) * 16 + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = tr * 16 + M::orow(g, r);
+            if (row < nsa && col < nsb) out[(int64_t)row * nsb + col] = (T)acc[u][v][r];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
 
 template <typename M>
 struct WSel;
@@ -229,59 +274,16 @@ template <typename T, typename M, int NT>
 __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__ c,
                          T *__restrict__ out, char *lds, uint64_t *tick) {
   uint64_t tk = __builtin_amdgcn_s_memrealtime();
-  using V = typename ListVals<T>::V;
   const int tid = threadIdx.x;
   const int nsa = I.ns_a, nsb = I.ns_b;
-  const int rt = P.rt, ld = rt + 1, nsub = rt / SV;
-  T *L = reinterpret_cast<T *>(lds);
-  V acc[SV];
-  // (1) beta same-spin, in-row, rt rows of C per tile
-  for (int r0 = 0; r0 < nsa; r0 += rt) {
-    for (int e = tid; e < rt * nsb; e += NT) {
-      const int r = e / nsb, j = e - r * nsb;
-      L[j * ld + r] = r0 + r < nsa ? c[(int64_t)(r0 + r) * nsb + j] : (T)0;
-    }
-    __syncthreads();
-    for (int it = tid; it < nsb * nsub; it += NT) {
-      const int i = it % nsb, sub = it / nsb;
-      same_item<T, V>(nsb, I.nf_b, ld, I.fcol_b, ListVals<T>::b(I), L, acc, i, sub);
-#pragma unroll
-      for (int v = 0; v < SV; ++v) {
-        const int r = r0 + sub * SV + v;
-        if (r < nsa) out[(int64_t)r * nsb + i] = (T)acc[v];
-      }
-    }
-    __syncthreads();
-  }
+  // (1) one-electron and same-spin parts of both spins (dense MFMA products)
+  if constexpr (std::is_same<T, double>::value)
+    wg_same_dense<double, MF64, NT>(I, c, out, P.kp, lds);
+  else
+    wg_same_dense<float, MF32, NT>(I, c, out, P.kp, lds);
   if (threadIdx.x == 0) {
     const uint64_t t = __builtin_amdgcn_s_memrealtime();
     tick[0] += t - tk;
-    tk = t;
-  }
-  // (2) alpha same-spin, cross-row, rt columns of C per tile
-  for (int c0 = 0; c0 < nsb; c0 += rt) {
-    for (int e = tid; e < rt * nsa; e += NT) {
-      const int j = e / rt, cc = e - j * rt;
-      L[j * ld + cc] = c0 + cc < nsb ? c[(int64_t)j * nsb + c0 + cc] : (T)0;
-    }
-    __syncthreads();
-    for (int it = tid; it < nsa * nsub; it += NT) {
-      const int i = it % nsa, sub = it / nsa;
-      same_item<T, V>(nsa, I.nf_a, ld, I.fcol_a, ListVals<T>::a(I), L, acc, i, sub);
-#pragma unroll
-      for (int v = 0; v < SV; ++v) {
-        const int cc = c0 + sub * SV + v;
-        if (cc < nsb) {
-          T *o = out + (int64_t)i * nsb + cc;
-          *o = (T)((V)*o + acc[v]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const uint64_t t = __builtin_amdgcn_s_memrealtime();
-    tick[1] += t - tk;
     tk = t;
   }
   // (3) opposite spin.  Each wavefront owns the rows Ia = wave, wave + NW, ...:
@@ -365,7 +367,7 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) tick[2] += __builtin_amdgcn_s_memrealtime() - tk;
+  if (threadIdx.x == 0) tick[1] += __builtin_amdgcn_s_memrealtime() - tk;
 }
 
 // ------------------------------------------------------------ vector passes
@@ -1077,7 +1079,7 @@ struct Solve {
       C.status = SBCI_OK;
       for (int i = 0; i < NVW; ++i) C.m64[i] = C.m32[i] = i;
       C.nsteps = C.nrestarts = C.nsig64 = C.nsiglow = 0;
-      C.tsig[0] = C.tsig[1] = C.tsig[2] = 0;
+      C.tsig[0] = C.tsig[1] = 0;
       C.E = 0;
       C.sx = 1;
       C.bestE = 0;
@@ -1123,7 +1125,7 @@ struct Solve {
       out.nrestarts = C.nrestarts;
       out.nsig64 = C.nsig64;
       out.nsiglow = C.nsiglow;
-      for (int q = 0; q < 3; ++q) out.tsig[q] = C.tsig[q];
+      for (int q = 0; q < 2; ++q) out.tsig[q] = C.tsig[q];
       int st = C.status;
       if (st == SBCI_OK && (!C.done || C.any_noconv)) st = SBCI_ENOCONV;
       out.status = st;
@@ -1164,18 +1166,25 @@ __global__ void k_batch_reset(unsigned *queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) queue[0] = 0u;
 }
 
-// Transposed same-spin lists: dst[f][i] = src[i][f].
-template <typename T>
-__global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t ns, int nf) {
+// Dense same-spin operator from its lists: H[i][col(i,f)] = F[i][f]
+// (H zero-initialised; the list columns of a row are distinct).
+__global__ void k_dense(const int32_t *__restrict__ fcol, const double *__restrict__ f64,
+                        int64_t ns, int nf, double *__restrict__ d64, float *__restrict__ d32) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= ns * nf) return;
-  const int64_t i = e / nf, f = e - i * nf;
-  dst[f * ns + i] = src[e];
+  const int64_t i = e / nf;
+  const int64_t j = fcol[e];
+  d64[i * ns + j] = f64[e];
+  d32[i * ns + j] = (float)f64[e];
 }
 
-size_t lds_bytes(int rt, int nsa, int nsb, int threads) {
-  const size_t same = sizeof(double) * (size_t)(rt + 1) * (size_t)std::max(nsa, nsb);
-  const size_t opp = kWBytes + sizeof(double) * BMAX_NS * (size_t)(threads / 64);
+size_t lds_bytes(int kp, int threads) {
+  const int nw = threads / 64;
+  const int rw = ((BMAX_NS + 15) / 16 + nw - 1) / nw;
+  const int cb = rw >= 8 ? 1 : 8 / rw;
+  const size_t same = sizeof(double) * ((size_t)((BMAX_NS + 15) / 16 * 16) * (kp + 1) +
+                                        (size_t)kp * (cb * 16 + 1));
+  const size_t opp = kWBytes + sizeof(double) * BMAX_NS * (size_t)nw;
   return std::max(same, opp);
 }
 
@@ -1186,9 +1195,8 @@ size_t lds_bytes(int rt, int nsa, int nsb, int threads) {
 using namespace sbci;
 
 struct SpinT {
-  int32_t *fcol = nullptr;
-  double *f64 = nullptr;
-  float *f32 = nullptr;
+  double *d64 = nullptr;  // dense same-spin operator [ns][ns]
+  float *d32 = nullptr;
 };
 
 struct sbci_batch {
@@ -1197,7 +1205,7 @@ struct sbci_batch {
   int ncu = 0;
   hipStream_t stream = nullptr;
   std::vector<sbci_ctx *> ctx;
-  std::vector<SpinT> la, lb;  // transposed lists per instance
+  std::vector<SpinT> la, lb;  // dense same-spin operators per instance
   std::vector<int> nroots;    // of the last solve
   BInst *d_inst = nullptr;
   BParams *d_params = nullptr;
@@ -1219,20 +1227,16 @@ int batch_error(int code, const std::string &m) { return set_error(code, m); }
 
 constexpr double kRealtimeHz = 100e6;  // s_memrealtime counter frequency
 
-int build_lists(sbci_batch *b, int i) {
+int build_dense(sbci_batch *b, int i) {
   sbci_ctx *c = b->ctx[i];
   auto mk = [&](const SpinTables &T, SpinT &o) -> int {
-    const int64_t n = T.ns * T.nf;
-    SBCI_HIP(hipMalloc(&o.fcol, sizeof(int32_t) * std::max<int64_t>(n, 1)));
-    SBCI_HIP(hipMalloc(&o.f64, sizeof(double) * std::max<int64_t>(n, 1)));
-    SBCI_HIP(hipMalloc(&o.f32, sizeof(float) * std::max<int64_t>(n, 1)));
-    if (n > 0) {
-      const unsigned g = (unsigned)((n + 255) / 256);
-      k_list_t<int32_t><<<g, 256, 0, b->stream>>>(T.fcol, o.fcol, T.ns, T.nf);
-      k_list_t<double><<<g, 256, 0, b->stream>>>(T.fval64, o.f64, T.ns, T.nf);
-      k_list_t<float><<<g, 256, 0, b->stream>>>(T.fval32, o.f32, T.ns, T.nf);
-      SBCI_CHECK_LAUNCH();
-    }
+    const int64_t n2 = T.ns * T.ns, n = T.ns * T.nf;
+    SBCI_HIP(hipMalloc(&o.d64, sizeof(double) * n2));
+    SBCI_HIP(hipMalloc(&o.d32, sizeof(float) * n2));
+    SBCI_HIP(hipMemsetAsync(o.d64, 0, sizeof(double) * n2, b->stream));
+    SBCI_HIP(hipMemsetAsync(o.d32, 0, sizeof(float) * n2, b->stream));
+    k_dense<<<(unsigned)((n + 255) / 256), 256, 0, b->stream>>>(T.fcol, T.fval64, T.ns, T.nf, o.d64, o.d32);
+    SBCI_CHECK_LAUNCH();
     return SBCI_OK;
   };
   SBCI_TRY(mk(c->A, b->la[i]));
@@ -1276,8 +1280,8 @@ int check_config(const sbci_batch_config &c) {
   if (c.wg_per_cu < 1 || c.wg_per_cu > 4)
     return batch_error(SBCI_EINVAL, "batch config: wg_per_cu must be in 1..4");
   if (c.order != 0 && c.order != 1) return batch_error(SBCI_EINVAL, "batch config: order must be 0 or 1");
-  if (c.row_tile != 8 && c.row_tile != 16)
-    return batch_error(SBCI_EINVAL, "batch config: row_tile must be 8 or 16");
+  if (c.k_panel != 8 && c.k_panel != 16)
+    return batch_error(SBCI_EINVAL, "batch config: k_panel must be 8 or 16");
   return SBCI_OK;
 }
 
@@ -1353,12 +1357,10 @@ int prepare(sbci_batch *b, const int *nroots, int precision) {
     I.ns_pad_b = c->B.ns_pad;
     I.tab_a = c->A.tab;
     I.pair_b = c->B.pair;
-    I.fcol_a = b->la[i].fcol;
-    I.fcol_b = b->lb[i].fcol;
-    I.fv64_a = b->la[i].f64;
-    I.fv64_b = b->lb[i].f64;
-    I.fv32_a = b->la[i].f32;
-    I.fv32_b = b->lb[i].f32;
+    I.H64_a = b->la[i].d64;
+    I.H64_b = b->lb[i].d64;
+    I.H32_a = b->la[i].d32;
+    I.H32_b = b->lb[i].d32;
     I.W64 = c->W64;
     I.W32 = c->W32;
     I.Wbf = reinterpret_cast<const __bf16 *>(c->Wbf);
@@ -1398,13 +1400,13 @@ int set_order(sbci_batch *b, int order) {
 
 int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, double *ms) {
   size_t lds = 0;
-  for (auto &I : b->h_inst) lds = std::max(lds, lds_bytes(cfg.row_tile, I.ns_a, I.ns_b, cfg.threads));
+  lds = lds_bytes(cfg.k_panel, cfg.threads);
   // The solve parameters are baked into the captured launch, so every call
   // captures a fresh graph (a few microseconds next to the solve).
   hipGraph_t g = nullptr;
   hipGraphExec_t x = nullptr;
   BParams Pc = P;
-  Pc.rt = cfg.row_tile;
+  Pc.kp = cfg.k_panel;
   SBCI_HIP(hipMemcpyAsync(b->d_params, &Pc, sizeof(BParams), hipMemcpyHostToDevice, b->stream));
   int rc = SBCI_OK;
   if (cfg.threads == 256)
@@ -1438,7 +1440,7 @@ sbci_batch_config default_config() {
   c.threads = 256;
   c.wg_per_cu = 2;
   c.order = 0;
-  c.row_tile = 16;
+  c.k_panel = 16;
   return c;
 }
 
@@ -1477,7 +1479,7 @@ int sbci_batch_create(int ninst, const int *norb, const int *nalpha, const int *
           16 * ((c->npair + 15) / 16) > BMAX_NP)
         rc = batch_error(SBCI_EINVAL, "batch instance exceeds the workgroup limits");
     }
-    if (rc == SBCI_OK) rc = build_lists(b, i);
+    if (rc == SBCI_OK) rc = build_dense(b, i);
     if (rc != SBCI_OK) {
       std::string m = sbci_last_error();
       sbci_batch_destroy(b);
@@ -1503,13 +1505,11 @@ int sbci_batch_destroy(sbci_batch *b) {
   if (b->stream) hipStreamSynchronize(b->stream);
   for (int i = 0; i < (int)b->ctx.size(); ++i) {
     const bool shared = b->ctx[i] && b->ctx[i]->B.shared;
-    hipFree(b->la[i].fcol);
-    hipFree(b->la[i].f64);
-    hipFree(b->la[i].f32);
+    hipFree(b->la[i].d64);
+    hipFree(b->la[i].d32);
     if (!shared) {
-      hipFree(b->lb[i].fcol);
-      hipFree(b->lb[i].f64);
-      hipFree(b->lb[i].f32);
+      hipFree(b->lb[i].d64);
+      hipFree(b->lb[i].d32);
     }
     if (b->ctx[i]) sbci_destroy(b->ctx[i]);
   }
@@ -1572,7 +1572,8 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
       f.t_start = (double)(q.t0 - tmin) / kRealtimeHz;
       f.t_end = (double)(q.t1 - tmin) / kRealtimeHz;
       for (int a = 0; a < 4; ++a) f.resid[a] = a < q.nconv ? q.dz[a] : NAN;
-      for (int a = 0; a < 3; ++a) f.t_sigma[a] = (double)q.tsig[a] / kRealtimeHz;
+      f.t_same = (double)q.tsig[0] / kRealtimeHz;
+      f.t_opp = (double)q.tsig[1] / kRealtimeHz;
     }
     if (q.status == SBCI_OK) r.ninst_converged += 1;
     else if (worst == SBCI_OK || q.status == SBCI_ENUMERIC) worst = q.status;
@@ -1586,7 +1587,7 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   r.threads = cfg.threads;
   r.wg_per_cu = cfg.wg_per_cu;
   r.order = cfg.order;
-  r.row_tile = cfg.row_tile;
+  r.k_panel = cfg.k_panel;
   if (rep) *rep = r;
   if (worst != SBCI_OK)
     return batch_error(worst, worst == SBCI_ENOCONV ? "some batch instances did not converge"
@@ -1620,7 +1621,7 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
       c.threads = nt;
       c.wg_per_cu = w;
       c.order = 0;
-      c.row_tile = 16;
+      c.k_panel = 16;
       SBCI_TRY(trial(c));
     }
   size_t bi = std::min_element(times.begin(), times.end()) - times.begin();
@@ -1630,7 +1631,7 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
     c.order = 1;
     SBCI_TRY(trial(c));
     c = w;
-    c.row_tile = 8;
+    c.k_panel = 8;
     SBCI_TRY(trial(c));
   }
   bi = std::min_element(times.begin(), times.end()) - times.begin();

@@ -96,16 +96,16 @@ def test_small_batch_mixed_precision_reaches_fp64(small_batch, prec):
         _check_eigenpairs(n, na, nb, I, r.energies[i], X)
 
 
-@pytest.mark.parametrize("cfg", [dict(threads=256, wg_per_cu=1, order=1, row_tile=8),
-                                 dict(threads=512, wg_per_cu=2, order=0, row_tile=16),
-                                 dict(threads=1024, wg_per_cu=1, order=0, row_tile=8)])
+@pytest.mark.parametrize("cfg", [dict(threads=256, wg_per_cu=1, order=1, k_panel=8),
+                                 dict(threads=512, wg_per_cu=2, order=0, k_panel=16),
+                                 dict(threads=1024, wg_per_cu=1, order=0, k_panel=8)])
 def test_launch_shapes_agree(small_batch, cfg):
     nroots = [t[3] for t in SMALL]
     base = small_batch.solve(nroots, tol=1e-10, config=dict(threads=256, wg_per_cu=2, order=0,
-                                                            row_tile=16))
+                                                            k_panel=16))
     r = small_batch.solve(nroots, tol=1e-10, config=cfg)
     assert (r.status == 0).all()
-    for k in ("threads", "wg_per_cu", "order", "row_tile"):
+    for k in ("threads", "wg_per_cu", "order", "k_panel"):
         assert r.report[k] == cfg[k]
     for a, b in zip(base.energies, r.energies):
         assert abs(a[0] - b[0]) < 1e-9
@@ -134,7 +134,7 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(sb.SbciError):
         b.solve([5])                                  # more roots than supported
     with pytest.raises(sb.SbciError):
-        b.solve([1], config=dict(threads=128, wg_per_cu=1, order=0, row_tile=16))
+        b.solve([1], config=dict(threads=128, wg_per_cu=1, order=0, k_panel=16))
     with pytest.raises(sb.SbciError):
         b.solve([1], opts=dict(precision=9))
     b.close()
