@@ -12,8 +12,8 @@
 // start of a segment (a restart normalises x without a separate pass) and
 // sy = 0 drops y, Y (y_0 = 0 at a segment start).
 //
-// Reductions are deterministic: each block writes its partial sums, and the
-// last block to finish (an atomic ticket) adds the partials in a fixed order.
+// Reductions are deterministic: each block writes its partial sums and a
+// one-block kernel adds the partials in a fixed order.
 #include "internal.h"
 
 namespace sbci {
@@ -33,12 +33,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Reduce v[0..nq) over the block; the last block of the grid writes out[q].
+// Reduce v[0..nq) over the block and store the block's partial sums;
+// k_reduce (launched next on the same stream) adds the partials of all
+// blocks in a fixed order.  The kernel boundary orders the two, so no
+// device-scope fence is needed (on this multi-XCD part such a fence writes
+// back and invalidates L2, which starves the streaming passes).
 template <int NQ>
-__device__ void grid_reduce(double (&v)[NQ], int nq, double *__restrict__ part,
-                            unsigned *__restrict__ ticket, double *__restrict__ out) {
+__device__ void grid_reduce(double (&v)[NQ], int nq, double *__restrict__ part, unsigned *,
+                            double *) {
   __shared__ double sh[BS / 64][NQ];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -52,39 +55,52 @@ __device__ void grid_reduce(double (&v)[NQ], int nq, double *__restrict__ part,
     for (int w = 0; w < BS / 64; ++w) s += sh[w][threadIdx.x];
     part[(size_t)blockIdx.x * MAXQ + threadIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    // all threads of the last block add the partials: thread t takes blocks
-    // t, t + BS, ... (fixed order), then a block reduction per slot
-    for (int q = 0; q < nq; ++q) {
-      double s = 0;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += BS) s += part[(size_t)b * MAXQ + q];
-      s = wave_sum(s);
-      __syncthreads();
-      if (lane == 0) sh[wave][0] = s;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double t = 0;
-        for (int w = 0; w < BS / 64; ++w) t += sh[w][0];
-        out[q] = t;
-      }
+}
+
+// out[q] = sum over blocks b (in order b = t, t + BS, ... per thread t, then
+// a fixed tree) of part[b][q].
+__global__ __launch_bounds__(BS) void k_reduce(const double *__restrict__ part, unsigned nblocks,
+                                               int nq, double *__restrict__ out) {
+  __shared__ double sh[BS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < nq; ++q) {
+    double s = 0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += BS) s += part[(size_t)b * MAXQ + q];
+    s = wave_sum(s);
+    if (lane == 0) sh[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < BS / 64; ++w) t += sh[w];
+      out[q] = t;
     }
-    if (threadIdx.x == 0) *ticket = 0u;
+    __syncthreads();
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_dots(int64_t n, const T *__restrict__ a, Ptrs bs, int nb,
                                              double *part, unsigned *ticket, double *out) {
+  constexpr int U = 2;
   double v[MAXV];
 #pragma unroll
   for (int q = 0; q < MAXV; ++q) v[q] = 0;
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    double ai = (double)a[i];
+  const int64_t S = (int64_t)gridDim.x * BS;
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double ai[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ai[u] = (double)a[i + u * S];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q)
+      if (q < nb) {
+        const T *bq = static_cast<const T *>(bs.p[q]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[q] += ai[u] * (double)bq[i + u * S];
+      }
+  }
+  for (; i < n; i += S) {
+    const double ai = (double)a[i];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q)
       if (q < nb) v[q] += ai * (double)static_cast<const T *>(bs.p[q])[i];
@@ -99,7 +115,24 @@ struct Coefs {
 template <typename T>
 __global__ __launch_bounds__(BS) void k_lincomb(int64_t n, T *__restrict__ out, Ptrs xs, Coefs cf,
                                                 int nx, double beta) {
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+  constexpr int U = 4;
+  const int64_t S = (int64_t)gridDim.x * BS;
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = beta == 0.0 ? 0.0 : beta * (double)out[i + u * S];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q)
+      if (q < nx) {
+        const T *xq = static_cast<const T *>(xs.p[q]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] += cf.c[q] * (double)xq[i + u * S];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) out[i + u * S] = (T)s[u];
+  }
+  for (; i < n; i += S) {
     double s = beta == 0.0 ? 0.0 : beta * (double)out[i];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q)
@@ -111,11 +144,22 @@ __global__ __launch_bounds__(BS) void k_lincomb(int64_t n, T *__restrict__ out, 
 template <typename Td, typename Ts>
 __global__ __launch_bounds__(BS) void k_convert(int64_t n, Td *__restrict__ dst,
                                                 const Ts *__restrict__ src, double scale) {
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
-    dst[i] = (Td)(scale * (double)src[i]);
+  constexpr int U = 4;
+  const int64_t S = (int64_t)gridDim.x * BS;
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    Ts v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[i + u * S];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[i + u * S] = (Td)(scale * (double)v[u]);
+  }
+  for (; i < n; i += S) dst[i] = (Td)(scale * (double)src[i]);
 }
 
-template <typename T>
+// NC: compile-time bound on the number of converged roots (a bucket of
+// a.nconv), so that only that many projection loads are kept in flight.
+template <typename T, int NC>
 __global__ __launch_bounds__(BS) void k_update(int64_t n, T *__restrict__ x, T *__restrict__ X,
                                                T *__restrict__ y, T *__restrict__ Y,
                                                const T *__restrict__ z, const T *__restrict__ Z,
@@ -123,31 +167,25 @@ __global__ __launch_bounds__(BS) void k_update(int64_t n, T *__restrict__ x, T *
                                                UpdateArgs a, double *part, unsigned *ticket,
                                                double *out) {
   // slots: 0 |z'|^2, 1 xx, 2 xy, 3 yy, 4 xX, 5 xY, 6 yY, 7 xw, 8 yw, 9 ww, 10+j xc_j.w
-  double v[10 + MAXV];
+  constexpr int U = 2;
+  double v[10 + NC];
 #pragma unroll
-  for (int q = 0; q < 10 + MAXV; ++q) v[q] = 0;
+  for (int q = 0; q < 10 + NC; ++q) v[q] = 0;
   const double b = a.b, c = a.c, E = a.E, inv = a.inv_norm, E0 = a.E0, fl = a.floor, sx = a.sx;
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    double zi = 0, Zi = 0, yi = 0, Yi = 0;
-    if (a.read_z) {
-      zi = (double)z[i];
-      Zi = (double)Z[i];
-    }
-    if (a.sy) {
-      yi = (double)y[i];
-      Yi = (double)Y[i];
-    }
+  const int64_t S = (int64_t)gridDim.x * BS;
+  auto element = [&](int64_t k, double zi, double Zi, double yi, double Yi, double xi, double Xi,
+                     double Di) {
     const double yn = yi - c * zi, Yn = Yi - c * Zi;
-    const double xn = sx * (double)x[i] + b * yn, Xn = sx * (double)X[i] + b * Yn;
+    const double xn = sx * xi + b * yn, Xn = sx * Xi + b * Yn;
     const double r = (Xn - E * xn) * inv;
-    double den = (double)D[i] - E0;
+    double den = Di - E0;
     if (fabs(den) < fl) den = fl;
     const double wi = r / den;
-    x[i] = (T)xn;
-    X[i] = (T)Xn;
-    y[i] = (T)yn;
-    Y[i] = (T)Yn;
-    w[i] = (T)wi;
+    x[k] = (T)xn;
+    X[k] = (T)Xn;
+    y[k] = (T)yn;
+    Y[k] = (T)Yn;
+    w[k] = (T)wi;
     // reduce what was stored (the next step sees the rounded vectors)
     const double xs = (double)(T)xn, ys = (double)(T)yn, Xs = (double)(T)Xn, Ys = (double)(T)Yn;
     const double ws = (double)(T)wi;
@@ -164,34 +202,69 @@ __global__ __launch_bounds__(BS) void k_update(int64_t n, T *__restrict__ x, T *
       v[9] += ws * ws;
     }
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < a.nconv) v[10 + j] += ws * (double)static_cast<const T *>(xc.p[j])[i];
+    for (int j = 0; j < NC; ++j)
+      if (j < a.nconv) v[10 + j] += ws * (double)static_cast<const T *>(xc.p[j])[k];
+  };
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double zi[U], Zi[U], yi[U], Yi[U], xi[U], Xi[U], Di[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = i + u * S;
+      zi[u] = a.read_z ? (double)z[k] : 0.0;
+      Zi[u] = a.read_z ? (double)Z[k] : 0.0;
+      yi[u] = a.sy ? (double)y[k] : 0.0;
+      Yi[u] = a.sy ? (double)Y[k] : 0.0;
+      xi[u] = (double)x[k];
+      Xi[u] = (double)X[k];
+      Di[u] = (double)D[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) element(i + u * S, zi[u], Zi[u], yi[u], Yi[u], xi[u], Xi[u], Di[u]);
   }
-  grid_reduce<10 + MAXV>(v, 10 + a.nconv, part, ticket, out);
+  for (; i < n; i += S)
+    element(i, a.read_z ? (double)z[i] : 0.0, a.read_z ? (double)Z[i] : 0.0,
+            a.sy ? (double)y[i] : 0.0, a.sy ? (double)Y[i] : 0.0, (double)x[i], (double)X[i],
+            (double)D[i]);
+  grid_reduce<10 + NC>(v, 10 + a.nconv, part, ticket, out);
 }
 
 // z = w - sum_j d_j xc_j (in place); reduces x.z, y.z, z.z
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(BS) void k_deflate(int64_t n, T *__restrict__ w, const T *__restrict__ x,
                                                 const T *__restrict__ y, Ptrs xc, int nconv,
                                                 const double *__restrict__ d, double *part,
                                                 unsigned *ticket, double *out) {
-  double dj[MAXV];
+  constexpr int U = 4;
+  double dj[NC];
 #pragma unroll
-  for (int j = 0; j < MAXV; ++j) dj[j] = j < nconv ? d[j] : 0.0;
+  for (int j = 0; j < NC; ++j) dj[j] = j < nconv ? d[j] : 0.0;
   double v[3] = {0, 0, 0};
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    double zi = (double)w[i];
+  const int64_t S = (int64_t)gridDim.x * BS;
+  auto element = [&](int64_t k, double zi, double xi, double yi) {
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nconv) zi -= dj[j] * (double)static_cast<const T *>(xc.p[j])[i];
+    for (int j = 0; j < NC; ++j)
+      if (j < nconv) zi -= dj[j] * (double)static_cast<const T *>(xc.p[j])[k];
     const T zt = (T)zi;
-    w[i] = zt;
+    w[k] = zt;
     const double zs = (double)zt;
-    v[0] += (double)x[i] * zs;
-    v[1] += (double)y[i] * zs;
+    v[0] += xi * zs;
+    v[1] += yi * zs;
     v[2] += zs * zs;
+  };
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double zi[U], xi[U], yi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      zi[u] = (double)w[i + u * S];
+      xi[u] = (double)x[i + u * S];
+      yi[u] = (double)y[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) element(i + u * S, zi[u], xi[u], yi[u]);
   }
+  for (; i < n; i += S) element(i, (double)w[i], (double)x[i], (double)y[i]);
   grid_reduce<3>(v, 3, part, ticket, out);
 }
 
@@ -201,8 +274,27 @@ __global__ __launch_bounds__(BS) void k_dots_xyz(int64_t n, const T *__restrict_
                                                  const T *__restrict__ y, const T *__restrict__ z,
                                                  const T *__restrict__ Z, double *part,
                                                  unsigned *ticket, double *out) {
+  constexpr int U = 4;
   double v[3] = {0, 0, 0};
-  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+  const int64_t S = (int64_t)gridDim.x * BS;
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double Zi[U], xi[U], yi[U], zi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      Zi[u] = (double)Z[i + u * S];
+      xi[u] = (double)x[i + u * S];
+      yi[u] = (double)y[i + u * S];
+      zi[u] = (double)z[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[0] += xi[u] * Zi[u];
+      v[1] += yi[u] * Zi[u];
+      v[2] += zi[u] * Zi[u];
+    }
+  }
+  for (; i < n; i += S) {
     const double Zi = (double)Z[i];
     v[0] += (double)x[i] * Zi;
     v[1] += (double)y[i] * Zi;
@@ -244,6 +336,7 @@ int dots(sbci_ctx *ctx, int64_t n, const T *a, const T *const *bs, int nb, doubl
   Ptrs p{};
   for (int i = 0; i < nb; ++i) p.p[i] = bs[i];
   k_dots<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, a, p, nb, r.part, r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), nb, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -278,8 +371,16 @@ int update(sbci_ctx *ctx, int64_t n, T *x, T *X, T *y, T *Y, const T *z, const T
   SBCI_TRY(red_buf(ctx, r));
   Ptrs p{};
   for (int i = 0; i < a.nconv; ++i) p.p[i] = xc[i];
-  k_update<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, y, Y, z, Z, w, D, p, a, r.part,
-                                                   r.ticket, out);
+  if (a.nconv == 0)
+    k_update<T, 1><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, y, Y, z, Z, w, D, p, a, r.part,
+                                                        r.ticket, out);
+  else if (a.nconv <= 4)
+    k_update<T, 4><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, y, Y, z, Z, w, D, p, a, r.part,
+                                                        r.ticket, out);
+  else
+    k_update<T, MAXV><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, y, Y, z, Z, w, D, p, a, r.part,
+                                                           r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), 10 + a.nconv, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -292,8 +393,13 @@ int deflate(sbci_ctx *ctx, int64_t n, T *w, const T *x, const T *y, const T *con
   SBCI_TRY(red_buf(ctx, r));
   Ptrs p{};
   for (int i = 0; i < nconv; ++i) p.p[i] = xc[i];
-  k_deflate<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, w, x, y, p, nconv, d_coef, r.part, r.ticket,
-                                                    out);
+  if (nconv <= 4)
+    k_deflate<T, 4><<<grid_for(n), BS, 0, ctx->stream>>>(n, w, x, y, p, nconv, d_coef, r.part,
+                                                         r.ticket, out);
+  else
+    k_deflate<T, MAXV><<<grid_for(n), BS, 0, ctx->stream>>>(n, w, x, y, p, nconv, d_coef, r.part,
+                                                            r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), 3, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -303,6 +409,7 @@ int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const
   RedBuf r;
   SBCI_TRY(red_buf(ctx, r));
   k_dots_xyz<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, y, z, Z, r.part, r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), 3, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
