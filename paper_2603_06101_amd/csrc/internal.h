@@ -42,8 +42,19 @@ struct SpinTables {
   double *fval64 = nullptr; // [ns][nf] FP64 values
   float *fval32 = nullptr;  // [ns][nf] FP32 values
   double *fdiag = nullptr;  // [ns] same-spin diagonal energy of each string
+  // transposed lists [nf][ns], built when the LDS-staged same-spin kernel
+  // applies (kSameLdsMinRows <= ns <= kSameLdsMaxRows)
+  int32_t *fcolT = nullptr;
+  double *fvalT64 = nullptr;
+  float *fvalT32 = nullptr;
   bool shared = false;      // aliases the alpha tables (n_alpha == n_beta)
 };
+
+// Row range of the LDS-staged same-spin kernel: a column stripe of 32 bytes
+// per source row (8 FP32 or 4 FP64 columns) must fit in 120 KB of LDS, and
+// below ~1024 rows the register-streaming kernel is already latency-bound.
+constexpr int64_t kSameLdsMinRows = 1024;
+constexpr int64_t kSameLdsMaxRows = 3840;
 
 struct Workspace {
   void *ptr = nullptr;

@@ -418,6 +418,100 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   return SBCI_OK;
 }
 
+// Same-spin part with the source stripe in LDS: one workgroup per (column
+// stripe of WC columns, block of list rows).  The stripe holds all R source
+// rows (R * 32 bytes), so each list entry costs one 32-byte LDS read instead
+// of a row-segment read from L2, and each list is read once per stripe with
+// coalesced loads from the transposed lists ([entry][row]).  Work items are
+// numbered row-block-major and dealt to the XCDs in contiguous ranges, so
+// the workgroups of one XCD sweep the same list rows together.
+template <typename T, typename V, int WC>
+__global__ __launch_bounds__(1024) void k_same_lds(
+    const int32_t *__restrict__ colT, const V *__restrict__ valT, int nf, int64_t R, int64_t C,
+    const T *__restrict__ src, T *__restrict__ dst, int64_t nstripes, int64_t rlen,
+    int64_t per_xcd, int64_t total) {
+  // Row j of the stripe is 32 bytes = two 16-byte halves; rows with bit 3 of
+  // j set store their halves swapped, so that the first-half reads of 64
+  // random rows spread over all 64 LDS banks instead of half of them.
+  constexpr int HW = WC / 2;  // elements per half
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *L = reinterpret_cast<T *>(smem);  // [R][WC], halves swizzled
+  const int64_t b = blockIdx.x;
+  const int64_t w = (b & 7) * per_xcd + (b >> 3);
+  if (w >= total) return;
+  const int64_t rb = w / nstripes, stripe = w - rb * nstripes;
+  const int64_t vo = (int64_t)blockIdx.z * R * C;
+  const int64_t c0 = stripe * WC;
+  for (int64_t e = threadIdx.x; e < R * WC; e += blockDim.x) {
+    const int64_t j = e / WC;
+    const int u = (int)(e - j * WC);
+    const int pos = u ^ ((int)((j >> 3) & 1) * HW);
+    L[j * WC + pos] = c0 + u < C ? src[vo + j * C + c0 + u] : (T)0;
+  }
+  __syncthreads();
+  const int64_t r0 = rb * rlen, r1 = r0 + rlen < R ? r0 + rlen : R;
+  constexpr int UN = sizeof(T) == 8 ? 4 : 8;  // list entries fetched ahead
+  for (int64_t I = r0 + threadIdx.x; I < r1; I += blockDim.x) {
+    T acc[WC];
+#pragma unroll
+    for (int u = 0; u < WC; ++u) acc[u] = 0;
+    auto apply = [&](int j, T v) {
+      const int sw = (j >> 3) & 1;
+      const T *row = L + (int64_t)j * WC;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T *half = row + (h ^ sw) * HW;
+#pragma unroll
+        for (int u = 0; u < HW; ++u) acc[h * HW + u] += v * half[u];
+      }
+    };
+    int f = 0;
+    for (; f + UN <= nf; f += UN) {
+      int j[UN];
+      T v[UN];
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        j[k] = colT[(int64_t)(f + k) * R + I];
+        v[k] = (T)valT[(int64_t)(f + k) * R + I];
+      }
+#pragma unroll
+      for (int k = 0; k < UN; ++k) apply(j[k], v[k]);
+    }
+    for (; f < nf; ++f) apply(colT[(int64_t)f * R + I], (T)valT[(int64_t)f * R + I]);
+    T *d = dst + vo + I * C + c0;
+#pragma unroll
+    for (int u = 0; u < WC; ++u)
+      if (c0 + u < C) d[u] = acc[u];
+  }
+}
+
+template <typename T, typename V>
+int launch_same_lds(sbci_ctx *ctx, const SpinTables &S, const V *fvalT, int64_t R, int64_t C,
+                    const T *src, T *dst, int nvec) {
+  constexpr int WC = 32 / sizeof(T);
+  const size_t lds = sizeof(T) * (size_t)R * WC;
+  static bool attr = false;
+  if (!attr) {
+    SBCI_HIP(hipFuncSetAttribute((const void *)k_same_lds<T, V, WC>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)(120 * 1024)));
+    attr = true;
+  }
+  const int64_t nstripes = (C + WC - 1) / WC;
+  // enough workgroups for several per CU, each with >= 1024 rows of work
+  int64_t rblocks = (1024 + nstripes - 1) / nstripes;
+  const int64_t rmax = (R + 1023) / 1024;
+  if (rblocks > rmax) rblocks = rmax;
+  if (rblocks < 1) rblocks = 1;
+  const int64_t rlen = (R + rblocks - 1) / rblocks;
+  const int64_t total = rblocks * nstripes;
+  const int64_t per_xcd = (total + 7) / 8;
+  dim3 grid((unsigned)(per_xcd * 8), 1, (unsigned)nvec);
+  k_same_lds<T, V, WC><<<grid, 1024, lds, ctx->stream>>>(S.fcolT, fvalT, S.nf, R, C, src, dst,
+                                                        nstripes, rlen, per_xcd, total);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
 template <typename T, typename V, int VC>
 void launch_same_vc(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, int64_t C,
                     const T *src, T *dst, int nvec, int accumulate) {
@@ -434,6 +528,12 @@ void launch_same_vc(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R
 template <typename T, typename V>
 int launch_same(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, int64_t C,
                 const T *src, T *dst, int nvec, int accumulate) {
+  if (!accumulate && S.fcolT && R >= kSameLdsMinRows && R <= kSameLdsMaxRows) {
+    if constexpr (std::is_same<V, double>::value)
+      return launch_same_lds<T, V>(ctx, S, S.fvalT64, R, C, src, dst, nvec);
+    else
+      return launch_same_lds<T, V>(ctx, S, S.fvalT32, R, C, src, dst, nvec);
+  }
   // widest column tile whose source rows (R x 64 VC elements) stay within
   // about half of one XCD's 4 MB L2
   const double tile1 = (double)R * 64 * sizeof(T);

@@ -120,6 +120,15 @@ __global__ void k_pair_table(int norb, int64_t ns, int64_t ns_pad, int npair, in
   pair[(int64_t)kl * ns_pad + j] = code;
 }
 
+// dst[f][i] = src[i][f] for an [ns][nf] list array
+template <typename T>
+__global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t ns, int nf) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= ns * nf) return;
+  const int64_t i = e / nf, f = e - i * nf;
+  dst[f * ns + i] = src[e];
+}
+
 __device__ __forceinline__ double G4(const double *__restrict__ g, int n, int p, int q, int r, int s) {
   return g[((p * n + q) * n + r) * n + s];
 }
@@ -271,6 +280,17 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
                                                               ctx->h1, ctx->eri, T.fcol, T.fval64,
                                                               T.fval32, T.fdiag);
   SBCI_CHECK_LAUNCH();
+  if (T.ns >= kSameLdsMinRows && T.ns <= kSameLdsMaxRows) {
+    const int64_t ne = T.ns * (int64_t)T.nf;
+    SBCI_HIP(hipMalloc(&T.fcolT, sizeof(int32_t) * ne));
+    SBCI_HIP(hipMalloc(&T.fvalT64, sizeof(double) * ne));
+    SBCI_HIP(hipMalloc(&T.fvalT32, sizeof(float) * ne));
+    const unsigned g = (unsigned)((ne + 255) / 256);
+    k_list_t<int32_t><<<g, 256, 0, st>>>(T.fcol, T.fcolT, T.ns, T.nf);
+    k_list_t<double><<<g, 256, 0, st>>>(T.fval64, T.fvalT64, T.ns, T.nf);
+    k_list_t<float><<<g, 256, 0, st>>>(T.fval32, T.fvalT32, T.ns, T.nf);
+    SBCI_CHECK_LAUNCH();
+  }
   return SBCI_OK;
 }
 
@@ -286,6 +306,9 @@ void free_spin(SpinTables &T) {
   hipFree(T.fval64);
   hipFree(T.fval32);
   hipFree(T.fdiag);
+  hipFree(T.fcolT);
+  hipFree(T.fvalT64);
+  hipFree(T.fvalT32);
   T = SpinTables();
 }
 

@@ -47,8 +47,11 @@ def test_hdiag(n, na, nb):
     ctx.close()
 
 
+# (13, 5, 5) and (13, 6, 5): 1287 / 1716 strings per spin, the row range of
+# the LDS-staged same-spin kernel (both spins, square and rectangular C)
 SIGMA_CASES = [(1, 1, 0), (2, 1, 1), (4, 0, 2), (4, 2, 2), (5, 5, 5), (5, 2, 3), (6, 3, 3),
-               (7, 4, 2), (8, 4, 4), (9, 4, 5), (10, 5, 5), (11, 3, 4), (12, 6, 6)]
+               (7, 4, 2), (8, 4, 4), (9, 4, 5), (10, 5, 5), (11, 3, 4), (12, 6, 6), (13, 5, 5),
+               (13, 6, 5)]
 
 
 @pytest.mark.parametrize("n,na,nb", SIGMA_CASES)
@@ -64,7 +67,7 @@ def test_sigma_f64_parity(n, na, nb):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
-@pytest.mark.parametrize("n,na,nb", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (9, 4, 5)])
+@pytest.mark.parametrize("n,na,nb", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (9, 4, 5), (13, 6, 5)])
 def test_sigma_low_precision_error(n, na, nb, dtype, tol):
     ctx, I = _ctx(n, na, nb, seed=2)
     c = sigma_inputs(4, 1, ctx.ndet)
