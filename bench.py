@@ -33,6 +33,7 @@ import json
 import os
 import sys
 import time
+from math import comb
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -54,11 +55,77 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-form section")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="profiling driver: run only the batching-form section and print it")
     ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
                     help="profiling driver: run --sigma-reps sigma calls of this dtype on the "
                          "workload and one 1 GiB device copy (the counter scale reference), "
                          "print their sizes and exit")
     return ap.parse_args()
+
+
+def roofline(cfg, ndet, kname, kdt, k_ms):
+    """Roofline of one sigma part for one launch (one vector) of the workload.
+
+    opp_mfma: MFMA-bound; algorithmic flops = 2 s^2 per determinant (the
+      minimum count of the D * (pq|rs) * E contraction); the row-stationary
+      MFMA form issues 2 npair s (reported as issue_frac).
+    same_*:   bound by arithmetic on gathered operands ("alu"); algorithmic
+      flops = 2 F per determinant (F same-spin list entries per string).
+    transpose / add_t: HBM-bound; 2 (or 3) vector passes.
+    """
+    n, m = cfg["norb"], cfg["na"]
+    s = m * (n - m + 1)
+    npair = n * (n + 1) // 2
+    nf = 1 + m * (n - m) + comb(m, 2) * comb(n - m, 2)
+    esz = 8 if kdt == "f64" else 4
+    t = k_ms / 1e3
+    if kname == "opp_mfma":
+        r = {"bound": "mfma", "achieved": 2.0 * s * s * ndet / t / 1e12, "peak": PEAK[kdt] / 1e12,
+             "unit": "TFLOP/s"}
+        r["issue_frac"] = 2.0 * npair * s * ndet / t / PEAK[kdt]
+    elif kname.startswith("same"):
+        vpk = PEAK["f64"] if kdt == "f64" else PEAK["f32"]
+        r = {"bound": "alu", "achieved": 2.0 * nf * ndet / t / 1e12, "peak": vpk / 1e12,
+             "unit": "TFLOP/s"}
+    else:
+        passes = 3.0 if kname == "add_t" else 2.0
+        r = {"bound": "hbm", "achieved": passes * esz * ndet / t / 1e9, "peak": PEAK["hbm"] / 1e9,
+             "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = measured_traffic(kname, kdt, cfg)
+    r["kernel"] = f"{kname} ({kdt})"
+    r["ms_per_launch"] = k_ms
+    return r
+
+
+KERNEL_SOURCE = {"opp_mfma": "sigma.hip", "same_alpha": "sigma.hip", "same_beta": "sigma.hip",
+                 "transpose": "sigma.hip", "add_t": "sigma.hip"}
+
+
+def measured_traffic(kname, kdt, cfg):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
+    kernel and workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of
+    known size), or None if there is none or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    name = f"pmc_{kname}_{kdt}_{cfg['name']}.md"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = os.path.join(ROOT, "paper_2603_06101_amd", "csrc", KERNEL_SOURCE[kname])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def batch_section(sb, precision):
@@ -148,11 +215,14 @@ def main():
     import paper_2603_06101_amd as sb
     from workloads import CONFIGS, make_integrals, sigma_inputs
 
-    cfg = CONFIGS[a.workload]
+    cfg = dict(CONFIGS[a.workload], name=a.workload)
     nroots = cfg["nroots"]
     I = make_integrals(cfg["norb"], cfg["rank"], cfg["seed"])
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.only_batch:
+        print(json.dumps(batch_section(sb, a.precision)))
+        return
     if a.kernel_driver:
         ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
         c = torch.from_numpy(sigma_inputs(0, 1, ctx.ndet)[0]).cuda()
@@ -189,6 +259,7 @@ def main():
     ndet = ctx.ndet
     nsig_f64 = sum(r.report["nsigma_f64"] for r in res) / a.steps
     nsig_low = sum(r.report["nsigma_low"] for r in res) / a.steps
+    nsig_bf16 = sum(r.report["nsigma_bf16"] for r in res) / a.steps
     value = ndet * (nsig_f64 + nsig_low) / (ms / 1e3) / 1e9
 
     # reference form: FP64 sigma throughout (outside the timed region)
@@ -212,26 +283,12 @@ def main():
     del c64, out
     ctx.close()
 
-    # dominant kernel of the step: sigma calls x per-kernel time
-    counts = {"f64": nsig_f64}
-    counts[a.precision] = counts.get(a.precision, 0.0) + nsig_low
-    share = {(p, dt): cnt * sig[dt]["kernels_ms"][p] for dt, cnt in counts.items() for p in parts}
+    # dominant kernel of the step: sigma calls per dtype x per-kernel time
+    counts = {"f64": nsig_f64, "f32": nsig_low - nsig_bf16, "bf16": nsig_bf16}
+    share = {(p, dt): cnt * sig[dt]["kernels_ms"][p] for dt, cnt in counts.items() for p in parts
+             if cnt > 0}
     (kname, kdt), _ = max(share.items(), key=lambda kv: kv[1])
-    na_s = cfg["na"] * (cfg["norb"] - cfg["na"] + 1)
-    k_ms = sig[kdt]["kernels_ms"][kname]
-    if kname == "opp_mfma":
-        flops = 2.0 * na_s * na_s * ndet       # minimum opposite-spin flops per determinant: 2 s^2
-        roof = {"bound": "mfma", "achieved": flops / (k_ms / 1e3) / 1e12,
-                "peak": PEAK[kdt] / 1e12, "unit": "TFLOP/s"}
-    else:
-        esz = 8 if kdt == "f64" else 4
-        byts = 2.0 * esz * ndet
-        roof = {"bound": "hbm", "achieved": byts / (k_ms / 1e3) / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = f"{kname} ({kdt})"
-    roof["ms_per_launch"] = k_ms
+    roof = roofline(cfg, ndet, kname, kdt, sig[kdt]["kernels_ms"][kname])
 
     line = {
         "metric": "sigma=H.c Gdet/s per root; time to |dE|<1e-8 Eh, mixed vs FP64 SBCI",
@@ -253,7 +310,7 @@ def main():
                           "speedup": round(t_f64 / (ms / 1e3), 3)},
         "energies": [float(e) for e in last.energies],
         "max_abs_dE_vs_fp64": dE,
-        "nsigma": {"f64": nsig_f64, "low": nsig_low},
+        "nsigma": {"f64": nsig_f64, "f32": nsig_low - nsig_bf16, "bf16": nsig_bf16},
         "sigma": sig,
         "roofline": roof,
     }

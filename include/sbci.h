@@ -84,6 +84,7 @@ typedef struct sbci_report {
   double t_converged[16];     /* seconds from solve start until root i converged        */
   double resid[16];           /* final |z'| (SBCI) or |r| (Davidson) of root i          */
   int64_t peak_vector_bytes;  /* device bytes of solver vectors at the peak             */
+  int64_t nsigma_bf16;        /* of nsigma_low, those with the BF16-MFMA contraction    */
 } sbci_report;
 
 /* One record per SBCI step (filled when tracing is on, sbci_set_trace). */

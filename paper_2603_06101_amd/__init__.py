@@ -52,7 +52,7 @@ class Report(ctypes.Structure):
         ("nsigma_f64", ctypes.c_int64), ("nsigma_low", ctypes.c_int64),
         ("seconds", ctypes.c_double),
         ("t_converged", ctypes.c_double * 16), ("resid", ctypes.c_double * 16),
-        ("peak_vector_bytes", ctypes.c_int64),
+        ("peak_vector_bytes", ctypes.c_int64), ("nsigma_bf16", ctypes.c_int64),
     ]
 
 
@@ -424,7 +424,7 @@ def _report_dict(rep: Report, nroots: int) -> dict:
     return dict(nroots_converged=rep.nroots_converged, nsteps=rep.nsteps, nrestarts=rep.nrestarts,
                 nsigma_f64=rep.nsigma_f64, nsigma_low=rep.nsigma_low, seconds=rep.seconds,
                 t_converged=list(rep.t_converged[:k]), resid=list(rep.resid[:k]),
-                peak_vector_bytes=rep.peak_vector_bytes)
+                peak_vector_bytes=rep.peak_vector_bytes, nsigma_bf16=rep.nsigma_bf16)
 
 
 def decode_table(raw, nstr, s):

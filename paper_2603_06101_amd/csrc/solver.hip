@@ -66,6 +66,7 @@ struct Solver {
   Ritz last;
   int stall = 0;
   double bestE = 0;
+  double last_dz = 0;     // |z'| of the latest step (the residual of a converged root)
   bool done = false;
   bool any_noconv = false;
   // report
@@ -220,6 +221,7 @@ int sigma_phase(sbci_ctx *ctx, Solver &S, const T *c, T *out) {
     return sigma(ctx, c, out, 1, SBCI_F64);
   }
   S.rep.nsigma_low += 1;
+  if (S.phase == SBCI_BF16) S.rep.nsigma_bf16 += 1;
   return sigma(ctx, c, out, 1, S.phase);
 }
 
@@ -283,6 +285,7 @@ int finish_root(sbci_ctx *ctx, Solver &S, double xn, bool second_ok) {
   }
   const double Enew = S.E;
   S.Ec.push_back(Enew);
+  S.rep.resid[std::min(S.alpha, 15)] = S.last_dz;
   S.rep.t_converged[std::min(S.alpha, 15)] = now_s() - S.t0;
   S.rep.nroots_converged = (int)S.Ec.size();
   if ((int)S.Ec.size() >= S.nroots) {
@@ -382,6 +385,7 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
       // N_det = 1) when its residual is below r0; otherwise unrecoverable.
       const double dz0 = std::sqrt(S.h1[0]);
       if (S.phase == SBCI_F64 && dz0 < S.o.r0) {
+        S.last_dz = dz0;
         record(ctx, S, S.E, 0.0, dz0, 0.0, 0.0, 1.0, std::sqrt(N[0]), 1);
         if (info) *info = ctx->trace.back();
         return finish_root(ctx, S, std::sqrt(S.h1[1]), false);
@@ -423,6 +427,7 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
   const double dz = std::sqrt(S.h1[0]);
   const double xn = std::sqrt(S.h1[1]);
   const double dE = std::fabs(Enew - S.E);
+  S.last_dz = dz;
   if (!std::isfinite(dz) || !std::isfinite(xn) || !std::isfinite(Enew))
     return set_error(SBCI_ENUMERIC, "non-finite residual or norm");
   int reason = 0;
