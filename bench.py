@@ -117,7 +117,7 @@ def measured_traffic(kname, kdt, cfg):
     for line in open(path):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
-            fields[k.strip()] = v.strip().strip("`")
+            fields[k.strip()] = v.split()[0].strip("`") if v.split() else ""
     src = os.path.join(ROOT, "paper_2603_06101_amd", "csrc", KERNEL_SOURCE[kname])
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("source_sha256") != sha:
