@@ -93,7 +93,10 @@ def roofline(cfg, ndet, kname, kdt, k_ms):
         r = {"bound": "hbm", "achieved": passes * esz * ndet / t / 1e9, "peak": PEAK["hbm"] / 1e9,
              "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = measured_traffic(kname, kdt, cfg)
+    meas = measured(kname, kdt, cfg)
+    r["traffic"] = meas.get("traffic_bytes_per_launch")
+    if kname == "opp_mfma":
+        r["mfma_busy"] = meas.get("mfma_busy")
     r["kernel"] = f"{kname} ({kdt})"
     r["ms_per_launch"] = k_ms
     return r
@@ -103,16 +106,17 @@ KERNEL_SOURCE = {"opp_mfma": "sigma.hip", "same_alpha": "sigma.hip", "same_beta"
                  "transpose": "sigma.hip", "add_t": "sigma.hip"}
 
 
-def measured_traffic(kname, kdt, cfg):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
-    kernel and workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of
-    known size), or None if there is none or the kernel source has changed
+def measured(kname, kdt, cfg):
+    """Counter figures from the committed rocprofv3 --pmc summary of this
+    kernel and workload: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled
+    by a plain copy of known size) and, for the contraction, the MFMA busy
+    fraction.  Empty if there is no summary or the kernel source has changed
     since the counters were taken."""
     import hashlib
     name = f"pmc_{kname}_{kdt}_{cfg['name']}.md"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
         if ":" in line and line.startswith("- "):
@@ -121,11 +125,14 @@ def measured_traffic(kname, kdt, cfg):
     src = os.path.join(ROOT, "paper_2603_06101_amd", "csrc", KERNEL_SOURCE[kname])
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("source_sha256") != sha:
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for key in ("traffic_bytes_per_launch", "mfma_busy"):
+        try:
+            out[key] = float(fields[key])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def batch_section(sb, precision):
