@@ -38,6 +38,12 @@ struct SpinTables {
   Ent *tab = nullptr;       // [ns][s]
   uint32_t *pair = nullptr; // [npair_pad][ns_pad] scatter codes
   int64_t ns_pad = 0;       // ns rounded up to 16 (pair-table row stride)
+  // The pair table regrouped for the opposite-spin kernel: for 16-row tile u,
+  // lane group g and column J, the four codes a lane scatters, in one 16-byte
+  // load.  quad_r: rows u*16 + 4g + r (FP32 / BF16 MFMA output layout);
+  // quad_s: rows u*16 + g + 4r (FP64 layout).  [npair_pad / 16][4][ns_pad].
+  uint4 *quad_r = nullptr;
+  uint4 *quad_s = nullptr;
   int32_t *fcol = nullptr;  // [ns][nf] same-spin list columns
   double *fval64 = nullptr; // [ns][nf] FP64 values
   float *fval32 = nullptr;  // [ns][nf] FP32 values

@@ -148,7 +148,7 @@ template <typename M, typename T, int MG, int KS, bool AREG, int NW>
 __global__ __launch_bounds__(64 * NW) void k_opp(
     int64_t nsa, int64_t nsb, int64_t nsb_pad, int s, int npair, int ngroups, int nkc,
     const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
-    const uint32_t *__restrict__ pairb, const T *__restrict__ c, T *__restrict__ sigma) {
+    const uint4 *__restrict__ quads, const T *__restrict__ c, T *__restrict__ sigma) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
@@ -238,14 +238,10 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
       for (int grp = 0; grp < ngroups; ++grp) {
-        uint32_t code[MG][4];
+        uint4 code[MG];
 #pragma unroll
         for (int u = 0; u < MG; ++u)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const uint32_t row = (uint32_t)(grp * GROWS + u * 16 + M::orow(g, r));
-            code[u][r] = pairb[row * pstride + J];
-          }
+          code[u] = quads[((uint32_t)(grp * MG + u) * 4u + (uint32_t)g) * pstride + J];
         if (grp == 0) {
           const uint32_t Jn = (uint32_t)((jt + NW) * 16 + li);
           const uint32_t jn = Jn < nsb32 ? Jn : nsb32 - 1;
@@ -270,16 +266,21 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
               a = M::load_a(&Ws[(grp * GROWS + u * 16 + li) * LDW + ks * M::KSTEP + g * M::KPL]);
             out[u] = M::mma(a, b[ks], out[u]);
           }
+        // only lanes with a valid code scatter (the others are masked off
+        // and cost no LDS bandwidth)
 #pragma unroll
-        for (int u = 0; u < MG; ++u)
+        for (int u = 0; u < MG; ++u) {
+          const uint32_t cds[4] = {code[u].x, code[u].y, code[u].z, code[u].w};
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const uint32_t cd = code[u][r];
-            const uint32_t tgt = cd == kInvalid ? nsb32 + (uint32_t)lane : cd >> 1;
-            Acc v = (Acc)out[u][r];
-            if (cd & 1u) v = -v;
-            atomicAdd(&acc[tgt], v);
+            const uint32_t cd = cds[r];
+            if (cd != kInvalid) {
+              Acc v = (Acc)out[u][r];
+              if (cd & 1u) v = -v;
+              atomicAdd(&acc[cd >> 1], v);
+            }
           }
+        }
       }
     }
   }
@@ -350,7 +351,8 @@ void launch_opp_k(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, c
   const SpinTables &A = ctx->A, &B = ctx->B;
   constexpr int NW = 8;
   k_opp<M, T, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
-      A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab, B.pair, c, out);
+      A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab,
+      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, out);
 }
 
 template <typename M, typename T, int MG>

@@ -120,6 +120,23 @@ __global__ void k_pair_table(int norb, int64_t ns, int64_t ns_pad, int npair, in
   pair[(int64_t)kl * ns_pad + j] = code;
 }
 
+// Pair-table quads: out[(u*4 + g) * ns_pad + J] = codes of rows
+// u*16 + orow(g, r), r = 0..3, with orow = g + 4r (GP4R) or 4g + r.
+template <bool GP4R>
+__global__ void k_pair_quads(const uint32_t *__restrict__ pair, int64_t ns_pad, int ntiles,
+                             uint4 *__restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ntiles * 4 * ns_pad) return;
+  const int64_t J = e % ns_pad, ug = e / ns_pad;
+  const int g = (int)(ug & 3), u = (int)(ug >> 2);
+  uint32_t c[4];
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = u * 16 + (GP4R ? g + 4 * r : 4 * g + r);
+    c[r] = pair[row * ns_pad + J];
+  }
+  out[e] = make_uint4(c[0], c[1], c[2], c[3]);
+}
+
 // dst[f][i] = src[i][f] for an [ns][nf] list array
 template <typename T>
 __global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t ns, int nf) {
@@ -275,6 +292,16 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
   k_pair_table<<<dim3(gxp, ctx->npair_pad), bs, 0, st>>>(n, T.ns, T.ns_pad, ctx->npair,
                                                          ctx->npair_pad, T.str, ctx->binom, T.pair);
   SBCI_CHECK_LAUNCH();
+  {
+    const int ntiles = ctx->npair_pad / 16;
+    const int64_t nq = (int64_t)ntiles * 4 * T.ns_pad;
+    SBCI_HIP(hipMalloc(&T.quad_r, sizeof(uint4) * nq));
+    SBCI_HIP(hipMalloc(&T.quad_s, sizeof(uint4) * nq));
+    const unsigned gq = (unsigned)((nq + 255) / 256);
+    k_pair_quads<false><<<gq, 256, 0, st>>>(T.pair, T.ns_pad, ntiles, T.quad_r);
+    k_pair_quads<true><<<gq, 256, 0, st>>>(T.pair, T.ns_pad, ntiles, T.quad_s);
+    SBCI_CHECK_LAUNCH();
+  }
   const int fbs = 64;  // heavy per-thread loops: small blocks
   k_flist<<<(unsigned)((T.ns + fbs - 1) / fbs), fbs, 0, st>>>(n, m, T.ns, T.nf, T.str, ctx->binom,
                                                               ctx->h1, ctx->eri, T.fcol, T.fval64,
@@ -306,6 +333,8 @@ void free_spin(SpinTables &T) {
   hipFree(T.fval64);
   hipFree(T.fval32);
   hipFree(T.fdiag);
+  hipFree(T.quad_r);
+  hipFree(T.quad_s);
   hipFree(T.fcolT);
   hipFree(T.fvalT64);
   hipFree(T.fvalT32);
