@@ -56,6 +56,7 @@ struct BInst {
   int64_t ndet, ns_pad_b;
   const Ent *tab_a;
   const uint32_t *pair_b;
+  const uint4 *quad_r_b, *quad_s_b;  // pair codes as per-lane quads (see internal.h)
   const double *H64_a, *H64_b;  // dense same-spin operators [ns][ns] (symmetric)
   const float *H32_a, *H32_b;
   const double *W64;
@@ -339,21 +340,45 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
       }
     }
     for (int j = lane; j < nsb; j += 64) sigw[j] = 0;
-    for (int jt = 0; jt < njt; ++jt) {
-      const int j = jt * 16 + li;
-      const uint32_t jc = (uint32_t)(j < nsb ? j : nsb - 1);
-      Frag bf[KSMAX];
+    // column tile jt + 1's B fragments and scatter codes are fetched before
+    // tile jt's MFMAs and scatter, so their latency overlaps that work
+    // (past the last tile a clamped, valid column is fetched and not used)
+    const uint4 *quads = std::is_same<typename M::A, double>::value ? I.quad_s_b : I.quad_r_b;
+    const uint32_t qs = (uint32_t)I.ns_pad_b;
+    Frag bn[KSMAX];
+    uint4 qn[NPT];
+    {
+      const uint32_t jc = (uint32_t)(li < nsb ? li : nsb - 1);
 #pragma unroll
-      for (int ks = 0; ks < KSMAX; ++ks) bf[ks] = M::load_b(c, boff[ks], jc);
+      for (int ks = 0; ks < KSMAX; ++ks) bn[ks] = M::load_b(c, boff[ks], jc);
+#pragma unroll
+      for (int u = 0; u < NPT; ++u) qn[u] = quads[((uint32_t)u * 4u + (uint32_t)g) * qs + (uint32_t)li];
+    }
+    for (int jt = 0; jt < njt; ++jt) {
+      Frag bf[KSMAX];
+      uint4 q[NPT];
+#pragma unroll
+      for (int ks = 0; ks < KSMAX; ++ks) bf[ks] = bn[ks];
+#pragma unroll
+      for (int u = 0; u < NPT; ++u) q[u] = qn[u];
+      {
+        const int jn = (jt + 1) * 16 + li;
+        const uint32_t jc = (uint32_t)(jn < nsb ? jn : nsb - 1);
+        const uint32_t jq = (uint32_t)(jn < (int)qs ? jn : (int)qs - 1);
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) bn[ks] = M::load_b(c, boff[ks], jc);
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) qn[u] = quads[((uint32_t)u * 4u + (uint32_t)g) * qs + jq];
+      }
 #pragma unroll
       for (int u = 0; u < NPT; ++u) {
         Out o = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < KSMAX; ++ks) o = M::mma(af[u][ks], bf[ks], o);
+        const uint32_t cds[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int kl = u * 16 + M::orow(g, r);
-          const uint32_t code = I.pair_b[(int64_t)kl * I.ns_pad_b + j];
+          const uint32_t code = cds[r];
           if (code != kInvalid) {
             const double val = (double)o[r];
             atomicAdd(&sigw[code >> 1], (code & 1u) ? -val : val);
@@ -1357,6 +1382,8 @@ int prepare(sbci_batch *b, const int *nroots, int precision) {
     I.ns_pad_b = c->B.ns_pad;
     I.tab_a = c->A.tab;
     I.pair_b = c->B.pair;
+    I.quad_r_b = c->B.quad_r;
+    I.quad_s_b = c->B.quad_s;
     I.H64_a = b->la[i].d64;
     I.H64_b = b->lb[i].d64;
     I.H32_a = b->la[i].d32;
