@@ -23,6 +23,9 @@ Reported (one JSON line):
   batch        the batching form on its own workload (512 instances of
                CAS(6..10), 1-3 roots each): autotuned persistent-kernel
                graph launch, makespan FP64 vs mixed, per-instance span;
+  cas6, cas10, cas16  the other workloads: launch latency (CAS(6,6)),
+               SBCI1 vs Davidson over 10 seeds (CAS(10,10)), and the
+               165.6 M-determinant ground state, mixed vs FP64 (CAS(16,16));
   cpu_baseline the CPU oracle's plain FP64 string sigma on the host cores,
                on a bounded sample of determinant rows.
 """
@@ -55,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-form section")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the cas6 / cas10 / cas16 sections")
     ap.add_argument("--only-batch", action="store_true",
                     help="profiling driver: run only the batching-form section and print it")
     ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
@@ -132,6 +137,100 @@ def measured(kname, kdt, cfg):
             out[key] = float(fields[key])
         except (KeyError, ValueError):
             pass
+    return out
+
+
+def small_sections(sb, stream):
+    """cas6: launch-latency regime (us per sigma and per step, noise start);
+    cas10 seeds 0..9: FP64 SBCI1 vs Davidson on the same sigma (time, sigma
+    calls, peak vector bytes)."""
+    import numpy as np
+    import torch
+
+    from workloads import CONFIGS, make_integrals, start_noise
+    out = {}
+    c6 = CONFIGS["cas6"]
+    I = make_integrals(c6["norb"], c6["rank"], c6["seed"])
+    ctx = sb.Context(6, 3, 3, I.h1, I.eri, stream=stream)
+    x0 = np.zeros(ctx.ndet)
+    x0[0] = 1.0
+    x0 = x0 + 1e-3 * start_noise(6, c6["rank"], c6["seed"], ctx.ndet)
+    c = torch.from_numpy(x0).cuda()
+    o = ctx.sigma(c)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(200):
+        ctx.sigma(c, out=o)
+    torch.cuda.synchronize()
+    us_sigma = (time.perf_counter() - t) / 200 * 1e6
+    ctx.solve(1, tol=1e-10, x0=x0, want_vectors=False)
+    r = ctx.solve(1, tol=1e-10, x0=x0, want_vectors=False)
+    out["cas6"] = {"ndet": ctx.ndet, "us_per_sigma": round(us_sigma, 1),
+                   "solve_ms": round(r.report["seconds"] * 1e3, 2), "steps": r.report["nsteps"],
+                   "us_per_step": round(r.report["seconds"] / max(1, r.report["nsteps"]) * 1e6, 1),
+                   "energy": float(r.energies[0])}
+    ctx.close()
+    rows = []
+    for seed in range(10):
+        I = make_integrals(10, 20, seed)
+        ctx = sb.Context(10, 5, 5, I.h1, I.eri, stream=stream)
+        if seed == 0:
+            ctx.solve(3, tol=1e-10, want_vectors=False)
+        s1 = ctx.solve(3, tol=1e-10, want_vectors=False)
+        dv = ctx.davidson(3, tol=1e-10, want_vectors=False)
+        rows.append((s1.report["seconds"], dv.report["seconds"], s1.report["nsigma_f64"],
+                     dv.report["nsigma_f64"], s1.report["peak_vector_bytes"],
+                     dv.report["peak_vector_bytes"], abs(s1.energies[0] - dv.energies[0])))
+        ctx.close()
+    a = np.array(rows)
+    out["cas10"] = {
+        "ndet": 63504, "roots": 3, "seeds": 10,
+        "sbci1_ms_median": round(float(np.median(a[:, 0])) * 1e3, 2),
+        "davidson_ms_median": round(float(np.median(a[:, 1])) * 1e3, 2),
+        "sbci1_sigma_median": float(np.median(a[:, 2])), "davidson_sigma_median": float(np.median(a[:, 3])),
+        "sbci1_peak_vector_MB": round(float(np.median(a[:, 4])) / 1e6, 2),
+        "davidson_peak_vector_MB": round(float(np.median(a[:, 5])) / 1e6, 2),
+        "max_root0_diff_Eh": float(np.max(a[:, 6])),
+    }
+    return out
+
+
+def cas16_section(sb, stream, precision):
+    """cas16 (165,636,900 determinants, ground state): sigma per dtype and the
+    time to 1e-8 Eh, mixed vs FP64."""
+    import torch
+
+    from workloads import CONFIGS, make_integrals
+    cf = CONFIGS["cas16"]
+    I = make_integrals(cf["norb"], cf["rank"], cf["seed"])
+    t = time.perf_counter()
+    ctx = sb.Context(16, 8, 8, I.h1, I.eri, stream=stream)
+    torch.cuda.synchronize()
+    out = {"ndet": ctx.ndet, "create_s": round(time.perf_counter() - t, 3), "sigma": {}}
+    parts = ["same_alpha", "opp_mfma", "transpose", "same_beta", "add_t"]
+    c = torch.randn(ctx.ndet, dtype=torch.float32, device="cuda")
+    for dt in ("bf16", "f32", "f64"):
+        x = c.double() if dt == "f64" else c
+        o, _ = ctx.sigma_timed(x, dt)
+        o, ms = ctx.sigma_timed(x, dt, out=o)
+        out["sigma"][dt] = {"gdet_per_s": round(ctx.ndet / (sum(ms) / 1e3) / 1e9, 3),
+                            "kernels_ms": dict(zip(parts, [round(v, 3) for v in ms]))}
+        del o, x
+    del c
+    res = {}
+    for prec in (precision, "f64"):
+        t = time.perf_counter()
+        r = ctx.solve(1, tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+        torch.cuda.synchronize()
+        res[prec] = (time.perf_counter() - t, r)
+    ctx.close()
+    tm, rm = res[precision]
+    t64, r64 = res["f64"]
+    out["time_to_1e8_s"] = {"mixed": round(tm, 3), "fp64": round(t64, 3), "speedup": round(t64 / tm, 3)}
+    out["nsigma"] = {"f64": rm.report["nsigma_f64"], "low": rm.report["nsigma_low"],
+                     "bf16": rm.report["nsigma_bf16"]}
+    out["abs_dE_vs_fp64"] = float(abs(rm.energies[0] - r64.energies[0]))
+    out["peak_vector_GB"] = round(rm.report["peak_vector_bytes"] / 1e9, 2)
     return out
 
 
@@ -325,6 +424,9 @@ def main():
     }
     if not a.no_batch:
         line["batch"] = batch_section(sb, a.precision)
+    if not a.no_configs:
+        line.update(small_sections(sb, stream))
+        line["cas16"] = cas16_section(sb, stream, a.precision)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
     print(json.dumps(line))

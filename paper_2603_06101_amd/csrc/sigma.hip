@@ -374,7 +374,8 @@ void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, co
   } else {
     if constexpr (std::is_same<typename M::A, double>::value) {
       if (p.KS == 4) launch_opp_k<M, T, MG, 4, false>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 7, false>(ctx, p, grid, Wf, Wd, c, out);
+      else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false>(ctx, p, grid, Wf, Wd, c, out);
+      else launch_opp_k<M, T, MG, 14, false>(ctx, p, grid, Wf, Wd, c, out);
     } else {
       if (p.KS == 8) launch_opp_k<M, T, MG, 8, false>(ctx, p, grid, Wf, Wd, c, out);
       else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false>(ctx, p, grid, Wf, Wd, c, out);
@@ -391,7 +392,7 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
     return set_error(SBCI_EINVAL, "opposite-spin sigma: N_det must be below 2^31");
   // K tiles (k-steps per chunk) offered to the planner; the register budget
   // of two waves per SIMD bounds them (B fragments are double-buffered)
-  static const int ks_d[2] = {4, 7};
+  static const int ks_d[3] = {4, 7, 14};
   static const int ks_f[3] = {8, 9, 14};
   static const int ks_b[3] = {1, 2, 3};
   static const int mg_d[3] = {4, 5, 7};
@@ -400,7 +401,7 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   if (M::KPL == 8)
     SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_b, 3, p));
   else if (std::is_same<typename M::A, double>::value)
-    SBCI_TRY(plan_opp<M>(ctx, mg_d, 3, ks_d, 2, p));
+    SBCI_TRY(plan_opp<M>(ctx, mg_d, 3, ks_d, 3, p));
   else
     SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_f, 3, p));
   const float *Wf = nullptr;
