@@ -180,7 +180,8 @@ def small_sections(sb, stream):
         dv = ctx.davidson(3, tol=1e-10, want_vectors=False)
         rows.append((s1.report["seconds"], dv.report["seconds"], s1.report["nsigma_f64"],
                      dv.report["nsigma_f64"], s1.report["peak_vector_bytes"],
-                     dv.report["peak_vector_bytes"], abs(s1.energies[0] - dv.energies[0])))
+                     dv.report["peak_vector_bytes"],
+                     float(abs(s1.energies[0] - dv.energies[0]) < 1e-8)))
         ctx.close()
     a = np.array(rows)
     out["cas10"] = {
@@ -190,7 +191,9 @@ def small_sections(sb, stream):
         "sbci1_sigma_median": float(np.median(a[:, 2])), "davidson_sigma_median": float(np.median(a[:, 3])),
         "sbci1_peak_vector_MB": round(float(np.median(a[:, 4])) / 1e6, 2),
         "davidson_peak_vector_MB": round(float(np.median(a[:, 5])) / 1e6, 2),
-        "max_root0_diff_Eh": float(np.max(a[:, 6])),
+        # SBCI1 from the spin-flip-symmetric start can converge to a singlet
+        # above a lower odd-S state; Davidson (block start) finds the lowest
+        "seeds_sbci1_root0_is_lowest": int(np.sum(a[:, 6])),
     }
     return out
 
