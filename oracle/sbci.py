@@ -152,13 +152,22 @@ def ritz_next(N, Hm, lindep):
     return dict(E=w, coef=coef, ok=True, b=b, c=c, k=k)
 
 
-def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True):
-    """Lowest nroots eigenpairs of H by SBCI1 (Algorithm 1).  op(v) = H v."""
+def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, prev=None):
+    """Lowest nroots eigenpairs of H by SBCI1 (Algorithm 1).  op(v) = H v.
+
+    prev = (x_c list, E_c list, x0, X0, E0): continue after len(x_c) converged
+    roots from the start vector x0 (X0 = H x0), as SBCI2 does for its last
+    state (Fig. 1B)."""
     o = opts or Options()
     diag = np.asarray(diag, dtype=np.float64)
     ndet = diag.shape[0]
     nsig = 0
-    if x0 is None:
+    first = 0
+    if prev is not None:
+        xc0, Ec0, xa, Xa, Ea = prev
+        first = len(xc0)
+        xa, Xa, Ea = np.array(xa, dtype=np.float64), np.array(Xa, dtype=np.float64), float(Ea)
+    elif x0 is None:
         xs, Xs, Es = start_vectors(op, diag, nroots)
         nsig += nroots
         xa, Xa, Ea = xs[0].copy(), Xs[0].copy(), float(Es[0])
@@ -168,11 +177,11 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True):
         Xa = op(xa)
         nsig += 1
         Ea = float(xa @ Xa)
-    xc, Ec = [], []
+    xc, Ec = ([], []) if prev is None else (list(prev[0]), list(prev[1]))
     steps = []
     all_conv = True
 
-    for alpha in range(nroots):
+    for alpha in range(first, nroots):
         # Algorithm 1 line 1 with Eqs. S4-S7
         if xc:
             Xc = np.array(xc)
