@@ -72,6 +72,8 @@ typedef struct sbci_opts {
   const double *x0;           /* host [ndet] start vector for root 0, or NULL for the
                                  Section S1.1 start from the lowest diagonal elements */
   double bf16_eps0, bf16_r0;  /* SBCI_BF16: BF16 phase hands over to FP32 at these   */
+  int max_cycle2;             /* SBCI2 steps per segment before a forced restart (10,
+                                 Section S2.5)                                          */
 } sbci_opts;
 
 typedef struct sbci_report {
@@ -175,6 +177,17 @@ int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max);
  * thresholds as sbci_solve; always FP64. */
 int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
                   double *energies, double *dev_vecs, sbci_report *rep);
+
+/* SBCI2 (Algorithm 2; Supplementary Sections S2.1-S2.5): the states of a
+ * pair (alpha, alpha + 1) are updated together, a 6 x 6 Rayleigh-Ritz problem
+ * in the canonically orthonormalised span of x, y, z of both states per step
+ * (two sigma applications); state alpha is accepted on Eq. S127, restarts
+ * follow Eqs. S130a-c and max_cycle2; the highest state is finished by SBCI1
+ * (Fig. 1B).  Start vectors: Section S2.2.  Arguments, outputs, errors and
+ * the trace as for sbci_solve; opt->precision must be SBCI_F64 and opt->x0
+ * is ignored.  energies[i] / dev_vecs row i are state i. */
+int sbci_solve2(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
+                double *energies, double *dev_vecs, sbci_report *rep);
 
 
 /* ------------------------------------------------------------------------

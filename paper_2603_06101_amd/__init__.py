@@ -43,6 +43,7 @@ class Opts(ctypes.Structure):
         ("max_space", ctypes.c_int),
         ("x0", ctypes.POINTER(ctypes.c_double)),
         ("bf16_eps0", ctypes.c_double), ("bf16_r0", ctypes.c_double),
+        ("max_cycle2", ctypes.c_int),
     ]
 
 
@@ -123,6 +124,7 @@ SIGNATURES = [
     ("sbci_set_trace", _I, [_P, _I]),
     ("sbci_trace", _I, [_P, ctypes.POINTER(StepInfo), _I]),
     ("sbci_davidson", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
+    ("sbci_solve2", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_batch_create", _I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     ("sbci_batch_destroy", _I, [_P]),
     ("sbci_batch_ndet", _I64, [_P, _I]),
@@ -281,6 +283,10 @@ class Context:
 
     def davidson(self, nroots, tol=1e-10, opts=None, want_vectors=True):
         return self._run(lib().sbci_davidson, nroots, tol, opts, want_vectors)
+
+    def solve2(self, nroots, tol=1e-10, opts=None, want_vectors=True):
+        """SBCI2 (pairs of states; FP64) for the lowest nroots states."""
+        return self._run(lib().sbci_solve2, nroots, tol, opts, want_vectors)
 
     def begin(self, nroots, tol=1e-10, opts=None, x0=None):
         o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))

@@ -13,6 +13,8 @@ int solver_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report
 void solver_free(sbci_ctx *ctx);
 int davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
              double *dev_vecs, sbci_report *rep);
+int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
+                double *dev_vecs, sbci_report *rep);
 
 namespace {
 thread_local std::string g_err;
@@ -103,6 +105,7 @@ void sbci_default_opts(sbci_opts *o) {
   o->x0 = nullptr;
   o->bf16_eps0 = 1e-5;
   o->bf16_r0 = 1e-2;
+  o->max_cycle2 = 10;
 }
 
 const char *sbci_last_error(void) { return g_err.c_str(); }
@@ -284,6 +287,12 @@ int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, d
                   double *dev_vecs, sbci_report *rep) {
   if (!ctx || !energies) return set_error(SBCI_EINVAL, "NULL argument");
   return davidson(ctx, nroots, tol, opt, energies, dev_vecs, rep);
+}
+
+int sbci_solve2(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
+                double *dev_vecs, sbci_report *rep) {
+  if (!ctx || !energies) return set_error(SBCI_EINVAL, "NULL argument");
+  return sbci2_solve(ctx, nroots, tol, opt, energies, dev_vecs, rep);
 }
 
 }  // extern "C"

@@ -159,5 +159,10 @@ int deflate(sbci_ctx *ctx, int64_t n, T *w, const T *x, const T *y, const T *con
             const double *d_coef, double *out);
 template <typename T>
 int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const T *Z, double *out);
+// Residual of one state: w = ((X - E x) * inv) / (D - E0) (|D - E0| floored),
+// out[0] = |(X - E x) * inv|^2, out[1 + j] = xc_j . w.
+template <typename T>
+int resid(sbci_ctx *ctx, int64_t n, const T *x, const T *X, const T *D, double E, double inv,
+          double E0, double floor, const T *const *xc, int nconv, T *w, double *out);
 
 }  // namespace sbci

@@ -858,3 +858,525 @@ int davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double
 }
 
 }  // namespace sbci
+
+// ------------------------------------------------------------ SBCI2
+// SBCI2 (Algorithm 2; Sections S2.1-S2.5).  The states of a pair
+// (alpha, alpha + 1) advance together: per step both preconditioned,
+// deflated residuals get their sigma images in one two-vector sigma call;
+// the overlap and H matrices of the basis (x^a, x^a+1, [y^a, y^a+1,]
+// z^a, z^a+1) come from FP64 dot passes; the host orthonormalises the basis
+// canonically, solves the small eigenproblem and derives A, B, C (Eqs. S93,
+// S112-S121); linear-combination passes update y, Y, x, X (Eqs. S94-S97,
+// S122-S125); one fused pass per state forms the next residual.  State alpha
+// is accepted on Eq. S127; the pair restarts on S130a-c or after max_cycle
+// (10) steps.  The highest state is finished by SBCI1 (Fig. 1B).
+namespace sbci {
+namespace {
+
+struct Pair {
+  double *x[2] = {}, *X[2] = {}, *y[2] = {}, *Y[2] = {};
+  double *z = nullptr, *Z = nullptr;  // [2][n] each (one sigma call, nvec = 2)
+  double *s[2] = {}, *S[2] = {};      // scratch: Ritz vectors of a restart and their images
+  double *dev = nullptr;              // reduction results
+  std::vector<double *> xs, Xs;       // start vectors of Eq. S75 and their images (S76)
+  std::vector<double> Es;
+  size_t bytes = 0;
+};
+
+void free_pair(Pair &P) {
+  for (int i = 0; i < 2; ++i) {
+    hipFree(P.x[i]);
+    hipFree(P.X[i]);
+    hipFree(P.y[i]);
+    hipFree(P.Y[i]);
+    hipFree(P.s[i]);
+    hipFree(P.S[i]);
+  }
+  hipFree(P.z);
+  hipFree(P.Z);
+  hipFree(P.dev);
+  for (auto p : P.xs) hipFree(p);
+  for (auto p : P.Xs) hipFree(p);
+}
+
+int dmalloc(Pair &P, double **p, size_t count) {
+  SBCI_HIP(hipMalloc(p, sizeof(double) * count));
+  P.bytes += sizeof(double) * count;
+  return SBCI_OK;
+}
+
+// host copies of dots a . b_j (j < nb)
+int dots_h(sbci_ctx *ctx, Pair &P, int64_t n, const double *a, const double *const *bs, int nb,
+           double *host) {
+  SBCI_TRY(dots<double>(ctx, n, a, bs, nb, P.dev));
+  SBCI_HIP(hipMemcpyAsync(host, P.dev, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  return SBCI_OK;
+}
+
+// Section S2.2 / Eqs. S74-S76: the k lowest diagonal determinants, H in
+// their span diagonalised; xs[i], Xs[i] = H xs[i], Es[i].
+int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
+  const int64_t n = ctx->ndet;
+  std::vector<int64_t> idx;
+  SBCI_TRY(lowest_diagonal(ctx, k, idx));
+  double *e = nullptr, *He = nullptr, *sub = nullptr;
+  int64_t *didx = nullptr;
+  SBCI_HIP(hipMalloc(&e, sizeof(double) * n * k));
+  SBCI_HIP(hipMalloc(&He, sizeof(double) * n * k));
+  SBCI_HIP(hipMalloc(&sub, sizeof(double) * k * k));
+  SBCI_HIP(hipMalloc(&didx, sizeof(int64_t) * k));
+  SBCI_HIP(hipMemsetAsync(e, 0, sizeof(double) * n * k, ctx->stream));
+  SBCI_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, ctx->stream));
+  k_unit<<<1, 64, 0, ctx->stream>>>(e, n, didx, k, nullptr);
+  SBCI_CHECK_LAUNCH();
+  SBCI_TRY(sigma(ctx, e, He, k, SBCI_F64));                                  // Eq. S74
+  S.rep.nsigma_f64 += k;
+  k_gather_sub<<<1, dim3(16, 16), 0, ctx->stream>>>(He, n, didx, k, sub);
+  SBCI_CHECK_LAUNCH();
+  std::vector<double> Hs((size_t)k * k), w(k), U((size_t)k * k);
+  SBCI_HIP(hipMemcpyAsync(Hs.data(), sub, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < i; ++j) Hs[i * k + j] = Hs[j * k + i] = 0.5 * (Hs[i * k + j] + Hs[j * k + i]);
+  jacobi_eigh<16>(k, Hs.data(), w.data(), U.data());
+  std::vector<const double *> es(k), Hes(k);
+  for (int i = 0; i < k; ++i) {
+    es[i] = e + (int64_t)i * n;
+    Hes[i] = He + (int64_t)i * n;
+  }
+  P.xs.assign(k, nullptr);
+  P.Xs.assign(k, nullptr);
+  P.Es.assign(w.begin(), w.end());
+  for (int a = 0; a < k; ++a) {
+    std::vector<double> cf(k);
+    for (int i = 0; i < k; ++i) cf[i] = U[i * k + a];
+    SBCI_TRY(dmalloc(P, &P.xs[a], n));
+    SBCI_TRY(dmalloc(P, &P.Xs[a], n));
+    SBCI_TRY(lincomb<double>(ctx, n, P.xs[a], es.data(), cf.data(), k, 0.0));   // Eq. S75
+    SBCI_TRY(lincomb<double>(ctx, n, P.Xs[a], Hes.data(), cf.data(), k, 0.0));  // Eq. S76
+  }
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  hipFree(e);
+  hipFree(He);
+  hipFree(sub);
+  hipFree(didx);
+  return SBCI_OK;
+}
+
+// v <- v - sum_j x_c^j (x_c^j . v), V <- V - sum_j E_c^j x_c^j (x_c^j . v)   (Eqs. S77-S78)
+int project_off(sbci_ctx *ctx, Solver &S, Pair &P, double *v, double *V) {
+  const int nc = (int)S.Ec.size();
+  if (nc == 0) return SBCI_OK;
+  std::vector<const double *> xcp(S.xc64.begin(), S.xc64.end());
+  double d[16];
+  SBCI_TRY(dots_h(ctx, P, S.n, v, xcp.data(), nc, d));
+  double cx[16], cX[16];
+  for (int j = 0; j < nc; ++j) {
+    cx[j] = -d[j];
+    cX[j] = -S.Ec[j] * d[j];
+  }
+  SBCI_TRY(lincomb<double>(ctx, S.n, v, xcp.data(), cx, nc, 1.0));
+  SBCI_TRY(lincomb<double>(ctx, S.n, V, xcp.data(), cX, nc, 1.0));
+  return SBCI_OK;
+}
+
+// Canonical orthogonalisation and Rayleigh-Ritz in an m-vector basis
+// (Eqs. S83-S87, S103-S107): returns false if fewer than two basis vectors
+// survive the 1e-14 overlap cut.  w ascending, Vp[k * r + i] = coefficient
+// of basis vector k in Ritz vector i (r kept vectors).
+bool canonical_ritz(int m, const double *Sm, const double *Hm, double lindep, double *w, double *Vp,
+                    int &r) {
+  double s[6], U[36];
+  jacobi_eigh<6>(m, Sm, s, U);
+  int keep[6];
+  r = 0;
+  for (int i = 0; i < m; ++i)
+    if (s[i] > lindep) keep[r++] = i;
+  if (r < 2) return false;
+  double Pm[36];  // m x r
+  for (int k = 0; k < m; ++k)
+    for (int j = 0; j < r; ++j) Pm[k * r + j] = U[k * m + keep[j]] / std::sqrt(s[keep[j]]);
+  double Hp[36];
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double acc = 0;
+      for (int k = 0; k < m; ++k)
+        for (int l = 0; l < m; ++l) acc += Pm[k * r + a] * Hm[k * m + l] * Pm[l * r + b];
+      Hp[a * r + b] = acc;
+    }
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < a; ++b) Hp[a * r + b] = Hp[b * r + a] = 0.5 * (Hp[a * r + b] + Hp[b * r + a]);
+  double V[36];
+  jacobi_eigh<6>(r, Hp, w, V);
+  for (int k = 0; k < m; ++k)
+    for (int i = 0; i < r; ++i) {
+      double acc = 0;
+      for (int j = 0; j < r; ++j) acc += Pm[k * r + j] * V[j * r + i];
+      Vp[k * r + i] = acc;  // V' = P V
+    }
+  return true;
+}
+
+struct PairCoef {
+  double k[2], A01, A10, B[2][2], C[2][2];
+};
+
+// Eqs. S92-S93 (first step; basis x^a, x^a+1, z^a, z^a+1)
+bool pair_coef_first(const double *Vp, int r, double lindep, PairCoef &c) {
+  auto V = [&](int k, int i) { return Vp[k * r + i]; };
+  const double d0 = V(0, 0), d1 = V(1, 1);
+  if (std::fabs(d0) < lindep || std::fabs(d1) < lindep) return false;
+  c.k[0] = 1.0 / d0;
+  c.k[1] = 1.0 / d1;
+  c.A01 = V(1, 0) / d0;
+  c.A10 = V(0, 1) / d1;
+  c.B[0][0] = c.B[1][1] = 1.0;
+  c.B[0][1] = c.B[1][0] = 0.0;
+  c.C[0][0] = -V(2, 0) / d0;
+  c.C[0][1] = -V(3, 0) / d0;
+  c.C[1][0] = -V(2, 1) / d1;
+  c.C[1][1] = -V(3, 1) / d1;
+  return true;
+}
+
+// Eqs. S112-S121 (later steps; basis x^a, x^a+1, y^a, y^a+1, z^a, z^a+1)
+bool pair_coef_next(const double *Vp, int r, double lindep, PairCoef &c) {
+  auto V = [&](int k, int i) { return Vp[k * r + i]; };
+  if (std::fabs(V(2, 0)) < lindep || std::fabs(V(3, 1)) < lindep) return false;
+  c.A01 = V(1, 0) / V(2, 0);                                   // S116
+  c.A10 = V(0, 1) / V(3, 1);
+  const double den0 = V(0, 0) - V(3, 0) * c.A10, den1 = V(1, 1) - V(2, 1) * c.A01;  // S117
+  if (std::fabs(den0) < lindep || std::fabs(den1) < lindep) return false;
+  c.k[0] = 1.0 / den0;
+  c.k[1] = 1.0 / den1;
+  c.B[0][0] = c.k[0] * V(2, 0);                                // S112
+  c.B[0][1] = c.k[0] * V(3, 0);
+  c.B[1][0] = c.k[1] * V(2, 1);
+  c.B[1][1] = c.k[1] * V(3, 1);
+  const double m00 = V(2, 0), m01 = V(3, 0), m10 = V(2, 1), m11 = V(3, 1);
+  const double det = m00 * m11 - m01 * m10;
+  const double mx = std::max(std::max(std::fabs(m00), std::fabs(m01)), std::max(std::fabs(m10), std::fabs(m11)));
+  if (!(std::fabs(det) > lindep * std::max(mx * mx, 1e-300))) return false;
+  const double r00 = V(4, 0), r01 = V(5, 0), r10 = V(4, 1), r11 = V(5, 1);
+  // C = -M^-1 R  (Eq. S121)
+  c.C[0][0] = -(m11 * r00 - m01 * r10) / det;
+  c.C[0][1] = -(m11 * r01 - m01 * r11) / det;
+  c.C[1][0] = -(-m10 * r00 + m00 * r10) / det;
+  c.C[1][1] = -(-m10 * r01 + m00 * r11) / det;
+  return true;
+}
+
+void record_pair(sbci_ctx *ctx, Solver &S, int seg, int t, double E, double dE, double dz,
+                 const PairCoef *c, double xn, int reason) {
+  if (!ctx->trace_on) return;
+  sbci_step_info r{};
+  r.root = S.alpha;
+  r.segment = seg;
+  r.t = t;
+  r.precision = SBCI_F64;
+  r.E = E;
+  r.dE = dE;
+  r.dz = dz;
+  r.b = c ? c->B[0][0] : NAN;
+  r.c = c ? c->C[0][0] : NAN;
+  r.k = c ? c->k[0] : NAN;
+  r.xnorm = xn;
+  r.seconds = now_s() - S.t0;
+  r.reason = reason;
+  ctx->trace.push_back(r);
+}
+
+// residuals of both states into the z pair (deflated), |z'|^2 into dz2
+int pair_residuals(sbci_ctx *ctx, Solver &S, Pair &P, const double *E, const double *inv,
+                   double E0, double *dz2) {
+  const int nc = (int)S.Ec.size();
+  std::vector<const double *> xcp(S.xc64.begin(), S.xc64.end());
+  for (int i = 0; i < 2; ++i) {
+    double *zi = P.z + (int64_t)i * S.n;
+    SBCI_TRY(resid<double>(ctx, S.n, P.x[i], P.X[i], ctx->hdiag, E[i], inv[i], E0, S.o.precond_floor,
+                           xcp.data(), nc, zi, P.dev + 16 * i));                  // S98/S100, S101
+    if (nc > 0)
+      SBCI_TRY(deflate<double>(ctx, S.n, zi, P.x[i], P.x[i], xcp.data(), nc, P.dev + 16 * i + 1,
+                               P.dev + 40 + 4 * i));
+  }
+  double h[32];
+  SBCI_HIP(hipMemcpyAsync(h, P.dev, sizeof(double) * 32, hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  dz2[0] = h[0];
+  dz2[1] = h[16];
+  return SBCI_OK;
+}
+
+int scale2(sbci_ctx *ctx, Solver &S, double *v, double s) {
+  return convert<double, double>(ctx, S.n, v, v, s);
+}
+
+}  // namespace
+
+int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
+                double *dev_vecs, sbci_report *rep_out) {
+  solver_free(ctx);
+  Solver *Sp = new Solver();
+  ctx->solver = Sp;
+  Solver &S = *Sp;
+  SBCI_TRY(resolve_opts(opt, tol, nroots, ctx->ndet, S.o));
+  if (S.o.precision != SBCI_F64)
+    return set_error(SBCI_EINVAL, "SBCI2 runs in FP64 only (precision must be SBCI_F64)");
+  S.nroots = nroots;
+  S.n = ctx->ndet;
+  S.t0 = now_s();
+  S.phase = SBCI_F64;
+  ctx->trace.clear();
+  SBCI_TRY(alloc_solver(ctx, S, false));
+  const int64_t n = S.n;
+  const int max_cycle2 = S.o.max_cycle2 > 0 ? S.o.max_cycle2 : 10;
+  Pair P;
+  struct Guard {
+    Pair &p;
+    ~Guard() { free_pair(p); }
+  } guard{P};
+  double *xa = nullptr, *Xa = nullptr;  // start of the highest state (SBCI1)
+  if (nroots >= 2) {
+    for (int i = 0; i < 2; ++i) {
+      SBCI_TRY(dmalloc(P, &P.x[i], n));
+      SBCI_TRY(dmalloc(P, &P.X[i], n));
+      SBCI_TRY(dmalloc(P, &P.y[i], n));
+      SBCI_TRY(dmalloc(P, &P.Y[i], n));
+      SBCI_TRY(dmalloc(P, &P.s[i], n));
+      SBCI_TRY(dmalloc(P, &P.S[i], n));
+    }
+    SBCI_TRY(dmalloc(P, &P.z, 2 * n));
+    SBCI_TRY(dmalloc(P, &P.Z, 2 * n));
+    SBCI_TRY(dmalloc(P, &P.dev, 128));
+    SBCI_TRY(pair_start_vectors(ctx, S, P, nroots));
+    // pair (0, 1) from Eq. S75
+    SBCI_TRY((convert<double, double>(ctx, n, P.x[0], P.xs[0], 1.0)));
+    SBCI_TRY((convert<double, double>(ctx, n, P.X[0], P.Xs[0], 1.0)));
+    SBCI_TRY((convert<double, double>(ctx, n, P.x[1], P.xs[1], 1.0)));
+    SBCI_TRY((convert<double, double>(ctx, n, P.X[1], P.Xs[1], 1.0)));
+  }
+  for (int alpha = 0; alpha + 1 < nroots; ++alpha) {
+    S.alpha = alpha;
+    // Algorithm 2 line 1 (Eqs. S77-S80)
+    double E[2];
+    for (int i = 0; i < 2; ++i) {
+      SBCI_TRY(project_off(ctx, S, P, P.x[i], P.X[i]));
+      const double *bs[2] = {P.x[i], P.X[i]};
+      double d[2];
+      SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 2, d));
+      if (!(d[0] > 0) || !std::isfinite(d[0]))
+        return set_error(SBCI_ENUMERIC, "SBCI2: start vector vanished after projection");
+      SBCI_TRY(scale2(ctx, S, P.x[i], 1.0 / std::sqrt(d[0])));
+      SBCI_TRY(scale2(ctx, S, P.X[i], 1.0 / std::sqrt(d[0])));
+      E[i] = d[1] / d[0];
+    }
+    int seg = 0, steps = 0;
+    bool conv = false, capped = false;
+    double inv[2] = {1.0, 1.0}, dz2[2];
+    double xn[2] = {1.0, 1.0};
+    while (!conv && !capped) {
+      // segment start (lines 2-4)
+      int t = 0;
+      SBCI_TRY(pair_residuals(ctx, S, P, E, inv, alpha == 0 ? E[0] : S.Ec[0], dz2));
+      while (true) {
+        SBCI_TRY(sigma(ctx, P.z, P.Z, 2, SBCI_F64));                         // S82 / S102
+        S.rep.nsigma_f64 += 2;
+        S.rep.nsteps += 1;
+        steps += 1;
+        const double *z[2] = {P.z, P.z + n};
+        const double *Z[2] = {P.Z, P.Z + n};
+        const double *basis[6], *img[6];
+        int m = 0;
+        for (int i = 0; i < 2; ++i, ++m) {
+          basis[m] = P.x[i];
+          img[m] = P.X[i];
+        }
+        if (t > 0)
+          for (int i = 0; i < 2; ++i, ++m) {
+            basis[m] = P.y[i];
+            img[m] = P.Y[i];
+          }
+        for (int i = 0; i < 2; ++i, ++m) {
+          basis[m] = z[i];
+          img[m] = Z[i];
+        }
+        double Sm[36], Hm[36];
+        for (int i = 0; i < m; ++i) {
+          const double *bs[12];
+          int nb = 0;
+          for (int j = i; j < m; ++j) bs[nb++] = basis[j];
+          for (int j = i; j < m; ++j) bs[nb++] = img[j];
+          double d[12];
+          SBCI_TRY(dots_h(ctx, P, n, basis[i], bs, nb, d));
+          for (int j = i; j < m; ++j) {
+            Sm[i * m + j] = Sm[j * m + i] = d[j - i];
+            Hm[i * m + j] = Hm[j * m + i] = d[(m - i) + (j - i)];  // H on the right vector
+          }
+        }
+        for (int i = 0; i < m * m; ++i)
+          if (!std::isfinite(Sm[i]) || !std::isfinite(Hm[i]))
+            return set_error(SBCI_ENUMERIC, "SBCI2: non-finite reduction");
+        double w[6], Vp[36];
+        int r = 0;
+        PairCoef cf{};
+        const bool rok = canonical_ritz(m, Sm, Hm, S.o.lindep, w, Vp, r);
+        const bool cok = rok && (t == 0 ? pair_coef_first(Vp, r, S.o.lindep, cf)
+                                        : pair_coef_next(Vp, r, S.o.lindep, cf));
+        if (!cok) {
+          // restart the pair from its two lowest Ritz vectors
+          if (rok) {
+            for (int i = 0; i < 2; ++i) {
+              double c1[6];
+              for (int k = 0; k < m; ++k) c1[k] = Vp[k * r + i];
+              SBCI_TRY(lincomb<double>(ctx, n, P.s[i], basis, c1, m, 0.0));
+              SBCI_TRY(lincomb<double>(ctx, n, P.S[i], img, c1, m, 0.0));
+            }
+            for (int i = 0; i < 2; ++i) {
+              std::swap(P.x[i], P.s[i]);
+              std::swap(P.X[i], P.S[i]);
+              E[i] = w[i];
+            }
+          }
+          for (int i = 0; i < 2; ++i) {
+            const double *bs[2] = {P.x[i], P.X[i]};
+            double d[2];
+            SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 2, d));
+            SBCI_TRY(scale2(ctx, S, P.x[i], 1.0 / std::sqrt(d[0])));
+            SBCI_TRY(scale2(ctx, S, P.X[i], 1.0 / std::sqrt(d[0])));
+            if (!rok) E[i] = d[1] / d[0];
+          }
+          record_pair(ctx, S, seg, t, E[0], NAN, NAN, nullptr, NAN, 7);
+          S.rep.nrestarts += 1;
+          seg += 1;
+          inv[0] = inv[1] = 1.0;
+          break;
+        }
+        const double Enew[2] = {w[0], w[1]};
+        // Eqs. S94-S97 (t = 0: y = A x - C z, x = x + y) and S122-S125
+        const double beta = t == 0 ? 0.0 : 1.0;
+        for (int i = 0; i < 2; ++i) {
+          const int o_ = 1 - i;
+          const double Ao = i == 0 ? cf.A01 : cf.A10;
+          const double *in1[3] = {z[0], z[1], P.x[o_]};
+          const double *in2[3] = {Z[0], Z[1], P.X[o_]};
+          double c3[3] = {-cf.C[i][0], -cf.C[i][1], Ao};
+          SBCI_TRY(lincomb<double>(ctx, n, P.y[i], in1, c3, 3, beta));
+          SBCI_TRY(lincomb<double>(ctx, n, P.Y[i], in2, c3, 3, beta));
+        }
+        for (int i = 0; i < 2; ++i) {
+          const double *in1[2] = {P.y[0], P.y[1]};
+          const double *in2[2] = {P.Y[0], P.Y[1]};
+          double c2[2] = {cf.B[i][0], cf.B[i][1]};
+          SBCI_TRY(lincomb<double>(ctx, n, P.x[i], in1, c2, 2, 1.0));
+          SBCI_TRY(lincomb<double>(ctx, n, P.X[i], in2, c2, 2, 1.0));
+        }
+        for (int i = 0; i < 2; ++i) {
+          const double *bs[1] = {P.x[i]};
+          double d;
+          SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 1, &d));
+          xn[i] = std::sqrt(d);
+          inv[i] = 1.0 / xn[i];
+        }
+        SBCI_TRY(pair_residuals(ctx, S, P, Enew, inv, alpha == 0 ? Enew[0] : S.Ec[0], dz2));
+        const double dz = std::sqrt(dz2[0]);
+        const double dE = std::fabs(Enew[0] - E[0]);
+        if (!std::isfinite(dz) || !std::isfinite(xn[0]) || !std::isfinite(xn[1]) ||
+            !std::isfinite(Enew[0]))
+          return set_error(SBCI_ENUMERIC, "SBCI2: non-finite residual or norm");
+        int reason = 0;
+        if (dE < S.o.eps0 && dz < S.o.r0) {                                      // S127
+          conv = true;
+          reason = 1;
+        } else {
+          const bool a_ = (std::fabs(cf.B[0][0]) < S.o.b_th || std::fabs(cf.B[1][1]) < S.o.b_th) &&
+                          dE < S.o.eps1;                                          // S130a
+          const bool b_ = xn[0] < S.o.x_th1 || xn[1] < S.o.x_th1 || xn[0] > S.o.x_th2 ||
+                          xn[1] > S.o.x_th2;                                      // S130b
+          const bool c_ = dz > S.o.r1 && t > 0;                                   // S130c
+          const bool cap = t + 1 >= max_cycle2;
+          reason = a_ ? 2 : b_ ? 3 : c_ ? 4 : cap ? 5 : 0;
+        }
+        record_pair(ctx, S, seg, t, Enew[0], dE, dz, &cf, xn[0], reason);
+        E[0] = Enew[0];
+        E[1] = Enew[1];
+        if (conv) break;
+        if (steps >= S.o.max_steps) {
+          capped = true;
+          S.any_noconv = true;
+          break;
+        }
+        if (reason >= 2) {
+          // line 19: normalised x, X; the residuals just formed are those of the
+          // normalised vectors; go to 4
+          for (int i = 0; i < 2; ++i) {
+            SBCI_TRY(scale2(ctx, S, P.x[i], inv[i]));
+            SBCI_TRY(scale2(ctx, S, P.X[i], inv[i]));
+          }
+          inv[0] = inv[1] = 1.0;
+          S.rep.nrestarts += 1;
+          seg += 1;
+          t = 0;
+          continue;
+        }
+        t += 1;
+      }
+    }
+    // accept state alpha (line 15); the partner starts the next pair
+    double *xc = nullptr;
+    SBCI_HIP(hipMalloc(&xc, sizeof(double) * n));
+    S.alloc_bytes += sizeof(double) * n;
+    SBCI_TRY((convert<double, double>(ctx, n, xc, P.x[0], 1.0 / xn[0])));
+    S.xc64.push_back(xc);
+    S.Ec.push_back(E[0]);
+    S.rep.t_converged[std::min(alpha, 15)] = now_s() - S.t0;
+    S.rep.resid[std::min(alpha, 15)] = std::sqrt(dz2[0]);
+    S.rep.nroots_converged = (int)S.Ec.size();
+    SBCI_TRY(scale2(ctx, S, P.x[1], 1.0 / xn[1]));
+    SBCI_TRY(scale2(ctx, S, P.X[1], 1.0 / xn[1]));
+    std::swap(P.x[0], P.x[1]);
+    std::swap(P.X[0], P.X[1]);
+    if (alpha + 2 < nroots) {
+      // Section S2.2: the next start vector, orthogonalised against the
+      // converged roots and against x_0^alpha
+      SBCI_TRY((convert<double, double>(ctx, n, P.x[1], P.xs[alpha + 2], 1.0)));
+      SBCI_TRY((convert<double, double>(ctx, n, P.X[1], P.Xs[alpha + 2], 1.0)));
+      SBCI_TRY(project_off(ctx, S, P, P.x[1], P.X[1]));
+      const double *bs[1] = {P.x[1]};
+      double pa;
+      SBCI_TRY(dots_h(ctx, P, n, P.x[0], bs, 1, &pa));
+      const double *a1[1] = {P.x[0]}, *a2[1] = {P.X[0]};
+      double cfa[1] = {-pa};
+      SBCI_TRY(lincomb<double>(ctx, n, P.x[1], a1, cfa, 1, 1.0));
+      SBCI_TRY(lincomb<double>(ctx, n, P.X[1], a2, cfa, 1, 1.0));
+    }
+    if (capped) break;
+  }
+  // the highest state with SBCI1 (Fig. 1B)
+  if ((int)S.Ec.size() < nroots) {
+    S.alpha = (int)S.Ec.size();
+    if (nroots >= 2) {
+      xa = P.x[0];
+      Xa = P.X[0];
+      SBCI_TRY((convert<double, double>(ctx, n, S.v64[X_], xa, 1.0)));
+      SBCI_TRY((convert<double, double>(ctx, n, S.v64[XX_], Xa, 1.0)));
+      const double *bs[2] = {S.v64[X_], S.v64[XX_]};
+      double d[2];
+      SBCI_TRY(dots_h(ctx, P, n, S.v64[X_], bs, 2, d));
+      S.E = d[1] / d[0];
+      SBCI_TRY(start_root<double>(ctx, S));
+    } else {
+      SBCI_TRY(initial_vector(ctx, S));
+      SBCI_TRY(start_root<double>(ctx, S));
+    }
+    while (!S.done) {
+      SBCI_TRY(step_t<double>(ctx, S, nullptr));
+    }
+  } else {
+    S.done = true;
+  }
+  S.alloc_bytes += P.bytes;
+  return solver_finish(ctx, energies, dev_vecs, rep_out);
+}
+
+}  // namespace sbci

@@ -229,6 +229,48 @@ __global__ __launch_bounds__(BS) void k_update(int64_t n, T *__restrict__ x, T *
   grid_reduce<10 + NC>(v, 10 + a.nconv, part, ticket, out);
 }
 
+// Residual pass of one state (SBCI2, Eqs. S98/S100, S126/S128 with Eq.
+// S101's preconditioner): r = (X - E x) * inv, w = r / (D - E0) (floored);
+// reduces |r|^2 and the projections xc_j . w.
+template <typename T, int NC>
+__global__ __launch_bounds__(BS) void k_resid(int64_t n, const T *__restrict__ x,
+                                              const T *__restrict__ X, const T *__restrict__ D,
+                                              double E, double inv, double E0, double fl, Ptrs xc,
+                                              int nconv, T *__restrict__ w, double *part,
+                                              unsigned *ticket, double *out) {
+  constexpr int U = 4;
+  double v[1 + NC];
+#pragma unroll
+  for (int q = 0; q < 1 + NC; ++q) v[q] = 0;
+  const int64_t S = (int64_t)gridDim.x * BS;
+  auto element = [&](int64_t k, double xi, double Xi, double Di) {
+    const double r = (Xi - E * xi) * inv;
+    double den = Di - E0;
+    if (fabs(den) < fl) den = fl;
+    const T wt = (T)(r / den);
+    w[k] = wt;
+    v[0] += r * r;
+    const double ws = (double)wt;
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < nconv) v[1 + j] += ws * (double)static_cast<const T *>(xc.p[j])[k];
+  };
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  for (; i + (U - 1) * S < n; i += U * S) {
+    double xi[U], Xi[U], Di[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xi[u] = (double)x[i + u * S];
+      Xi[u] = (double)X[i + u * S];
+      Di[u] = (double)D[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) element(i + u * S, xi[u], Xi[u], Di[u]);
+  }
+  for (; i < n; i += S) element(i, (double)x[i], (double)X[i], (double)D[i]);
+  grid_reduce<1 + NC>(v, 1 + nconv, part, ticket, out);
+}
+
 // z = w - sum_j d_j xc_j (in place); reduces x.z, y.z, z.z
 template <typename T, int NC>
 __global__ __launch_bounds__(BS) void k_deflate(int64_t n, T *__restrict__ w, const T *__restrict__ x,
@@ -405,6 +447,25 @@ int deflate(sbci_ctx *ctx, int64_t n, T *w, const T *x, const T *y, const T *con
 }
 
 template <typename T>
+int resid(sbci_ctx *ctx, int64_t n, const T *x, const T *X, const T *D, double E, double inv,
+          double E0, double floor, const T *const *xc, int nconv, T *w, double *out) {
+  if (nconv < 0 || nconv > MAXV) return set_error(SBCI_EINVAL, "resid: too many roots");
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  Ptrs p{};
+  for (int i = 0; i < nconv; ++i) p.p[i] = xc[i];
+  if (nconv <= 4)
+    k_resid<T, 4><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, D, E, inv, E0, floor, p, nconv, w,
+                                                       r.part, r.ticket, out);
+  else
+    k_resid<T, MAXV><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, X, D, E, inv, E0, floor, p, nconv,
+                                                          w, r.part, r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), 1 + nconv, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename T>
 int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const T *Z, double *out) {
   RedBuf r;
   SBCI_TRY(red_buf(ctx, r));
@@ -421,7 +482,9 @@ int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const
                          const T *, const T *const *, const UpdateArgs &, double *);              \
   template int deflate<T>(sbci_ctx *, int64_t, T *, const T *, const T *, const T *const *, int,  \
                           const double *, double *);                                              \
-  template int dots_xyz<T>(sbci_ctx *, int64_t, const T *, const T *, const T *, const T *, double *);
+  template int dots_xyz<T>(sbci_ctx *, int64_t, const T *, const T *, const T *, const T *, double *); \
+  template int resid<T>(sbci_ctx *, int64_t, const T *, const T *, const T *, double, double, double,  \
+                        double, const T *const *, int, T *, double *);
 INST(double)
 INST(float)
 #undef INST

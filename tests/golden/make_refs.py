@@ -11,7 +11,11 @@ Contents (all FP64, electronic energies, Eh):
          (master seed 2603): oracle SBCI1 with that instance's roots and
          the lowest eigenvalues from Lanczos eigsh on the oracle sigma.
 
-"python tests/golden/make_refs.py batch" recomputes only the batch section.
+  sbci2  oracle SBCI2 (Algorithm 2) energies: CAS(10,10) seeds 0..2 with 3
+         roots, rank 20.
+
+"python tests/golden/make_refs.py batch" (or "sbci2") recomputes only that
+section.
 """
 import json
 import os
@@ -27,6 +31,7 @@ from scipy.sparse.linalg import LinearOperator, eigsh  # noqa: E402
 
 from oracle import hamiltonian as H  # noqa: E402
 from oracle import sbci  # noqa: E402
+from oracle import sbci2  # noqa: E402
 from oracle import sigma as S  # noqa: E402
 from workloads import batch_instances, make_integrals, start_noise  # noqa: E402
 
@@ -52,11 +57,27 @@ def batch_section():
     return sec
 
 
+def sbci2_section():
+    sec = {}
+    for seed in range(3):
+        t = time.time()
+        I = make_integrals(10, 20, seed)
+        op = S.Operator(10, 5, 5, I.h1, I.eri)
+        r = sbci2.sbci2(op, op.diag(), 3)
+        sec[str(seed)] = {"sbci2": r.energies.tolist(), "nsigma": r.nsigma, "converged": r.converged,
+                          "digest": I.digest()}
+        print("sbci2", seed, r.energies, f"{time.time() - t:.1f}s", flush=True)
+    return sec
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] == "batch":
+    if len(sys.argv) > 1 and sys.argv[1] in ("batch", "sbci2"):
         with open(REFS) as f:
             out = json.load(f)
-        out["batch512"] = batch_section()
+        if sys.argv[1] == "batch":
+            out["batch512"] = batch_section()
+        else:
+            out["sbci2"] = sbci2_section()
         with open(REFS, "w") as f:
             json.dump(out, f, indent=1)
         return
@@ -88,6 +109,7 @@ def main():
                                    "davidson_nsigma": rd.nsigma, "digest": I.digest()}
         print(seed, ev[:3], rs.energies, rd.energies, f"{time.time() - t:.1f}s", flush=True)
     out["batch512"] = batch_section()
+    out["sbci2"] = sbci2_section()
     with open(REFS, "w") as f:
         json.dump(out, f, indent=1)
 
