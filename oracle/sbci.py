@@ -18,7 +18,7 @@ in the paper's notation:
 * the next root starts from the second Ritz vector of the converging step
   (Section S1.4).
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   residual scale (the z' of Algorithm 1 line 12, positive 1/|x|);
   preconditioner shift E^0 = current energy for the ground state, E_c^0
   for excited roots; |D - E^0| floored at 1e-8; max_cycle per segment;
@@ -155,16 +155,17 @@ def ritz_next(N, Hm, lindep):
 def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, prev=None):
     """Lowest nroots eigenpairs of H by SBCI1 (Algorithm 1).  op(v) = H v.
 
-    prev = (x_c list, E_c list, x0, X0, E0): continue after len(x_c) converged
-    roots from the start vector x0 (X0 = H x0), as SBCI2 does for its last
-    state (Fig. 1B)."""
+    prev = (x_c list, E_c list, x0, X0, E0[, images]): continue after len(x_c)
+    converged roots from the start vector x0 (X0 = H x0), as SBCI2 does for
+    its last state (Fig. 1B).  images, if given and not None, are H x_c of
+    those roots and replace E_c x_c in Eq. S5 for them."""
     o = opts or Options()
     diag = np.asarray(diag, dtype=np.float64)
     ndet = diag.shape[0]
     nsig = 0
     first = 0
     if prev is not None:
-        xc0, Ec0, xa, Xa, Ea = prev
+        xc0, Ec0, xa, Xa, Ea = prev[:5]
         first = len(xc0)
         xa, Xa, Ea = np.array(xa, dtype=np.float64), np.array(Xa, dtype=np.float64), float(Ea)
     elif x0 is None:
@@ -178,6 +179,7 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, p
         nsig += 1
         Ea = float(xa @ Xa)
     xc, Ec = ([], []) if prev is None else (list(prev[0]), list(prev[1]))
+    Hxc = [] if prev is None or len(prev) < 6 or prev[5] is None else list(prev[5])
     steps = []
     all_conv = True
 
@@ -187,7 +189,9 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, p
             Xc = np.array(xc)
             proj = Xc @ xa
             xa = xa - Xc.T @ proj
-            Xa = Xa - Xc.T @ (np.array(Ec) * proj)
+            # Eq. S5: E_c x_c stands for H x_c, except where H x_c is given
+            img = np.array([Hxc[i] if i < len(Hxc) else Ec[i] * xc[i] for i in range(len(xc))])
+            Xa = Xa - img.T @ proj
         nrm = np.linalg.norm(xa)
         x, X, E = xa / nrm, Xa / nrm, Ea
         seg = 0

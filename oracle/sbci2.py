@@ -22,7 +22,7 @@ paper's steps in its order and notation:
 * state alpha converges on Eq. S127; otherwise the pair restarts on S130a,
   S130b, S130c or after max_cycle = 10 steps (Section S2.5).
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   residual scale 1/|x| (Algorithm 2 line 12); preconditioner shift E^0 = the
   current energy of state 0 while alpha = 0, else E_c^0, |D - E^0| floored
   at 1e-8; a restart ("go to 4") zeroes y and uses the t = 0 step; a
@@ -30,6 +30,16 @@ Readings of points the paper leaves open (each also listed in the design doc):
   basis vectors, restarts the pair from its two lowest Ritz vectors (or
   from the normalised x's); the partner's starting energy is its Rayleigh
   quotient after the projection of Section S2.2.
+  Eq. S78 (and the same projection in Section S2.2) takes E_c x_c for the
+  image H x_c of a converged root, which holds for an exact eigenvector
+  only.  An accepted x_c still carries a residual r_c (|z'| < r0), and the
+  printed form leaves r_c (x_c . x) in X for good: the Ritz energies of the
+  later states then differ from the Rayleigh quotients of their vectors at
+  first order in r_c (10^-8 - 10^-7 Eh at 12-14 orbitals), because the
+  partner from Eq. S75 overlaps the converged roots strongly.  The image
+  carried to acceptance (X of the accepted state, normalised) is H x_c up to
+  rounding, so the projection uses it (s78_images = True, the default);
+  s78_images = False keeps the printed E_c x_c.
 """
 from __future__ import annotations
 
@@ -43,6 +53,7 @@ from . import sbci as S1
 @dataclass
 class Options2(S1.Options):
     max_cycle2: int = 10    # Section S2.5
+    s78_images: bool = True  # H x_c from the carried image in Eq. S78 (reading)
 
 
 @dataclass
@@ -126,13 +137,19 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
         return Result2(r.energies, r.vectors, r.nsigma, [], r.converged)
     xs, Xs, Es = S1.start_vectors(op, diag, nroots)       # Eqs. S74-S76
     nsig = nroots
-    xc, Ec = [], []
+    xc, Ec, Xcs = [], [], []
     steps = []
     all_conv = True
 
     def floor_den(E0):
         den = diag - E0
         return np.where(np.abs(den) < o.precond_floor, o.precond_floor, den)
+
+    def images():
+        # H x_c of the converged roots: carried images, or E_c x_c (Eq. S78 as printed)
+        if o.s78_images:
+            return np.array(Xcs)
+        return np.array(Ec)[:, None] * np.array(xc)
 
     def deflate(w):
         if not xc:
@@ -151,7 +168,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 Xc = np.array(xc)
                 proj = Xc @ xv[i]
                 xv[i] = xv[i] - Xc.T @ proj
-                Xv[i] = Xv[i] - Xc.T @ (np.array(Ec) * proj)
+                Xv[i] = Xv[i] - images().T @ proj
             nrm = np.linalg.norm(xv[i])
             xv[i], Xv[i] = xv[i] / nrm, Xv[i] / nrm
         x = np.array(xv)
@@ -249,6 +266,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 break
         xn = np.linalg.norm(x, axis=1)
         xc.append(x[0] / xn[0])                   # line 15
+        Xcs.append(X[0] / xn[0])
         Ec.append(float(E[0]))
         # next pair: the converged partner, and the next start vector of Eq. S75
         xa, Xa = x[1] / xn[1], X[1] / xn[1]
@@ -258,11 +276,12 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
             Xc = np.array(xc)
             proj = Xc @ xb
             xb = xb - Xc.T @ proj
-            Xb = Xb - Xc.T @ (np.array(Ec) * proj)
+            Xb = Xb - images().T @ proj
             pa = xa @ xb
             xb = xb - pa * xa
             Xb = Xb - pa * Xa
     # the highest state with SBCI1 (Fig. 1B), from the last partner
     Ea = float(xa @ Xa / (xa @ xa))
-    r1 = S1.sbci1(op, diag, nroots, o, record=False, prev=(xc, Ec, xa, Xa, Ea))
+    prev = (xc, Ec, xa, Xa, Ea, Xcs if o.s78_images else None)
+    r1 = S1.sbci1(op, diag, nroots, o, record=False, prev=prev)
     return Result2(r1.energies, r1.vectors, nsig + r1.nsigma, steps, all_conv and r1.converged)
