@@ -178,10 +178,13 @@ def small_sections(sb, stream):
             ctx.solve(3, tol=1e-10, want_vectors=False)
         s1 = ctx.solve(3, tol=1e-10, want_vectors=False)
         dv = ctx.davidson(3, tol=1e-10, want_vectors=False)
+        s2 = ctx.solve2(3, tol=1e-10, want_vectors=False)
         rows.append((s1.report["seconds"], dv.report["seconds"], s1.report["nsigma_f64"],
                      dv.report["nsigma_f64"], s1.report["peak_vector_bytes"],
                      dv.report["peak_vector_bytes"],
-                     float(abs(s1.energies[0] - dv.energies[0]) < 1e-8)))
+                     float(abs(s1.energies[0] - dv.energies[0]) < 1e-8),
+                     s2.report["seconds"], s2.report["nsigma_f64"], s2.report["peak_vector_bytes"],
+                     float(np.abs(np.sort(s2.energies) - np.sort(dv.energies)).max() < 1e-7)))
         ctx.close()
     a = np.array(rows)
     out["cas10"] = {
@@ -194,6 +197,10 @@ def small_sections(sb, stream):
         # SBCI1 from the spin-flip-symmetric start can converge to a singlet
         # above a lower odd-S state; Davidson (block start) finds the lowest
         "seeds_sbci1_root0_is_lowest": int(np.sum(a[:, 6])),
+        "sbci2_ms_median": round(float(np.median(a[:, 7])) * 1e3, 2),
+        "sbci2_sigma_median": float(np.median(a[:, 8])),
+        "sbci2_peak_vector_MB": round(float(np.median(a[:, 9])) / 1e6, 2),
+        "seeds_sbci2_equals_davidson_roots": int(np.sum(a[:, 10])),
     }
     return out
 
@@ -378,6 +385,12 @@ def main():
     ref = ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"), want_vectors=False)
     torch.cuda.synchronize()
     t_f64 = time.perf_counter() - t
+    # SBCI2 (pairs of states, FP64), outside the timed region
+    t = time.perf_counter()
+    r2 = ctx.solve2(nroots, tol=1e-10, want_vectors=False)
+    torch.cuda.synchronize()
+    sbci2 = {"fp64_s": round(time.perf_counter() - t, 4), "nsigma": r2.report["nsigma_f64"],
+             "energies": [float(e) for e in r2.energies]}
     dE = float(np.max(np.abs(np.sort(ref.energies) - np.sort(last.energies))))
 
     # sigma per precision, per kernel (HIP events on the library stream)
@@ -421,6 +434,7 @@ def main():
                           "speedup": round(t_f64 / (ms / 1e3), 3)},
         "energies": [float(e) for e in last.energies],
         "max_abs_dE_vs_fp64": dE,
+        "sbci2": sbci2,
         "nsigma": {"f64": nsig_f64, "f32": nsig_low - nsig_bf16, "bf16": nsig_bf16},
         "sigma": sig,
         "roofline": roof,

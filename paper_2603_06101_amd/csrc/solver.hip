@@ -54,6 +54,9 @@ struct Solver {
   float *v32[NV] = {};
   std::vector<double *> xc64;
   std::vector<float *> xc32;
+  // H x_c of the first Hxc64.size() converged roots (SBCI2 keeps them); where
+  // present they replace E_c x_c in the projections of X (Eqs. S5, S78)
+  std::vector<double *> Hxc64;
   std::vector<double> Ec;
   double *red = nullptr;  // device results: [0,32) update, [32,36) deflate, [36,40) dots_xyz, [40,64) misc
   double h1[32] = {}, h2[4] = {}, h3[4] = {};
@@ -198,7 +201,15 @@ int start_root(sbci_ctx *ctx, Solver &S) {
       cX[i] = -S.Ec[i] * d[i];
     }
     SBCI_TRY(lincomb<T>(ctx, S.n, x, xcp.data(), cx, nconv, 1.0));   // Eq. S4
-    SBCI_TRY(lincomb<T>(ctx, S.n, X, xcp.data(), cX, nconv, 1.0));   // Eq. S5
+    // Eq. S5; roots with a kept image H x_c use it in place of E_c x_c
+    const int nimg = std::is_same<T, double>::value ? (int)std::min(S.Hxc64.size(), (size_t)nconv) : 0;
+    if (nimg > 0) {
+      std::vector<const T *> hp(nimg);
+      for (int i = 0; i < nimg; ++i) hp[i] = reinterpret_cast<const T *>(S.Hxc64[i]);
+      SBCI_TRY(lincomb<T>(ctx, S.n, X, hp.data(), cx, nimg, 1.0));
+    }
+    if (nconv > nimg)
+      SBCI_TRY(lincomb<T>(ctx, S.n, X, xcp.data() + nimg, cX + nimg, nconv - nimg, 1.0));
   }
   const T *xp[1] = {x};
   SBCI_TRY(dots<T>(ctx, S.n, x, xp, 1, S.red + 40));
@@ -579,8 +590,10 @@ void free_solver(Solver &S) {
   }
   for (auto p : S.xc64) hipFree(p);
   for (auto p : S.xc32) hipFree(p);
+  for (auto p : S.Hxc64) hipFree(p);
   S.xc64.clear();
   S.xc32.clear();
+  S.Hxc64.clear();
   hipFree(S.red);
   S.red = nullptr;
 }
@@ -964,20 +977,23 @@ int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
   return SBCI_OK;
 }
 
-// v <- v - sum_j x_c^j (x_c^j . v), V <- V - sum_j E_c^j x_c^j (x_c^j . v)   (Eqs. S77-S78)
+// v <- v - sum_j x_c^j (x_c^j . v), V <- V - sum_j (H x_c^j) (x_c^j . v)
+// (Eqs. S77-S78).  Eq. S78 writes E_c^j x_c^j for H x_c^j, exact only for an
+// exact eigenvector; an accepted x_c^j keeps a residual, and E_c x_c would
+// leave it in V for the rest of the run, shifting the later Ritz energies at
+// first order.  The image carried to acceptance is H x_c^j up to rounding.
 int project_off(sbci_ctx *ctx, Solver &S, Pair &P, double *v, double *V) {
   const int nc = (int)S.Ec.size();
   if (nc == 0) return SBCI_OK;
+  if ((int)S.Hxc64.size() != nc) return set_error(SBCI_ENUMERIC, "SBCI2: internal: a converged root has no image");
   std::vector<const double *> xcp(S.xc64.begin(), S.xc64.end());
+  std::vector<const double *> hcp(S.Hxc64.begin(), S.Hxc64.end());
   double d[16];
   SBCI_TRY(dots_h(ctx, P, S.n, v, xcp.data(), nc, d));
-  double cx[16], cX[16];
-  for (int j = 0; j < nc; ++j) {
-    cx[j] = -d[j];
-    cX[j] = -S.Ec[j] * d[j];
-  }
+  double cx[16];
+  for (int j = 0; j < nc; ++j) cx[j] = -d[j];
   SBCI_TRY(lincomb<double>(ctx, S.n, v, xcp.data(), cx, nc, 1.0));
-  SBCI_TRY(lincomb<double>(ctx, S.n, V, xcp.data(), cX, nc, 1.0));
+  SBCI_TRY(lincomb<double>(ctx, S.n, V, hcp.data(), cx, nc, 1.0));
   return SBCI_OK;
 }
 
@@ -1328,6 +1344,11 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     S.alloc_bytes += sizeof(double) * n;
     SBCI_TRY((convert<double, double>(ctx, n, xc, P.x[0], 1.0 / xn[0])));
     S.xc64.push_back(xc);
+    double *hxc = nullptr;
+    SBCI_HIP(hipMalloc(&hxc, sizeof(double) * n));
+    S.alloc_bytes += sizeof(double) * n;
+    S.Hxc64.push_back(hxc);
+    SBCI_TRY((convert<double, double>(ctx, n, hxc, P.X[0], 1.0 / xn[0])));
     S.Ec.push_back(E[0]);
     S.rep.t_converged[std::min(alpha, 15)] = now_s() - S.t0;
     S.rep.resid[std::min(alpha, 15)] = std::sqrt(dz2[0]);
