@@ -431,7 +431,8 @@ def main():
                    "nbeta": cfg["nb"], "ndet": ndet, "nroots": nroots, "eri_rank": cfg["rank"],
                    "seed": cfg["seed"], "precision": a.precision, "parallelism": "1 GPU"},
         "time_to_1e8_s": {"mixed": round(ms / 1e3, 4), "fp64": round(t_f64, 4),
-                          "speedup": round(t_f64 / (ms / 1e3), 3)},
+                          "speedup": round(t_f64 / (ms / 1e3), 3),
+                          "fp64_nsigma": ref.report["nsigma_f64"]},
         "energies": [float(e) for e in last.energies],
         "max_abs_dE_vs_fp64": dE,
         "sbci2": sbci2,
