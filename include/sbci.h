@@ -49,6 +49,19 @@ typedef enum sbci_dtype {
                      accumulation, one-electron and same-spin parts in FP32         */
 } sbci_dtype;
 
+/* Form of the opposite-spin contraction sum (kl|k'l') E^alpha_kl E^beta_k'l'
+ * (the two-electron part between the spins of the Hamiltonian of the
+ * Results section): SBCI_OPP_PAIR contracts over every unordered orbital
+ * pair {k'l'} per beta string, the cheaper form near half filling;
+ * SBCI_OPP_ORBITAL groups beta strings by the orbital q that E_pq empties,
+ * the cheaper form when few electrons occupy many orbitals; SBCI_OPP_AUTO
+ * picks one per sigma dtype from the sizes. */
+typedef enum sbci_opp_form {
+  SBCI_OPP_AUTO = 0,
+  SBCI_OPP_PAIR = 1,
+  SBCI_OPP_ORBITAL = 2
+} sbci_opp_form;
+
 typedef struct sbci_ctx sbci_ctx;
 
 /* Thresholds and policies.  Defaults (sbci_default_opts) are the paper's
@@ -147,6 +160,16 @@ int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int 
  * transpose of c, same-spin beta lists on the transpose, transposed add. */
 int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype,
                      float *ms_parts);
+
+/* Force the opposite-spin form of later sigma calls (sbci_opp_form value),
+ * or SBCI_OPP_AUTO (the default).  A forced form that does not fit this
+ * context makes the sigma call fail with SBCI_EINVAL.  Both forms compute
+ * the same sigma up to rounding order. */
+int sbci_set_opp_form(sbci_ctx *ctx, int form);
+
+/* The opposite-spin form sigma calls of this dtype use (SBCI_OPP_PAIR or
+ * SBCI_OPP_ORBITAL) into *form; SBCI_EINVAL if no form fits. */
+int sbci_get_opp_form(sbci_ctx *ctx, int dtype, int *form);
 
 /* SBCI1 (Algorithm 1 with Sections S1.1-S1.5) for the lowest nroots states.
  * tol > 0 overrides opt: eps0 = tol, r0 = sqrt(tol) (the paper's two pairs,

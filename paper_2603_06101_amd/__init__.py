@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsbci.so")
 SBCI_OK, SBCI_EINVAL, SBCI_ENOMEM, SBCI_EDEVICE, SBCI_ENOCONV, SBCI_ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2}
 REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
            7: "coef", 8: "refine"}
 
@@ -117,6 +118,8 @@ SIGNATURES = [
     ("sbci_hdiag", _I, [_P, _P]),
     ("sbci_sigma", _I, [_P, _P, _P, _I, _I]),
     ("sbci_sigma_timed", _I, [_P, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
+    ("sbci_set_opp_form", _I, [_P, _I]),
+    ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
     ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
@@ -248,6 +251,16 @@ class Context:
         _check(lib().sbci_sigma(self.h, ctypes.c_void_p(c.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), nvec, code))
         return out
+
+    def set_opp_form(self, form):
+        """Force the opposite-spin form ("auto", "pair" or "orbital") of later sigma calls."""
+        _check(lib().sbci_set_opp_form(self.h, OPP_FORMS[form]))
+
+    def opp_form(self, dtype="f64"):
+        """The opposite-spin form ("pair" or "orbital") sigma calls of this dtype use."""
+        f = _I(0)
+        _check(lib().sbci_get_opp_form(self.h, DTYPES[dtype], ctypes.byref(f)))
+        return {v: k for k, v in OPP_FORMS.items()}[f.value]
 
     def sigma_timed(self, c, dtype="f64", out=None):
         """sigma with per-kernel HIP-event timings: (out, [alpha, opp, transpose, beta, add] ms)."""

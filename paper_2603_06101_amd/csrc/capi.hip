@@ -170,6 +170,7 @@ int sbci_destroy(sbci_ctx *ctx) {
   hipFree(ctx->ws_t.ptr);
   hipFree(ctx->ws_s.ptr);
   hipFree(ctx->ws_red.ptr);
+  hipFree(ctx->ws_q.ptr);
   if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
   delete ctx;
   return SBCI_OK;
@@ -243,6 +244,21 @@ int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec
   if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
     return set_error(SBCI_EINVAL, "unknown dtype");
   return sigma_profile(ctx, dev_c, dev_sigma, nvec, dtype, ms_parts);
+}
+
+int sbci_set_opp_form(sbci_ctx *ctx, int form) {
+  if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
+  if (form != SBCI_OPP_AUTO && form != SBCI_OPP_PAIR && form != SBCI_OPP_ORBITAL)
+    return set_error(SBCI_EINVAL, "unknown opposite-spin form");
+  ctx->opp_form = form;
+  return SBCI_OK;
+}
+
+int sbci_get_opp_form(sbci_ctx *ctx, int dtype, int *form) {
+  if (!ctx || !form) return set_error(SBCI_EINVAL, "NULL argument");
+  if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
+    return set_error(SBCI_EINVAL, "unknown dtype");
+  return opp_form(ctx, dtype, form);
 }
 
 int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {

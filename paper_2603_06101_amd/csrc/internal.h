@@ -44,6 +44,17 @@ struct SpinTables {
   // quad_s: rows u*16 + g + 4r (FP64 layout).  [npair_pad / 16][4][ns_pad].
   uint4 *quad_r = nullptr;
   uint4 *quad_s = nullptr;
+  // Orbital-grouped scatter tables (the opposite-spin form for dilute
+  // spaces): colq[q][j] is the j-th string (ascending) that holds orbital q,
+  // nq = C(N-1, m-1) per orbital; qquad_r / qquad_s [q][mt][4][nq_pad] hold,
+  // for 16-row tile u of orbitals p and lane group g, the scatter codes of
+  // E_pq colq[q][j] for p = u*16 + 4g + r (qquad_r) or u*16 + g + 4r
+  // (qquad_s), r = 0..3; columns j >= nq and orbitals p >= N are kInvalid.
+  int64_t nq = 0, nq_pad = 0;
+  int mt = 0;
+  int32_t *colq = nullptr;
+  uint4 *qquad_r = nullptr;
+  uint4 *qquad_s = nullptr;
   int32_t *fcol = nullptr;  // [ns][nf] same-spin list columns
   double *fval64 = nullptr; // [ns][nf] FP64 values
   float *fval32 = nullptr;  // [ns][nf] FP32 values
@@ -90,6 +101,8 @@ struct sbci_ctx {
   float *hdiag32 = nullptr;       // device [ndet]
   sbci::Workspace ws_t, ws_s;     // transposed input / output scratch of sigma
   sbci::Workspace ws_red;         // reduction partials + results
+  sbci::Workspace ws_q;           // orbital-grouped copy of c (opposite-spin, dilute form)
+  int opp_form = 0;               // SBCI_OPP_AUTO / _PAIR / _ORBITAL
   sbci::Solver *solver = nullptr;
   bool trace_on = true;
   std::vector<sbci_step_info> trace;
@@ -132,6 +145,8 @@ int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
 // Same, with HIP events around its five parts; ms[0..4] = alpha lists,
 // opposite spin, transpose, beta lists, transposed add (milliseconds).
 int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms);
+// opposite-spin form (SBCI_OPP_PAIR / SBCI_OPP_ORBITAL) used for this dtype
+int opp_form(sbci_ctx *ctx, int mode, int *form);
 
 // ---- vec.hip: vector kernels with FP64 reductions ----
 // Reductions write `nq` doubles to `out` (device); deterministic order.

@@ -385,25 +385,8 @@ void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, co
 }
 
 template <typename M, typename T>
-int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
-  const SpinTables &A = ctx->A, &B = ctx->B;
-  if (A.s == 0 || B.m == 0) return SBCI_OK;
-  if (ctx->ndet >= ((int64_t)1 << 31))
-    return set_error(SBCI_EINVAL, "opposite-spin sigma: N_det must be below 2^31");
-  // K tiles (k-steps per chunk) offered to the planner; the register budget
-  // of two waves per SIMD bounds them (B fragments are double-buffered)
-  static const int ks_d[3] = {4, 7, 14};
-  static const int ks_f[3] = {8, 9, 14};
-  static const int ks_b[3] = {1, 2, 3};
-  static const int mg_d[3] = {4, 5, 7};
-  static const int mg_f[3] = {4, 7, 9};
-  OppPlan p{};
-  if (M::KPL == 8)
-    SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_b, 3, p));
-  else if (std::is_same<typename M::A, double>::value)
-    SBCI_TRY(plan_opp<M>(ctx, mg_d, 3, ks_d, 3, p));
-  else
-    SBCI_TRY(plan_opp<M>(ctx, mg_f, 3, ks_f, 3, p));
+int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const T *c, T *out, int nvec) {
+  const SpinTables &A = ctx->A;
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
@@ -419,6 +402,312 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   }
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
+}
+
+// Orbital-grouped opposite-spin contraction, the form for dilute spaces
+// (few electrons in many orbitals), where most orbital pairs {k, l} connect
+// a string to nothing and k_opp's M[kl][J] is mostly discarded.  E_pq acts
+// on a beta string only if it holds q, and then yields a string for every p
+// that is q or empty.  For output row Ia and beta orbital q:
+//   M_q[p][j] = sum_e sign_e (pq|kl_e) Cq[q][J_e][j]      p = 0..N-1
+//   sigma[Ia][I'] += sign' M_q[p][j]   for E_pq colq[q][j] = sign' |I'>
+// Cq[q][Ia][j] = C[Ia][colq[q][j]] is gathered once per sigma (k_gather_q),
+// so B fragments are contiguous row segments as in k_opp.  Per determinant
+// this issues 2 N m_beta s flops (k_opp: 2 npair s; minimum 2 s^2).
+// LDS (dynamic): acc[nsb + 64] | Ws[MT*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
+template <typename M, typename T, int MT, int KS, int NW>
+__global__ __launch_bounds__(64 * NW) void k_opp_q(
+    int64_t nsa, int64_t nsb, int norb, int64_t nq, int64_t nq_pad, int s, int npair, int nkc,
+    const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
+    const uint4 *__restrict__ quads, const T *__restrict__ cq, T *__restrict__ sigma) {
+  using A = typename M::A;
+  using Acc = typename M::Acc;
+  using Frag = typename M::Frag;
+  constexpr int KW = KS * M::KSTEP;
+  constexpr int LDW = KW + M::PAD;
+  constexpr int ROWS = MT * 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ia = blockIdx.x;
+  const int64_t vo = (int64_t)blockIdx.y * nsa * nsb;
+  const int ktot = nkc * KW;
+  Acc *acc = reinterpret_cast<Acc *>(smem);
+  size_t off = ((size_t)(nsb + 64) * sizeof(Acc) + 15) & ~(size_t)15;
+  A *Ws = reinterpret_cast<A *>(smem + off);
+  off += (((size_t)ROWS * LDW * sizeof(A)) + 15) & ~(size_t)15;
+  uint32_t *eoff = reinterpret_cast<uint32_t *>(smem + off);
+  off += (size_t)ktot * sizeof(uint32_t);
+  int32_t *eW = reinterpret_cast<int32_t *>(smem + off);
+
+  const uint32_t nq32 = (uint32_t)nq;
+  for (int e = tid; e < ktot; e += 64 * NW) {
+    if (e < s) {
+      Ent t = taba[ia * s + e];
+      eoff[e] = (uint32_t)t.J * nq32;
+      int kl = pair_index(t.p, t.q);
+      eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
+    } else {
+      eoff[e] = 0;  // row 0 of Cq: a valid address; its A column is zero
+      eW[e] = kPadEntry;
+    }
+  }
+  for (int64_t j = tid; j < nsb + 64; j += 64 * NW) acc[j] = (Acc)0;
+
+  const int njt = (int)(nq_pad / 16);
+  const int g = lane >> 4;
+  const int li = lane & 15;
+  const uint32_t pstride = (uint32_t)nq_pad;
+  for (int q = 0; q < norb; ++q) {
+    const T *__restrict__ cv = cq + ((int64_t)blockIdx.y * norb + q) * nsa * nq;
+    const uint4 *__restrict__ qq = quads + (int64_t)q * MT * 4 * nq_pad;
+    for (int kc = 0; kc < nkc; ++kc) {
+      __syncthreads();  // entries ready; the previous A tile is no longer read
+      for (int idx = tid; idx < ROWS * KW; idx += 64 * NW) {
+        const int p = idx / KW, k = idx - p * KW;
+        const int w = eW[kc * KW + k];
+        A v = M::cvt(0.0f);
+        if (w != kPadEntry && p < norb) {
+          const int kl = w & 0x7fffffff;
+          const int64_t pq = pair_index(p, q);
+          const double x = Wd ? Wd[pq * npair + kl] : (double)Wf[pq * npair + kl];
+          v = M::cvt(w < 0 ? -x : x);
+        }
+        Ws[p * LDW + k] = v;
+      }
+      __syncthreads();
+      uint32_t boff[KS][M::KPL];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < M::KPL; ++t) boff[ks][t] = eoff[kc * KW + ks * M::KSTEP + g * M::KPL + t];
+      // As in k_opp: codes of this tile, then the next tile's B fragments
+      // (clamped to a valid column past the end), then MFMAs and the
+      // scatter.  Columns past nq carry invalid codes.
+      int jt = wave;
+      Frag bn[KS];
+      {
+        const uint32_t J = (uint32_t)(jt * 16 + li);
+        const uint32_t jl = J < nq32 ? J : nq32 - 1;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bn[ks] = M::load_b(cv, boff[ks], jl);
+      }
+      for (; jt < njt; jt += NW) {
+        const uint32_t J = (uint32_t)(jt * 16 + li);
+        Frag b[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
+        uint4 code[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u) code[u] = qq[((uint32_t)u * 4u + (uint32_t)g) * pstride + J];
+        {
+          const uint32_t Jn = (uint32_t)((jt + NW) * 16 + li);
+          const uint32_t jn = Jn < nq32 ? Jn : nq32 - 1;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) bn[ks] = M::load_b(cv, boff[ks], jn);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        typename M::Out out[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[u][r] = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int u = 0; u < MT; ++u) {
+            const Frag a = M::load_a(&Ws[(u * 16 + li) * LDW + ks * M::KSTEP + g * M::KPL]);
+            out[u] = M::mma(a, b[ks], out[u]);
+          }
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+          const uint32_t cds[4] = {code[u].x, code[u].y, code[u].z, code[u].w};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t cd = cds[r];
+            if (cd != kInvalid) {
+              Acc v = (Acc)out[u][r];
+              if (cd & 1u) v = -v;
+              atomicAdd(&acc[cd >> 1], v);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  T *__restrict__ sv = sigma + vo + ia * nsb;
+  for (int64_t j = tid; j < nsb; j += 64 * NW) sv[j] += (T)acc[j];
+}
+
+// cq[v][q][Ia][j] = c[v][Ia][colq[q][j]]; blocks of one row Ia are adjacent
+// in launch order, so the row is read from HBM about once.
+template <typename T>
+__global__ void k_gather_q(const T *__restrict__ c, T *__restrict__ cq,
+                           const int32_t *__restrict__ colq, int64_t nsa, int64_t nsb, int norb,
+                           int64_t nq, int64_t jblocks) {
+  const int64_t b = blockIdx.x;
+  const int64_t ia = b / (norb * jblocks);
+  const int64_t r = b - ia * norb * jblocks;
+  const int q = (int)(r / jblocks);
+  const int64_t j = (r - (int64_t)q * jblocks) * blockDim.x + threadIdx.x;
+  if (j >= nq) return;
+  const int64_t v = blockIdx.y;
+  cq[((v * norb + q) * nsa + ia) * nq + j] = c[v * nsa * nsb + ia * nsb + colq[(int64_t)q * nq + j]];
+}
+
+struct OppQPlan {
+  int KS = 0, nkc = 0;
+  size_t lds = 0;
+};
+
+template <typename M>
+size_t oppq_lds(int64_t nsb, int MT, int KS, int nkc) {
+  const int KW = KS * M::KSTEP, LDW = KW + M::PAD;
+  size_t b = ((size_t)(nsb + 64) * sizeof(typename M::Acc) + 15) & ~(size_t)15;
+  b += (((size_t)MT * 16 * LDW * sizeof(typename M::A)) + 15) & ~(size_t)15;
+  b += (size_t)nkc * KW * 8;
+  return b;
+}
+
+// K tile (k-steps per chunk) with the least K padding that fits in LDS
+// (ties: fewer chunks); false if none fits.
+template <typename M>
+bool plan_opp_q(const sbci_ctx *ctx, OppQPlan &p) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  if (B.nq == 0 || B.mt < 1 || B.mt > 4) return false;
+  static const int ks_w[3] = {9, 12, 17};
+  static const int ks_b[3] = {1, 3, 5};
+  const int *opts = M::KPL == 8 ? ks_b : ks_w;
+  const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
+  p = OppQPlan();
+  int best = 1 << 30;
+  for (int i = 0; i < 3; ++i) {
+    const int ks = opts[i], nkc = (kst + ks - 1) / ks;
+    if (oppq_lds<M>(B.ns, B.mt, ks, nkc) > 160 * 1024) continue;
+    const int padded = nkc * ks;
+    if (padded < best || (padded == best && nkc < p.nkc)) {
+      best = padded;
+      p.KS = ks;
+      p.nkc = nkc;
+    }
+  }
+  if (p.KS == 0) return false;
+  p.lds = oppq_lds<M>(B.ns, B.mt, p.KS, p.nkc);
+  return true;
+}
+
+template <typename M, typename T, int MT, int KS>
+int launch_opp_q_k(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const double *Wd,
+                   const T *cq, T *out, int nvec) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  constexpr int NW = 8;
+  auto kern = k_opp_q<M, T, MT, KS, NW>;
+  static bool attr = false;
+  if (!attr) {
+    SBCI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 160 * 1024));
+    attr = true;
+  }
+  const uint4 *quads = std::is_same<typename M::A, double>::value ? B.qquad_s : B.qquad_r;
+  kern<<<dim3((unsigned)A.ns, (unsigned)nvec), 64 * NW, p.lds, ctx->stream>>>(
+      A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, Wf, Wd, A.tab, quads, cq, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+template <typename M, typename T, int MT>
+int dispatch_q_ks(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const double *Wd, const T *cq,
+                  T *out, int nvec) {
+  if constexpr (M::KPL == 8) {
+    if (p.KS == 1) return launch_opp_q_k<M, T, MT, 1>(ctx, p, Wf, Wd, cq, out, nvec);
+    if (p.KS == 3) return launch_opp_q_k<M, T, MT, 3>(ctx, p, Wf, Wd, cq, out, nvec);
+    return launch_opp_q_k<M, T, MT, 5>(ctx, p, Wf, Wd, cq, out, nvec);
+  } else {
+    if (p.KS == 9) return launch_opp_q_k<M, T, MT, 9>(ctx, p, Wf, Wd, cq, out, nvec);
+    if (p.KS == 12) return launch_opp_q_k<M, T, MT, 12>(ctx, p, Wf, Wd, cq, out, nvec);
+    return launch_opp_q_k<M, T, MT, 17>(ctx, p, Wf, Wd, cq, out, nvec);
+  }
+}
+
+template <typename M, typename T>
+int launch_opp_q(sbci_ctx *ctx, const OppQPlan &p, const T *c, T *out, int nvec) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  const int n = ctx->norb;
+  const size_t bytes = sizeof(T) * (size_t)nvec * n * A.ns * B.nq;
+  SBCI_TRY(ensure(ctx->ws_q, bytes));
+  T *cq = static_cast<T *>(ctx->ws_q.ptr);
+  const int64_t jblocks = (B.nq + 255) / 256;
+  const int64_t nblk = A.ns * n * jblocks;
+  if (nblk >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "opposite-spin sigma: grid too large");
+  k_gather_q<T><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(c, cq, B.colq, A.ns,
+                                                                             B.ns, n, B.nq, jblocks);
+  SBCI_CHECK_LAUNCH();
+  const float *Wf = nullptr;
+  const double *Wd = nullptr;
+  if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
+  switch (B.mt) {
+    case 1: return dispatch_q_ks<M, T, 1>(ctx, p, Wf, Wd, cq, out, nvec);
+    case 2: return dispatch_q_ks<M, T, 2>(ctx, p, Wf, Wd, cq, out, nvec);
+    case 3: return dispatch_q_ks<M, T, 3>(ctx, p, Wf, Wd, cq, out, nvec);
+    default: return dispatch_q_ks<M, T, 4>(ctx, p, Wf, Wd, cq, out, nvec);
+  }
+}
+
+// Opposite-spin form for this context and flavour: the pair form (k_opp) or
+// the orbital-grouped form (k_opp_q).  Automatic choice: the orbital form
+// when the pair form does not fit in LDS, or when it issues at most 2/3 of
+// the pair form's MFMA tiles (its B operand is read m_beta times per row).
+template <typename M>
+int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  const bool qok = plan_opp_q<M>(ctx, pq) && (uint64_t)A.ns * (uint64_t)B.nq < (1ull << 32);
+  bool pok = false;
+  {
+    // K tiles (k-steps per chunk) offered to the pair planner; the register
+    // budget of two waves per SIMD bounds them (B fragments double-buffered)
+    static const int ks_d[3] = {4, 7, 14};
+    static const int ks_f[3] = {8, 9, 14};
+    static const int ks_b[3] = {1, 2, 3};
+    static const int mg_d[3] = {4, 5, 7};
+    static const int mg_f[3] = {4, 7, 9};
+    int rc;
+    if (M::KPL == 8) rc = plan_opp<M>(ctx, mg_f, 3, ks_b, 3, pp);
+    else if (std::is_same<typename M::A, double>::value) rc = plan_opp<M>(ctx, mg_d, 3, ks_d, 3, pp);
+    else rc = plan_opp<M>(ctx, mg_f, 3, ks_f, 3, pp);
+    pok = rc == SBCI_OK;
+  }
+  if (ctx->opp_form == SBCI_OPP_PAIR) {
+    if (!pok) return set_error(SBCI_EINVAL, "opposite-spin sigma: the pair form does not fit in LDS");
+    form = SBCI_OPP_PAIR;
+    return SBCI_OK;
+  }
+  if (ctx->opp_form == SBCI_OPP_ORBITAL) {
+    if (!qok) return set_error(SBCI_EINVAL, "opposite-spin sigma: the orbital form does not fit");
+    form = SBCI_OPP_ORBITAL;
+    return SBCI_OK;
+  }
+  if (!pok && !qok)
+    return set_error(SBCI_EINVAL, "opposite-spin sigma: beta string count too large for LDS");
+  if (!qok) { form = SBCI_OPP_PAIR; return SBCI_OK; }
+  if (!pok) { form = SBCI_OPP_ORBITAL; return SBCI_OK; }
+  const double tiles_pair = (double)pp.ngroups * pp.MG * ((B.ns + 15) / 16) * (pp.nkc * pp.KS);
+  const double tiles_q = (double)ctx->norb * B.mt * (B.nq_pad / 16) * (pq.nkc * pq.KS);
+  form = 3.0 * tiles_q <= 2.0 * tiles_pair ? SBCI_OPP_ORBITAL : SBCI_OPP_PAIR;
+  return SBCI_OK;
+}
+
+template <typename M, typename T>
+int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  if (A.s == 0 || B.m == 0) return SBCI_OK;
+  if (ctx->ndet >= ((int64_t)1 << 31))
+    return set_error(SBCI_EINVAL, "opposite-spin sigma: N_det must be below 2^31");
+  int form = 0;
+  OppPlan pp{};
+  OppQPlan pq{};
+  SBCI_TRY(choose_opp<M>(ctx, form, pp, pq));
+  if (form == SBCI_OPP_ORBITAL) return launch_opp_q<M, T>(ctx, pq, c, out, nvec);
+  return launch_opp_pair<M, T>(ctx, pp, c, out, nvec);
 }
 
 // Same-spin part with the source stripe in LDS: one workgroup per (column
@@ -628,6 +917,17 @@ int sigma_dispatch(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, 
 
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
   return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
+}
+
+int opp_form(sbci_ctx *ctx, int mode, int *form) {
+  OppPlan pp{};
+  OppQPlan pq{};
+  switch (mode) {
+    case SBCI_F64: return choose_opp<MF64>(ctx, *form, pp, pq);
+    case SBCI_F32: return choose_opp<MF32>(ctx, *form, pp, pq);
+    case SBCI_BF16: return choose_opp<MBF16>(ctx, *form, pp, pq);
+    default: return set_error(SBCI_EINVAL, "unknown sigma dtype");
+  }
 }
 
 int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms) {

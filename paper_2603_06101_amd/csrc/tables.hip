@@ -137,6 +137,54 @@ __global__ void k_pair_quads(const uint32_t *__restrict__ pair, int64_t ns_pad, 
   out[e] = make_uint4(c[0], c[1], c[2], c[3]);
 }
 
+// Orbital-grouped tables.  Strings holding orbital q correspond, in the same
+// (ascending) order, to the (m-1)-subsets of the other N-1 orbitals: unrank
+// j over C(N-1, m-1), lift the orbitals >= q by one and add q.
+__global__ void k_colq(int norb, int m, int64_t nq, const int64_t *__restrict__ binom,
+                       int32_t *__restrict__ colq) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (j >= nq) return;
+  int64_t r = j;
+  uint64_t mask = 1ull << q;
+  int o = norb - 2;
+  for (int k = m - 1; k >= 1; --k) {
+    while (binom[o * 65 + k] > r) --o;
+    mask |= 1ull << (o >= q ? o + 1 : o);
+    r -= binom[o * 65 + k];
+    --o;
+  }
+  colq[(int64_t)q * nq + j] = (int32_t)rank_of(mask, binom);
+}
+
+// out[((q * mt + u) * 4 + g) * nq_pad + j] = codes of E_pq colq[q][j] for
+// p = u*16 + orow(g, r), r = 0..3 (orow = g + 4r if GP4R, else 4g + r).
+template <bool GP4R>
+__global__ void k_q_quads(int norb, int mt, int64_t nq, int64_t nq_pad,
+                          const int32_t *__restrict__ colq, const uint64_t *__restrict__ str,
+                          const int64_t *__restrict__ binom, uint4 *__restrict__ out) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int qug = blockIdx.y;  // (q * mt + u) * 4 + g
+  if (j >= nq_pad) return;
+  const int g = qug & 3, u = (qug >> 2) % mt, q = (qug >> 2) / mt;
+  uint32_t c[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
+  if (j < nq) {
+    const int64_t J = colq[(int64_t)q * nq + j];
+    const uint64_t mask = str[J];
+    for (int r = 0; r < 4; ++r) {
+      const int p = u * 16 + (GP4R ? g + 4 * r : 4 * g + r);
+      if (p >= norb) continue;
+      if (p == q) {
+        c[r] = (uint32_t)J << 1;
+      } else if (!((mask >> p) & 1)) {
+        const uint64_t nm = (mask & ~(1ull << q)) | (1ull << p);
+        c[r] = ((uint32_t)rank_of(nm, binom) << 1) | (uint32_t)parity_between(mask, p, q);
+      }
+    }
+  }
+  out[(int64_t)qug * nq_pad + j] = make_uint4(c[0], c[1], c[2], c[3]);
+}
+
 // dst[f][i] = src[i][f] for an [ns][nf] list array
 template <typename T>
 __global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t ns, int nf) {
@@ -302,6 +350,23 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
     k_pair_quads<true><<<gq, 256, 0, st>>>(T.pair, T.ns_pad, ntiles, T.quad_s);
     SBCI_CHECK_LAUNCH();
   }
+  if (m > 0) {
+    T.nq = choose_host(n - 1, m - 1);
+    T.nq_pad = (T.nq + 15) / 16 * 16;
+    T.mt = (n + 15) / 16;
+    SBCI_HIP(hipMalloc(&T.colq, sizeof(int32_t) * T.nq * n));
+    const int64_t nqq = (int64_t)n * T.mt * 4 * T.nq_pad;
+    SBCI_HIP(hipMalloc(&T.qquad_r, sizeof(uint4) * nqq));
+    SBCI_HIP(hipMalloc(&T.qquad_s, sizeof(uint4) * nqq));
+    k_colq<<<dim3((unsigned)((T.nq + bs - 1) / bs), n), bs, 0, st>>>(n, m, T.nq, ctx->binom, T.colq);
+    SBCI_CHECK_LAUNCH();
+    const dim3 gq((unsigned)((T.nq_pad + bs - 1) / bs), (unsigned)(n * T.mt * 4));
+    k_q_quads<false><<<gq, bs, 0, st>>>(n, T.mt, T.nq, T.nq_pad, T.colq, T.str, ctx->binom,
+                                        T.qquad_r);
+    k_q_quads<true><<<gq, bs, 0, st>>>(n, T.mt, T.nq, T.nq_pad, T.colq, T.str, ctx->binom,
+                                       T.qquad_s);
+    SBCI_CHECK_LAUNCH();
+  }
   const int fbs = 64;  // heavy per-thread loops: small blocks
   k_flist<<<(unsigned)((T.ns + fbs - 1) / fbs), fbs, 0, st>>>(n, m, T.ns, T.nf, T.str, ctx->binom,
                                                               ctx->h1, ctx->eri, T.fcol, T.fval64,
@@ -335,6 +400,9 @@ void free_spin(SpinTables &T) {
   hipFree(T.fdiag);
   hipFree(T.quad_r);
   hipFree(T.quad_s);
+  hipFree(T.colq);
+  hipFree(T.qquad_r);
+  hipFree(T.qquad_s);
   hipFree(T.fcolT);
   hipFree(T.fvalT64);
   hipFree(T.fvalT32);

@@ -1,0 +1,108 @@
+"""The two opposite-spin forms of sigma (pair and orbital-grouped) against the
+oracle, through the C ABI.  Both compute the two-electron part between the
+spins of the Hamiltonian of the Results section; they differ only in how the
+contraction is grouped, so each must match the oracle's sigma."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sigma as OS  # noqa: E402
+from workloads import CONFIGS, make_integrals, sigma_inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(n, na, nb, rank=None, seed=0):
+    import paper_2603_06101_amd as sb
+    I = make_integrals(n, rank or 2 * n, seed)
+    return sb.Context(n, na, nb, I.h1, I.eri), I
+
+
+# 16-row orbital tiles MT = 1..4, ragged and single-column string groups
+# (nq = C(N-1, m_beta-1) = 1, 17, 19, 49, 55), Sz != 0, half filling, a
+# fully occupied spin and empty spins
+CASES = [(8, 4, 4), (12, 2, 3), (18, 3, 2), (20, 2, 2), (33, 2, 1), (40, 1, 1), (50, 1, 2),
+         (9, 4, 5), (5, 5, 5), (7, 0, 3), (6, 3, 0)]
+
+
+def _forms(ctx, n):
+    import paper_2603_06101_amd as sb
+    out = ["orbital"]
+    try:
+        ctx.set_opp_form("pair")
+        ctx.opp_form("f64")
+        out.append("pair")
+    except sb.SbciError:
+        assert n >= 40          # the pair form's ERI tile outgrows LDS only there
+    return out
+
+
+@pytest.mark.parametrize("n,na,nb", CASES)
+def test_opp_forms_f64_match_oracle(n, na, nb):
+    ctx, I = _ctx(n, na, nb, seed=3)
+    c = sigma_inputs(5, 2, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    scale = np.abs(want).max()
+    for form in _forms(ctx, n):
+        ctx.set_opp_form(form)
+        if nb > 0 and na > 0:
+            assert ctx.opp_form("f64") == form
+        got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+        err = np.abs(got - want).max() / scale
+        assert err <= 1e-12, (form, err)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,na,nb", [(12, 2, 3), (20, 2, 2), (50, 1, 2), (9, 4, 5)])
+def test_opp_orbital_low_precision(n, na, nb, dtype, tol):
+    ctx, I = _ctx(n, na, nb, seed=4)
+    c = sigma_inputs(6, 1, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    ctx.set_opp_form("orbital")
+    got = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype=dtype).cpu().numpy()
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < tol, rel
+    ctx.close()
+
+
+def test_automatic_form_choice():
+    """Near half filling the pair form issues fewer MFMA tiles; with few
+    electrons in many orbitals the orbital form does (and at 45 orbitals the
+    pair form's ERI tile does not fit in LDS)."""
+    ctx, _ = _ctx(14, 7, 7)
+    assert all(ctx.opp_form(d) == "pair" for d in ("f64", "f32", "bf16"))
+    ctx.close()
+    ctx, _ = _ctx(20, 2, 2)
+    assert ctx.opp_form("f64") == "orbital"
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_sigma_full_size_dilute45_sampled(dtype):
+    """CAS(6e,45o), 201,356,100 determinants (orbital form): sampled rows
+    against the oracle; for FP64 also u.sigma(v) = v.sigma(u)."""
+    cfg = CONFIGS["dilute45"]
+    n, na, nb = cfg["norb"], cfg["na"], cfg["nb"]
+    ctx, I = _ctx(n, na, nb, rank=cfg["rank"], seed=cfg["seed"])
+    assert ctx.opp_form(dtype) == "orbital"
+    c = sigma_inputs(0, 1, ctx.ndet)[0]
+    ct = torch.from_numpy(c if dtype == "f64" else c.astype(np.float32)).cuda()
+    s = ctx.sigma(ct, dtype=dtype)
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([[0, ctx.ndet - 1], rng.integers(0, ctx.ndet, 200)]))
+    want = OS.sigma_rows(n, na, nb, I.h1, I.eri, c, rows)
+    got = s.cpu().numpy()[rows].astype(np.float64)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-2}[dtype]
+    assert err <= tol, err
+    if dtype == "f64":
+        v = torch.from_numpy(sigma_inputs(1, 1, ctx.ndet)[0]).cuda()
+        sv = ctx.sigma(v)
+        a, b = float(ct @ sv), float(v @ s)
+        assert abs(a - b) <= 1e-10 * max(abs(a), 1.0)
+        del v, sv
+    del s, ct
+    ctx.close()
+    torch.cuda.empty_cache()

@@ -117,4 +117,8 @@ CONFIGS = {
     "cas10": dict(norb=10, na=5, nb=5, rank=20, seed=0, nroots=3),
     "cas14": dict(norb=14, na=7, nb=7, rank=28, seed=0, nroots=5),
     "cas16": dict(norb=16, na=8, nb=8, rank=32, seed=0, nroots=1),
+    # few electrons in many orbitals: the shape of the paper's CAS(6e,45o)
+    # instance (201,356,100 determinants), where most orbital pairs connect a
+    # string to nothing
+    "dilute45": dict(norb=45, na=3, nb=3, rank=90, seed=0, nroots=1),
 }
