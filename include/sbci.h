@@ -62,6 +62,18 @@ typedef enum sbci_opp_form {
   SBCI_OPP_ORBITAL = 2
 } sbci_opp_form;
 
+/* Form of the one-electron and same-spin parts H_alpha + H_beta:
+ * SBCI_SAME_LISTS applies each spin's operator from its Slater-Condon lists
+ * (one entry per connected string); SBCI_SAME_DENSE multiplies by the dense
+ * operator on MFMA, the cheaper form when the lists cover a sizeable
+ * fraction of each row (few electrons in many orbitals); SBCI_SAME_AUTO
+ * picks per spin from the sizes. */
+typedef enum sbci_same_form {
+  SBCI_SAME_AUTO = 0,
+  SBCI_SAME_LISTS = 1,
+  SBCI_SAME_DENSE = 2
+} sbci_same_form;
+
 typedef struct sbci_ctx sbci_ctx;
 
 /* Thresholds and policies.  Defaults (sbci_default_opts) are the paper's
@@ -170,6 +182,17 @@ int sbci_set_opp_form(sbci_ctx *ctx, int form);
 /* The opposite-spin form sigma calls of this dtype use (SBCI_OPP_PAIR or
  * SBCI_OPP_ORBITAL) into *form; SBCI_EINVAL if no form fits. */
 int sbci_get_opp_form(sbci_ctx *ctx, int dtype, int *form);
+
+/* Force the same-spin form of later sigma calls (sbci_same_form value), or
+ * SBCI_SAME_AUTO (the default).  The dense form keeps an N_s x N_s operator
+ * per spin and precision (built on first use) and is limited to N_s <= 32768
+ * strings; beyond that a forced dense form makes sigma fail with
+ * SBCI_EINVAL. */
+int sbci_set_same_form(sbci_ctx *ctx, int form);
+
+/* The same-spin form (SBCI_SAME_LISTS or SBCI_SAME_DENSE) sigma calls use
+ * for spin 0 (alpha) or 1 (beta), into *form. */
+int sbci_get_same_form(sbci_ctx *ctx, int spin, int *form);
 
 /* SBCI1 (Algorithm 1 with Sections S1.1-S1.5) for the lowest nroots states.
  * tol > 0 overrides opt: eps0 = tol, r0 = sqrt(tol) (the paper's two pairs,

@@ -20,6 +20,7 @@ SBCI_OK, SBCI_EINVAL, SBCI_ENOMEM, SBCI_EDEVICE, SBCI_ENOCONV, SBCI_ENUMERIC = 0
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2}
+SAME_FORMS = {"auto": 0, "lists": 1, "dense": 2}
 REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
            7: "coef", 8: "refine"}
 
@@ -120,6 +121,8 @@ SIGNATURES = [
     ("sbci_sigma_timed", _I, [_P, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
     ("sbci_set_opp_form", _I, [_P, _I]),
     ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),
+    ("sbci_set_same_form", _I, [_P, _I]),
+    ("sbci_get_same_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
     ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
@@ -261,6 +264,16 @@ class Context:
         f = _I(0)
         _check(lib().sbci_get_opp_form(self.h, DTYPES[dtype], ctypes.byref(f)))
         return {v: k for k, v in OPP_FORMS.items()}[f.value]
+
+    def set_same_form(self, form):
+        """Force the same-spin form ("auto", "lists" or "dense") of later sigma calls."""
+        _check(lib().sbci_set_same_form(self.h, SAME_FORMS[form]))
+
+    def same_form(self, spin=0):
+        """The same-spin form ("lists" or "dense") sigma calls use for spin 0 (alpha) or 1."""
+        f = _I(0)
+        _check(lib().sbci_get_same_form(self.h, spin, ctypes.byref(f)))
+        return {v: k for k, v in SAME_FORMS.items()}[f.value]
 
     def sigma_timed(self, c, dtype="f64", out=None):
         """sigma with per-kernel HIP-event timings: (out, [alpha, opp, transpose, beta, add] ms)."""

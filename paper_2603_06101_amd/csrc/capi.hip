@@ -261,6 +261,20 @@ int sbci_get_opp_form(sbci_ctx *ctx, int dtype, int *form) {
   return opp_form(ctx, dtype, form);
 }
 
+int sbci_set_same_form(sbci_ctx *ctx, int form) {
+  if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
+  if (form != SBCI_SAME_AUTO && form != SBCI_SAME_LISTS && form != SBCI_SAME_DENSE)
+    return set_error(SBCI_EINVAL, "unknown same-spin form");
+  ctx->same_form = form;
+  return SBCI_OK;
+}
+
+int sbci_get_same_form(sbci_ctx *ctx, int spin, int *form) {
+  if (!ctx || !form) return set_error(SBCI_EINVAL, "NULL argument");
+  if (spin != 0 && spin != 1) return set_error(SBCI_EINVAL, "spin must be 0 or 1");
+  return same_form(ctx, spin, form);
+}
+
 int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {
   if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
   return solver_begin(ctx, nroots, tol, opt);

@@ -64,6 +64,10 @@ struct SpinTables {
   int32_t *fcolT = nullptr;
   double *fvalT64 = nullptr;
   float *fvalT32 = nullptr;
+  // dense same-spin operator [ns][ns] (one-electron and same-spin parts),
+  // built on first use by the dense form
+  double *hd64 = nullptr;
+  float *hd32 = nullptr;
   bool shared = false;      // aliases the alpha tables (n_alpha == n_beta)
 };
 
@@ -72,6 +76,11 @@ struct SpinTables {
 // below ~1024 rows the register-streaming kernel is already latency-bound.
 constexpr int64_t kSameLdsMinRows = 1024;
 constexpr int64_t kSameLdsMaxRows = 3840;
+// Dense same-spin form: chosen automatically above the LDS range when the
+// lists hold at least a tenth of a row (there the MFMA product's extra flops
+// cost less than streaming 8 bytes of source per list entry from L2); the
+// dense operator takes ns^2 elements, so it is limited to 32768 strings.
+constexpr int64_t kDenseMaxRows = 32768;
 
 struct Workspace {
   void *ptr = nullptr;
@@ -103,6 +112,7 @@ struct sbci_ctx {
   sbci::Workspace ws_red;         // reduction partials + results
   sbci::Workspace ws_q;           // orbital-grouped copy of c (opposite-spin, dilute form)
   int opp_form = 0;               // SBCI_OPP_AUTO / _PAIR / _ORBITAL
+  int same_form = 0;              // SBCI_SAME_AUTO / _LISTS / _DENSE
   sbci::Solver *solver = nullptr;
   bool trace_on = true;
   std::vector<sbci_step_info> trace;
@@ -147,6 +157,8 @@ int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
 int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms);
 // opposite-spin form (SBCI_OPP_PAIR / SBCI_OPP_ORBITAL) used for this dtype
 int opp_form(sbci_ctx *ctx, int mode, int *form);
+// same-spin form (SBCI_SAME_LISTS / SBCI_SAME_DENSE) of one spin
+int same_form(sbci_ctx *ctx, int spin, int *form);
 
 // ---- vec.hip: vector kernels with FP64 reductions ----
 // Reductions write `nq` doubles to `out` (device); deterministic order.

@@ -63,6 +63,112 @@ __global__ void k_add_t(const T *__restrict__ src, T *__restrict__ dst, int64_t 
   }
 }
 
+// Dense same-spin product, the form for dilute spaces where a spin's
+// same-spin operator is a sizeable fraction dense (about 19 % at
+// CAS(6e,45o)) and its lists are too long to stream from L2:
+//   out (+)= A B      A row-major [Mr][K], B row-major [K][N], out [Mr][N]
+// with A = H_alpha (dense), B = C for the alpha part and A = C, B = H_beta
+// for the beta part (both are plain row-major products, so no transposes).
+// 256 threads per 128 x 128 output tile; K panels of 16 pass through
+// registers into double-buffered LDS; each wave owns a 64 x 64 quadrant of
+// 4 x 4 MFMA tiles (FP64 16x16x4 or FP32 16x16x4).  Tiles are dealt to the
+// 8 XCDs in contiguous ranges, row-panel-major, so the workgroups of one XCD
+// share A's row panel in L2.  blockIdx.y selects the vector (strides sA,
+// sB, sC; 0 for the shared operator).
+template <typename M, typename T>
+__global__ __launch_bounds__(256) void k_gemm(int64_t Mr, int64_t N, int64_t K,
+                                              const T *__restrict__ A, int64_t lda, int64_t sA,
+                                              const T *__restrict__ B, int64_t ldb, int64_t sB,
+                                              T *__restrict__ out, int64_t ldc, int64_t sC,
+                                              int accumulate, int64_t tiles_n, int64_t per_xcd,
+                                              int64_t total) {
+  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int LDA = BK + 1, LDB = BN + 4;
+  __shared__ T As[2][BM * LDA];
+  __shared__ T Bs[2][BK * LDB];
+  const int64_t b = blockIdx.x;
+  const int64_t w = (b & 7) * per_xcd + (b >> 3);
+  if (w >= total) return;
+  const int64_t tm = w / tiles_n, tn = w - tm * tiles_n;
+  const int64_t r0 = tm * BM, c0 = tn * BN;
+  const int64_t v = blockIdx.y;
+  A += v * sA;
+  B += v * sB;
+  out += v * sC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  // staging: A rows ar (8 consecutive k from ak), B row bk (8 consecutive columns from bc)
+  const int ar = tid >> 1, ak = (tid & 1) * 8;
+  const int bkr = tid >> 4, bc = (tid & 15) * 8;
+  T ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    const int64_t row = r0 + ar;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = k0 + ak + u;
+      ra[u] = (row < Mr && k < K) ? A[row * lda + k] : (T)0;
+    }
+    const int64_t kb = k0 + bkr;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t c = c0 + bc + u;
+      rb[u] = (kb < K && c < N) ? B[kb * ldb + c] : (T)0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) As[buf][ar * LDA + ak + u] = ra[u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Bs[buf][bkr * LDB + bc + u] = rb[u];
+  };
+  typename M::Out acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+  const int64_t np = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t p = 0; p < np; ++p) {
+    const int buf = (int)(p & 1);
+    if (p + 1 < np) load((p + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      typename M::Frag fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = As[buf][(wm + 16 * i + li) * LDA + ks * 4 + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = Bs[buf][(ks * 4 + g) * LDB + wn + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
+    }
+    if (p + 1 < np) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wm + 16 * i + M::orow(g, r);
+      if (row >= Mr) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + wn + 16 * j + li;
+        if (c < N) {
+          T *d = out + row * ldc + c;
+          const T x = (T)acc[i][j][r];
+          *d = accumulate ? *d + x : x;
+        }
+      }
+    }
+}
+
 // One wave per list row r; each lane owns VC columns c, c + 64, ... so that
 // every load instruction of the wave reads 64 consecutive elements.  Work
 // items (row group, column tile) are numbered column-tile-major and dealt to
@@ -863,26 +969,104 @@ int rec(sbci_ctx *ctx, PartEvents *pe, int i) {
   return SBCI_OK;
 }
 
+// Row r of the dense same-spin operator: zeros, then the list entries
+// (one workgroup per row; a kernel, not a memset, so that a captured sigma
+// records no memset node).
+template <typename V>
+__global__ void k_densify(const int32_t *__restrict__ fcol, const V *__restrict__ fval, int nf,
+                          int64_t ns, V *__restrict__ H) {
+  const int64_t r = blockIdx.x;
+  V *row = H + r * ns;
+  for (int64_t j = threadIdx.x; j < ns; j += blockDim.x) row[j] = (V)0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nf; e += blockDim.x) row[fcol[r * nf + e]] = fval[r * nf + e];
+}
+
+bool use_dense(const sbci_ctx *ctx, const SpinTables &S) {
+  if (ctx->same_form == SBCI_SAME_DENSE) return true;
+  if (ctx->same_form == SBCI_SAME_LISTS) return false;
+  return S.ns > kSameLdsMaxRows && S.ns <= kDenseMaxRows && (int64_t)S.nf * 10 >= S.ns;
+}
+
+// The dense operator of a spin in the precision of T, built on first use
+// from the lists (beta uses alpha's when the two spins share tables).
+template <typename T>
+int dense_same(sbci_ctx *ctx, SpinTables &S, const T **out) {
+  SpinTables &O = S.shared ? ctx->A : S;
+  if (O.ns > kDenseMaxRows)
+    return set_error(SBCI_EINVAL, "same-spin sigma: too many strings for the dense form");
+  T **slot;
+  const T *vals;
+  if constexpr (std::is_same<T, double>::value) {
+    slot = &O.hd64;
+    vals = O.fval64;
+  } else {
+    slot = &O.hd32;
+    vals = O.fval32;
+  }
+  if (!*slot) {
+    const size_t bytes = sizeof(T) * (size_t)O.ns * O.ns;
+    SBCI_HIP(hipMalloc(slot, bytes));
+    k_densify<T><<<(unsigned)O.ns, 256, 0, ctx->stream>>>(O.fcol, vals, O.nf, O.ns, *slot);
+    SBCI_CHECK_LAUNCH();
+  }
+  if (&O != &S) {
+    if constexpr (std::is_same<T, double>::value) S.hd64 = O.hd64; else S.hd32 = O.hd32;
+  }
+  *out = *slot;
+  return SBCI_OK;
+}
+
+template <typename T>
+int launch_gemm(sbci_ctx *ctx, int64_t Mr, int64_t N, int64_t K, const T *A, int64_t lda,
+                int64_t sA, const T *B, int64_t ldb, int64_t sB, T *out, int64_t ldc, int64_t sC,
+                int nvec, int accumulate) {
+  using G = typename std::conditional<std::is_same<T, double>::value, MF64, MF32>::type;
+  const int64_t tm = (Mr + 127) / 128, tn = (N + 127) / 128;
+  const int64_t total = tm * tn, per_xcd = (total + 7) / 8;
+  if (per_xcd * 8 >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "same-spin sigma: grid too large");
+  k_gemm<G, T><<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec), 256, 0, ctx->stream>>>(
+      Mr, N, K, A, lda, sA, B, ldb, sB, out, ldc, sC, accumulate, tn, per_xcd, total);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
 template <typename T, typename M>
 int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullptr) {
-  const SpinTables &A = ctx->A, &B = ctx->B;
-  const int64_t na = A.ns, nb = B.ns;
-  const size_t vbytes = sizeof(T) * (size_t)ctx->ndet * nvec;
+  SpinTables &A = ctx->A, &B = ctx->B;
+  const int64_t na = A.ns, nb = B.ns, nd = ctx->ndet;
+  const bool dbl = std::is_same<T, double>::value;
+  const bool denseA = use_dense(ctx, A), denseB = use_dense(ctx, B);
+  // alpha part (plain write), then opposite-spin (accumulate)
+  SBCI_TRY(rec(ctx, pe, 0));
+  if (denseA) {
+    const T *H = nullptr;
+    SBCI_TRY(dense_same<T>(ctx, A, &H));
+    SBCI_TRY(launch_gemm<T>(ctx, na, nb, na, H, na, 0, c, nb, nd, out, nb, nd, nvec, 0));
+  } else if (dbl) {
+    SBCI_TRY((launch_same<T, double>(ctx, A, A.fval64, na, nb, c, out, nvec, 0)));
+  } else {
+    SBCI_TRY((launch_same<T, float>(ctx, A, A.fval32, na, nb, c, out, nvec, 0)));
+  }
+  SBCI_TRY(rec(ctx, pe, 1));
+  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec)));
+  SBCI_TRY(rec(ctx, pe, 2));
+  if (denseB) {
+    // beta part as C H_beta, accumulated in place (no transposes)
+    const T *H = nullptr;
+    SBCI_TRY(dense_same<T>(ctx, B, &H));
+    SBCI_TRY(rec(ctx, pe, 3));
+    SBCI_TRY(launch_gemm<T>(ctx, na, nb, nb, c, nb, nd, H, nb, 0, out, nb, nd, nvec, 1));
+    SBCI_TRY(rec(ctx, pe, 4));
+    SBCI_TRY(rec(ctx, pe, 5));
+    return SBCI_OK;
+  }
+  // beta part on C^T, added back transposed
+  const size_t vbytes = sizeof(T) * (size_t)nd * nvec;
   SBCI_TRY(ensure(ctx->ws_t, vbytes));
   SBCI_TRY(ensure(ctx->ws_s, vbytes));
   T *ct = static_cast<T *>(ctx->ws_t.ptr);
   T *st = static_cast<T *>(ctx->ws_s.ptr);
-  const bool dbl = std::is_same<T, double>::value;
-  // alpha part (plain write), then opposite-spin (accumulate)
-  SBCI_TRY(rec(ctx, pe, 0));
-  if (dbl)
-    SBCI_TRY((launch_same<T, double>(ctx, A, A.fval64, na, nb, c, out, nvec, 0)));
-  else
-    SBCI_TRY((launch_same<T, float>(ctx, A, A.fval32, na, nb, c, out, nvec, 0)));
-  SBCI_TRY(rec(ctx, pe, 1));
-  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec)));
-  SBCI_TRY(rec(ctx, pe, 2));
-  // beta part on C^T, added back transposed
   SBCI_TRY(launch_transpose<T>(ctx, c, ct, na, nb, nvec, false));
   SBCI_TRY(rec(ctx, pe, 3));
   if (dbl)
@@ -917,6 +1101,11 @@ int sigma_dispatch(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, 
 
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
   return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
+}
+
+int same_form(sbci_ctx *ctx, int spin, int *form) {
+  *form = use_dense(ctx, spin == 0 ? ctx->A : ctx->B) ? SBCI_SAME_DENSE : SBCI_SAME_LISTS;
+  return SBCI_OK;
 }
 
 int opp_form(sbci_ctx *ctx, int mode, int *form) {

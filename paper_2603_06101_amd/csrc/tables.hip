@@ -401,6 +401,8 @@ void free_spin(SpinTables &T) {
   hipFree(T.quad_r);
   hipFree(T.quad_s);
   hipFree(T.colq);
+  hipFree(T.hd64);
+  hipFree(T.hd32);
   hipFree(T.qquad_r);
   hipFree(T.qquad_s);
   hipFree(T.fcolT);

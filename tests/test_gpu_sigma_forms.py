@@ -1,7 +1,8 @@
-"""The two opposite-spin forms of sigma (pair and orbital-grouped) against the
-oracle, through the C ABI.  Both compute the two-electron part between the
-spins of the Hamiltonian of the Results section; they differ only in how the
-contraction is grouped, so each must match the oracle's sigma."""
+"""The forms of sigma against the oracle, through the C ABI: the two
+opposite-spin forms (pair and orbital-grouped) and the two same-spin forms
+(lists and dense MFMA product).  All compute the Hamiltonian of the Results
+section; they differ only in how the work is grouped, so every combination
+must match the oracle's sigma."""
 import numpy as np
 import pytest
 
@@ -54,6 +55,47 @@ def test_opp_forms_f64_match_oracle(n, na, nb):
     ctx.close()
 
 
+# dense same-spin form: ragged 128-row tiles and K panels (190, 528, 1287,
+# 1716 strings), Sz != 0 (different alpha and beta operators), one string
+# per spin and empty spins
+DENSE_CASES = [(8, 4, 4), (12, 2, 3), (9, 4, 5), (13, 6, 5), (20, 2, 2), (33, 2, 1), (5, 5, 5),
+               (7, 0, 3), (6, 3, 0)]
+
+
+@pytest.mark.parametrize("n,na,nb", DENSE_CASES)
+def test_same_dense_f64_matches_oracle(n, na, nb):
+    ctx, I = _ctx(n, na, nb, seed=5)
+    c = sigma_inputs(7, 2, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    scale = np.abs(want).max()
+    ctx.set_same_form("dense")
+    assert ctx.same_form(0) == ctx.same_form(1) == "dense"
+    for form in _forms(ctx, n):
+        ctx.set_opp_form(form)
+        got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+        err = np.abs(got - want).max() / scale
+        assert err <= 1e-12, (form, err)
+    # the lists form on the same context still agrees (dense operators cached)
+    ctx.set_same_form("lists")
+    ctx.set_opp_form("auto")
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,na,nb", [(12, 2, 3), (13, 6, 5), (20, 2, 2)])
+def test_same_dense_low_precision(n, na, nb, dtype, tol):
+    ctx, I = _ctx(n, na, nb, seed=6)
+    c = sigma_inputs(8, 1, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    ctx.set_same_form("dense")
+    got = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype=dtype).cpu().numpy()
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < tol, rel
+    ctx.close()
+
+
 @pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
 @pytest.mark.parametrize("n,na,nb", [(12, 2, 3), (20, 2, 2), (50, 1, 2), (9, 4, 5)])
 def test_opp_orbital_low_precision(n, na, nb, dtype, tol):
@@ -73,6 +115,7 @@ def test_automatic_form_choice():
     pair form's ERI tile does not fit in LDS)."""
     ctx, _ = _ctx(14, 7, 7)
     assert all(ctx.opp_form(d) == "pair" for d in ("f64", "f32", "bf16"))
+    assert ctx.same_form(0) == ctx.same_form(1) == "lists"
     ctx.close()
     ctx, _ = _ctx(20, 2, 2)
     assert ctx.opp_form("f64") == "orbital"
@@ -81,12 +124,14 @@ def test_automatic_form_choice():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_sigma_full_size_dilute45_sampled(dtype):
-    """CAS(6e,45o), 201,356,100 determinants (orbital form): sampled rows
+    """CAS(6e,45o), 201,356,100 determinants (orbital opposite-spin form,
+    dense same-spin form): sampled rows
     against the oracle; for FP64 also u.sigma(v) = v.sigma(u)."""
     cfg = CONFIGS["dilute45"]
     n, na, nb = cfg["norb"], cfg["na"], cfg["nb"]
     ctx, I = _ctx(n, na, nb, rank=cfg["rank"], seed=cfg["seed"])
     assert ctx.opp_form(dtype) == "orbital"
+    assert ctx.same_form(0) == ctx.same_form(1) == "dense"
     c = sigma_inputs(0, 1, ctx.ndet)[0]
     ct = torch.from_numpy(c if dtype == "f64" else c.astype(np.float32)).cuda()
     s = ctx.sigma(ct, dtype=dtype)
