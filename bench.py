@@ -26,6 +26,8 @@ Reported (one JSON line):
   cas6, cas10, cas16  the other workloads: launch latency (CAS(6,6)),
                SBCI1 vs Davidson over 10 seeds (CAS(10,10)), and the
                165.6 M-determinant ground state, mixed vs FP64 (CAS(16,16));
+  dilute45     CAS(6e,45o), 201.4 M determinants (few electrons in many
+               orbitals): sigma forms and rates, ground state mixed vs FP64;
   cpu_baseline the CPU oracle's plain FP64 string sigma on the host cores,
                on a bounded sample of determinant rows.
 """
@@ -244,6 +246,60 @@ def cas16_section(sb, stream, precision):
     return out
 
 
+def dilute45_section(sb, stream, precision):
+    """dilute45, CAS(6e,45o) (201,356,100 determinants; the shape of the
+    paper's few-electrons-in-many-orbitals instances): the sigma forms chosen,
+    sigma per dtype with the MFMA rate of its two dominant parts, and the
+    ground state to 1e-8 Eh, mixed vs FP64."""
+    import torch
+
+    from workloads import CONFIGS, make_integrals
+    cf = CONFIGS["dilute45"]
+    n, m = cf["norb"], cf["na"]
+    I = make_integrals(n, cf["rank"], cf["seed"])
+    t = time.perf_counter()
+    ctx = sb.Context(n, m, cf["nb"], I.h1, I.eri, stream=stream)
+    torch.cuda.synchronize()
+    ns, s = comb(n, m), m * (n - m + 1)
+    out = {"ndet": ctx.ndet, "create_s": round(time.perf_counter() - t, 3),
+           "forms": {"same_spin": ctx.same_form(0), "opposite_spin": ctx.opp_form("f64")},
+           "sigma": {}}
+    parts = ["same_alpha", "opp_mfma", "transpose", "same_beta", "add_t"]
+    c = torch.randn(ctx.ndet, dtype=torch.float32, device="cuda")
+    for dt in ("bf16", "f32", "f64"):
+        x = c.double() if dt == "f64" else c
+        o, _ = ctx.sigma_timed(x, dt)
+        o, ms = ctx.sigma_timed(x, dt, out=o)
+        out["sigma"][dt] = {
+            "gdet_per_s": round(ctx.ndet / (sum(ms) / 1e3) / 1e9, 3),
+            "kernels_ms": dict(zip(parts, [round(v, 3) for v in ms])),
+            # algorithmic rates: 2 s^2 flops per determinant for the opposite-
+            # spin contraction, 2 N_s per determinant and spin for the dense
+            # same-spin product
+            "opp_tflops": round(2 * s * s * ctx.ndet / (ms[1] / 1e3) / 1e12, 1),
+            "same_dense_tflops": round(2 * ns * ctx.ndet / (ms[0] / 1e3) / 1e12, 1),
+        }
+        del o, x
+    del c
+    res = {}
+    for prec in (precision, "f64"):
+        t = time.perf_counter()
+        r = ctx.solve(1, tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+        torch.cuda.synchronize()
+        res[prec] = (time.perf_counter() - t, r)
+    ctx.close()
+    tm, rm = res[precision]
+    t64, r64 = res["f64"]
+    out["time_to_1e8_s"] = {"mixed": round(tm, 3), "fp64": round(t64, 3), "speedup": round(t64 / tm, 3)}
+    out["nsigma"] = {"f64": rm.report["nsigma_f64"], "low": rm.report["nsigma_low"],
+                     "bf16": rm.report["nsigma_bf16"], "fp64_form": r64.report["nsigma_f64"]}
+    out["energy"] = float(r64.energies[0])
+    out["abs_dE_vs_fp64"] = float(abs(rm.energies[0] - r64.energies[0]))
+    out["peak_vector_GB"] = round(rm.report["peak_vector_bytes"] / 1e9, 2)
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_section(sb, precision):
     """Batching form: 512 uneven instances, one persistent-kernel graph launch per solve,
     in the FP64 form and both mixed forms (each autotuned)."""
@@ -445,6 +501,7 @@ def main():
     if not a.no_configs:
         line.update(small_sections(sb, stream))
         line["cas16"] = cas16_section(sb, stream, a.precision)
+        line["dilute45"] = dilute45_section(sb, stream, a.precision)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
     print(json.dumps(line))
