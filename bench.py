@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cas14", choices=["cas6", "cas10", "cas14", "cas16"])
+    ap.add_argument("--workload", default="cas14",
+                    choices=["cas6", "cas10", "cas14", "cas16", "dilute45"])
     ap.add_argument("--precision", default="bf16", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -110,7 +111,30 @@ def roofline(cfg, ndet, kname, kdt, k_ms):
 
 
 KERNEL_SOURCE = {"opp_mfma": "sigma.hip", "same_alpha": "sigma.hip", "same_beta": "sigma.hip",
-                 "transpose": "sigma.hip", "add_t": "sigma.hip"}
+                 "transpose": "sigma.hip", "add_t": "sigma.hip", "opp_orbital": "sigma.hip",
+                 "same_dense": "sigma.hip"}
+
+
+def kernel_text_sha(path, func):
+    """SHA-256 of one kernel's definition in a source file: from its
+    template line to the closing brace at column 0 (comments above it are
+    not part of it).  Counter figures stay valid while this text is
+    unchanged, whatever else the file gains."""
+    import hashlib
+    import re
+    lines = open(path).read().split("\n")
+    i = next((k for k, ln in enumerate(lines) if re.search(r"\bvoid " + func + r"\(", ln)), None)
+    if i is None:
+        return ""
+    j = i
+    while j > 0 and not lines[j].startswith("template"):
+        if lines[j - 1].strip() == "" or lines[j - 1].startswith("//"):
+            break
+        j -= 1
+    k = i
+    while k < len(lines) and lines[k] != "}":
+        k += 1
+    return hashlib.sha256("\n".join(lines[j:k + 1]).encode()).hexdigest()
 
 
 def measured(kname, kdt, cfg):
@@ -130,8 +154,10 @@ def measured(kname, kdt, cfg):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.split()[0].strip("`") if v.split() else ""
     src = os.path.join(ROOT, "paper_2603_06101_amd", "csrc", KERNEL_SOURCE[kname])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("source_sha256") != sha:
+    if "kernel_sha256" in fields and "kernel" in fields:
+        if fields["kernel_sha256"] != kernel_text_sha(src, fields["kernel"]):
+            return {}
+    elif fields.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return {}
     out = {}
     for key in ("traffic_bytes_per_launch", "mfma_busy"):
@@ -281,6 +307,19 @@ def dilute45_section(sb, stream, precision):
         }
         del o, x
     del c
+    # rooflines of the two MFMA kernels in FP64 (counter figures from the
+    # committed summaries while the kernels' text is unchanged)
+    cfgd = dict(cf, name="dilute45")
+    ms64 = out["sigma"]["f64"]["kernels_ms"]
+    for key, kname, flops, t_ms in (
+            ("roofline_opp_orbital", "opp_orbital", 2 * s * s * ctx.ndet, ms64["opp_mfma"]),
+            ("roofline_same_dense", "same_dense", 2 * ns * ctx.ndet, ms64["same_alpha"])):
+        ach = flops / (t_ms / 1e3) / 1e12
+        meas = measured(kname, "f64", cfgd)
+        out[key] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f64"] / 1e12,
+                    "unit": "TFLOP/s", "frac": round(ach / (PEAK["f64"] / 1e12), 4),
+                    "traffic": meas.get("traffic_bytes_per_launch"),
+                    "mfma_busy": meas.get("mfma_busy"), "ms_per_launch": t_ms}
     res = {}
     for prec in (precision, "f64"):
         t = time.perf_counter()
