@@ -69,21 +69,25 @@ __global__ void k_add_t(const T *__restrict__ src, T *__restrict__ dst, int64_t 
 //   out (+)= A B      A row-major [Mr][K], B row-major [K][N], out [Mr][N]
 // with A = H_alpha (dense), B = C for the alpha part and A = C, B = H_beta
 // for the beta part (both are plain row-major products, so no transposes).
-// 256 threads per 128 x 128 output tile; K panels of 16 pass through
-// registers into double-buffered LDS; each wave owns a 64 x 64 quadrant of
-// 4 x 4 MFMA tiles (FP64 16x16x4 or FP32 16x16x4).  Tiles are dealt to the
-// 8 XCDs in contiguous ranges, row-panel-major, so the workgroups of one XCD
-// share A's row panel in L2.  blockIdx.y selects the vector (strides sA,
+// WM x WN waves per (64 WM) x (64 WN) output tile; K panels of 16 pass
+// through registers into double-buffered LDS; each wave owns a 64 x 64 block
+// of 4 x 4 MFMA tiles (FP64 16x16x4 or FP32 16x16x4).  Tiles are dealt to
+// the 8 XCDs in contiguous ranges, row-panel-major, so the workgroups of one
+// XCD share A's row panel in L2.  blockIdx.y selects the vector (strides sA,
 // sB, sC; 0 for the shared operator).
-template <typename M, typename T>
-__global__ __launch_bounds__(256) void k_gemm(int64_t Mr, int64_t N, int64_t K,
+template <typename M, typename T, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(int64_t Mr, int64_t N, int64_t K,
                                               const T *__restrict__ A, int64_t lda, int64_t sA,
                                               const T *__restrict__ B, int64_t ldb, int64_t sB,
                                               T *__restrict__ out, int64_t ldc, int64_t sC,
                                               int accumulate, int64_t tiles_n, int64_t per_xcd,
                                               int64_t total) {
-  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int BM = 64 * WM, BN = 64 * WN, BK = 16, NT = 64 * WM * WN;
   constexpr int LDA = BK + 1, LDB = BN + 4;
+  // staging: each thread moves AE consecutive k of one A row and BE
+  // consecutive columns of one B row per panel
+  constexpr int AE = BM * BK / NT, BE = BK * BN / NT;
+  static_assert(AE >= 1 && BE >= 1 && BK % AE == 0 && BN % BE == 0, "staging layout");
   __shared__ T As[2][BM * LDA];
   __shared__ T Bs[2][BK * LDB];
   const int64_t b = blockIdx.x;
@@ -97,30 +101,29 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t Mr, int64_t N, int64_t K,
   out += v * sC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  // staging: A rows ar (8 consecutive k from ak), B row bk (8 consecutive columns from bc)
-  const int ar = tid >> 1, ak = (tid & 1) * 8;
-  const int bkr = tid >> 4, bc = (tid & 15) * 8;
-  T ra[8], rb[8];
+  const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
+  const int ar = tid / (BK / AE), ak = (tid % (BK / AE)) * AE;
+  const int bkr = tid / (BN / BE), bc = (tid % (BN / BE)) * BE;
+  T ra[AE], rb[BE];
   auto load = [&](int64_t k0) {
     const int64_t row = r0 + ar;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < AE; ++u) {
       const int64_t k = k0 + ak + u;
       ra[u] = (row < Mr && k < K) ? A[row * lda + k] : (T)0;
     }
     const int64_t kb = k0 + bkr;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < BE; ++u) {
       const int64_t c = c0 + bc + u;
       rb[u] = (kb < K && c < N) ? B[kb * ldb + c] : (T)0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) As[buf][ar * LDA + ak + u] = ra[u];
+    for (int u = 0; u < AE; ++u) As[buf][ar * LDA + ak + u] = ra[u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Bs[buf][bkr * LDB + bc + u] = rb[u];
+    for (int u = 0; u < BE; ++u) Bs[buf][bkr * LDB + bc + u] = rb[u];
   };
   typename M::Out acc[4][4];
 #pragma unroll
@@ -1021,11 +1024,15 @@ template <typename T>
 int launch_gemm(sbci_ctx *ctx, int64_t Mr, int64_t N, int64_t K, const T *A, int64_t lda,
                 int64_t sA, const T *B, int64_t ldb, int64_t sB, T *out, int64_t ldc, int64_t sC,
                 int nvec, int accumulate) {
+  // tile shapes measured on gfx950 at 14190^3: FP64 128 x 256 (8 waves,
+  // 48 TF/s; 16 waves spill the accumulators), FP32 256 x 256 (16 waves,
+  // 97 TF/s); both about 1.4x the 128 x 128 tile
   using G = typename std::conditional<std::is_same<T, double>::value, MF64, MF32>::type;
-  const int64_t tm = (Mr + 127) / 128, tn = (N + 127) / 128;
+  constexpr int WM = std::is_same<T, double>::value ? 2 : 4, WN = 4;
+  const int64_t tm = (Mr + 64 * WM - 1) / (64 * WM), tn = (N + 64 * WN - 1) / (64 * WN);
   const int64_t total = tm * tn, per_xcd = (total + 7) / 8;
   if (per_xcd * 8 >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "same-spin sigma: grid too large");
-  k_gemm<G, T><<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec), 256, 0, ctx->stream>>>(
+  k_gemm<G, T, WM, WN><<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec), 64 * WM * WN, 0, ctx->stream>>>(
       Mr, N, K, A, lda, sA, B, ldb, sB, out, ldc, sC, accumulate, tn, per_xcd, total);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
