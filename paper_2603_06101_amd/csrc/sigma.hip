@@ -522,13 +522,17 @@ int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const T *c, T *out, int nve
 //   sigma[Ia][I'] += sign' M_q[p][j]   for E_pq colq[q][j] = sign' |I'>
 // Cq[q][Ia][j] = C[Ia][colq[q][j]] is gathered once per sigma (k_gather_q),
 // so B fragments are contiguous row segments as in k_opp.  Per determinant
-// this issues 2 N m_beta s flops (k_opp: 2 npair s; minimum 2 s^2).
+// this issues 2 N m_beta s flops (k_opp: 2 npair s; minimum 2 s^2).  Rows
+// are dealt to the 8 XCDs in contiguous ranges: neighbouring rows differ in
+// one orbital and share many excited strings J_e, so the workgroups of one
+// XCD, which sweep q together, find the same Cq rows in its L2.
 // LDS (dynamic): acc[nsb + 64] | Ws[MT*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
 template <typename M, typename T, int MT, int KS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_opp_q(
     int64_t nsa, int64_t nsb, int norb, int64_t nq, int64_t nq_pad, int s, int npair, int nkc,
-    const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
-    const uint4 *__restrict__ quads, const T *__restrict__ cq, T *__restrict__ sigma) {
+    int64_t per_xcd, const float *__restrict__ Wf, const double *__restrict__ Wd,
+    const Ent *__restrict__ taba, const uint4 *__restrict__ quads, const T *__restrict__ cq,
+    T *__restrict__ sigma) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
@@ -537,7 +541,8 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
   constexpr int ROWS = MT * 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ia = blockIdx.x;
+  const int64_t ia = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (ia >= nsa) return;  // uniform over the workgroup
   const int64_t vo = (int64_t)blockIdx.y * nsa * nsb;
   const int ktot = nkc * KW;
   Acc *acc = reinterpret_cast<Acc *>(smem);
@@ -566,24 +571,49 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
   const int g = lane >> 4;
   const int li = lane & 15;
   const uint32_t pstride = (uint32_t)nq_pad;
-  for (int q = 0; q < norb; ++q) {
-    const T *__restrict__ cv = cq + ((int64_t)blockIdx.y * norb + q) * nsa * nq;
-    const uint4 *__restrict__ qq = quads + (int64_t)q * MT * 4 * nq_pad;
-    for (int kc = 0; kc < nkc; ++kc) {
-      __syncthreads();  // entries ready; the previous A tile is no longer read
-      for (int idx = tid; idx < ROWS * KW; idx += 64 * NW) {
+  // The A tile of chunk (q, kc) is fetched into registers while the previous
+  // chunk's MFMAs run, and stored to LDS between two barriers.
+  constexpr int NA = (ROWS * KW + 64 * NW - 1) / (64 * NW);
+  A va[NA];
+  auto fetch_a = [&](int q, int kc) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int idx = tid + i * 64 * NW;
+      A v = M::cvt(0.0f);
+      if (idx < ROWS * KW) {
         const int p = idx / KW, k = idx - p * KW;
         const int w = eW[kc * KW + k];
-        A v = M::cvt(0.0f);
         if (w != kPadEntry && p < norb) {
           const int kl = w & 0x7fffffff;
           const int64_t pq = pair_index(p, q);
           const double x = Wd ? Wd[pq * npair + kl] : (double)Wf[pq * npair + kl];
           v = M::cvt(w < 0 ? -x : x);
         }
-        Ws[p * LDW + k] = v;
+      }
+      va[i] = v;
+    }
+  };
+  __syncthreads();  // entries ready
+  fetch_a(0, 0);
+  for (int q = 0; q < norb; ++q) {
+    const T *__restrict__ cv = cq + ((int64_t)blockIdx.y * norb + q) * nsa * nq;
+    const uint4 *__restrict__ qq = quads + (int64_t)q * MT * 4 * nq_pad;
+    for (int kc = 0; kc < nkc; ++kc) {
+      __syncthreads();  // the previous A tile is no longer read
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int idx = tid + i * 64 * NW;
+        if (idx < ROWS * KW) {
+          const int p = idx / KW, k = idx - p * KW;
+          Ws[p * LDW + k] = va[i];
+        }
       }
       __syncthreads();
+      {
+        const int kn = kc + 1 < nkc ? kc + 1 : 0;
+        const int qn = kc + 1 < nkc ? q : q + 1;
+        if (qn < norb) fetch_a(qn, kn);
+      }
       uint32_t boff[KS][M::KPL];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
@@ -718,8 +748,10 @@ int launch_opp_q_k(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const doub
     attr = true;
   }
   const uint4 *quads = std::is_same<typename M::A, double>::value ? B.qquad_s : B.qquad_r;
-  kern<<<dim3((unsigned)A.ns, (unsigned)nvec), 64 * NW, p.lds, ctx->stream>>>(
-      A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, Wf, Wd, A.tab, quads, cq, out);
+  const int64_t per_xcd = (A.ns + 7) / 8;
+  kern<<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec), 64 * NW, p.lds, ctx->stream>>>(
+      A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, per_xcd, Wf, Wd, A.tab, quads,
+      cq, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
