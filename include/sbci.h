@@ -55,11 +55,17 @@ typedef enum sbci_dtype {
  * pair {k'l'} per beta string, the cheaper form near half filling;
  * SBCI_OPP_ORBITAL groups beta strings by the orbital q that E_pq empties,
  * the cheaper form when few electrons occupy many orbitals; SBCI_OPP_AUTO
- * picks one per sigma dtype from the sizes. */
+ * picks one per sigma dtype from the sizes.  When a row of sigma (one alpha
+ * string, all beta strings) does not fit in LDS, the orbital form splits it
+ * into windows of beta strings, each recomputing the contraction (more
+ * MFMA work, no size limit); SBCI_OPP_ORBITAL_WINDOWED forces at least two
+ * windows.  sbci_get_opp_form reports either orbital variant as
+ * SBCI_OPP_ORBITAL. */
 typedef enum sbci_opp_form {
   SBCI_OPP_AUTO = 0,
   SBCI_OPP_PAIR = 1,
-  SBCI_OPP_ORBITAL = 2
+  SBCI_OPP_ORBITAL = 2,
+  SBCI_OPP_ORBITAL_WINDOWED = 3
 } sbci_opp_form;
 
 /* Form of the one-electron and same-spin parts H_alpha + H_beta:

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsbci.so")
 SBCI_OK, SBCI_EINVAL, SBCI_ENOMEM, SBCI_EDEVICE, SBCI_ENOCONV, SBCI_ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
-OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2}
+OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2, "orbital_windowed": 3}
 SAME_FORMS = {"auto": 0, "lists": 1, "dense": 2}
 REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
            7: "coef", 8: "refine"}
@@ -263,7 +263,7 @@ class Context:
         """The opposite-spin form ("pair" or "orbital") sigma calls of this dtype use."""
         f = _I(0)
         _check(lib().sbci_get_opp_form(self.h, DTYPES[dtype], ctypes.byref(f)))
-        return {v: k for k, v in OPP_FORMS.items()}[f.value]
+        return {1: "pair", 2: "orbital"}[f.value]
 
     def set_same_form(self, form):
         """Force the same-spin form ("auto", "lists" or "dense") of later sigma calls."""

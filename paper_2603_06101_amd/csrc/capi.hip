@@ -248,7 +248,8 @@ int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec
 
 int sbci_set_opp_form(sbci_ctx *ctx, int form) {
   if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
-  if (form != SBCI_OPP_AUTO && form != SBCI_OPP_PAIR && form != SBCI_OPP_ORBITAL)
+  if (form != SBCI_OPP_AUTO && form != SBCI_OPP_PAIR && form != SBCI_OPP_ORBITAL &&
+      form != SBCI_OPP_ORBITAL_WINDOWED)
     return set_error(SBCI_EINVAL, "unknown opposite-spin form");
   ctx->opp_form = form;
   return SBCI_OK;

@@ -525,12 +525,15 @@ int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const T *c, T *out, int nve
 // this issues 2 N m_beta s flops (k_opp: 2 npair s; minimum 2 s^2).  Rows
 // are dealt to the 8 XCDs in contiguous ranges: neighbouring rows differ in
 // one orbital and share many excited strings J_e, so the workgroups of one
-// XCD, which sweep q together, find the same Cq rows in its L2.
-// LDS (dynamic): acc[nsb + 64] | Ws[MT*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
+// XCD, which sweep q together, find the same Cq rows in its L2.  When
+// sigma's row does not fit in LDS, blockIdx.z selects a window of win
+// target strings: the workgroup computes every M_q but scatters only the
+// targets in its window (nwin windows cost nwin times the MFMA work).
+// LDS (dynamic): acc[win + 64] | Ws[MT*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
 template <typename M, typename T, int MT, int KS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_opp_q(
     int64_t nsa, int64_t nsb, int norb, int64_t nq, int64_t nq_pad, int s, int npair, int nkc,
-    int64_t per_xcd, const float *__restrict__ Wf, const double *__restrict__ Wd,
+    int64_t per_xcd, int64_t win, const float *__restrict__ Wf, const double *__restrict__ Wd,
     const Ent *__restrict__ taba, const uint4 *__restrict__ quads, const T *__restrict__ cq,
     T *__restrict__ sigma) {
   using A = typename M::A;
@@ -544,9 +547,12 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
   const int64_t ia = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (ia >= nsa) return;  // uniform over the workgroup
   const int64_t vo = (int64_t)blockIdx.y * nsa * nsb;
+  const int64_t t0 = (int64_t)blockIdx.z * win;
+  const int64_t tlen = t0 >= nsb ? 0 : (nsb - t0 < win ? nsb - t0 : win);
+  const uint32_t t032 = (uint32_t)t0, tlen32 = (uint32_t)tlen;
   const int ktot = nkc * KW;
   Acc *acc = reinterpret_cast<Acc *>(smem);
-  size_t off = ((size_t)(nsb + 64) * sizeof(Acc) + 15) & ~(size_t)15;
+  size_t off = ((size_t)(win + 64) * sizeof(Acc) + 15) & ~(size_t)15;
   A *Ws = reinterpret_cast<A *>(smem + off);
   off += (((size_t)ROWS * LDW * sizeof(A)) + 15) & ~(size_t)15;
   uint32_t *eoff = reinterpret_cast<uint32_t *>(smem + off);
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
       eW[e] = kPadEntry;
     }
   }
-  for (int64_t j = tid; j < nsb + 64; j += 64 * NW) acc[j] = (Acc)0;
+  for (int64_t j = tid; j < win + 64; j += 64 * NW) acc[j] = (Acc)0;
 
   const int njt = (int)(nq_pad / 16);
   const int g = lane >> 4;
@@ -663,10 +669,11 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const uint32_t cd = cds[r];
-            if (cd != kInvalid) {
+            const uint32_t tw = (cd >> 1) - t032;  // wraps above tlen if below t0
+            if (cd != kInvalid && tw < tlen32) {
               Acc v = (Acc)out[u][r];
               if (cd & 1u) v = -v;
-              atomicAdd(&acc[cd >> 1], v);
+              atomicAdd(&acc[tw], v);
             }
           }
         }
@@ -674,8 +681,8 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
     }
   }
   __syncthreads();
-  T *__restrict__ sv = sigma + vo + ia * nsb;
-  for (int64_t j = tid; j < nsb; j += 64 * NW) sv[j] += (T)acc[j];
+  T *__restrict__ sv = sigma + vo + ia * nsb + t0;
+  for (int64_t j = tid; j < tlen; j += 64 * NW) sv[j] += (T)acc[j];
 }
 
 // cq[v][q][Ia][j] = c[v][Ia][colq[q][j]]; blocks of one row Ia are adjacent
@@ -696,43 +703,53 @@ __global__ void k_gather_q(const T *__restrict__ c, T *__restrict__ cq,
 
 struct OppQPlan {
   int KS = 0, nkc = 0;
+  int64_t win = 0, nwin = 0;  // target window of sigma's row and window count
   size_t lds = 0;
 };
 
 template <typename M>
-size_t oppq_lds(int64_t nsb, int MT, int KS, int nkc) {
+size_t oppq_lds(int64_t win, int MT, int KS, int nkc) {
   const int KW = KS * M::KSTEP, LDW = KW + M::PAD;
-  size_t b = ((size_t)(nsb + 64) * sizeof(typename M::Acc) + 15) & ~(size_t)15;
+  size_t b = ((size_t)(win + 64) * sizeof(typename M::Acc) + 15) & ~(size_t)15;
   b += (((size_t)MT * 16 * LDW * sizeof(typename M::A)) + 15) & ~(size_t)15;
   b += (size_t)nkc * KW * 8;
   return b;
 }
 
-// K tile (k-steps per chunk) with the least K padding that fits in LDS
-// (ties: fewer chunks); false if none fits.
+// K tile (k-steps per chunk) and target windows: the fewest windows that
+// fit in LDS (at least min_win), then the least K padding (ties: fewer
+// chunks); false if nothing fits.
 template <typename M>
-bool plan_opp_q(const sbci_ctx *ctx, OppQPlan &p) {
+bool plan_opp_q(const sbci_ctx *ctx, OppQPlan &p, int64_t min_win) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (B.nq == 0 || B.mt < 1 || B.mt > 4) return false;
   static const int ks_w[3] = {9, 12, 17};
   static const int ks_b[3] = {1, 3, 5};
   const int *opts = M::KPL == 8 ? ks_b : ks_w;
   const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
+  const size_t cap = 160 * 1024;
   p = OppQPlan();
-  int best = 1 << 30;
+  int64_t best = -1;
   for (int i = 0; i < 3; ++i) {
     const int ks = opts[i], nkc = (kst + ks - 1) / ks;
-    if (oppq_lds<M>(B.ns, B.mt, ks, nkc) > 160 * 1024) continue;
-    const int padded = nkc * ks;
-    if (padded < best || (padded == best && nkc < p.nkc)) {
-      best = padded;
+    const size_t fixed = oppq_lds<M>(0, B.mt, ks, nkc) + 16;
+    if (fixed + 128 * sizeof(typename M::Acc) > cap) continue;
+    const int64_t wmax = (int64_t)((cap - fixed) / sizeof(typename M::Acc)) - 64;
+    int64_t nwin = (B.ns + wmax - 1) / wmax;
+    if (nwin < min_win) nwin = min_win;
+    if (nwin > B.ns) nwin = B.ns;
+    const int64_t cost = nwin * 4096 + (int64_t)nkc * ks;  // windows first, then K padding
+    if (best < 0 || cost < best || (cost == best && nkc < p.nkc)) {
+      best = cost;
       p.KS = ks;
       p.nkc = nkc;
+      p.win = (B.ns + nwin - 1) / nwin;
+      p.nwin = (B.ns + p.win - 1) / p.win;  // every window non-empty
     }
   }
-  if (p.KS == 0) return false;
-  p.lds = oppq_lds<M>(B.ns, B.mt, p.KS, p.nkc);
-  return true;
+  if (p.KS == 0 || p.nwin > 65535) return false;
+  p.lds = oppq_lds<M>(p.win, B.mt, p.KS, p.nkc);
+  return p.lds <= cap;
 }
 
 template <typename M, typename T, int MT, int KS>
@@ -749,9 +766,9 @@ int launch_opp_q_k(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const doub
   }
   const uint4 *quads = std::is_same<typename M::A, double>::value ? B.qquad_s : B.qquad_r;
   const int64_t per_xcd = (A.ns + 7) / 8;
-  kern<<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec), 64 * NW, p.lds, ctx->stream>>>(
-      A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, per_xcd, Wf, Wd, A.tab, quads,
-      cq, out);
+  kern<<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec, (unsigned)p.nwin), 64 * NW, p.lds,
+         ctx->stream>>>(A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, per_xcd, p.win,
+                        Wf, Wd, A.tab, quads, cq, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -801,7 +818,8 @@ int launch_opp_q(sbci_ctx *ctx, const OppQPlan &p, const T *c, T *out, int nvec)
 template <typename M>
 int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
   const SpinTables &A = ctx->A, &B = ctx->B;
-  const bool qok = plan_opp_q<M>(ctx, pq) && (uint64_t)A.ns * (uint64_t)B.nq < (1ull << 32);
+  const int64_t min_win = ctx->opp_form == SBCI_OPP_ORBITAL_WINDOWED ? 2 : 1;
+  const bool qok = plan_opp_q<M>(ctx, pq, min_win) && (uint64_t)A.ns * (uint64_t)B.nq < (1ull << 32);
   bool pok = false;
   {
     // K tiles (k-steps per chunk) offered to the pair planner; the register
@@ -822,7 +840,7 @@ int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
     form = SBCI_OPP_PAIR;
     return SBCI_OK;
   }
-  if (ctx->opp_form == SBCI_OPP_ORBITAL) {
+  if (ctx->opp_form == SBCI_OPP_ORBITAL || ctx->opp_form == SBCI_OPP_ORBITAL_WINDOWED) {
     if (!qok) return set_error(SBCI_EINVAL, "opposite-spin sigma: the orbital form does not fit");
     form = SBCI_OPP_ORBITAL;
     return SBCI_OK;
@@ -832,7 +850,8 @@ int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
   if (!qok) { form = SBCI_OPP_PAIR; return SBCI_OK; }
   if (!pok) { form = SBCI_OPP_ORBITAL; return SBCI_OK; }
   const double tiles_pair = (double)pp.ngroups * pp.MG * ((B.ns + 15) / 16) * (pp.nkc * pp.KS);
-  const double tiles_q = (double)ctx->norb * B.mt * (B.nq_pad / 16) * (pq.nkc * pq.KS);
+  const double tiles_q =
+      (double)ctx->norb * B.mt * (B.nq_pad / 16) * (pq.nkc * pq.KS) * (double)pq.nwin;
   form = 3.0 * tiles_q <= 2.0 * tiles_pair ? SBCI_OPP_ORBITAL : SBCI_OPP_PAIR;
   return SBCI_OK;
 }

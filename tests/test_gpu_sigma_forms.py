@@ -29,7 +29,7 @@ CASES = [(8, 4, 4), (12, 2, 3), (18, 3, 2), (20, 2, 2), (33, 2, 1), (40, 1, 1), 
 
 def _forms(ctx, n):
     import paper_2603_06101_amd as sb
-    out = ["orbital"]
+    out = ["orbital", "orbital_windowed"]
     try:
         ctx.set_opp_form("pair")
         ctx.opp_form("f64")
@@ -48,7 +48,7 @@ def test_opp_forms_f64_match_oracle(n, na, nb):
     for form in _forms(ctx, n):
         ctx.set_opp_form(form)
         if nb > 0 and na > 0:
-            assert ctx.opp_form("f64") == form
+            assert ctx.opp_form("f64") == form.replace("_windowed", "")
         got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
         err = np.abs(got - want).max() / scale
         assert err <= 1e-12, (form, err)
@@ -102,10 +102,11 @@ def test_opp_orbital_low_precision(n, na, nb, dtype, tol):
     ctx, I = _ctx(n, na, nb, seed=4)
     c = sigma_inputs(6, 1, ctx.ndet)
     want = OS.sigma(n, na, nb, I.h1, I.eri, c)
-    ctx.set_opp_form("orbital")
-    got = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype=dtype).cpu().numpy()
-    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
-    assert rel < tol, rel
+    for form in ("orbital", "orbital_windowed"):
+        ctx.set_opp_form(form)
+        got = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype=dtype).cpu().numpy()
+        rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert rel < tol, (form, rel)
     ctx.close()
 
 
@@ -148,6 +149,29 @@ def test_sigma_full_size_dilute45_sampled(dtype):
         a, b = float(ct @ sv), float(v @ s)
         assert abs(a - b) <= 1e-10 * max(abs(a), 1.0)
         del v, sv
+    del s, ct
+    ctx.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sigma_full_size_dilute29_sampled(dtype):
+    """CAS(8e,29o), 564,110,001 determinants: a row of sigma (23,751 beta
+    strings) exceeds LDS, so the orbital form runs in target windows;
+    sampled rows against the oracle."""
+    cfg = CONFIGS["dilute29"]
+    n, na, nb = cfg["norb"], cfg["na"], cfg["nb"]
+    ctx, I = _ctx(n, na, nb, rank=cfg["rank"], seed=cfg["seed"])
+    assert ctx.opp_form(dtype) == "orbital"
+    c = sigma_inputs(2, 1, ctx.ndet)[0]
+    ct = torch.from_numpy(c if dtype == "f64" else c.astype(np.float32)).cuda()
+    s = ctx.sigma(ct, dtype=dtype)
+    rng = np.random.default_rng(13)
+    rows = np.unique(np.concatenate([[0, ctx.ndet - 1], rng.integers(0, ctx.ndet, 150)]))
+    want = OS.sigma_rows(n, na, nb, I.h1, I.eri, c, rows)
+    got = s.cpu().numpy()[rows].astype(np.float64)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= {"f64": 1e-12, "f32": 1e-5}[dtype], err
     del s, ct
     ctx.close()
     torch.cuda.empty_cache()

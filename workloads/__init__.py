@@ -121,4 +121,7 @@ CONFIGS = {
     # instance (201,356,100 determinants), where most orbital pairs connect a
     # string to nothing
     "dilute45": dict(norb=45, na=3, nb=3, rank=90, seed=0, nroots=1),
+    # the shape of the paper's CAS(8e,29o) instance (564,110,001 determinants):
+    # one row of sigma (23,751 beta strings) exceeds LDS
+    "dilute29": dict(norb=29, na=4, nb=4, rank=58, seed=0, nroots=1),
 }
