@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-form section")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the cas6 / cas10 / cas16 sections")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="run only the solver comparison on dilute45 with 6 roots (the shape of "
+                         "the paper's CAS(6e,45o) excited-state instance; several minutes) and "
+                         "print it")
     ap.add_argument("--only-batch", action="store_true",
                     help="profiling driver: run only the batching-form section and print it")
     ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
@@ -339,6 +343,56 @@ def dilute45_section(sb, stream, precision):
     return out
 
 
+def paper_shapes_section(sb, stream, precision):
+    """dilute45 with 6 roots, the shape of the paper's CAS(6e,45o) excited-
+    state instance: SBCI1 (mixed and FP64), SBCI2 and Davidson on the same
+    sigma; time to 1e-8 Eh, sigma applications, peak vector memory and the
+    agreement of the roots.  A progress line goes to stderr after each solve."""
+    import numpy as np
+    import torch
+
+    from workloads import CONFIGS, make_integrals
+    cf = CONFIGS["dilute45"]
+    nroots = 6
+    I = make_integrals(cf["norb"], cf["rank"], cf["seed"])
+    ctx = sb.Context(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri, stream=stream)
+    out = {"workload": "dilute45", "ndet": ctx.ndet, "nroots": nroots, "solvers": {}}
+    runs = (("sbci1_" + precision, lambda: ctx.solve(nroots, tol=1e-10, opts=dict(precision=precision),
+                                                     want_vectors=False)),
+            ("sbci1_f64", lambda: ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"),
+                                            want_vectors=False)),
+            ("sbci2_f64", lambda: ctx.solve2(nroots, tol=1e-10, want_vectors=False)),
+            ("davidson_f64", lambda: ctx.davidson(nroots, tol=1e-10, want_vectors=False)))
+    energies = {}
+    last = [time.perf_counter()]
+
+    def progress(step):
+        # a line from the solve's own step records, at most every 20 s
+        now = time.perf_counter()
+        if now - last[0] >= 20.0:
+            last[0] = now
+            print(f"paper-shapes:   root {step['root']} step {step['t']} E {step['E']:.10f} "
+                  f"|z'| {step['dz']:.2e} at {step['seconds']:.0f} s", file=sys.stderr, flush=True)
+
+    ctx.set_progress(progress)
+    for name, fn in runs:
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        energies[name] = np.sort(np.asarray(r.energies))
+        out["solvers"][name] = {"seconds": round(dt, 2), "nsigma_f64": r.report["nsigma_f64"],
+                                "nsigma_low": r.report.get("nsigma_low", 0),
+                                "peak_vector_GB": round(r.report["peak_vector_bytes"] / 1e9, 2),
+                                "status": r.status}
+        print(f"paper-shapes: {name} {dt:.1f} s", file=sys.stderr, flush=True)
+    ctx.close()
+    ref = energies["davidson_f64"]
+    out["energies_davidson"] = [float(e) for e in ref]
+    out["max_abs_dE_vs_davidson"] = {k: float(np.abs(v - ref).max()) for k, v in energies.items()}
+    return out
+
+
 def batch_section(sb, precision):
     """Batching form: 512 uneven instances, one persistent-kernel graph launch per solve,
     in the FP64 form and both mixed forms (each autotuned)."""
@@ -435,6 +489,9 @@ def main():
     stream = torch.cuda.current_stream()
     if a.only_batch:
         print(json.dumps(batch_section(sb, a.precision)))
+        return
+    if a.paper_shapes:
+        print(json.dumps(paper_shapes_section(sb, stream, a.precision)))
         return
     if a.kernel_driver:
         ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)

@@ -223,6 +223,16 @@ int sbci_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report *
 int sbci_set_trace(sbci_ctx *ctx, int on);
 int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max);
 
+/* Progress of long solves: fn(info, user) is called on the host thread that
+ * runs the solve, after every step of sbci_solve / sbci_step / sbci_solve2
+ * (the record the trace would hold, whether or not tracing is on) and after
+ * every iteration of sbci_davidson (root = lowest unconverged root, t = the
+ * iteration, E its Ritz value, dE its change, dz its residual norm, reason 1
+ * once every root has converged).  fn = NULL removes it.  The callback must
+ * not call into the library with this context. */
+typedef void (*sbci_progress_fn)(const sbci_step_info *info, void *user);
+int sbci_set_progress(sbci_ctx *ctx, sbci_progress_fn fn, void *user);
+
 /* Block Davidson-Liu on the same sigma (the paper's baseline method):
  * block = nroots, preconditioner (D - theta_k)^-1, subspace cap max_space
  * (12 + nroots by default), collapse to the Ritz vectors.  Same outputs and

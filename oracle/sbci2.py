@@ -40,6 +40,12 @@ Readings of points the paper leaves open:
   carried to acceptance (X of the accepted state, normalised) is H x_c up to
   rounding, so the projection uses it (s78_images = True, the default);
   s78_images = False keeps the printed E_c x_c.
+  S130a and S130b need only the step's coefficients (|x_{t+1}| = |k|, since
+  the updated vectors are k times S-orthonormal Ritz vectors), so they are
+  tested before the update, and their restart takes the two Ritz vectors
+  from the basis: identical to normalising the updated vectors in exact
+  arithmetic, but free of the cancellation x_t + B y ~ 0 that the update
+  suffers when |k| << 1, which otherwise leaves X inconsistent with H x.
 """
 from __future__ import annotations
 
@@ -221,6 +227,30 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                     break
                 Enew = np.array(w[:2], dtype=float)
                 A, B, C = cf["A"], cf["B"], cf["C"]
+                dE = abs(Enew[0] - E[0])
+                # S130a and S130b are decided by the step's coefficients: the
+                # updated vectors are k times the two lowest Ritz vectors, which
+                # are orthonormal in the overlap metric, so |x_{t+1}| = |k|
+                kn = np.abs(np.array(cf["k"], dtype=float))
+                s130a = (abs(B[0, 0]) < o.b_th or abs(B[1, 1]) < o.b_th) and dE < o.eps1
+                s130b = (kn < o.x_th1).any() or (kn > o.x_th2).any()
+                if s130a or s130b:
+                    # restart (line 19): x_{t+1}/|x_{t+1}| are the Ritz vectors
+                    # themselves; take them from the basis, since the update
+                    # reaches them through cancellation when |k| << 1
+                    v = Vp[:, :2].T @ basis
+                    V = Vp[:, :2].T @ imgs
+                    nv = np.linalg.norm(v, axis=1)
+                    x, X = v / nv[:, None], V / nv[:, None]
+                    dz = np.linalg.norm(X[0] - Enew[0] * x[0])
+                    conv = dE < o.eps0 and dz < o.r0                              # S127
+                    reason = "converged" if conv else ("S130a" if s130a else "S130b")
+                    if record:
+                        steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason))
+                    E = Enew
+                    if not conv:
+                        seg += 1
+                    break
                 if t == 0:
                     # Eqs. S94-S97: y_1 = A x_0 - C z_0, x_1 = x_0 + y_1
                     y = A @ x - C @ z
@@ -235,19 +265,15 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                     X = X + B @ Y
                 xn = np.linalg.norm(x, axis=1)
                 zp = np.array([(X[i] - Enew[i] * x[i]) / xn[i] for i in range(2)])  # S126, S128
-                dE = abs(Enew[0] - E[0])
                 dz = np.linalg.norm(zp[0])
                 reason = ""
                 if dE < o.eps0 and dz < o.r0:                                    # S127
                     conv = True
                     reason = "converged"
                 else:
-                    s130a = ((abs(B[0, 0]) < o.b_th or abs(B[1, 1]) < o.b_th) and dE < o.eps1)
-                    s130b = (xn < o.x_th1).any() or (xn > o.x_th2).any()
                     s130c = dz > o.r1 and t > 0
                     cap = t + 1 == o.max_cycle2
-                    reason = ("S130a" if s130a else "S130b" if s130b else "S130c" if s130c
-                              else "max_cycle" if cap else "")
+                    reason = "S130c" if s130c else "max_cycle" if cap else ""
                 if record:
                     steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason))
                 E = Enew

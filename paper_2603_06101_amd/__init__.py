@@ -107,6 +107,8 @@ class BatchReport(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(StepInfo), ctypes.c_void_p)
+
 SIGNATURES = [
     ("sbci_default_opts", None, [ctypes.POINTER(Opts)]),
     ("sbci_last_error", ctypes.c_char_p, []),
@@ -122,6 +124,7 @@ SIGNATURES = [
     ("sbci_set_opp_form", _I, [_P, _I]),
     ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_set_same_form", _I, [_P, _I]),
+    ("sbci_set_progress", _I, [_P, PROGRESS_FN, _P]),
     ("sbci_get_same_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
@@ -264,6 +267,18 @@ class Context:
         f = _I(0)
         _check(lib().sbci_get_opp_form(self.h, DTYPES[dtype], ctypes.byref(f)))
         return {1: "pair", 2: "orbital"}[f.value]
+
+    def set_progress(self, fn):
+        """Call fn(step: dict) after every solver step (None removes it).  fn runs on
+        the calling thread, inside the solve."""
+        if fn is None:
+            self._progress = None
+            _check(lib().sbci_set_progress(self.h, PROGRESS_FN(), None))
+            return
+        def tramp(info, _user):
+            fn(info.contents.as_dict())
+        self._progress = PROGRESS_FN(tramp)   # kept alive while set
+        _check(lib().sbci_set_progress(self.h, self._progress, None))
 
     def set_same_form(self, form):
         """Force the same-spin form ("auto", "lists" or "dense") of later sigma calls."""

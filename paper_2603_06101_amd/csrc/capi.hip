@@ -306,6 +306,13 @@ int sbci_set_trace(sbci_ctx *ctx, int on) {
   return SBCI_OK;
 }
 
+int sbci_set_progress(sbci_ctx *ctx, sbci_progress_fn fn, void *user) {
+  if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
+  ctx->progress = fn;
+  ctx->progress_user = user;
+  return SBCI_OK;
+}
+
 int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max) {
   if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
   int n = (int)std::min<size_t>(ctx->trace.size(), max > 0 ? (size_t)max : 0);

@@ -116,6 +116,8 @@ struct sbci_ctx {
   sbci::Solver *solver = nullptr;
   bool trace_on = true;
   std::vector<sbci_step_info> trace;
+  sbci_progress_fn progress = nullptr;
+  void *progress_user = nullptr;
 };
 
 namespace sbci {

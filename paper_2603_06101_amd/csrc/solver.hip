@@ -129,7 +129,7 @@ int alloc_solver(sbci_ctx *ctx, Solver &S, bool need32) {
 
 void record(sbci_ctx *ctx, Solver &S, double Enew, double dE, double dz, double b, double c,
             double k, double xn, int reason) {
-  if (!ctx->trace_on) return;
+  if (!ctx->trace_on && !ctx->progress) return;
   sbci_step_info r{};
   r.root = S.alpha;
   r.segment = S.seg;
@@ -144,7 +144,8 @@ void record(sbci_ctx *ctx, Solver &S, double Enew, double dE, double dz, double 
   r.xnorm = xn;
   r.seconds = now_s() - S.t0;
   r.reason = reason;
-  ctx->trace.push_back(r);
+  if (ctx->trace_on) ctx->trace.push_back(r);
+  if (ctx->progress) ctx->progress(&r, ctx->progress_user);
 }
 
 // Segment start: x, X hold an unnormalised start vector (scale sx pending);
@@ -810,9 +811,24 @@ int davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double
       if (!std::isfinite(th[k]) || !std::isfinite(rn[k]))
         return set_error(SBCI_ENUMERIC, "Davidson: non-finite Ritz value or residual");
     }
+    all = std::all_of(conv.begin(), conv.end(), [](int c) { return c != 0; });
+    if (ctx->progress) {
+      int k0 = 0;
+      while (k0 < nroots - 1 && conv[k0]) ++k0;
+      sbci_step_info r{};
+      r.root = k0;
+      r.t = it;
+      r.precision = SBCI_F64;
+      r.E = th[k0];
+      r.dE = std::fabs(th[k0] - th_old[k0]);
+      r.dz = rn[k0];
+      r.b = r.c = r.k = r.xnorm = NAN;
+      r.seconds = now_s() - t0;
+      r.reason = all ? 1 : 0;
+      ctx->progress(&r, ctx->progress_user);
+    }
     th_old = th;
     rep.nsteps += 1;
-    all = std::all_of(conv.begin(), conv.end(), [](int c) { return c != 0; });
     if (all) break;
     int nnew = 0;
     for (int k = 0; k < nroots; ++k) nnew += conv[k] ? 0 : 1;
@@ -1085,7 +1101,7 @@ bool pair_coef_next(const double *Vp, int r, double lindep, PairCoef &c) {
 
 void record_pair(sbci_ctx *ctx, Solver &S, int seg, int t, double E, double dE, double dz,
                  const PairCoef *c, double xn, int reason) {
-  if (!ctx->trace_on) return;
+  if (!ctx->trace_on && !ctx->progress) return;
   sbci_step_info r{};
   r.root = S.alpha;
   r.segment = seg;
@@ -1100,7 +1116,8 @@ void record_pair(sbci_ctx *ctx, Solver &S, int seg, int t, double E, double dE, 
   r.xnorm = xn;
   r.seconds = now_s() - S.t0;
   r.reason = reason;
-  ctx->trace.push_back(r);
+  if (ctx->trace_on) ctx->trace.push_back(r);
+  if (ctx->progress) ctx->progress(&r, ctx->progress_user);
 }
 
 // residuals of both states into the z pair (deflated), |z'|^2 into dz2
@@ -1269,6 +1286,62 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
           break;
         }
         const double Enew[2] = {w[0], w[1]};
+        const double dE = std::fabs(Enew[0] - E[0]);
+        // S130a and S130b are decided by the step's coefficients: the updated
+        // vectors are k times the two lowest Ritz vectors, orthonormal in the
+        // overlap metric, so |x_{t+1}| = |k|.  Their restart takes the Ritz
+        // vectors from the basis: the same vectors in exact arithmetic, but
+        // without the cancellation x_t + B y ~ 0 the update suffers when
+        // |k| << 1, which would leave X inconsistent with H x.
+        {
+          const double kn[2] = {std::fabs(cf.k[0]), std::fabs(cf.k[1])};
+          const bool a_ = (std::fabs(cf.B[0][0]) < S.o.b_th || std::fabs(cf.B[1][1]) < S.o.b_th) &&
+                          dE < S.o.eps1;                                          // S130a
+          const bool b_ = kn[0] < S.o.x_th1 || kn[1] < S.o.x_th1 || kn[0] > S.o.x_th2 ||
+                          kn[1] > S.o.x_th2;                                      // S130b
+          if (a_ || b_) {
+            for (int i = 0; i < 2; ++i) {
+              double c1[6];
+              for (int k = 0; k < m; ++k) c1[k] = Vp[k * r + i];
+              SBCI_TRY(lincomb<double>(ctx, n, P.s[i], basis, c1, m, 0.0));
+              SBCI_TRY(lincomb<double>(ctx, n, P.S[i], img, c1, m, 0.0));
+            }
+            for (int i = 0; i < 2; ++i) {
+              std::swap(P.x[i], P.s[i]);
+              std::swap(P.X[i], P.S[i]);
+              E[i] = Enew[i];
+              const double *bs[1] = {P.x[i]};
+              double d;
+              SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 1, &d));
+              if (!(d > 0) || !std::isfinite(d))
+                return set_error(SBCI_ENUMERIC, "SBCI2: vanishing Ritz vector");
+              SBCI_TRY(scale2(ctx, S, P.x[i], 1.0 / std::sqrt(d)));
+              SBCI_TRY(scale2(ctx, S, P.X[i], 1.0 / std::sqrt(d)));
+            }
+            inv[0] = inv[1] = 1.0;
+            xn[0] = xn[1] = 1.0;  // the acceptance below rescales by 1 / xn
+            SBCI_TRY(pair_residuals(ctx, S, P, E, inv, alpha == 0 ? E[0] : S.Ec[0], dz2));
+            const double dz = std::sqrt(dz2[0]);
+            if (!std::isfinite(dz)) return set_error(SBCI_ENUMERIC, "SBCI2: non-finite residual");
+            int reason = a_ ? 2 : 3;
+            if (dE < S.o.eps0 && dz < S.o.r0) {                                 // S127
+              conv = true;
+              reason = 1;
+            }
+            record_pair(ctx, S, seg, t, E[0], dE, dz, &cf, kn[0], reason);
+            if (conv) break;
+            if (steps >= S.o.max_steps) {
+              capped = true;
+              S.any_noconv = true;
+              break;
+            }
+            // go to 4 with the residuals just formed
+            S.rep.nrestarts += 1;
+            seg += 1;
+            t = 0;
+            continue;
+          }
+        }
         // Eqs. S94-S97 (t = 0: y = A x - C z, x = x + y) and S122-S125
         const double beta = t == 0 ? 0.0 : 1.0;
         for (int i = 0; i < 2; ++i) {
@@ -1296,7 +1369,6 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
         }
         SBCI_TRY(pair_residuals(ctx, S, P, Enew, inv, alpha == 0 ? Enew[0] : S.Ec[0], dz2));
         const double dz = std::sqrt(dz2[0]);
-        const double dE = std::fabs(Enew[0] - E[0]);
         if (!std::isfinite(dz) || !std::isfinite(xn[0]) || !std::isfinite(xn[1]) ||
             !std::isfinite(Enew[0]))
           return set_error(SBCI_ENUMERIC, "SBCI2: non-finite residual or norm");
@@ -1305,13 +1377,9 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
           conv = true;
           reason = 1;
         } else {
-          const bool a_ = (std::fabs(cf.B[0][0]) < S.o.b_th || std::fabs(cf.B[1][1]) < S.o.b_th) &&
-                          dE < S.o.eps1;                                          // S130a
-          const bool b_ = xn[0] < S.o.x_th1 || xn[1] < S.o.x_th1 || xn[0] > S.o.x_th2 ||
-                          xn[1] > S.o.x_th2;                                      // S130b
           const bool c_ = dz > S.o.r1 && t > 0;                                   // S130c
           const bool cap = t + 1 >= max_cycle2;
-          reason = a_ ? 2 : b_ ? 3 : c_ ? 4 : cap ? 5 : 0;
+          reason = c_ ? 4 : cap ? 5 : 0;
         }
         record_pair(ctx, S, seg, t, Enew[0], dE, dz, &cf, xn[0], reason);
         E[0] = Enew[0];

@@ -160,3 +160,30 @@ def test_step_cap_reports_noconv():
     assert r.status == sb.SBCI_ENOCONV
     assert np.isfinite(r.energies[0])
     ctx.close()
+
+
+def test_progress_callback_sees_every_step():
+    """The progress callback receives the trace records of SBCI1 and SBCI2
+    (one per step, in order) and one record per Davidson iteration, the last
+    one marked converged."""
+    import paper_2603_06101_amd as sb
+    I = make_integrals(6, 12, 0)
+    ctx = sb.Context(6, 3, 3, I.h1, I.eri)
+    seen = []
+    ctx.set_progress(seen.append)
+    for solve in (ctx.solve, ctx.solve2):
+        seen.clear()
+        r = solve(3, tol=1e-10)
+        assert len(seen) == len(r.trace) > 0
+        for a, b in zip(seen, r.trace):
+            assert (a["root"], a["segment"], a["t"], a["reason"]) == (b["root"], b["segment"], b["t"], b["reason"])
+            assert a["E"] == b["E"]
+    seen.clear()
+    r = ctx.davidson(3, tol=1e-10)
+    assert len(seen) == r.report["nsteps"]
+    assert seen[-1]["reason"] == "converged" and abs(seen[-1]["E"] - r.energies[seen[-1]["root"]]) < 1e-8
+    ctx.set_progress(None)
+    seen.clear()
+    ctx.solve(1, tol=1e-10)
+    assert seen == []
+    ctx.close()

@@ -42,6 +42,11 @@ def test_pair_update_gives_the_two_lowest_ritz_vectors(seed):
     x1 = x + B @ y1
     wq, Rq = _ritz_qr(basis, Hf)
     assert np.allclose(w[:2], wq[:2], atol=1e-10)
+    # V' is orthonormal in the overlap metric, so |x_{t+1}| = |k| (what the
+    # S130b test before the update relies on)
+    assert np.allclose(Vp.T @ S @ Vp, np.eye(Vp.shape[1]), atol=1e-10)
+    for i in range(2):
+        assert abs(np.linalg.norm(x1[i]) - abs(cf["k"][i])) < 1e-8
     for i in range(2):
         assert _parallel(x1[i], Rq[i]) > 1 - 1e-10
         assert abs(x1[i] @ Hf @ x1[i] / (x1[i] @ x1[i]) - wq[i]) < 1e-10
