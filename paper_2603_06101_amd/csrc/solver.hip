@@ -520,9 +520,84 @@ __global__ void k_unit(double *v, int64_t n, const int64_t *idx, int k, double *
   if (i < k) v[(int64_t)i * n + idx[i]] = 1.0;
 }
 
-__global__ void k_gather_sub(const double *X, int64_t n, const int64_t *idx, int k, double *out) {
-  int i = threadIdx.x, j = threadIdx.y;
-  if (i < k && j < k) out[i * k + j] = X[(int64_t)j * n + idx[i]];
+__global__ void k_sparse_set(double *v, const int64_t *idx, const double *val, int k) {
+  const int i = threadIdx.x;
+  if (i < k) v[idx[i]] = val[i];
+}
+
+__global__ void k_gather_rows(const double *v, const int64_t *idx, int k, double *out) {
+  const int i = threadIdx.x;
+  if (i < k) out[i] = v[idx[i]];
+}
+
+// The k x k block of H on the k lowest diagonal determinants (Sections S1.1,
+// S2.2) and its eigenpairs: column j is gathered from sigma of the unit
+// vector e_j, one column at a time, so only the two scratch vectors e, He
+// ([n] each) are needed.  w ascending; U[i * k + a] = coefficient of
+// e_{idx[i]} in eigenvector a.
+int start_block(sbci_ctx *ctx, int k, double *e, double *He, std::vector<int64_t> &idx,
+                std::vector<double> &w, std::vector<double> &U, int64_t &nsig) {
+  const int64_t n = ctx->ndet;
+  SBCI_TRY(lowest_diagonal(ctx, k, idx));
+  int64_t *didx = nullptr;
+  double *dval = nullptr;
+  SBCI_HIP(hipMalloc(&didx, sizeof(int64_t) * k));
+  SBCI_HIP(hipMalloc(&dval, sizeof(double) * 2 * k));
+  struct Free {
+    void *a, *b;
+    ~Free() { hipFree(a); hipFree(b); }
+  } guard{didx, dval};
+  SBCI_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, ctx->stream));
+  const double one = 1.0;
+  SBCI_HIP(hipMemcpyAsync(dval, &one, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  std::vector<double> Hs((size_t)k * k), col(k);
+  for (int j = 0; j < k; ++j) {
+    SBCI_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, ctx->stream));
+    k_sparse_set<<<1, 64, 0, ctx->stream>>>(e, didx + j, dval, 1);
+    SBCI_CHECK_LAUNCH();
+    SBCI_TRY(sigma(ctx, e, He, 1, SBCI_F64));                                // Eqs. S1 / S74
+    k_gather_rows<<<1, 64, 0, ctx->stream>>>(He, didx, k, dval + k);
+    SBCI_CHECK_LAUNCH();
+    SBCI_HIP(hipMemcpyAsync(col.data(), dval + k, sizeof(double) * k, hipMemcpyDeviceToHost,
+                            ctx->stream));
+    SBCI_HIP(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < k; ++i) Hs[(size_t)i * k + j] = col[i];
+  }
+  nsig += k;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < i; ++j) Hs[i * k + j] = Hs[j * k + i] = 0.5 * (Hs[i * k + j] + Hs[j * k + i]);
+  w.assign(k, 0.0);
+  U.assign((size_t)k * k, 0.0);
+  jacobi_eigh<16>(k, Hs.data(), w.data(), U.data());
+  return SBCI_OK;
+}
+
+// Start vector a of the block (Eqs. S2 / S75): x = sum_i U[i][a] e_{idx[i]}
+// (k non-zeros) and its image X = H x by one sigma, which equals the
+// combination of the unit vectors' images (Eqs. S3 / S76) without keeping
+// those images.
+int start_vector(sbci_ctx *ctx, int k, const std::vector<int64_t> &idx,
+                 const std::vector<double> &U, int a, double *x, double *X, int64_t &nsig) {
+  const int64_t n = ctx->ndet;
+  int64_t *didx = nullptr;
+  double *dval = nullptr;
+  SBCI_HIP(hipMalloc(&didx, sizeof(int64_t) * k));
+  SBCI_HIP(hipMalloc(&dval, sizeof(double) * k));
+  struct Free {
+    void *a, *b;
+    ~Free() { hipFree(a); hipFree(b); }
+  } guard{didx, dval};
+  std::vector<double> v(k);
+  for (int i = 0; i < k; ++i) v[i] = U[(size_t)i * k + a];
+  SBCI_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, ctx->stream));
+  SBCI_HIP(hipMemcpyAsync(dval, v.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+  SBCI_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, ctx->stream));
+  k_sparse_set<<<1, 64, 0, ctx->stream>>>(x, didx, dval, k);
+  SBCI_CHECK_LAUNCH();
+  SBCI_TRY(sigma(ctx, x, X, 1, SBCI_F64));
+  nsig += 1;
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));  // host staging above must outlive the copies
+  return SBCI_OK;
 }
 
 int initial_vector(sbci_ctx *ctx, Solver &S) {
@@ -543,42 +618,13 @@ int initial_vector(sbci_ctx *ctx, Solver &S) {
   }
   const int k = (int)std::min<int64_t>(S.nroots, n);
   std::vector<int64_t> idx;
-  SBCI_TRY(lowest_diagonal(ctx, k, idx));
-  double *e = nullptr, *He = nullptr, *sub = nullptr;
-  int64_t *didx = nullptr;
-  SBCI_HIP(hipMalloc(&e, sizeof(double) * n * k));
-  SBCI_HIP(hipMalloc(&He, sizeof(double) * n * k));
-  SBCI_HIP(hipMalloc(&sub, sizeof(double) * k * k));
-  SBCI_HIP(hipMalloc(&didx, sizeof(int64_t) * k));
-  SBCI_HIP(hipMemsetAsync(e, 0, sizeof(double) * n * k, ctx->stream));
-  SBCI_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, ctx->stream));
-  k_unit<<<1, 64, 0, ctx->stream>>>(e, n, didx, k, nullptr);
-  SBCI_CHECK_LAUNCH();
-  SBCI_TRY(sigma(ctx, e, He, k, SBCI_F64));                                  // Eq. S1
-  S.rep.nsigma_f64 += k;
-  k_gather_sub<<<1, dim3(16, 16), 0, ctx->stream>>>(He, n, didx, k, sub);
-  SBCI_CHECK_LAUNCH();
-  std::vector<double> Hs((size_t)k * k), w(k), U((size_t)k * k);
-  SBCI_HIP(hipMemcpyAsync(Hs.data(), sub, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
-  SBCI_HIP(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < i; ++j) Hs[i * k + j] = Hs[j * k + i] = 0.5 * (Hs[i * k + j] + Hs[j * k + i]);
-  jacobi_eigh<16>(k, Hs.data(), w.data(), U.data());
-  std::vector<const double *> es(k), Hes(k);
-  std::vector<double> cf(k);
-  for (int i = 0; i < k; ++i) {
-    es[i] = e + (int64_t)i * n;
-    Hes[i] = He + (int64_t)i * n;
-    cf[i] = U[i * k + 0];
-  }
-  SBCI_TRY(lincomb<double>(ctx, n, x, es.data(), cf.data(), k, 0.0));      // Eq. S2
-  SBCI_TRY(lincomb<double>(ctx, n, X, Hes.data(), cf.data(), k, 0.0));     // Eq. S3
+  std::vector<double> w, U;
+  // the solver's y and Y slots are free until the first step
+  SBCI_TRY(start_block(ctx, k, S.v64[Y_], S.v64[YY_], idx, w, U, S.rep.nsigma_f64));
+  SBCI_HIP(hipMemsetAsync(S.v64[Y_], 0, sizeof(double) * n, ctx->stream));
+  SBCI_HIP(hipMemsetAsync(S.v64[YY_], 0, sizeof(double) * n, ctx->stream));
+  SBCI_TRY(start_vector(ctx, k, idx, U, 0, x, X, S.rep.nsigma_f64));         // Eqs. S2-S3
   S.E = w[0];
-  SBCI_HIP(hipStreamSynchronize(ctx->stream));
-  hipFree(e);
-  hipFree(He);
-  hipFree(sub);
-  hipFree(didx);
   return SBCI_OK;
 }
 
@@ -907,8 +953,11 @@ struct Pair {
   double *z = nullptr, *Z = nullptr;  // [2][n] each (one sigma call, nvec = 2)
   double *s[2] = {}, *S[2] = {};      // scratch: Ritz vectors of a restart and their images
   double *dev = nullptr;              // reduction results
-  std::vector<double *> xs, Xs;       // start vectors of Eq. S75 and their images (S76)
-  std::vector<double> Es;
+  // the k x k block of Eq. S74 on the lowest diagonal determinants: its
+  // eigenvectors U give the start vectors of Eq. S75, rebuilt when needed
+  int k = 0;
+  std::vector<int64_t> idx;
+  std::vector<double> U, w;
   size_t bytes = 0;
 };
 
@@ -924,8 +973,6 @@ void free_pair(Pair &P) {
   hipFree(P.z);
   hipFree(P.Z);
   hipFree(P.dev);
-  for (auto p : P.xs) hipFree(p);
-  for (auto p : P.Xs) hipFree(p);
 }
 
 int dmalloc(Pair &P, double **p, size_t count) {
@@ -946,50 +993,11 @@ int dots_h(sbci_ctx *ctx, Pair &P, int64_t n, const double *a, const double *con
 // Section S2.2 / Eqs. S74-S76: the k lowest diagonal determinants, H in
 // their span diagonalised; xs[i], Xs[i] = H xs[i], Es[i].
 int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
-  const int64_t n = ctx->ndet;
-  std::vector<int64_t> idx;
-  SBCI_TRY(lowest_diagonal(ctx, k, idx));
-  double *e = nullptr, *He = nullptr, *sub = nullptr;
-  int64_t *didx = nullptr;
-  SBCI_HIP(hipMalloc(&e, sizeof(double) * n * k));
-  SBCI_HIP(hipMalloc(&He, sizeof(double) * n * k));
-  SBCI_HIP(hipMalloc(&sub, sizeof(double) * k * k));
-  SBCI_HIP(hipMalloc(&didx, sizeof(int64_t) * k));
-  SBCI_HIP(hipMemsetAsync(e, 0, sizeof(double) * n * k, ctx->stream));
-  SBCI_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, ctx->stream));
-  k_unit<<<1, 64, 0, ctx->stream>>>(e, n, didx, k, nullptr);
-  SBCI_CHECK_LAUNCH();
-  SBCI_TRY(sigma(ctx, e, He, k, SBCI_F64));                                  // Eq. S74
-  S.rep.nsigma_f64 += k;
-  k_gather_sub<<<1, dim3(16, 16), 0, ctx->stream>>>(He, n, didx, k, sub);
-  SBCI_CHECK_LAUNCH();
-  std::vector<double> Hs((size_t)k * k), w(k), U((size_t)k * k);
-  SBCI_HIP(hipMemcpyAsync(Hs.data(), sub, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
-  SBCI_HIP(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < i; ++j) Hs[i * k + j] = Hs[j * k + i] = 0.5 * (Hs[i * k + j] + Hs[j * k + i]);
-  jacobi_eigh<16>(k, Hs.data(), w.data(), U.data());
-  std::vector<const double *> es(k), Hes(k);
-  for (int i = 0; i < k; ++i) {
-    es[i] = e + (int64_t)i * n;
-    Hes[i] = He + (int64_t)i * n;
-  }
-  P.xs.assign(k, nullptr);
-  P.Xs.assign(k, nullptr);
-  P.Es.assign(w.begin(), w.end());
-  for (int a = 0; a < k; ++a) {
-    std::vector<double> cf(k);
-    for (int i = 0; i < k; ++i) cf[i] = U[i * k + a];
-    SBCI_TRY(dmalloc(P, &P.xs[a], n));
-    SBCI_TRY(dmalloc(P, &P.Xs[a], n));
-    SBCI_TRY(lincomb<double>(ctx, n, P.xs[a], es.data(), cf.data(), k, 0.0));   // Eq. S75
-    SBCI_TRY(lincomb<double>(ctx, n, P.Xs[a], Hes.data(), cf.data(), k, 0.0));  // Eq. S76
-  }
-  SBCI_HIP(hipStreamSynchronize(ctx->stream));
-  hipFree(e);
-  hipFree(He);
-  hipFree(sub);
-  hipFree(didx);
+  // scratch: the pair's y slots (unused until the first step)
+  P.k = k;
+  SBCI_TRY(start_block(ctx, k, P.y[0], P.y[1], P.idx, P.w, P.U, S.rep.nsigma_f64));   // Eq. S74
+  for (int i = 0; i < 2; ++i)
+    SBCI_HIP(hipMemsetAsync(P.y[i], 0, sizeof(double) * ctx->ndet, ctx->stream));
   return SBCI_OK;
 }
 
@@ -1184,10 +1192,8 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     SBCI_TRY(dmalloc(P, &P.dev, 128));
     SBCI_TRY(pair_start_vectors(ctx, S, P, nroots));
     // pair (0, 1) from Eq. S75
-    SBCI_TRY((convert<double, double>(ctx, n, P.x[0], P.xs[0], 1.0)));
-    SBCI_TRY((convert<double, double>(ctx, n, P.X[0], P.Xs[0], 1.0)));
-    SBCI_TRY((convert<double, double>(ctx, n, P.x[1], P.xs[1], 1.0)));
-    SBCI_TRY((convert<double, double>(ctx, n, P.X[1], P.Xs[1], 1.0)));
+    for (int i = 0; i < 2; ++i)
+      SBCI_TRY(start_vector(ctx, P.k, P.idx, P.U, i, P.x[i], P.X[i], S.rep.nsigma_f64));
   }
   for (int alpha = 0; alpha + 1 < nroots; ++alpha) {
     S.alpha = alpha;
@@ -1428,8 +1434,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     if (alpha + 2 < nroots) {
       // Section S2.2: the next start vector, orthogonalised against the
       // converged roots and against x_0^alpha
-      SBCI_TRY((convert<double, double>(ctx, n, P.x[1], P.xs[alpha + 2], 1.0)));
-      SBCI_TRY((convert<double, double>(ctx, n, P.X[1], P.Xs[alpha + 2], 1.0)));
+      SBCI_TRY(start_vector(ctx, P.k, P.idx, P.U, alpha + 2, P.x[1], P.X[1], S.rep.nsigma_f64));
       SBCI_TRY(project_off(ctx, S, P, P.x[1], P.X[1]));
       const double *bs[1] = {P.x[1]};
       double pa;
