@@ -67,6 +67,9 @@ def parse():
                     help="run only the solver comparison on dilute45 with 6 roots (the shape of "
                          "the paper's CAS(6e,45o) excited-state instance; several minutes) and "
                          "print it")
+    ap.add_argument("--solve-driver", choices=["sbci1", "sbci2", "davidson"], default=None,
+                    help="profiling driver: one FP64 solve of the workload with this solver; print "
+                         "its report and exit")
     ap.add_argument("--only-batch", action="store_true",
                     help="profiling driver: run only the batching-form section and print it")
     ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
@@ -492,6 +495,18 @@ def main():
         return
     if a.paper_shapes:
         print(json.dumps(paper_shapes_section(sb, stream, a.precision)))
+        return
+    if a.solve_driver:
+        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+        fn = {"sbci1": lambda: ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"), want_vectors=False),
+              "sbci2": lambda: ctx.solve2(nroots, tol=1e-10, want_vectors=False),
+              "davidson": lambda: ctx.davidson(nroots, tol=1e-10, want_vectors=False)}[a.solve_driver]
+        r = fn()
+        torch.cuda.synchronize()
+        print(json.dumps({"driver": a.solve_driver, "workload": a.workload, "ndet": ctx.ndet,
+                          "nroots": nroots, "energies": [float(e) for e in r.energies],
+                          "seconds": r.report["seconds"], "nsigma_f64": r.report["nsigma_f64"]}))
+        ctx.close()
         return
     if a.kernel_driver:
         ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
