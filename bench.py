@@ -558,6 +558,12 @@ def main():
     torch.cuda.synchronize()
     sbci2 = {"fp64_s": round(time.perf_counter() - t, 4), "nsigma": r2.report["nsigma_f64"],
              "energies": [float(e) for e in r2.energies]}
+    t = time.perf_counter()
+    r2m = ctx.solve2(nroots, tol=1e-10, opts=dict(precision="f32"), want_vectors=False)
+    torch.cuda.synchronize()
+    sbci2["f32_ladder_s"] = round(time.perf_counter() - t, 4)
+    sbci2["f32_ladder_nsigma"] = {"f64": r2m.report["nsigma_f64"], "low": r2m.report["nsigma_low"]}
+    sbci2["f32_ladder_max_abs_dE"] = float(np.abs(np.sort(r2m.energies) - np.sort(r2.energies)).max())
     dE = float(np.max(np.abs(np.sort(ref.energies) - np.sort(last.energies))))
 
     # sigma per precision, per kernel (HIP events on the library stream)

@@ -246,8 +246,12 @@ int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
  * (two sigma applications); state alpha is accepted on Eq. S127, restarts
  * follow Eqs. S130a-c and max_cycle2; the highest state is finished by SBCI1
  * (Fig. 1B).  Start vectors: Section S2.2.  Arguments, outputs, errors and
- * the trace as for sbci_solve; opt->precision must be SBCI_F64 and opt->x0
- * is ignored.  energies[i] / dev_vecs row i are state i. */
+ * the trace as for sbci_solve; opt->x0 is ignored.  opt->precision selects
+ * the precision form: each pair starts on the BF16-MFMA or FP32 sigma (its
+ * vectors and reductions stay FP64), hands over at the thresholds of
+ * sbci_opts with X recomputed (trace reason 8), and a state is accepted only
+ * in FP64; the highest state runs SBCI1's ladder.  energies[i] / dev_vecs
+ * row i are state i. */
 int sbci_solve2(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
                 double *energies, double *dev_vecs, sbci_report *rep);
 

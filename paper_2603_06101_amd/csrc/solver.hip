@@ -952,6 +952,7 @@ struct Pair {
   double *x[2] = {}, *X[2] = {}, *y[2] = {}, *Y[2] = {};
   double *z = nullptr, *Z = nullptr;  // [2][n] each (one sigma call, nvec = 2)
   double *s[2] = {}, *S[2] = {};      // scratch: Ritz vectors of a restart and their images
+  float *z32 = nullptr, *Z32 = nullptr;  // [2][n]: the low-precision phases' sigma operands
   double *dev = nullptr;              // reduction results
   // the k x k block of Eq. S74 on the lowest diagonal determinants: its
   // eigenvectors U give the start vectors of Eq. S75, rebuilt when needed
@@ -972,6 +973,8 @@ void free_pair(Pair &P) {
   }
   hipFree(P.z);
   hipFree(P.Z);
+  hipFree(P.z32);
+  hipFree(P.Z32);
   hipFree(P.dev);
 }
 
@@ -992,6 +995,46 @@ int dots_h(sbci_ctx *ctx, Pair &P, int64_t n, const double *a, const double *con
 
 // Section S2.2 / Eqs. S74-S76: the k lowest diagonal determinants, H in
 // their span diagonalised; xs[i], Xs[i] = H xs[i], Es[i].
+// Z = sigma(z) for the pair's two residuals in the phase's precision: the
+// low-precision phases convert z to FP32, run the FP32 or BF16-MFMA sigma
+// and widen the result (the vectors and every reduction stay FP64).
+int pair_sigma(sbci_ctx *ctx, Solver &S, Pair &P, int phase, const double *z, double *Z) {
+  const int64_t n2 = 2 * S.n;
+  if (phase == SBCI_F64) {
+    SBCI_TRY(sigma(ctx, z, Z, 2, SBCI_F64));
+    S.rep.nsigma_f64 += 2;
+    return SBCI_OK;
+  }
+  SBCI_TRY((convert<float, double>(ctx, n2, P.z32, z, 1.0)));
+  SBCI_TRY(sigma(ctx, P.z32, P.Z32, 2, phase));
+  SBCI_TRY((convert<double, float>(ctx, n2, Z, P.Z32, 1.0)));
+  S.rep.nsigma_low += 2;
+  if (phase == SBCI_BF16) S.rep.nsigma_bf16 += 2;
+  return SBCI_OK;
+}
+
+// Hand-over of the pair to the next precision (the ladder of the precision
+// form): x normalised, X = sigma(x) recomputed in the new precision (the
+// carried X holds the previous sigma's error), E the Rayleigh quotients.
+int pair_rebase(sbci_ctx *ctx, Solver &S, Pair &P, int phase, double *E) {
+  const int64_t n = S.n;
+  for (int i = 0; i < 2; ++i) {
+    const double *bs[1] = {P.x[i]};
+    double d;
+    SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 1, &d));
+    if (!(d > 0) || !std::isfinite(d)) return set_error(SBCI_ENUMERIC, "SBCI2: vanishing vector");
+    SBCI_TRY((convert<double, double>(ctx, n, P.z + i * n, P.x[i], 1.0 / std::sqrt(d))));
+    SBCI_TRY((convert<double, double>(ctx, n, P.x[i], P.z + i * n, 1.0)));
+  }
+  SBCI_TRY(pair_sigma(ctx, S, P, phase, P.z, P.Z));
+  for (int i = 0; i < 2; ++i) {
+    SBCI_TRY((convert<double, double>(ctx, n, P.X[i], P.Z + i * n, 1.0)));
+    const double *bs[1] = {P.X[i]};
+    SBCI_TRY(dots_h(ctx, P, n, P.x[i], bs, 1, &E[i]));
+  }
+  return SBCI_OK;
+}
+
 int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
   // scratch: the pair's y slots (unused until the first step)
   P.k = k;
@@ -1114,7 +1157,7 @@ void record_pair(sbci_ctx *ctx, Solver &S, int seg, int t, double E, double dE, 
   r.root = S.alpha;
   r.segment = seg;
   r.t = t;
-  r.precision = SBCI_F64;
+  r.precision = S.phase;
   r.E = E;
   r.dE = dE;
   r.dz = dz;
@@ -1162,14 +1205,13 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
   ctx->solver = Sp;
   Solver &S = *Sp;
   SBCI_TRY(resolve_opts(opt, tol, nroots, ctx->ndet, S.o));
-  if (S.o.precision != SBCI_F64)
-    return set_error(SBCI_EINVAL, "SBCI2 runs in FP64 only (precision must be SBCI_F64)");
+  const int first_phase = S.o.precision;  // each pair starts here and ends in FP64
   S.nroots = nroots;
   S.n = ctx->ndet;
   S.t0 = now_s();
   S.phase = SBCI_F64;
   ctx->trace.clear();
-  SBCI_TRY(alloc_solver(ctx, S, false));
+  SBCI_TRY(alloc_solver(ctx, S, first_phase != SBCI_F64));
   const int64_t n = S.n;
   const int max_cycle2 = S.o.max_cycle2 > 0 ? S.o.max_cycle2 : 10;
   Pair P;
@@ -1189,6 +1231,11 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     }
     SBCI_TRY(dmalloc(P, &P.z, 2 * n));
     SBCI_TRY(dmalloc(P, &P.Z, 2 * n));
+    if (first_phase != SBCI_F64) {
+      SBCI_HIP(hipMalloc(&P.z32, sizeof(float) * 2 * n));
+      SBCI_HIP(hipMalloc(&P.Z32, sizeof(float) * 2 * n));
+      P.bytes += sizeof(float) * 4 * n;
+    }
     SBCI_TRY(dmalloc(P, &P.dev, 128));
     SBCI_TRY(pair_start_vectors(ctx, S, P, nroots));
     // pair (0, 1) from Eq. S75
@@ -1214,13 +1261,38 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     bool conv = false, capped = false;
     double inv[2] = {1.0, 1.0}, dz2[2];
     double xn[2] = {1.0, 1.0};
+    int phase = first_phase;
+    int stall = 0;
+    double bestE = E[0];
+    S.phase = phase;  // recorded with each pair step
+    // low-precision phases: state alpha hands over (instead of converging)
+    // at the phase's thresholds or after mix_stall steps without a decrease
+    auto hand_over = [&](double Ea, double dEa, double dza) {
+      if (phase == SBCI_F64) return false;
+      if (Ea < bestE - 1e-15 * std::fabs(bestE)) {
+        bestE = Ea;
+        stall = 0;
+      } else {
+        stall += 1;
+      }
+      const bool bf = phase == SBCI_BF16;
+      const double e0 = bf ? S.o.bf16_eps0 : S.o.mix_eps0, r0 = bf ? S.o.bf16_r0 : S.o.mix_r0;
+      return (dEa < e0 && dza < r0) || stall >= S.o.mix_stall || steps >= S.o.max_steps;
+    };
+    auto next_phase = [&]() {
+      phase = phase == SBCI_BF16 ? SBCI_F32 : SBCI_F64;
+      S.phase = phase;
+      stall = 0;
+      const int rc = pair_rebase(ctx, S, P, phase, E);
+      bestE = E[0];
+      return rc;
+    };
     while (!conv && !capped) {
       // segment start (lines 2-4)
       int t = 0;
       SBCI_TRY(pair_residuals(ctx, S, P, E, inv, alpha == 0 ? E[0] : S.Ec[0], dz2));
       while (true) {
-        SBCI_TRY(sigma(ctx, P.z, P.Z, 2, SBCI_F64));                         // S82 / S102
-        S.rep.nsigma_f64 += 2;
+        SBCI_TRY(pair_sigma(ctx, S, P, phase, P.z, P.Z));                      // S82 / S102
         S.rep.nsteps += 1;
         steps += 1;
         const double *z[2] = {P.z, P.z + n};
@@ -1330,12 +1402,20 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
             const double dz = std::sqrt(dz2[0]);
             if (!std::isfinite(dz)) return set_error(SBCI_ENUMERIC, "SBCI2: non-finite residual");
             int reason = a_ ? 2 : 3;
-            if (dE < S.o.eps0 && dz < S.o.r0) {                                 // S127
+            const bool ho = hand_over(E[0], dE, dz);
+            if (phase == SBCI_F64 && dE < S.o.eps0 && dz < S.o.r0) {            // S127
               conv = true;
               reason = 1;
+            } else if (ho) {
+              reason = 8;
             }
             record_pair(ctx, S, seg, t, E[0], dE, dz, &cf, kn[0], reason);
             if (conv) break;
+            if (reason == 8) {
+              SBCI_TRY(next_phase());
+              seg += 1;
+              break;  // go to 4 in the new precision
+            }
             if (steps >= S.o.max_steps) {
               capped = true;
               S.any_noconv = true;
@@ -1379,9 +1459,11 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
             !std::isfinite(Enew[0]))
           return set_error(SBCI_ENUMERIC, "SBCI2: non-finite residual or norm");
         int reason = 0;
-        if (dE < S.o.eps0 && dz < S.o.r0) {                                      // S127
+        if (phase == SBCI_F64 && dE < S.o.eps0 && dz < S.o.r0) {                // S127
           conv = true;
           reason = 1;
+        } else if (hand_over(Enew[0], dE, dz)) {
+          reason = 8;
         } else {
           const bool c_ = dz > S.o.r1 && t > 0;                                   // S130c
           const bool cap = t + 1 >= max_cycle2;
@@ -1391,6 +1473,13 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
         E[0] = Enew[0];
         E[1] = Enew[1];
         if (conv) break;
+        if (reason == 8) {
+          SBCI_TRY(next_phase());  // normalises x, recomputes X and E
+          inv[0] = inv[1] = 1.0;
+          xn[0] = xn[1] = 1.0;
+          seg += 1;
+          break;  // go to 4 in the new precision
+        }
         if (steps >= S.o.max_steps) {
           capped = true;
           S.any_noconv = true;
@@ -1418,6 +1507,13 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     S.alloc_bytes += sizeof(double) * n;
     SBCI_TRY((convert<double, double>(ctx, n, xc, P.x[0], 1.0 / xn[0])));
     S.xc64.push_back(xc);
+    if (first_phase != SBCI_F64) {  // FP32 copy for the low phases' deflation
+      float *x32 = nullptr;
+      SBCI_HIP(hipMalloc(&x32, sizeof(float) * n));
+      S.alloc_bytes += sizeof(float) * n;
+      SBCI_TRY((convert<float, double>(ctx, n, x32, xc, 1.0)));
+      S.xc32.push_back(x32);
+    }
     double *hxc = nullptr;
     SBCI_HIP(hipMalloc(&hxc, sizeof(double) * n));
     S.alloc_bytes += sizeof(double) * n;
@@ -1447,6 +1543,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
     if (capped) break;
   }
   // the highest state with SBCI1 (Fig. 1B)
+  S.phase = SBCI_F64;
   if ((int)S.Ec.size() < nroots) {
     S.alpha = (int)S.Ec.size();
     if (nroots >= 2) {
@@ -1458,13 +1555,23 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
       double d[2];
       SBCI_TRY(dots_h(ctx, P, n, S.v64[X_], bs, 2, d));
       S.E = d[1] / d[0];
-      SBCI_TRY(start_root<double>(ctx, S));
     } else {
       SBCI_TRY(initial_vector(ctx, S));
+    }
+    if (first_phase != SBCI_F64) {
+      // SBCI1 with its own precision ladder (as for every later root there)
+      SBCI_TRY((convert<float, double>(ctx, n, S.v32[X_], S.v64[X_], 1.0)));
+      SBCI_TRY((convert<float, double>(ctx, n, S.v32[XX_], S.v64[XX_], 1.0)));
+      S.phase = first_phase;
+      SBCI_TRY(start_root<float>(ctx, S));
+    } else {
       SBCI_TRY(start_root<double>(ctx, S));
     }
     while (!S.done) {
-      SBCI_TRY(step_t<double>(ctx, S, nullptr));
+      if (S.phase == SBCI_F64)
+        SBCI_TRY(step_t<double>(ctx, S, nullptr));
+      else
+        SBCI_TRY(step_t<float>(ctx, S, nullptr));
     }
   } else {
     S.done = true;

@@ -114,6 +114,9 @@ def test_sbci2_cas14_five_roots():
     assert res.max() < 3e-5
     G = (X @ X.T).cpu().numpy()
     assert np.abs(G - np.eye(5)).max() < 1e-8
+    rm = ctx.solve2(5, tol=1e-10, opts=dict(precision="bf16"), want_vectors=False)
+    assert rm.status == 0
+    assert np.abs(np.sort(rm.energies) - np.sort(r1.energies)).max() < 1e-8
     ctx.close()
 
 
@@ -124,7 +127,22 @@ def test_sbci2_single_root_and_bad_arguments():
     r1 = ctx.solve(1, tol=1e-10)
     assert abs(r2.energies[0] - r1.energies[0]) < 1e-10
     with pytest.raises(sb.SbciError):
-        ctx.solve2(2, opts=dict(precision="f32"))
-    with pytest.raises(sb.SbciError):
         ctx.solve2(0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+@pytest.mark.parametrize("seed", range(3))
+def test_sbci2_precision_ladder_cas10(seed, precision):
+    """SBCI2 with the precision form: pair steps on the FP32 or BF16-MFMA sigma
+    hand over to FP64 (X recomputed) before a state may be accepted, and the
+    last state runs SBCI1's ladder; the energies are those of the FP64 form."""
+    ref = REFS["sbci2"][str(seed)]
+    ctx, I20 = _ctx(10, 5, 5, seed)
+    r = ctx.solve2(3, tol=1e-10, opts=dict(precision=precision))
+    assert r.status == 0
+    assert np.abs(r.energies - np.array(ref["sbci2"])).max() < 1e-8
+    assert r.report["nsigma_low"] > 0
+    assert any(s["reason"] == "refine" for s in r.trace)
+    _check_eigenpairs(10, 5, 5, I20, r.energies, r.vectors.cpu().numpy())
     ctx.close()
