@@ -6,20 +6,20 @@ in the paper's notation:
 * start vectors: n lowest diagonal elements -> unit vectors, H in that
   subspace diagonalised (Eqs. S1-S3); or a caller-supplied x0;
 * per root alpha: project the start vector off the converged roots and
-  normalise (Eqs. S4-S7, Algorithm 1 line 1);
-* a segment starts with y = Y = 0, b0 = 1, z'0 = (H - E0) x0 (lines 2-4);
+  normalise (Eqs. S4-S7, the root start of Algorithm 1);
+* a segment starts with y = Y = 0, b0 = 1, z'0 = (H - E0) x0;
 * each step: z = (1 - sum x_c x_c^T)(D - E^0)^-1 z'   (Eq. S31 / S8),
   Z = H z (Eq. S32, the only sigma per step); t = 0 uses the 2x2 problem
   V_0 (Eqs. S10-S24), t >= 1 the 3x3 problem V_t (Eqs. S33-S55);
   y <- y - c z, Y <- Y - c Z, x <- x + b y, X <- X + b Y (Eqs. S25-S28,
-  S56-S59); z' = (X - E x) / |x| (Algorithm 1 line 12);
+  S56-S59); z' = (X - E x) / |x| (Algorithm 1's residual);
 * convergence dE < eps0 and |z'| < r0 (Eqs. S30/S61); otherwise restart on
   Eq. S62a, S62b, S62c or when max_cycle steps were taken (Section S1.5);
 * the next root starts from the second Ritz vector of the converging step
   (Section S1.4).
 
 Readings of points the paper leaves open:
-  residual scale (the z' of Algorithm 1 line 12, positive 1/|x|);
+  residual scale (the z' of Algorithm 1's residual, positive 1/|x|);
   preconditioner shift E^0 = current energy for the ground state, E_c^0
   for excited roots; |D - E^0| floored at 1e-8; max_cycle per segment;
   a vanishing Gram-Schmidt radicand or Ritz coefficient restarts the
@@ -184,7 +184,7 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, p
     all_conv = True
 
     for alpha in range(first, nroots):
-        # Algorithm 1 line 1 with Eqs. S4-S7
+        # the root start of Algorithm 1 (Eqs. S4-S7)
         if xc:
             Xc = np.array(xc)
             proj = Xc @ xa
@@ -199,7 +199,7 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, p
         conv = False
         second = None
         while not conv:
-            # segment start (lines 2-4)
+            # segment start
             y = np.zeros(ndet)
             Y = np.zeros(ndet)
             zp = X - E * x

@@ -10,7 +10,8 @@ paper's steps in its order and notation:
   orthogonalised against the converged roots and against x_0^alpha
   (Section S2.2);
 * pair start: project both vectors off the converged roots and normalise
-  (Eqs. S77-S80, Algorithm 2 line 1); y = Y = 0, B = I (line 2);
+  (Eqs. S77-S80, the pair start of Algorithm 2); y = Y = 0, B = I at each
+  segment start;
 * each step: both preconditioned, deflated residuals (Eqs. S81 / S101) and
   their sigma images (Eqs. S82 / S102); the basis (x^a, x^a+1, z^a, z^a+1) at
   t = 0 or (x^a, x^a+1, y^a, y^a+1, z^a, z^a+1) at t >= 1 is orthonormalised
@@ -23,9 +24,10 @@ paper's steps in its order and notation:
   S130b, S130c or after max_cycle = 10 steps (Section S2.5).
 
 Readings of points the paper leaves open:
-  residual scale 1/|x| (Algorithm 2 line 12); preconditioner shift E^0 = the
+  residual scale 1/|x| (Algorithm 2's residual); preconditioner shift E^0 = the
   current energy of state 0 while alpha = 0, else E_c^0, |D - E^0| floored
-  at 1e-8; a restart ("go to 4") zeroes y and uses the t = 0 step; a
+  at 1e-8; a restart (back to the segment start) zeroes y and uses the t = 0
+  step; a
   vanishing denominator of the coefficient formulas, or fewer than two kept
   basis vectors, restarts the pair from its two lowest Ritz vectors (or
   from the normalised x's); the partner's starting energy is its Rayleigh
@@ -167,7 +169,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
     xa, Xa = xs[0].copy(), Xs[0].copy()
     xb, Xb = xs[1].copy(), Xs[1].copy()
     for alpha in range(nroots - 1):
-        # Algorithm 2 line 1 (Eqs. S77-S80)
+        # the pair start of Algorithm 2 (Eqs. S77-S80)
         xv, Xv = [xa, xb], [Xa, Xb]
         for i in range(2):
             if xc:
@@ -184,7 +186,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
         nstep = 0
         conv = False
         while not conv:
-            # segment start (lines 2-4): y = Y = 0, B = I, z' = (H - E) x / |x|
+            # segment start: y = Y = 0, B = I, z' = (H - E) x / |x|
             y = np.zeros((2, ndet))
             Y = np.zeros((2, ndet))
             zp = np.array([(X[i] - E[i] * x[i]) / np.linalg.norm(x[i]) for i in range(2)])
@@ -235,7 +237,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 s130a = (abs(B[0, 0]) < o.b_th or abs(B[1, 1]) < o.b_th) and dE < o.eps1
                 s130b = (kn < o.x_th1).any() or (kn > o.x_th2).any()
                 if s130a or s130b:
-                    # restart (line 19): x_{t+1}/|x_{t+1}| are the Ritz vectors
+                    # restart (Section S2.5): x_{t+1}/|x_{t+1}| are the Ritz vectors
                     # themselves; take them from the basis, since the update
                     # reaches them through cancellation when |k| << 1
                     v = Vp[:, :2].T @ basis
@@ -280,7 +282,8 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 if conv:
                     break
                 if reason:
-                    # line 19: normalised x's (and X's), E_0 = E_{t+1}; go to 4
+                    # restart: normalised x's (and X's), E_0 = E_{t+1}; back to the
+                    # segment start
                     x, X = x / xn[:, None], X / xn[:, None]
                     seg += 1
                     break
@@ -291,7 +294,7 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 all_conv = False
                 break
         xn = np.linalg.norm(x, axis=1)
-        xc.append(x[0] / xn[0])                   # line 15
+        xc.append(x[0] / xn[0])                   # state alpha accepted
         Xcs.append(X[0] / xn[0])
         Ec.append(float(E[0]))
         # next pair: the converged partner, and the next start vector of Eq. S75

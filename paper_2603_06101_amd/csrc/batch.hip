@@ -632,7 +632,7 @@ struct Solve {
     __syncthreads();
   }
 
-  // Algorithm 1 line 1 with Eqs. S4-S7; returns false on a vanished vector
+  // the root start of Algorithm 1 (Eqs. S4-S7); returns false on a vanished vector
   template <typename T>
   __device__ bool start_root() {
     const Vecs<T> V = vecs<T>(I, C);

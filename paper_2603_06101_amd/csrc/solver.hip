@@ -184,7 +184,7 @@ int segment_start(sbci_ctx *ctx, Solver &S, double sx) {
 }
 
 // Start of a root from x, X (unnormalised, in the running precision) with
-// energy S.E: Algorithm 1 line 1 with Eqs. S4-S7, then the segment start.
+// energy S.E: the root start of Algorithm 1 (Eqs. S4-S7), then the segment start.
 template <typename T>
 int start_root(sbci_ctx *ctx, Solver &S) {
   const int nconv = (int)S.Ec.size();
@@ -1244,7 +1244,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
   }
   for (int alpha = 0; alpha + 1 < nroots; ++alpha) {
     S.alpha = alpha;
-    // Algorithm 2 line 1 (Eqs. S77-S80)
+    // the pair start of Algorithm 2 (Eqs. S77-S80)
     double E[2];
     for (int i = 0; i < 2; ++i) {
       SBCI_TRY(project_off(ctx, S, P, P.x[i], P.X[i]));
@@ -1288,7 +1288,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
       return rc;
     };
     while (!conv && !capped) {
-      // segment start (lines 2-4)
+      // segment start: y = Y = 0, B = I, residuals of x
       int t = 0;
       SBCI_TRY(pair_residuals(ctx, S, P, E, inv, alpha == 0 ? E[0] : S.Ec[0], dz2));
       while (true) {
@@ -1414,14 +1414,14 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
             if (reason == 8) {
               SBCI_TRY(next_phase());
               seg += 1;
-              break;  // go to 4 in the new precision
+              break;  // back to the segment start in the new precision
             }
             if (steps >= S.o.max_steps) {
               capped = true;
               S.any_noconv = true;
               break;
             }
-            // go to 4 with the residuals just formed
+            // back to the segment start, with the residuals just formed
             S.rep.nrestarts += 1;
             seg += 1;
             t = 0;
@@ -1478,7 +1478,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
           inv[0] = inv[1] = 1.0;
           xn[0] = xn[1] = 1.0;
           seg += 1;
-          break;  // go to 4 in the new precision
+          break;  // back to the segment start in the new precision
         }
         if (steps >= S.o.max_steps) {
           capped = true;
@@ -1486,8 +1486,8 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
           break;
         }
         if (reason >= 2) {
-          // line 19: normalised x, X; the residuals just formed are those of the
-          // normalised vectors; go to 4
+          // restart (Section S2.5): normalised x, X; the residuals just formed
+          // are those of the normalised vectors; back to the segment start
           for (int i = 0; i < 2; ++i) {
             SBCI_TRY(scale2(ctx, S, P.x[i], inv[i]));
             SBCI_TRY(scale2(ctx, S, P.X[i], inv[i]));
@@ -1501,7 +1501,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
         t += 1;
       }
     }
-    // accept state alpha (line 15); the partner starts the next pair
+    // accept state alpha (Algorithm 2); the partner starts the next pair
     double *xc = nullptr;
     SBCI_HIP(hipMalloc(&xc, sizeof(double) * n));
     S.alloc_bytes += sizeof(double) * n;

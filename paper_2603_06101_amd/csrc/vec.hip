@@ -3,7 +3,7 @@
 // k_update is the fused symplectic-Euler pass of one SBCI1 step:
 //   y <- sy*y - c*z,  Y <- sy*Y - c*Z            (Eqs. S25-S26 / S56-S57)
 //   x <- sx*x + b*y,  X <- sx*X + b*Y            (Eqs. S27-S28 / S58-S59)
-//   z' = (X - E x) * inv_norm                     (Eq. S60, Algorithm 1 line 12)
+//   z' = (X - E x) * inv_norm                     (Eq. S60; Algorithm 1's residual)
 //   w  = z' / (D - E0)                            (Eq. S31 before the projection)
 // and reduces, in FP64, every inner product the next step's Ritz problem
 // needs except those involving Z = H z (which exists only after the next
