@@ -166,6 +166,9 @@ int same_form(sbci_ctx *ctx, int spin, int *form);
 // Reductions write `nq` doubles to `out` (device); deterministic order.
 template <typename T>
 int dots(sbci_ctx *ctx, int64_t n, const T *a, const T *const *bs, int nb, double *out);
+// b_i . b_j and b_i . h_j (i <= j) of a 4- or 6-vector FP64 basis in one pass
+int gram(sbci_ctx *ctx, int64_t n, const double *const *b, const double *const *h, int m,
+         double *out);
 template <typename T>
 int lincomb(sbci_ctx *ctx, int64_t n, T *out, const T *const *xs, const double *coef, int nx,
             double beta);

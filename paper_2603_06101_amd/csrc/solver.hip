@@ -993,8 +993,6 @@ int dots_h(sbci_ctx *ctx, Pair &P, int64_t n, const double *a, const double *con
   return SBCI_OK;
 }
 
-// Section S2.2 / Eqs. S74-S76: the k lowest diagonal determinants, H in
-// their span diagonalised; xs[i], Xs[i] = H xs[i], Es[i].
 // Z = sigma(z) for the pair's two residuals in the phase's precision: the
 // low-precision phases convert z to FP32, run the FP32 or BF16-MFMA sigma
 // and widen the result (the vectors and every reduction stay FP64).
@@ -1035,6 +1033,8 @@ int pair_rebase(sbci_ctx *ctx, Solver &S, Pair &P, int phase, double *E) {
   return SBCI_OK;
 }
 
+// Section S2.2 / Eq. S74: the k lowest diagonal determinants and H in their
+// span diagonalised (its eigenvectors give the start vectors of Eq. S75).
 int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
   // scratch: the pair's y slots (unused until the first step)
   P.k = k;
@@ -1313,17 +1313,19 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
           img[m] = Z[i];
         }
         double Sm[36], Hm[36];
-        for (int i = 0; i < m; ++i) {
-          const double *bs[12];
-          int nb = 0;
-          for (int j = i; j < m; ++j) bs[nb++] = basis[j];
-          for (int j = i; j < m; ++j) bs[nb++] = img[j];
-          double d[12];
-          SBCI_TRY(dots_h(ctx, P, n, basis[i], bs, nb, d));
-          for (int j = i; j < m; ++j) {
-            Sm[i * m + j] = Sm[j * m + i] = d[j - i];
-            Hm[i * m + j] = Hm[j * m + i] = d[(m - i) + (j - i)];  // H on the right vector
-          }
+        {
+          double g[42];
+          const int np = m * (m + 1) / 2;
+          SBCI_TRY(gram(ctx, n, basis, img, m, P.dev));
+          SBCI_HIP(hipMemcpyAsync(g, P.dev, sizeof(double) * 2 * np, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+          SBCI_HIP(hipStreamSynchronize(ctx->stream));
+          int q = 0;
+          for (int i = 0; i < m; ++i)
+            for (int j = i; j < m; ++j, ++q) {
+              Sm[i * m + j] = Sm[j * m + i] = g[q];
+              Hm[i * m + j] = Hm[j * m + i] = g[np + q];  // H on the right vector
+            }
         }
         for (int i = 0; i < m * m; ++i)
           if (!std::isfinite(Sm[i]) || !std::isfinite(Hm[i]))

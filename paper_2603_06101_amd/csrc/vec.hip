@@ -21,7 +21,7 @@ namespace sbci {
 namespace {
 
 constexpr int BS = 256;
-constexpr int MAXQ = 32;
+constexpr int MAXQ = 48;
 constexpr int MAXV = 16;
 
 struct Ptrs {
@@ -345,6 +345,37 @@ __global__ __launch_bounds__(BS) void k_dots_xyz(int64_t n, const T *__restrict_
   grid_reduce<3>(v, 3, part, ticket, out);
 }
 
+// Overlap and H matrices of an m-vector basis in one pass (the pair steps
+// of Algorithm 2, Eqs. S83-S87 / S103-S107): out[q] = b_i . b_j and
+// out[P + q] = b_i . h_j (H on the right-hand vector) for the upper
+// triangle i <= j in row-major order, P = m (m + 1) / 2, h_j the image of b_j.
+template <int M>
+__global__ __launch_bounds__(BS) void k_gram(int64_t n, Ptrs b, Ptrs h, double *part,
+                                             unsigned *ticket, double *out) {
+  constexpr int P = M * (M + 1) / 2;
+  double v[2 * P];
+#pragma unroll
+  for (int q = 0; q < 2 * P; ++q) v[q] = 0;
+  const int64_t S = (int64_t)gridDim.x * BS;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += S) {
+    double bi[M], hi[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      bi[a] = static_cast<const double *>(b.p[a])[i];
+      hi[a] = static_cast<const double *>(h.p[a])[i];
+    }
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int c = a; c < M; ++c, ++q) {
+        v[q] += bi[a] * bi[c];
+        v[P + q] += bi[a] * hi[c];
+      }
+  }
+  grid_reduce<2 * P>(v, 2 * P, part, ticket, out);
+}
+
 unsigned grid_for(int64_t n) {
   int64_t b = (n + BS - 1) / BS;
   if (b > 2048) b = 2048;
@@ -471,6 +502,26 @@ int dots_xyz(sbci_ctx *ctx, int64_t n, const T *x, const T *y, const T *z, const
   SBCI_TRY(red_buf(ctx, r));
   k_dots_xyz<T><<<grid_for(n), BS, 0, ctx->stream>>>(n, x, y, z, Z, r.part, r.ticket, out);
   k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), 3, out);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+int gram(sbci_ctx *ctx, int64_t n, const double *const *b, const double *const *h, int m,
+         double *out) {
+  if (m != 4 && m != 6) return set_error(SBCI_EINVAL, "gram: a basis of 4 or 6 vectors");
+  RedBuf r;
+  SBCI_TRY(red_buf(ctx, r));
+  Ptrs pb{}, ph{};
+  for (int i = 0; i < m; ++i) {
+    pb.p[i] = b[i];
+    ph.p[i] = h[i];
+  }
+  const int nq = m * (m + 1);
+  if (m == 4)
+    k_gram<4><<<grid_for(n), BS, 0, ctx->stream>>>(n, pb, ph, r.part, r.ticket, out);
+  else
+    k_gram<6><<<grid_for(n), BS, 0, ctx->stream>>>(n, pb, ph, r.part, r.ticket, out);
+  k_reduce<<<1, BS, 0, ctx->stream>>>(r.part, grid_for(n), nq, out);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
