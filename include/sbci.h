@@ -193,12 +193,14 @@ int sbci_get_opp_form(sbci_ctx *ctx, int dtype, int *form);
  * SBCI_SAME_AUTO (the default).  The dense form keeps an N_s x N_s operator
  * per spin and precision (built on first use) and is limited to N_s <= 32768
  * strings; beyond that a forced dense form makes sigma fail with
- * SBCI_EINVAL. */
+ * SBCI_EINVAL.  For the SBCI_BF16 sigma the dense form runs on BF16 MFMA
+ * with FP32 accumulation (the operator's diagonal stays FP32) and is the
+ * automatic choice from 1024 to 32768 strings. */
 int sbci_set_same_form(sbci_ctx *ctx, int form);
 
-/* The same-spin form (SBCI_SAME_LISTS or SBCI_SAME_DENSE) sigma calls use
- * for spin 0 (alpha) or 1 (beta), into *form. */
-int sbci_get_same_form(sbci_ctx *ctx, int spin, int *form);
+/* The same-spin form (SBCI_SAME_LISTS or SBCI_SAME_DENSE) sigma calls of
+ * this dtype use for spin 0 (alpha) or 1 (beta), into *form. */
+int sbci_get_same_form(sbci_ctx *ctx, int spin, int dtype, int *form);
 
 /* SBCI1 (Algorithm 1 with Sections S1.1-S1.5) for the lowest nroots states.
  * tol > 0 overrides opt: eps0 = tol, r0 = sqrt(tol) (the paper's two pairs,

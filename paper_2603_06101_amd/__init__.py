@@ -125,7 +125,7 @@ SIGNATURES = [
     ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_set_same_form", _I, [_P, _I]),
     ("sbci_set_progress", _I, [_P, PROGRESS_FN, _P]),
-    ("sbci_get_same_form", _I, [_P, _I, ctypes.POINTER(_I)]),
+    ("sbci_get_same_form", _I, [_P, _I, _I, ctypes.POINTER(_I)]),
     ("sbci_solve", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
     ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
@@ -284,10 +284,10 @@ class Context:
         """Force the same-spin form ("auto", "lists" or "dense") of later sigma calls."""
         _check(lib().sbci_set_same_form(self.h, SAME_FORMS[form]))
 
-    def same_form(self, spin=0):
-        """The same-spin form ("lists" or "dense") sigma calls use for spin 0 (alpha) or 1."""
+    def same_form(self, spin=0, dtype="f64"):
+        """The same-spin form ("lists" or "dense") sigma calls of this dtype use for spin 0 or 1."""
         f = _I(0)
-        _check(lib().sbci_get_same_form(self.h, spin, ctypes.byref(f)))
+        _check(lib().sbci_get_same_form(self.h, spin, DTYPES[dtype], ctypes.byref(f)))
         return {v: k for k, v in SAME_FORMS.items()}[f.value]
 
     def sigma_timed(self, c, dtype="f64", out=None):

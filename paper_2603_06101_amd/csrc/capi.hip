@@ -270,10 +270,12 @@ int sbci_set_same_form(sbci_ctx *ctx, int form) {
   return SBCI_OK;
 }
 
-int sbci_get_same_form(sbci_ctx *ctx, int spin, int *form) {
+int sbci_get_same_form(sbci_ctx *ctx, int spin, int dtype, int *form) {
   if (!ctx || !form) return set_error(SBCI_EINVAL, "NULL argument");
   if (spin != 0 && spin != 1) return set_error(SBCI_EINVAL, "spin must be 0 or 1");
-  return same_form(ctx, spin, form);
+  if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
+    return set_error(SBCI_EINVAL, "unknown dtype");
+  return same_form(ctx, spin, dtype, form);
 }
 
 int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {

@@ -68,6 +68,10 @@ struct SpinTables {
   // built on first use by the dense form
   double *hd64 = nullptr;
   float *hd32 = nullptr;
+  // BF16 form of the dense operator without its diagonal, and the diagonal
+  // in FP32 (applied in the product's epilogue: it is too large to round)
+  __hip_bfloat16 *hdbf = nullptr;
+  float *hdd32 = nullptr;
   bool shared = false;      // aliases the alpha tables (n_alpha == n_beta)
 };
 
@@ -159,8 +163,8 @@ int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
 int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms);
 // opposite-spin form (SBCI_OPP_PAIR / SBCI_OPP_ORBITAL) used for this dtype
 int opp_form(sbci_ctx *ctx, int mode, int *form);
-// same-spin form (SBCI_SAME_LISTS / SBCI_SAME_DENSE) of one spin
-int same_form(sbci_ctx *ctx, int spin, int *form);
+// same-spin form (SBCI_SAME_LISTS / SBCI_SAME_DENSE) of one spin for a sigma dtype
+int same_form(sbci_ctx *ctx, int spin, int dtype, int *form);
 
 // ---- vec.hip: vector kernels with FP64 reductions ----
 // Reductions write `nq` doubles to `out` (device); deterministic order.

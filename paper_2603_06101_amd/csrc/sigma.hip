@@ -172,6 +172,137 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(int64_t Mr, int64_t N, in
     }
 }
 
+// The same products with BF16 operands on 16x16x32 BF16 MFMA (FP32
+// accumulation), for the BF16 sigma.  Both operands are BF16 with k
+// contiguous and rows padded with zeros to a multiple of 64 (ld):
+// out[r][c] = sum_k A'[r][k] B'[c][k].  Alpha part: A' = H_alpha without
+// diagonal, B' = C^T; beta part: A' = C, B' = H_beta without diagonal
+// (symmetric, so its rows are its columns).  The padding makes every K
+// panel whole and every row 16-byte aligned, so staging is 16-byte vector
+// loads with no bounds tests (rows past the end read a clamped valid row
+// and are masked at the store).  The epilogue adds the diagonal term in
+// FP32 from the FP32 vector: C[r][c] * dd[r] (DSIDE 0) or C[r][c] * dd[c]
+// (DSIDE 1).  128 x 256 tiles on 8 waves, K panels of 64.
+template <int DSIDE>
+__global__ __launch_bounds__(512) void k_gemm_bf16(
+    int64_t Mr, int64_t N, int64_t Kp, const __bf16 *__restrict__ Ab, int64_t lda, int64_t sA,
+    const __bf16 *__restrict__ Bb, int64_t ldb, int64_t sB, const float *__restrict__ C,
+    int64_t sCin, const float *__restrict__ dd, float *__restrict__ out, int64_t ldc, int64_t sC,
+    int accumulate, int64_t tiles_n, int64_t per_xcd, int64_t total) {
+  constexpr int WM = 2, WN = 4, BM = 64 * WM, BN = 64 * WN, BK = 64, NT = 64 * WM * WN;
+  constexpr int LD = BK + 8;  // 144-byte rows: fragments stay 16-byte aligned
+  constexpr int AV = BM * BK / NT / 8, BV = BN * BK / NT / 8;  // 16-byte vectors per thread: 2, 4
+  __shared__ __align__(16) __bf16 As[2][BM * LD];
+  __shared__ __align__(16) __bf16 Bs[2][BN * LD];
+  const int64_t b = blockIdx.x;
+  const int64_t w = (b & 7) * per_xcd + (b >> 3);
+  if (w >= total) return;
+  const int64_t tm = w / tiles_n, tn = w - tm * tiles_n;
+  const int64_t r0 = tm * BM, c0 = tn * BN;
+  const int64_t v = blockIdx.y;
+  Ab += v * sA;
+  Bb += v * sB;
+  C += v * sCin;
+  out += v * sC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wm = (wave / WN) * 64, wn = (wave % WN) * 64;
+  // A' panel: thread -> row ar, 8 AV consecutive k from ak; B' likewise
+  const int ar = tid / (BK / (8 * AV)), ak = (tid % (BK / (8 * AV))) * 8 * AV;
+  const int br = tid / (BK / (8 * BV)), bk = (tid % (BK / (8 * BV))) * 8 * BV;
+  const int64_t arow = r0 + ar < Mr ? r0 + ar : Mr - 1;
+  const int64_t brow = c0 + br < N ? c0 + br : N - 1;
+  const uint4 *pa = reinterpret_cast<const uint4 *>(Ab + arow * lda + ak);
+  const uint4 *pb = reinterpret_cast<const uint4 *>(Bb + brow * ldb + bk);
+  uint4 ra[AV], rb[BV];
+  auto load = [&](int64_t p) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) ra[u] = pa[p * (BK / 8) + u];
+#pragma unroll
+    for (int u = 0; u < BV; ++u) rb[u] = pb[p * (BK / 8) + u];
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) *reinterpret_cast<uint4 *>(&As[buf][ar * LD + ak + 8 * u]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < BV; ++u) *reinterpret_cast<uint4 *>(&Bs[buf][br * LD + bk + 8 * u]) = rb[u];
+  };
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0f;
+  const int64_t np = Kp / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t p = 0; p < np; ++p) {
+    const int buf = (int)(p & 1);
+    if (p + 1 < np) load(p + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      bf8_t fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fa[i] = *reinterpret_cast<const bf8_t *>(&As[buf][(wm + 16 * i + li) * LD + ks * 32 + g * 8]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][(wn + 16 * j + li) * LD + ks * 32 + g * 8]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (p + 1 < np) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wm + 16 * i + 4 * g + r;
+      if (row >= Mr) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + wn + 16 * j + li;
+        if (c < N) {
+          const float x = acc[i][j][r] + C[row * ldc + c] * (DSIDE == 0 ? dd[row] : dd[c]);
+          float *d = out + row * ldc + c;
+          *d = accumulate ? *d + x : x;
+        }
+      }
+    }
+}
+
+// BF16 copies of an [R][C] FP32 matrix (per vector z) with rows padded with
+// zeros to ld: transposed (dst[c][r], ld >= R, for the alpha part) or not
+// (dst[r][c], ld >= C, for the beta part).
+template <bool TRANS>
+__global__ void k_to_bf16(const float *__restrict__ src, __bf16 *__restrict__ dst, int64_t R,
+                          int64_t C, int64_t ld) {
+  __shared__ float tile[TT][TT + 1];
+  const int64_t vo = (int64_t)blockIdx.z * R * C;
+  const int64_t vd = (int64_t)blockIdx.z * (TRANS ? C : R) * ld;
+  const int64_t r0 = (int64_t)blockIdx.y * TT, c0 = (int64_t)blockIdx.x * TT;
+  for (int i = threadIdx.y; i < TT; i += blockDim.y) {
+    const int64_t r = r0 + i, c = c0 + threadIdx.x;
+    tile[i][threadIdx.x] = (r < R && c < C) ? src[vo + r * C + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < TT; i += blockDim.y) {
+    if (TRANS) {
+      const int64_t c = c0 + i, r = r0 + threadIdx.x;  // dst row c, column r (< ld)
+      if (c < C && r < ld) dst[vd + c * ld + r] = (__bf16)tile[threadIdx.x][i];
+    } else {
+      const int64_t r = r0 + i, c = c0 + threadIdx.x;
+      if (r < R && c < ld) dst[vd + r * ld + c] = (__bf16)tile[i][threadIdx.x];
+    }
+  }
+}
+
 // One wave per list row r; each lane owns VC columns c, c + 64, ... so that
 // every load instruction of the wave reads 64 consecutive elements.  Work
 // items (row group, column tile) are numbered column-tile-major and dealt to
@@ -1036,6 +1167,84 @@ __global__ void k_densify(const int32_t *__restrict__ fcol, const V *__restrict_
   for (int e = threadIdx.x; e < nf; e += blockDim.x) row[fcol[r * nf + e]] = fval[r * nf + e];
 }
 
+// Row r of the BF16 operator without its diagonal, and the diagonal in FP32.
+__global__ void k_densify_bf16(const int32_t *__restrict__ fcol, const float *__restrict__ fval,
+                               int nf, int64_t ns, int64_t ld, __hip_bfloat16 *__restrict__ H,
+                               float *__restrict__ dd) {
+  const int64_t r = blockIdx.x;
+  __hip_bfloat16 *row = H + r * ld;
+  for (int64_t j = threadIdx.x; j < ld; j += blockDim.x) row[j] = __float2bfloat16(0.0f);
+  __syncthreads();
+  for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+    const int32_t c = fcol[r * nf + e];
+    if (c == r) dd[r] = fval[r * nf + e];
+    else row[c] = __float2bfloat16(fval[r * nf + e]);
+  }
+}
+
+// The BF16 sigma's same-spin part: the dense BF16 product wherever the
+// dense operator fits (kDenseMaxRows), from the LDS-stripe range up (below
+// it the lists are already fast); SBCI_SAME_LISTS / _DENSE force it.
+bool use_dense_bf16(const sbci_ctx *ctx, const SpinTables &S) {
+  if (ctx->same_form == SBCI_SAME_DENSE) return true;
+  if (ctx->same_form == SBCI_SAME_LISTS) return false;
+  return S.ns >= kSameLdsMinRows && S.ns <= kDenseMaxRows;
+}
+
+int dense_same_bf16(sbci_ctx *ctx, SpinTables &S, const __hip_bfloat16 **H, const float **dd) {
+  SpinTables &O = S.shared ? ctx->A : S;
+  if (O.ns > kDenseMaxRows)
+    return set_error(SBCI_EINVAL, "same-spin sigma: too many strings for the dense form");
+  if (!O.hdbf) {
+    const int64_t ld = (O.ns + 63) / 64 * 64;  // rows padded with zeros (whole K panels)
+    SBCI_HIP(hipMalloc(&O.hdbf, sizeof(__hip_bfloat16) * (size_t)O.ns * ld));
+    SBCI_HIP(hipMalloc(&O.hdd32, sizeof(float) * (size_t)O.ns));
+    k_densify_bf16<<<(unsigned)O.ns, 256, 0, ctx->stream>>>(O.fcol, O.fval32, O.nf, O.ns, ld,
+                                                            O.hdbf, O.hdd32);
+    SBCI_CHECK_LAUNCH();
+  }
+  if (&O != &S) {
+    S.hdbf = O.hdbf;
+    S.hdd32 = O.hdd32;
+  }
+  *H = O.hdbf;
+  *dd = O.hdd32;
+  return SBCI_OK;
+}
+
+// BF16 same-spin products of the BF16 sigma: alpha (side 0) writes
+// out = H_alpha C from C^T in BF16, beta (side 1) adds C H_beta from C in
+// BF16; H is [ns][ldh] with ldh = ns rounded up to 64 (zero padded).
+int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
+
+int launch_gemm_bf16(sbci_ctx *ctx, int side, const float *c, const __hip_bfloat16 *H,
+                     const float *dd, float *out, int nvec) {
+  const int64_t na = ctx->A.ns, nb = ctx->B.ns, nd = ctx->ndet;
+  const int64_t K = side == 0 ? na : nb, Kp = pad64(K);
+  const int64_t tm = (na + 127) / 128, tn = (nb + 255) / 256;
+  const int64_t total = tm * tn, per_xcd = (total + 7) / 8;
+  if (per_xcd * 8 >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "same-spin sigma: grid too large");
+  const dim3 grid((unsigned)(per_xcd * 8), (unsigned)nvec);
+  const __bf16 *Hb = reinterpret_cast<const __bf16 *>(H);
+  // the vector's BF16 copy: alpha needs C^T [nb][pad(na)], beta C [na][pad(nb)]
+  const int64_t rows = side == 0 ? nb : na;
+  SBCI_TRY(ensure(ctx->ws_t, sizeof(__bf16) * (size_t)rows * Kp * nvec));
+  __bf16 *cb = static_cast<__bf16 *>(ctx->ws_t.ptr);
+  if (side == 0) {
+    const dim3 gt((unsigned)((nb + TT - 1) / TT), (unsigned)((Kp + TT - 1) / TT), (unsigned)nvec);
+    k_to_bf16<true><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, cb, na, nb, Kp);
+    k_gemm_bf16<0><<<grid, 512, 0, ctx->stream>>>(na, nb, Kp, Hb, Kp, 0, cb, Kp, nb * Kp, c, nd, dd,
+                                                  out, nb, nd, 0, tn, per_xcd, total);
+  } else {
+    const dim3 gt((unsigned)((Kp + TT - 1) / TT), (unsigned)((na + TT - 1) / TT), (unsigned)nvec);
+    k_to_bf16<false><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, cb, na, nb, Kp);
+    k_gemm_bf16<1><<<grid, 512, 0, ctx->stream>>>(na, nb, Kp, cb, Kp, na * Kp, Hb, Kp, 0, c, nd, dd,
+                                                  out, nb, nd, 1, tn, per_xcd, total);
+  }
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
 bool use_dense(const sbci_ctx *ctx, const SpinTables &S) {
   if (ctx->same_form == SBCI_SAME_DENSE) return true;
   if (ctx->same_form == SBCI_SAME_LISTS) return false;
@@ -1094,10 +1303,21 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
   SpinTables &A = ctx->A, &B = ctx->B;
   const int64_t na = A.ns, nb = B.ns, nd = ctx->ndet;
   const bool dbl = std::is_same<T, double>::value;
-  const bool denseA = use_dense(ctx, A), denseB = use_dense(ctx, B);
+  constexpr bool bf = std::is_same<M, MBF16>::value;
+  const bool bfA = bf && use_dense_bf16(ctx, A), bfB = bf && use_dense_bf16(ctx, B);
+  const bool denseA = !bfA && use_dense(ctx, A), denseB = !bfB && use_dense(ctx, B);
   // alpha part (plain write), then opposite-spin (accumulate)
   SBCI_TRY(rec(ctx, pe, 0));
-  if (denseA) {
+  if constexpr (bf) {
+    if (bfA) {
+      const __hip_bfloat16 *H = nullptr;
+      const float *dd = nullptr;
+      SBCI_TRY(dense_same_bf16(ctx, A, &H, &dd));
+      SBCI_TRY(launch_gemm_bf16(ctx, 0, c, H, dd, out, nvec));
+    }
+  }
+  if (bfA) {
+  } else if (denseA) {
     const T *H = nullptr;
     SBCI_TRY(dense_same<T>(ctx, A, &H));
     SBCI_TRY(launch_gemm<T>(ctx, na, nb, na, H, na, 0, c, nb, nd, out, nb, nd, nvec, 0));
@@ -1109,6 +1329,19 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
   SBCI_TRY(rec(ctx, pe, 1));
   SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec)));
   SBCI_TRY(rec(ctx, pe, 2));
+  if constexpr (bf) {
+    if (bfB) {
+      // beta part as C H_beta on BF16 MFMA, accumulated in place
+      const __hip_bfloat16 *H = nullptr;
+      const float *dd = nullptr;
+      SBCI_TRY(dense_same_bf16(ctx, B, &H, &dd));
+      SBCI_TRY(rec(ctx, pe, 3));
+      SBCI_TRY(launch_gemm_bf16(ctx, 1, c, H, dd, out, nvec));
+      SBCI_TRY(rec(ctx, pe, 4));
+      SBCI_TRY(rec(ctx, pe, 5));
+      return SBCI_OK;
+    }
+  }
   if (denseB) {
     // beta part as C H_beta, accumulated in place (no transposes)
     const T *H = nullptr;
@@ -1161,8 +1394,10 @@ int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
   return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
 }
 
-int same_form(sbci_ctx *ctx, int spin, int *form) {
-  *form = use_dense(ctx, spin == 0 ? ctx->A : ctx->B) ? SBCI_SAME_DENSE : SBCI_SAME_LISTS;
+int same_form(sbci_ctx *ctx, int spin, int dtype, int *form) {
+  const SpinTables &S = spin == 0 ? ctx->A : ctx->B;
+  const bool dense = dtype == SBCI_BF16 ? use_dense_bf16(ctx, S) : use_dense(ctx, S);
+  *form = dense ? SBCI_SAME_DENSE : SBCI_SAME_LISTS;
   return SBCI_OK;
 }
 

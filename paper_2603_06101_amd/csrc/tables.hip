@@ -403,6 +403,8 @@ void free_spin(SpinTables &T) {
   hipFree(T.colq);
   hipFree(T.hd64);
   hipFree(T.hd32);
+  hipFree(T.hdbf);
+  hipFree(T.hdd32);
   hipFree(T.qquad_r);
   hipFree(T.qquad_s);
   hipFree(T.fcolT);

@@ -83,6 +83,25 @@ def test_same_dense_f64_matches_oracle(n, na, nb):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,na,nb", [(13, 6, 5), (12, 6, 6), (20, 2, 2), (7, 0, 3), (33, 2, 1)])
+def test_same_dense_bf16_error(n, na, nb):
+    """BF16 sigma with the dense BF16-MFMA same-spin product (FP32 diagonal in
+    the epilogue): error against the FP64 oracle of the order of the BF16
+    opposite-spin contraction's, and no worse than twice the lists form's."""
+    ctx, I = _ctx(n, na, nb, seed=9)
+    c = sigma_inputs(10, 1, ctx.ndet)
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    c32 = torch.from_numpy(c.astype(np.float32)).cuda()
+    errs = {}
+    for form in ("lists", "dense"):
+        ctx.set_same_form(form)
+        got = ctx.sigma(c32, dtype="bf16").cpu().numpy()
+        errs[form] = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert errs["dense"] < 1e-2, errs
+    assert errs["dense"] < 2 * errs["lists"] + 1e-3, errs
+    ctx.close()
+
+
 @pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
 @pytest.mark.parametrize("n,na,nb", [(12, 2, 3), (13, 6, 5), (20, 2, 2)])
 def test_same_dense_low_precision(n, na, nb, dtype, tol):
@@ -117,6 +136,9 @@ def test_automatic_form_choice():
     ctx, _ = _ctx(14, 7, 7)
     assert all(ctx.opp_form(d) == "pair" for d in ("f64", "f32", "bf16"))
     assert ctx.same_form(0) == ctx.same_form(1) == "lists"
+    assert ctx.same_form(0, "f32") == "lists"
+    # the BF16 sigma takes the dense BF16-MFMA product from 1024 strings up
+    assert ctx.same_form(0, "bf16") == ctx.same_form(1, "bf16") == "dense"
     ctx.close()
     ctx, _ = _ctx(20, 2, 2)
     assert ctx.opp_form("f64") == "orbital"
