@@ -383,12 +383,15 @@ constexpr int32_t kPadEntry = -1;  // K padding: zero column of A
 // next tile's fragment is fetched before the current tile's MFMAs), runs all
 // M tiles of its group, and scatters through the packed pair codes.  K and M
 // are padded to compile-time tile counts, so the inner loops carry no bound
-// checks; no workgroup barrier sits inside the column loop.
-template <typename M, typename T, int MG, int KS, bool AREG, int NW>
+// checks; no workgroup barrier sits inside the column loop.  c (type TC,
+// row stride ldc) is the vector itself, or for the BF16 flavour its BF16
+// copy, which halves the bytes of the gathers.
+template <typename M, typename T, typename TC, int MG, int KS, bool AREG, int NW>
 __global__ __launch_bounds__(64 * NW) void k_opp(
     int64_t nsa, int64_t nsb, int64_t nsb_pad, int s, int npair, int ngroups, int nkc,
     const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
-    const uint4 *__restrict__ quads, const T *__restrict__ c, T *__restrict__ sigma) {
+    const uint4 *__restrict__ quads, const TC *__restrict__ c, int64_t ldc,
+    T *__restrict__ sigma) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
@@ -412,17 +415,17 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
   for (int e = tid; e < ktot; e += 64 * NW) {
     if (e < s) {
       Ent t = taba[ia * s + e];
-      eoff[e] = (uint32_t)t.J * (uint32_t)nsb;
+      eoff[e] = (uint32_t)t.J * (uint32_t)ldc;
       int kl = pair_index(t.p, t.q);
       eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
     } else {
-      eoff[e] = (uint32_t)ia * (uint32_t)nsb;  // any valid row: its A column is zero
+      eoff[e] = (uint32_t)ia * (uint32_t)ldc;  // any valid row: its A column is zero
       eW[e] = kPadEntry;
     }
   }
   for (int64_t j = tid; j < nsb + 64; j += 64 * NW) acc[j] = (Acc)0;
 
-  const T *__restrict__ cv = c + vo;
+  const TC *__restrict__ cv = c + (int64_t)blockIdx.y * nsa * ldc;
   const uint32_t nsb32 = (uint32_t)nsb;
   const uint32_t pstride = (uint32_t)nsb_pad;
   const int njt = (int)((nsb + 15) / 16);
@@ -585,60 +588,60 @@ int plan_opp(sbci_ctx *ctx, const int *mg_options, int nmg, const int *ks_option
   return SBCI_OK;
 }
 
-template <typename M, typename T, int MG, int KS, bool AREG>
+template <typename M, typename T, int MG, int KS, bool AREG, typename TC>
 void launch_opp_k(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
-                  const T *c, T *out) {
+                  const TC *c, int64_t ldc, T *out) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   constexpr int NW = 8;
-  k_opp<M, T, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
+  k_opp<M, T, TC, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
       A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab,
-      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, out);
+      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, ldc, out);
 }
 
-template <typename M, typename T, int MG>
+template <typename M, typename T, int MG, typename TC>
 void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
-                 const T *c, T *out) {
+                 const TC *c, int64_t ldc, T *out) {
   if constexpr (M::KPL == 8) {
     // A fragments in registers when they are few enough (MG * KS <= 18)
     const bool areg = p.ngroups == 1 && MG * p.KS <= 18;
     if (p.KS == 1) {
-      if (areg) launch_opp_k<M, T, MG, 1, true>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 1, false>(ctx, p, grid, Wf, Wd, c, out);
+      if (areg) launch_opp_k<M, T, MG, 1, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else launch_opp_k<M, T, MG, 1, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     } else if (p.KS == 2) {
-      if (areg) launch_opp_k<M, T, MG, 2, true>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 2, false>(ctx, p, grid, Wf, Wd, c, out);
+      if (areg) launch_opp_k<M, T, MG, 2, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else launch_opp_k<M, T, MG, 2, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     } else {
-      if (areg) launch_opp_k<M, T, MG, 3, true>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 3, false>(ctx, p, grid, Wf, Wd, c, out);
+      if (areg) launch_opp_k<M, T, MG, 3, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else launch_opp_k<M, T, MG, 3, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     }
   } else {
     if constexpr (std::is_same<typename M::A, double>::value) {
-      if (p.KS == 4) launch_opp_k<M, T, MG, 4, false>(ctx, p, grid, Wf, Wd, c, out);
-      else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 14, false>(ctx, p, grid, Wf, Wd, c, out);
+      if (p.KS == 4) launch_opp_k<M, T, MG, 4, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     } else {
-      if (p.KS == 8) launch_opp_k<M, T, MG, 8, false>(ctx, p, grid, Wf, Wd, c, out);
-      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false>(ctx, p, grid, Wf, Wd, c, out);
-      else launch_opp_k<M, T, MG, 14, false>(ctx, p, grid, Wf, Wd, c, out);
+      if (p.KS == 8) launch_opp_k<M, T, MG, 8, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     }
   }
 }
 
-template <typename M, typename T>
-int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const T *c, T *out, int nvec) {
+template <typename M, typename T, typename TC>
+int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const TC *c, int64_t ldc, T *out, int nvec) {
   const SpinTables &A = ctx->A;
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
   dim3 grid((unsigned)A.ns, (unsigned)nvec);
   if constexpr (std::is_same<typename M::A, double>::value) {
-    if (p.MG == 4) dispatch_ks<M, T, 4>(ctx, p, grid, Wf, Wd, c, out);
-    else if (p.MG == 5) dispatch_ks<M, T, 5>(ctx, p, grid, Wf, Wd, c, out);
-    else dispatch_ks<M, T, 7>(ctx, p, grid, Wf, Wd, c, out);
+    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else if (p.MG == 5) dispatch_ks<M, T, 5, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
   } else {
-    if (p.MG == 4) dispatch_ks<M, T, 4>(ctx, p, grid, Wf, Wd, c, out);
-    else if (p.MG == 7) dispatch_ks<M, T, 7>(ctx, p, grid, Wf, Wd, c, out);
-    else dispatch_ks<M, T, 9>(ctx, p, grid, Wf, Wd, c, out);
+    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
   }
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
@@ -988,7 +991,8 @@ int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
 }
 
 template <typename M, typename T>
-int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
+int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec, const __bf16 *cb = nullptr,
+               int64_t ldcb = 0) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (A.s == 0 || B.m == 0) return SBCI_OK;
   if (ctx->ndet >= ((int64_t)1 << 31))
@@ -998,7 +1002,12 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec) {
   OppQPlan pq{};
   SBCI_TRY(choose_opp<M>(ctx, form, pp, pq));
   if (form == SBCI_OPP_ORBITAL) return launch_opp_q<M, T>(ctx, pq, c, out, nvec);
-  return launch_opp_pair<M, T>(ctx, pp, c, out, nvec);
+  if (cb) {
+    if ((uint64_t)A.ns * (uint64_t)ldcb >= (1ull << 32))
+      return set_error(SBCI_EINVAL, "opposite-spin sigma: BF16 copy too large for 32-bit offsets");
+    return launch_opp_pair<M, T, __bf16>(ctx, pp, cb, ldcb, out, nvec);
+  }
+  return launch_opp_pair<M, T, T>(ctx, pp, c, B.ns, out, nvec);
 }
 
 // Same-spin part with the source stripe in LDS: one workgroup per (column
@@ -1217,30 +1226,43 @@ int dense_same_bf16(sbci_ctx *ctx, SpinTables &S, const __hip_bfloat16 **H, cons
 // BF16; H is [ns][ldh] with ldh = ns rounded up to 64 (zero padded).
 int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
 
-int launch_gemm_bf16(sbci_ctx *ctx, int side, const float *c, const __hip_bfloat16 *H,
-                     const float *dd, float *out, int nvec) {
+// The vector's BF16 copy for one side's product, rows zero padded to 64:
+// alpha takes C^T [nb][pad(na)], beta C [na][pad(nb)] (which also feeds the
+// gathers of the opposite-spin pair form).  It lives in ws_t until the next
+// copy replaces it.
+int bf16_copy(sbci_ctx *ctx, int side, const float *c, int nvec, const __bf16 **cb) {
+  const int64_t na = ctx->A.ns, nb = ctx->B.ns;
+  const int64_t Kp = pad64(side == 0 ? na : nb), rows = side == 0 ? nb : na;
+  SBCI_TRY(ensure(ctx->ws_t, sizeof(__bf16) * (size_t)rows * Kp * nvec));
+  __bf16 *d = static_cast<__bf16 *>(ctx->ws_t.ptr);
+  if (side == 0) {
+    const dim3 gt((unsigned)((nb + TT - 1) / TT), (unsigned)((Kp + TT - 1) / TT), (unsigned)nvec);
+    k_to_bf16<true><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, d, na, nb, Kp);
+  } else {
+    const dim3 gt((unsigned)((Kp + TT - 1) / TT), (unsigned)((na + TT - 1) / TT), (unsigned)nvec);
+    k_to_bf16<false><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, d, na, nb, Kp);
+  }
+  SBCI_CHECK_LAUNCH();
+  *cb = d;
+  return SBCI_OK;
+}
+
+// The product on the copy cb that bf16_copy made for the same side.
+int launch_gemm_bf16(sbci_ctx *ctx, int side, const float *c, const __bf16 *cb,
+                     const __hip_bfloat16 *H, const float *dd, float *out, int nvec) {
   const int64_t na = ctx->A.ns, nb = ctx->B.ns, nd = ctx->ndet;
-  const int64_t K = side == 0 ? na : nb, Kp = pad64(K);
+  const int64_t Kp = pad64(side == 0 ? na : nb);
   const int64_t tm = (na + 127) / 128, tn = (nb + 255) / 256;
   const int64_t total = tm * tn, per_xcd = (total + 7) / 8;
   if (per_xcd * 8 >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "same-spin sigma: grid too large");
   const dim3 grid((unsigned)(per_xcd * 8), (unsigned)nvec);
   const __bf16 *Hb = reinterpret_cast<const __bf16 *>(H);
-  // the vector's BF16 copy: alpha needs C^T [nb][pad(na)], beta C [na][pad(nb)]
-  const int64_t rows = side == 0 ? nb : na;
-  SBCI_TRY(ensure(ctx->ws_t, sizeof(__bf16) * (size_t)rows * Kp * nvec));
-  __bf16 *cb = static_cast<__bf16 *>(ctx->ws_t.ptr);
-  if (side == 0) {
-    const dim3 gt((unsigned)((nb + TT - 1) / TT), (unsigned)((Kp + TT - 1) / TT), (unsigned)nvec);
-    k_to_bf16<true><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, cb, na, nb, Kp);
+  if (side == 0)
     k_gemm_bf16<0><<<grid, 512, 0, ctx->stream>>>(na, nb, Kp, Hb, Kp, 0, cb, Kp, nb * Kp, c, nd, dd,
                                                   out, nb, nd, 0, tn, per_xcd, total);
-  } else {
-    const dim3 gt((unsigned)((Kp + TT - 1) / TT), (unsigned)((na + TT - 1) / TT), (unsigned)nvec);
-    k_to_bf16<false><<<gt, dim3(TT, 8), 0, ctx->stream>>>(c, cb, na, nb, Kp);
+  else
     k_gemm_bf16<1><<<grid, 512, 0, ctx->stream>>>(na, nb, Kp, cb, Kp, na * Kp, Hb, Kp, 0, c, nd, dd,
                                                   out, nb, nd, 1, tn, per_xcd, total);
-  }
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -1312,8 +1334,10 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
     if (bfA) {
       const __hip_bfloat16 *H = nullptr;
       const float *dd = nullptr;
+      const __bf16 *ct = nullptr;
       SBCI_TRY(dense_same_bf16(ctx, A, &H, &dd));
-      SBCI_TRY(launch_gemm_bf16(ctx, 0, c, H, dd, out, nvec));
+      SBCI_TRY(bf16_copy(ctx, 0, c, nvec, &ct));
+      SBCI_TRY(launch_gemm_bf16(ctx, 0, c, ct, H, dd, out, nvec));
     }
   }
   if (bfA) {
@@ -1326,8 +1350,16 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
   } else {
     SBCI_TRY((launch_same<T, float>(ctx, A, A.fval32, na, nb, c, out, nvec, 0)));
   }
+  // the BF16 copy of C that the beta product needs is made here, before the
+  // opposite-spin part, whose pair form then gathers from it (half the bytes
+  // of the FP32 vector, and the values it rounds them to anyway); its time
+  // is counted with the alpha part
+  const __bf16 *cbeta = nullptr;
+  if constexpr (bf) {
+    if (bfB) SBCI_TRY(bf16_copy(ctx, 1, c, nvec, &cbeta));
+  }
   SBCI_TRY(rec(ctx, pe, 1));
-  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec)));
+  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec, cbeta, cbeta ? pad64(nb) : 0)));
   SBCI_TRY(rec(ctx, pe, 2));
   if constexpr (bf) {
     if (bfB) {
@@ -1336,7 +1368,7 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
       const float *dd = nullptr;
       SBCI_TRY(dense_same_bf16(ctx, B, &H, &dd));
       SBCI_TRY(rec(ctx, pe, 3));
-      SBCI_TRY(launch_gemm_bf16(ctx, 1, c, H, dd, out, nvec));
+      SBCI_TRY(launch_gemm_bf16(ctx, 1, c, cbeta, H, dd, out, nvec));
       SBCI_TRY(rec(ctx, pe, 4));
       SBCI_TRY(rec(ctx, pe, 5));
       return SBCI_OK;

@@ -129,6 +129,30 @@ def test_opp_orbital_low_precision(n, na, nb, dtype, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,na,nb", [(13, 6, 5), (12, 6, 6), (9, 4, 5), (20, 2, 2), (7, 0, 3)])
+def test_bf16_opp_pair_matches_orbital(n, na, nb):
+    """The BF16 sigma's two opposite-spin forms multiply the same BF16-rounded
+    integrals and coefficients (the pair form gathers from the BF16 copy of C
+    that the dense beta product also reads, rows padded to 64) and add the
+    products in FP32 MFMAs and FP64 rows, so they agree to accumulation
+    rounding, far below the BF16 error; three vectors cover the per-vector
+    offsets into the padded copy."""
+    ctx, I = _ctx(n, na, nb, seed=2)
+    c = sigma_inputs(12, 3, ctx.ndet)
+    c32 = torch.from_numpy(c.astype(np.float32)).cuda()
+    ctx.set_same_form("dense")
+    got = {}
+    for form in ("pair", "orbital"):
+        ctx.set_opp_form(form)
+        got[form] = ctx.sigma(c32, dtype="bf16").cpu().numpy().astype(np.float64)
+    for v in range(3):
+        a, b = got["pair"][v], got["orbital"][v]
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b), (v, np.linalg.norm(a - b))
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    assert np.linalg.norm(got["pair"] - want) < 2e-2 * np.linalg.norm(want)
+    ctx.close()
+
+
 def test_automatic_form_choice():
     """Near half filling the pair form issues fewer MFMA tiles; with few
     electrons in many orbitals the orbital form does (and at 45 orbitals the
