@@ -1002,10 +1002,12 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec, const __bf16 *cb = n
   OppQPlan pq{};
   SBCI_TRY(choose_opp<M>(ctx, form, pp, pq));
   if (form == SBCI_OPP_ORBITAL) return launch_opp_q<M, T>(ctx, pq, c, out, nvec);
-  if (cb) {
-    if ((uint64_t)A.ns * (uint64_t)ldcb >= (1ull << 32))
-      return set_error(SBCI_EINVAL, "opposite-spin sigma: BF16 copy too large for 32-bit offsets");
-    return launch_opp_pair<M, T, __bf16>(ctx, pp, cb, ldcb, out, nvec);
+  if constexpr (std::is_same<M, MBF16>::value) {
+    if (cb) {
+      if ((uint64_t)A.ns * (uint64_t)ldcb >= (1ull << 32))
+        return set_error(SBCI_EINVAL, "opposite-spin sigma: BF16 copy too large for 32-bit offsets");
+      return launch_opp_pair<M, T, __bf16>(ctx, pp, cb, ldcb, out, nvec);
+    }
   }
   return launch_opp_pair<M, T, T>(ctx, pp, c, B.ns, out, nvec);
 }
