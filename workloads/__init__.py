@@ -16,6 +16,13 @@ orbital counts and the same 8-fold symmetric structure):
   4. for k in 1..K: v ~ N(0,1), N(N+1)/2 draws in triu_indices(N) order:
          L_k[p, q] = L_k[q, p] = 0.1 * v * exp(-|p - q| / 4)
   5. (pq|rs) = sum_k L_k[p, q] * L_k[r, s]        (PSD as an N^2 x N^2 matrix)
+
+Point-group symmetric variant (``make_sym_integrals``): orbital p carries the
+D2h-like irrep label orbsym[p] (``orbital_irreps``: p mod 8); after the same
+draws, h[p, q] is kept only where orbsym[p] == orbsym[q], and L_k only on the
+orbital pairs whose irrep product orbsym[p] ^ orbsym[q] equals k mod 8.  Then
+(pq|rs) vanishes unless the four labels XOR to zero (totally symmetric
+integrals) and stays PSD.
 """
 from __future__ import annotations
 
@@ -30,6 +37,8 @@ __all__ = [
     "start_noise",
     "sigma_inputs",
     "batch_instances",
+    "orbital_irreps",
+    "make_sym_integrals",
     "CONFIGS",
 ]
 
@@ -49,7 +58,7 @@ class Integrals:
         return m.hexdigest()
 
 
-def _draw(norb: int, rank: int, rng: np.random.Generator):
+def _draw(norb: int, rank: int, rng: np.random.Generator, orbsym=None):
     n = norb
     h = np.zeros((n, n))
     h[np.arange(n), np.arange(n)] = -1.0 + 0.25 * np.arange(n)
@@ -64,6 +73,12 @@ def _draw(norb: int, rank: int, rng: np.random.Generator):
         v = rng.standard_normal(len(it[0]))
         L[k][it] = 0.1 * v * damp
         L[k][(it[1], it[0])] = 0.1 * v * damp
+    if orbsym is not None:
+        g = np.asarray(orbsym, dtype=np.int64)
+        pair = g[:, None] ^ g[None, :]
+        h = np.where(pair == 0, h, 0.0)
+        for k in range(rank):
+            L[k] = np.where(pair == (k % 8), L[k], 0.0)
     Lm = L.reshape(rank, n * n)
     eri = (Lm.T @ Lm).reshape(n, n, n, n)
     return h, eri
@@ -73,6 +88,20 @@ def make_integrals(norb: int, rank: int, seed: int) -> Integrals:
     """Seeded integrals G(norb, rank, seed) following the recipe above."""
     rng = np.random.default_rng(seed)
     h, eri = _draw(norb, rank, rng)
+    return Integrals(norb, rank, seed, h, eri)
+
+
+def orbital_irreps(norb: int) -> np.ndarray:
+    """D2h-like irrep labels 0..7 of the orbitals (orbital p carries p mod 8)."""
+    return np.arange(norb, dtype=np.int64) % 8
+
+
+def make_sym_integrals(norb: int, rank: int, seed: int, orbsym=None) -> Integrals:
+    """Seeded totally symmetric integrals (the symmetric variant of the recipe)."""
+    if orbsym is None:
+        orbsym = orbital_irreps(norb)
+    rng = np.random.default_rng(seed)
+    h, eri = _draw(norb, rank, rng, orbsym)
     return Integrals(norb, rank, seed, h, eri)
 
 
@@ -124,4 +153,10 @@ CONFIGS = {
     # the shape of the paper's CAS(8e,29o) instance (564,110,001 determinants):
     # one row of sigma (23,751 beta strings) exceeds LDS
     "dilute29": dict(norb=29, na=4, nb=4, rank=58, seed=0, nroots=1),
+    # point-group blocked: CAS(14e,14o) with orbital irreps p mod 8 and
+    # totally symmetric integrals, lowest states of irrep 0
+    # (1,472,928 of the 11,778,624 determinants)
+    "cas14_sym": dict(norb=14, na=7, nb=7, rank=28, seed=0, nroots=5, irrep=0),
+    # CAS(16e,16o) blocked the same way (20,708,900 determinants), ground state
+    "cas16_sym": dict(norb=16, na=8, nb=8, rank=32, seed=0, nroots=1, irrep=0),
 }
