@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cas14",
-                    choices=["cas6", "cas10", "cas14", "cas16", "dilute45"])
+                    choices=["cas6", "cas10", "cas14", "cas16", "dilute45", "cas14_sym", "cas16_sym"])
     ap.add_argument("--precision", default="bf16", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--solve-driver", choices=["sbci1", "sbci2", "davidson"], default=None,
                     help="profiling driver: one FP64 solve of the workload with this solver; print "
                          "its report and exit")
+    ap.add_argument("--only-sym", action="store_true",
+                    help="print only the point-group blocked section")
     ap.add_argument("--only-batch", action="store_true",
                     help="profiling driver: run only the batching-form section and print it")
     ap.add_argument("--kernel-driver", choices=["f64", "f32", "bf16"], default=None,
@@ -276,6 +278,97 @@ def cas16_section(sb, stream, precision):
                      "bf16": rm.report["nsigma_bf16"]}
     out["abs_dE_vs_fp64"] = float(abs(rm.energies[0] - r64.energies[0]))
     out["peak_vector_GB"] = round(rm.report["peak_vector_bytes"] / 1e9, 2)
+    return out
+
+
+def sym_pair_count(norb, na, nb, orbsym, irrep):
+    """Multiply-adds of the blocked opposite-spin part: for each determinant of
+    the irrep, the pairs (alpha excitation e, beta excitation f) of equal
+    class orbsym[p] ^ orbsym[q], summed block by block."""
+    from itertools import combinations
+
+    import numpy as np
+
+    def per_irrep(m):
+        tot = np.zeros((8, 8))        # [string irrep][class] -> excitations summed over strings
+        cnt = np.zeros(8)
+        for occ in combinations(range(norb), m):
+            g = 0
+            for p in occ:
+                g ^= int(orbsym[p])
+            cnt[g] += 1
+            occs = set(occ)
+            for q in occ:
+                for p in range(norb):
+                    if p == q or p not in occs:
+                        tot[g][int(orbsym[p]) ^ int(orbsym[q])] += 1
+        return tot, cnt
+
+    ta, ca = per_irrep(na)
+    tb, cb = per_irrep(nb) if nb != na else (ta, ca)
+    pairs = 0.0
+    for a in range(8):
+        b = a ^ irrep
+        for x in range(8):
+            pairs += ta[a][x] * tb[b][x]
+    return pairs
+
+
+def sym_section(sb, stream):
+    """Point-group blocked workloads (irrep 0 of orbital labels p mod 8, totally
+    symmetric integrals): CAS(14e,14o) with 5 roots and CAS(16e,16o) with the
+    ground state.  Blocked sigma per dtype and the time to 1e-8 Eh in FP64 and
+    in the FP32 precision form (the blocked sigma has no BF16 form)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from workloads import CONFIGS, make_sym_integrals, orbital_irreps, sigma_inputs
+    out = {}
+    for name in ("cas14_sym", "cas16_sym"):
+        cf = CONFIGS[name]
+        o = orbital_irreps(cf["norb"])
+        I = make_sym_integrals(cf["norb"], cf["rank"], cf["seed"], o)
+        t = time.perf_counter()
+        ctx = sb.Context(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri, stream=stream, orbsym=o,
+                         irrep=cf["irrep"])
+        torch.cuda.synchronize()
+        sec = {"ndet": ctx.ndet, "irrep": cf["irrep"], "create_s": round(time.perf_counter() - t, 3),
+               "sigma": {}}
+        pairs = sym_pair_count(cf["norb"], cf["na"], cf["nb"], o, cf["irrep"])
+        c = torch.from_numpy(sigma_inputs(0, 1, ctx.ndet)[0]).cuda()
+        for dt in ("f32", "f64"):
+            x = c if dt == "f64" else c.float()
+            y, _ = ctx.sigma_timed(x, dt)
+            runs = []
+            for _ in range(5):
+                y, ms = ctx.sigma_timed(x, dt, out=y)
+                runs.append(ms)
+            same = statistics.median(r[0] for r in runs)
+            opp = statistics.median(r[1] for r in runs)
+            sec["sigma"][dt] = {"gdet_per_s": round(ctx.ndet / ((same + opp) / 1e3) / 1e9, 3),
+                                "kernels_ms": {"same": round(same, 4), "opp": round(opp, 4)},
+                                "opp_gflops": round(2 * pairs / (opp / 1e3) / 1e9, 1)}
+            del y, x
+        sec["opp_pairs_per_det"] = round(pairs / ctx.ndet, 1)
+        del c
+        res = {}
+        for prec in ("f32", "f64"):
+            t = time.perf_counter()
+            r = ctx.solve(cf["nroots"], tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+            torch.cuda.synchronize()
+            res[prec] = (time.perf_counter() - t, r)
+        ctx.close()
+        tm, rm = res["f32"]
+        t64, r64 = res["f64"]
+        sec["time_to_1e8_s"] = {"mixed_f32": round(tm, 3), "fp64": round(t64, 3),
+                                "speedup": round(t64 / tm, 3)}
+        sec["energies"] = [float(e) for e in r64.energies]
+        sec["max_abs_dE_mixed_vs_fp64"] = float(np.abs(np.sort(rm.energies) - np.sort(r64.energies)).max())
+        sec["nsigma"] = {"fp64_form": r64.report["nsigma_f64"], "mixed_f64": rm.report["nsigma_f64"],
+                         "mixed_f32": rm.report["nsigma_low"]}
+        out[name] = sec
     return out
 
 
@@ -487,17 +580,36 @@ def main():
 
     cfg = dict(CONFIGS[a.workload], name=a.workload)
     nroots = cfg["nroots"]
-    I = make_integrals(cfg["norb"], cfg["rank"], cfg["seed"])
+    sym = "irrep" in cfg
+    if sym:
+        from workloads import make_sym_integrals, orbital_irreps
+        orbsym = orbital_irreps(cfg["norb"])
+        I = make_sym_integrals(cfg["norb"], cfg["rank"], cfg["seed"], orbsym)
+        if not (a.solve_driver or a.kernel_driver):
+            print("bench.py: the blocked workloads run under --solve-driver or --kernel-driver "
+                  "(the default run reports them in its 'symmetry' section)", file=sys.stderr)
+            sys.exit(2)
+    else:
+        I = make_integrals(cfg["norb"], cfg["rank"], cfg["seed"])
+
+    def context():
+        if sym:
+            return sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream,
+                              orbsym=orbsym, irrep=cfg["irrep"])
+        return sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if a.only_batch:
         print(json.dumps(batch_section(sb, a.precision)))
         return
+    if a.only_sym:
+        print(json.dumps(sym_section(sb, stream)))
+        return
     if a.paper_shapes:
         print(json.dumps(paper_shapes_section(sb, stream, a.precision)))
         return
     if a.solve_driver:
-        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+        ctx = context()
         fn = {"sbci1": lambda: ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"), want_vectors=False),
               "sbci2": lambda: ctx.solve2(nroots, tol=1e-10, want_vectors=False),
               "davidson": lambda: ctx.davidson(nroots, tol=1e-10, want_vectors=False)}[a.solve_driver]
@@ -509,7 +621,7 @@ def main():
         ctx.close()
         return
     if a.kernel_driver:
-        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+        ctx = context()
         c = torch.from_numpy(sigma_inputs(0, 1, ctx.ndet)[0]).cuda()
         if a.kernel_driver != "f64":
             c = c.float()
@@ -619,6 +731,7 @@ def main():
         line.update(small_sections(sb, stream))
         line["cas16"] = cas16_section(sb, stream, a.precision)
         line["dilute45"] = dilute45_section(sb, stream, a.precision)
+        line["symmetry"] = sym_section(sb, stream)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
     print(json.dumps(line))

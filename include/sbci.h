@@ -145,12 +145,42 @@ int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double 
                 sbci_ctx **out);
 int sbci_destroy(sbci_ctx *ctx);
 
+/* A context restricted to the determinants of one irreducible representation
+ * of an abelian point group with irreps 0..7 multiplying by XOR (D2h and its
+ * subgroups).  Every instance of the paper is solved inside one irrep
+ * (Results, problem statement; the determinant counts of Section S3.1 are
+ * per symmetry block).
+ *   orbsym host [norb], irrep label 0..7 of each orbital;
+ *   irrep  0..7, the irrep of the states sought.
+ * A string's irrep is the XOR of its occupied orbitals' labels and |Ia, Ib>
+ * has irrep irr(Ia) ^ irr(Ib).  Vectors of this context (sigma's c and
+ * sigma, the solvers' vectors, sbci_hdiag) hold only the N_det =
+ * sum_a n_alpha(a) * n_beta(a ^ irrep) determinants of the irrep, as blocks
+ * a = 0..7 of [alpha strings of irrep a] x [beta strings of irrep a ^ irrep]
+ * (row-major, strings in ascending mask order inside their irrep), one
+ * block after another; sbci_sym_blocks reports the block shapes.  The
+ * integrals must be totally symmetric: entries that break the symmetry must
+ * be below 1e-10 of the largest entry (they are left out).  sigma runs in
+ * FP64 and FP32; the BF16 dtype is refused (SBCI_EINVAL), and with it the
+ * BF16 precision form.  The caller keeps ownership of every host array.
+ * Errors: as sbci_create, plus SBCI_EINVAL for labels out of range,
+ * integrals that are not totally symmetric, or an irrep with no
+ * determinant. */
+int sbci_create_sym(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                    const int *orbsym, int irrep, sbci_ctx **out);
+
+/* Block shapes of a symmetry-blocked context: out[0..7] alpha strings of
+ * irrep a, out[8..15] beta strings of irrep a ^ irrep, out[16..23] block
+ * offsets.  SBCI_EINVAL for a context without symmetry blocking. */
+int sbci_sym_blocks(const sbci_ctx *ctx, int64_t *out /* host [24] */);
+
 /* Use this HIP stream (hipStream_t passed as void*) for all later work; NULL
  * selects the null (legacy default) stream.  A new context uses a
  * non-blocking stream of its own until this is called. */
 int sbci_set_stream(sbci_ctx *ctx, void *hip_stream);
 
-/* Sizes: N_det = C(norb, nalpha) * C(norb, nbeta) and the string counts. */
+/* Sizes: N_det = C(norb, nalpha) * C(norb, nbeta) (the blocked count for a
+ * symmetry-blocked context) and the string counts. */
 int64_t sbci_ndet(const sbci_ctx *ctx);
 int64_t sbci_nstrings(const sbci_ctx *ctx, int spin /* 0 alpha, 1 beta */);
 

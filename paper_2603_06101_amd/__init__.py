@@ -113,6 +113,8 @@ SIGNATURES = [
     ("sbci_default_opts", None, [ctypes.POINTER(Opts)]),
     ("sbci_last_error", ctypes.c_char_p, []),
     ("sbci_create", _I, [_I, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    ("sbci_create_sym", _I, [_I, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_P)]),
+    ("sbci_sym_blocks", _I, [_P, _P]),
     ("sbci_destroy", _I, [_P]),
     ("sbci_set_stream", _I, [_P, _P]),
     ("sbci_ndet", _I64, [_P]),
@@ -191,9 +193,13 @@ class SolveResult:
 
 
 class Context:
-    """One FCI problem (norb, nalpha, nbeta, h1, eri) resident on the GPU."""
+    """One FCI problem (norb, nalpha, nbeta, h1, eri) resident on the GPU.
 
-    def __init__(self, norb, nalpha, nbeta, h1, eri, stream=None):
+    With orbsym (irrep label 0..7 per orbital) the context holds only the
+    determinants of irreducible representation ``irrep`` (sbci_create_sym):
+    vectors are in its block layout and ``ndet`` is the blocked count."""
+
+    def __init__(self, norb, nalpha, nbeta, h1, eri, stream=None, orbsym=None, irrep=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libsbci needs a HIP device")
@@ -202,8 +208,16 @@ class Context:
         eri = np.ascontiguousarray(eri, dtype=np.float64)
         self._keep = (h1, eri)
         h = _P()
-        _check(lib().sbci_create(norb, nalpha, nbeta, h1.ctypes.data, eri.ctypes.data,
-                                 ctypes.byref(h)))
+        if orbsym is None:
+            _check(lib().sbci_create(norb, nalpha, nbeta, h1.ctypes.data, eri.ctypes.data,
+                                     ctypes.byref(h)))
+        else:
+            os_ = np.ascontiguousarray(orbsym, dtype=np.int32)
+            if os_.shape != (norb,):
+                raise ValueError("orbsym must have norb entries")
+            _check(lib().sbci_create_sym(norb, nalpha, nbeta, h1.ctypes.data, eri.ctypes.data,
+                                         os_.ctypes.data, int(irrep), ctypes.byref(h)))
+        self.symmetric = orbsym is not None
         self.h = h
         self.ndet = lib().sbci_ndet(h)
         s = stream if stream is not None else torch.cuda.current_stream()
@@ -219,6 +233,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def sym_blocks(self):
+        """(alpha rows, beta columns, offsets) of the eight irrep blocks."""
+        out = np.zeros(24, dtype=np.int64)
+        _check(lib().sbci_sym_blocks(self.h, out.ctypes.data))
+        return out[:8].copy(), out[8:16].copy(), out[16:].copy()
 
     def nstrings(self, spin):
         return lib().sbci_nstrings(self.h, spin)

@@ -36,11 +36,6 @@
 struct sbci_batch;
 
 namespace sbci {
-int create_context(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
-                   hipStream_t stream, bool own_stream, sbci_ctx **out);
-}
-
-namespace sbci {
 namespace {
 
 constexpr int BMAXR = 4;     // roots per instance

@@ -116,7 +116,8 @@ namespace sbci {
 // Context on a given stream; own_stream = false leaves the stream to the caller
 // (the batch form builds many contexts on one stream).
 int create_context(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
-                   hipStream_t stream, bool own_stream, sbci_ctx **out) {
+                   hipStream_t stream, bool own_stream, sbci_ctx **out, const int *orbsym,
+                   int irrep) {
   if (!out) return set_error(SBCI_EINVAL, "out is NULL");
   *out = nullptr;
   if (norb < 1 || norb > 63) return set_error(SBCI_EINVAL, "norb must be in [1, 63]");
@@ -145,6 +146,7 @@ int create_context(int norb, int nalpha, int nbeta, const double *h1, const doub
     ctx->stream = stream;
   }
   int rc = build_tables(ctx, h1, eri);
+  if (rc == SBCI_OK && orbsym) rc = setup_symmetry(ctx, orbsym, irrep, h1, eri);
   if (rc != SBCI_OK) {
     std::string msg = g_err;
     sbci_destroy(ctx);
@@ -162,10 +164,22 @@ int sbci_create(int norb, int nalpha, int nbeta, const double *h1, const double 
   return create_context(norb, nalpha, nbeta, h1, eri, nullptr, true, out);
 }
 
+int sbci_create_sym(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                    const int *orbsym, int irrep, sbci_ctx **out) {
+  if (!orbsym) return set_error(SBCI_EINVAL, "orbsym is NULL");
+  return create_context(norb, nalpha, nbeta, h1, eri, nullptr, true, out, orbsym, irrep);
+}
+
+int sbci_sym_blocks(const sbci_ctx *ctx, int64_t *out) {
+  if (!ctx || !out) return set_error(SBCI_EINVAL, "NULL argument");
+  return sym_blocks(ctx, out);
+}
+
 int sbci_destroy(sbci_ctx *ctx) {
   if (!ctx) return SBCI_OK;
   hipStreamSynchronize(ctx->stream);
   solver_free(ctx);
+  free_symmetry(ctx);
   free_tables(ctx);
   hipFree(ctx->ws_t.ptr);
   hipFree(ctx->ws_s.ptr);

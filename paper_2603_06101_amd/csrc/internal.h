@@ -93,6 +93,25 @@ struct Workspace {
 
 struct Solver;  // SBCI1 driver state (solver.hip)
 
+// Point-group blocking of a context (symmetry.hip): the determinants of one
+// irrep, stored as blocks a = 0..7 of [alpha strings of irrep a] x [beta
+// strings of irrep a ^ irrep], row-major, in order of a.
+struct SymInfo {
+  int irrep = 0;
+  int orbsym[64] = {};
+  int64_t cntA[8] = {}, cntB[8] = {};    // strings per irrep
+  int64_t startA[9] = {}, startB[9] = {};// first irrep-sorted index per irrep
+  int64_t off[9] = {};                   // block offsets; off[8] = blocked ndet
+  int32_t *irrA = nullptr, *posA = nullptr, *idxA = nullptr;  // [nsa] irrep, rank in irrep, sorted -> global
+  int32_t *irrB = nullptr, *posB = nullptr, *idxB = nullptr;  // [nsb]
+  int32_t *orbsym_d = nullptr;           // [norb]
+  // same-spin lists compacted to the string's own irrep: [ns][nf*] ranks and values
+  int nfA = 0, nfB = 0;
+  int32_t *colA = nullptr, *colB = nullptr;
+  double *valA64 = nullptr, *valB64 = nullptr;
+  float *valA32 = nullptr, *valB32 = nullptr;
+};
+
 }  // namespace sbci
 
 struct sbci_ctx {
@@ -118,6 +137,7 @@ struct sbci_ctx {
   int opp_form = 0;               // SBCI_OPP_AUTO / _PAIR / _ORBITAL
   int same_form = 0;              // SBCI_SAME_AUTO / _LISTS / _DENSE
   sbci::Solver *solver = nullptr;
+  sbci::SymInfo *sym = nullptr;   // set when the context is symmetry-blocked
   bool trace_on = true;
   std::vector<sbci_step_info> trace;
   sbci_progress_fn progress = nullptr;
@@ -149,6 +169,24 @@ int set_error(int code, const std::string &msg);
   } while (0)
 
 int ensure(Workspace &w, size_t bytes);
+
+// ---- capi.hip ----
+// Context on a given stream (own_stream = false leaves it to the caller);
+// orbsym != NULL restricts it to the determinants of one irrep.
+int create_context(int norb, int nalpha, int nbeta, const double *h1, const double *eri,
+                   hipStream_t stream, bool own_stream, sbci_ctx **out,
+                   const int *orbsym = nullptr, int irrep = 0);
+
+// ---- symmetry.hip ----
+// Block layout, compacted lists and the blocked diagonal; replaces ndet and
+// hdiag by their blocked forms.
+int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1,
+                   const double *eri);
+void free_symmetry(sbci_ctx *ctx);
+// sigma on the blocked layout; ev (optional) receives 6 events around the
+// same-spin part (ev[0..1]) and the opposite-spin part (ev[1..2]).
+int sigma_sym(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, hipEvent_t *ev);
+int sym_blocks(const sbci_ctx *ctx, int64_t *out);
 
 // ---- tables.hip ----
 int build_tables(sbci_ctx *ctx, const double *h1_host, const double *eri_host);

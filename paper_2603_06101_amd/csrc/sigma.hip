@@ -1408,6 +1408,7 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
 
 namespace {
 int sigma_dispatch(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, PartEvents *pe) {
+  if (ctx->sym) return sigma_sym(ctx, c, out, nvec, mode, pe ? pe->ev : nullptr);
   switch (mode) {
     case SBCI_F64:
       return sigma_t<double, MF64>(ctx, static_cast<const double *>(c), static_cast<double *>(out),

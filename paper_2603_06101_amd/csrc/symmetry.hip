@@ -1,0 +1,425 @@
+// Point-group symmetry blocking: sigma on the determinants of one irrep.
+//
+// Every molecule of the paper is solved inside one irreducible
+// representation of its point group (Results, problem statement; the
+// determinant counts of Section S3.1 are per symmetry block).  For an abelian
+// group with irreps 0..7 that multiply by XOR (D2h and its subgroups), a
+// string's irrep is the XOR of its occupied orbitals' irreps and |Ia, Ib> has
+// irrep irr(Ia) ^ irr(Ib).  Totally symmetric integrals make H block
+// diagonal, so the states of irrep G live on
+//   block a = 0..7:  [alpha strings of irrep a] x [beta strings of irrep a ^ G]
+// stored row-major, blocks one after another.  Within a block strings keep
+// their ascending-mask order; pos[I] is a string's rank inside its irrep.
+//
+// sigma on that layout (no full-space vector is ever formed):
+//   same-spin  sigma[a](r, q) = sum_g Fb[Ib][g] c[a](r, posB[J_g])
+//                             + sum_g Fa[Ia][g] c[a](posA[J_g], q)
+//              over the same-spin lists compacted to entries inside the
+//              string's own irrep (the others are exactly zero);
+//   opposite   sigma[a](r, q) += sum_f sign_f sum_{e: cls(e) = cls(f)}
+//              (pq_e|rs_f) sign_e c[a ^ cls](posA[J_e], posB[J_f])
+//              over the single-excitation tables of Ia (e) and Ib (f), where
+//              cls(E_pq) = orbsym[p] ^ orbsym[q]; the integral vanishes when
+//              the classes differ, and when they agree the source
+//              determinant lies in block a ^ cls.
+// Both are gather kernels (one output element per thread); the opposite-spin
+// one keeps the workgroup's alpha excitations, sorted by class, in LDS.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+#include "mfma.h"
+
+namespace sbci {
+
+namespace {
+
+// Block geometry passed by value to the kernels.
+struct SymArgs {
+  int64_t off[9];     // block offsets in a vector (off[8] = ndet)
+  int64_t rowsA[8];   // alpha strings of irrep a
+  int64_t ncol[8];    // beta strings of irrep a ^ G (block a's row length)
+  int64_t startA[9];  // first irrep-sorted alpha index of irrep a
+  int64_t startBc[8]; // first irrep-sorted beta index of irrep a ^ G
+};
+
+__device__ __forceinline__ int find_block(const SymArgs &g, int64_t d) {
+  int a = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (g.off[k] <= d) a = k;
+  return a;
+}
+
+// Keep the same-spin list entries whose target lies in the row string's
+// irrep, as (rank inside the irrep, value); pad with (own rank, 0).
+__global__ void k_sym_count(const int32_t *__restrict__ fcol, int nf, int64_t ns,
+                            const int32_t *__restrict__ irr, int32_t *__restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  int k = 0;
+  for (int e = 0; e < nf; ++e) k += irr[fcol[i * nf + e]] == irr[i];
+  cnt[i] = k;
+}
+
+__global__ void k_sym_compact(const int32_t *__restrict__ fcol, const double *__restrict__ f64,
+                              int nf, int64_t ns, const int32_t *__restrict__ irr,
+                              const int32_t *__restrict__ pos, int nfs, int32_t *__restrict__ col,
+                              double *__restrict__ v64, float *__restrict__ v32) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  int k = 0;
+  for (int e = 0; e < nf; ++e) {
+    const int32_t J = fcol[i * nf + e];
+    if (irr[J] != irr[i]) continue;
+    col[i * nfs + k] = pos[J];
+    v64[i * nfs + k] = f64[i * nf + e];
+    v32[i * nfs + k] = (float)f64[i * nf + e];
+    ++k;
+  }
+  for (; k < nfs; ++k) {
+    col[i * nfs + k] = pos[i];
+    v64[i * nfs + k] = 0.0;
+    v32[i * nfs + k] = 0.0f;
+  }
+}
+
+// Blocked copy of a full-space array (the diagonal): one blocked element per thread.
+template <typename T>
+__global__ void k_sym_gather(SymArgs g, const int32_t *__restrict__ idxA,
+                             const int32_t *__restrict__ idxB, int64_t nsb,
+                             const T *__restrict__ full, T *__restrict__ out) {
+  const int64_t nd = g.off[8];
+  for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < nd;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    const int a = find_block(g, d);
+    const int64_t nc = g.ncol[a], rel = d - g.off[a];
+    const int64_t r = rel / nc, q = rel - r * nc;
+    const int64_t Ia = idxA[g.startA[a] + r], Ib = idxB[g.startBc[a] + q];
+    out[d] = full[Ia * nsb + Ib];
+  }
+}
+
+// One-electron and same-spin part, plain write.
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_sym_same(
+    SymArgs g, const int32_t *__restrict__ idxA, const int32_t *__restrict__ idxB,
+    const int32_t *__restrict__ colA, const V *__restrict__ valA, int nfA,
+    const int32_t *__restrict__ colB, const V *__restrict__ valB, int nfB,
+    const T *__restrict__ c, T *__restrict__ out) {
+  const int64_t nd = g.off[8];
+  const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (d >= nd) return;
+  const int64_t vo = (int64_t)blockIdx.y * nd;
+  const int a = find_block(g, d);
+  const int64_t nc = g.ncol[a], rel = d - g.off[a];
+  const int64_t r = rel / nc, q = rel - r * nc;
+  const int64_t Ia = idxA[g.startA[a] + r], Ib = idxB[g.startBc[a] + q];
+  const T *__restrict__ blk = c + vo + g.off[a];
+  T acc = 0;
+  const int32_t *cb = colB + Ib * nfB;
+  const V *vb = valB + Ib * nfB;
+  for (int e = 0; e < nfB; ++e) acc += (T)vb[e] * blk[r * nc + cb[e]];
+  const int32_t *ca = colA + Ia * nfA;
+  const V *va = valA + Ia * nfA;
+  for (int e = 0; e < nfA; ++e) acc += (T)va[e] * blk[(int64_t)ca[e] * nc + q];
+  out[vo + d] = acc;
+}
+
+// Opposite-spin part, accumulated: one workgroup per alpha string (irrep-sorted
+// index k), threads over the row's beta columns.
+// LDS: srcoff[sA] (int64, source row offset in the vector) | wro[sA] (int32,
+// pair row of W) | sg[sA] (T, sign) | ord[sA] (class-sorted entry) | cs[9].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_opp(
+    SymArgs g, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
+    const int32_t *__restrict__ idxB, const int32_t *__restrict__ posA,
+    const int32_t *__restrict__ posB, const Ent *__restrict__ tabA, int sA,
+    const Ent *__restrict__ tabB, int sB, const T *__restrict__ W, int npair,
+    const T *__restrict__ c, T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int64_t *srcoff = reinterpret_cast<int64_t *>(smem);
+  int32_t *wro = reinterpret_cast<int32_t *>(srcoff + sA);
+  int32_t *ord = wro + sA;
+  int32_t *cls = ord + sA;
+  int32_t *cs = cls + sA;  // [9]
+  T *sg = reinterpret_cast<T *>(smem + (((size_t)sA * 20 + 36 + 15) & ~(size_t)15));
+  const int64_t k = blockIdx.x;
+  int a = 0;
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (g.startA[t] <= k) a = t;
+  const int64_t nc = g.ncol[a];
+  if (nc == 0) return;  // uniform over the workgroup
+  const int64_t r = k - g.startA[a];
+  const int64_t Ia = idxA[k];
+  const int64_t nd = g.off[8];
+  const int64_t vo = (int64_t)blockIdx.y * nd;
+  for (int e = threadIdx.x; e < sA; e += blockDim.x) {
+    const Ent t = tabA[Ia * sA + e];
+    const int x = orbsym[t.p] ^ orbsym[t.q];
+    const int b = a ^ x;  // block of the source determinants
+    cls[e] = x;
+    srcoff[e] = g.off[b] + (int64_t)posA[t.J] * g.ncol[b];
+    wro[e] = pair_index(t.p, t.q) * npair;
+    sg[e] = (T)t.sign;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // counting sort of the entries by class
+    int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = 0; e < sA; ++e) ++n[cls[e]];
+    cs[0] = 0;
+    for (int x = 0; x < 8; ++x) cs[x + 1] = cs[x] + n[x];
+    int fill[8];
+    for (int x = 0; x < 8; ++x) fill[x] = cs[x];
+    for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
+  }
+  __syncthreads();
+  const T *__restrict__ cv = c + vo;
+  T *__restrict__ row = out + vo + g.off[a] + r * nc;
+  for (int64_t q = threadIdx.x; q < nc; q += blockDim.x) {
+    const int64_t Ib = idxB[g.startBc[a] + q];
+    T acc = 0;
+    for (int f = 0; f < sB; ++f) {
+      const Ent t = tabB[Ib * sB + f];
+      const int x = orbsym[t.p] ^ orbsym[t.q];
+      const int kl = pair_index(t.p, t.q);
+      const int64_t jp = posB[t.J];
+      T inner = 0;
+      for (int i = cs[x]; i < cs[x + 1]; ++i) {
+        const int e = ord[i];
+        inner += sg[e] * W[wro[e] + kl] * cv[srcoff[e] + jp];
+      }
+      acc += (T)t.sign * inner;
+    }
+    row[q] += acc;
+  }
+}
+
+size_t opp_lds_bytes(int sA, size_t tsize) {
+  return (((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * tsize;
+}
+
+SymArgs make_args(const SymInfo &S) {
+  SymArgs g{};
+  for (int a = 0; a < 9; ++a) {
+    g.off[a] = S.off[a];
+    g.startA[a] = S.startA[a];
+  }
+  for (int a = 0; a < 8; ++a) {
+    g.rowsA[a] = S.cntA[a];
+    g.ncol[a] = S.cntB[a ^ S.irrep];
+    g.startBc[a] = S.startB[a ^ S.irrep];
+  }
+  return g;
+}
+
+// Irreps, ranks inside the irrep and the irrep-sorted index of one spin's
+// strings, from the masks (host).
+void spin_layout(const std::vector<uint64_t> &str, const int *orbsym, int norb,
+                 std::vector<int32_t> &irr, std::vector<int32_t> &pos, std::vector<int32_t> &idx,
+                 int64_t cnt[8], int64_t start[9]) {
+  const int64_t ns = (int64_t)str.size();
+  irr.resize(ns);
+  pos.resize(ns);
+  idx.resize(ns);
+  for (int a = 0; a < 8; ++a) cnt[a] = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    int x = 0;
+    for (int p = 0; p < norb; ++p)
+      if ((str[i] >> p) & 1ull) x ^= orbsym[p];
+    irr[i] = x;
+    pos[i] = (int32_t)cnt[x]++;
+  }
+  start[0] = 0;
+  for (int a = 0; a < 8; ++a) start[a + 1] = start[a] + cnt[a];
+  for (int64_t i = 0; i < ns; ++i) idx[start[irr[i]] + pos[i]] = (int32_t)i;
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &v, hipStream_t st) {
+  SBCI_HIP(hipMalloc(dst, sizeof(T) * std::max<size_t>(v.size(), 1)));
+  if (!v.empty())
+    SBCI_HIP(hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return SBCI_OK;
+}
+
+// Compacted same-spin lists of one spin (see k_sym_compact).
+int compact_lists(sbci_ctx *ctx, const SpinTables &T, const int32_t *irr, const int32_t *pos,
+                  int *nfs, int32_t **col, double **v64, float **v32) {
+  const int64_t ns = T.ns;
+  int32_t *cnt = nullptr;
+  SBCI_HIP(hipMalloc(&cnt, sizeof(int32_t) * ns));
+  const unsigned nb = (unsigned)((ns + 255) / 256);
+  k_sym_count<<<nb, 256, 0, ctx->stream>>>(T.fcol, T.nf, ns, irr, cnt);
+  SBCI_CHECK_LAUNCH();
+  std::vector<int32_t> h(ns);
+  SBCI_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  hipFree(cnt);
+  int m = 1;
+  for (int64_t i = 0; i < ns; ++i) m = std::max(m, (int)h[i]);
+  *nfs = m;
+  SBCI_HIP(hipMalloc(col, sizeof(int32_t) * ns * m));
+  SBCI_HIP(hipMalloc(v64, sizeof(double) * ns * m));
+  SBCI_HIP(hipMalloc(v32, sizeof(float) * ns * m));
+  k_sym_compact<<<nb, 256, 0, ctx->stream>>>(T.fcol, T.fval64, T.nf, ns, irr, pos, m, *col, *v64,
+                                             *v32);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
+}  // namespace
+
+int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1,
+                   const double *eri) {
+  const int n = ctx->norb;
+  if (irrep < 0 || irrep > 7) return set_error(SBCI_EINVAL, "irrep must be in [0, 7]");
+  for (int p = 0; p < n; ++p)
+    if (orbsym[p] < 0 || orbsym[p] > 7) return set_error(SBCI_EINVAL, "orbsym entries must be in [0, 7]");
+  // totally symmetric integrals: the entries that break the symmetry must be
+  // (numerically) zero, since the blocked sigma leaves them out
+  double hmax = 0, gmax = 0;
+  for (int i = 0; i < n * n; ++i) hmax = std::fmax(hmax, std::fabs(h1[i]));
+  const size_t n4 = (size_t)n * n * n * n;
+  for (size_t i = 0; i < n4; ++i) gmax = std::fmax(gmax, std::fabs(eri[i]));
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      if (orbsym[p] != orbsym[q] && std::fabs(h1[p * n + q]) > 1e-10 * std::fmax(hmax, 1.0))
+        return set_error(SBCI_EINVAL, "h1 couples orbitals of different irreps");
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      for (int r = 0; r < n; ++r)
+        for (int s = 0; s < n; ++s)
+          if ((orbsym[p] ^ orbsym[q] ^ orbsym[r] ^ orbsym[s]) != 0 &&
+              std::fabs(eri[(((size_t)p * n + q) * n + r) * n + s]) > 1e-10 * std::fmax(gmax, 1.0))
+            return set_error(SBCI_EINVAL, "eri is not totally symmetric under orbsym");
+  SymInfo *S = new SymInfo();
+  ctx->sym = S;
+  S->irrep = irrep;
+  for (int p = 0; p < n; ++p) S->orbsym[p] = orbsym[p];
+  hipStream_t st = ctx->stream;
+  std::vector<uint64_t> sa(ctx->A.ns), sb(ctx->B.ns);
+  SBCI_HIP(hipMemcpyAsync(sa.data(), ctx->A.str, sizeof(uint64_t) * ctx->A.ns, hipMemcpyDeviceToHost, st));
+  SBCI_HIP(hipMemcpyAsync(sb.data(), ctx->B.str, sizeof(uint64_t) * ctx->B.ns, hipMemcpyDeviceToHost, st));
+  SBCI_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> irA, poA, ixA, irB, poB, ixB;
+  spin_layout(sa, orbsym, n, irA, poA, ixA, S->cntA, S->startA);
+  spin_layout(sb, orbsym, n, irB, poB, ixB, S->cntB, S->startB);
+  S->off[0] = 0;
+  for (int a = 0; a < 8; ++a) S->off[a + 1] = S->off[a] + S->cntA[a] * S->cntB[a ^ irrep];
+  if (S->off[8] == 0) return set_error(SBCI_EINVAL, "no determinant has the requested irrep");
+  if (S->off[8] >= ((int64_t)1 << 40)) return set_error(SBCI_EINVAL, "blocked space too large");
+  SBCI_TRY(upload(&S->irrA, irA, st));
+  SBCI_TRY(upload(&S->posA, poA, st));
+  SBCI_TRY(upload(&S->idxA, ixA, st));
+  SBCI_TRY(upload(&S->irrB, irB, st));
+  SBCI_TRY(upload(&S->posB, poB, st));
+  SBCI_TRY(upload(&S->idxB, ixB, st));
+  std::vector<int32_t> os(orbsym, orbsym + n);
+  SBCI_TRY(upload(&S->orbsym_d, os, st));
+  SBCI_TRY(compact_lists(ctx, ctx->A, S->irrA, S->posA, &S->nfA, &S->colA, &S->valA64, &S->valA32));
+  SBCI_TRY(compact_lists(ctx, ctx->B, S->irrB, S->posB, &S->nfB, &S->colB, &S->valB64, &S->valB32));
+  // the diagonal in the blocked layout replaces the full-space one
+  const SymArgs g = make_args(*S);
+  const int64_t nd = S->off[8];
+  double *d64 = nullptr;
+  float *d32 = nullptr;
+  SBCI_HIP(hipMalloc(&d64, sizeof(double) * nd));
+  SBCI_HIP(hipMalloc(&d32, sizeof(float) * nd));
+  const unsigned blocks = (unsigned)std::min<int64_t>((nd + 255) / 256, 8192);
+  k_sym_gather<double><<<blocks, 256, 0, st>>>(g, S->idxA, S->idxB, ctx->B.ns, ctx->hdiag, d64);
+  k_sym_gather<float><<<blocks, 256, 0, st>>>(g, S->idxA, S->idxB, ctx->B.ns, ctx->hdiag32, d32);
+  SBCI_CHECK_LAUNCH();
+  SBCI_HIP(hipStreamSynchronize(st));
+  hipFree(ctx->hdiag);
+  hipFree(ctx->hdiag32);
+  ctx->hdiag = d64;
+  ctx->hdiag32 = d32;
+  ctx->ndet = nd;
+  return SBCI_OK;
+}
+
+void free_symmetry(sbci_ctx *ctx) {
+  SymInfo *S = ctx->sym;
+  if (!S) return;
+  hipFree(S->irrA);
+  hipFree(S->posA);
+  hipFree(S->idxA);
+  hipFree(S->irrB);
+  hipFree(S->posB);
+  hipFree(S->idxB);
+  hipFree(S->orbsym_d);
+  hipFree(S->colA);
+  hipFree(S->valA64);
+  hipFree(S->valA32);
+  hipFree(S->colB);
+  hipFree(S->valB64);
+  hipFree(S->valB32);
+  delete S;
+  ctx->sym = nullptr;
+}
+
+namespace {
+template <typename T>
+int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
+  const SymInfo &S = *ctx->sym;
+  const SymArgs g = make_args(S);
+  const int64_t nd = S.off[8];
+  constexpr bool dbl = std::is_same<T, double>::value;
+  if (ev) SBCI_HIP(hipEventRecord(ev[0], ctx->stream));
+  const int64_t nblk = (nd + 255) / 256;
+  if (nblk >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "blocked space too large");
+  if constexpr (dbl)
+    k_sym_same<double, double><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
+        g, S.idxA, S.idxB, S.colA, S.valA64, S.nfA, S.colB, S.valB64, S.nfB, c, out);
+  else
+    k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
+        g, S.idxA, S.idxB, S.colA, S.valA32, S.nfA, S.colB, S.valB32, S.nfB, c, out);
+  SBCI_CHECK_LAUNCH();
+  if (ev) SBCI_HIP(hipEventRecord(ev[1], ctx->stream));
+  const SpinTables &A = ctx->A, &B = ctx->B;
+  if (A.s > 0 && B.s > 0) {
+    const size_t lds = opp_lds_bytes(A.s, sizeof(T));
+    if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");
+    const T *W;
+    if constexpr (dbl) W = ctx->W64; else W = ctx->W32;
+    k_sym_opp<T><<<dim3((unsigned)A.ns, (unsigned)nvec), 256, lds, ctx->stream>>>(
+        g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB, A.tab, A.s, B.tab, B.s, W,
+        ctx->npair, c, out);
+    SBCI_CHECK_LAUNCH();
+  }
+  if (ev)
+    for (int i = 2; i < 6; ++i) SBCI_HIP(hipEventRecord(ev[i], ctx->stream));
+  return SBCI_OK;
+}
+}  // namespace
+
+int sigma_sym(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, hipEvent_t *ev) {
+  switch (mode) {
+    case SBCI_F64:
+      return sigma_sym_t<double>(ctx, static_cast<const double *>(c), static_cast<double *>(out),
+                                 nvec, ev);
+    case SBCI_F32:
+      return sigma_sym_t<float>(ctx, static_cast<const float *>(c), static_cast<float *>(out),
+                                nvec, ev);
+    case SBCI_BF16:
+      return set_error(SBCI_EINVAL, "the symmetry-blocked sigma has FP64 and FP32 forms only");
+    default:
+      return set_error(SBCI_EINVAL, "unknown sigma dtype");
+  }
+}
+
+int sym_blocks(const sbci_ctx *ctx, int64_t *out) {
+  if (!ctx->sym) return set_error(SBCI_EINVAL, "context is not symmetry-blocked");
+  const SymInfo &S = *ctx->sym;
+  for (int a = 0; a < 8; ++a) {
+    out[a] = S.cntA[a];
+    out[8 + a] = S.cntB[a ^ S.irrep];
+    out[16 + a] = S.off[a];
+  }
+  return SBCI_OK;
+}
+
+}  // namespace sbci
