@@ -130,8 +130,10 @@ __global__ __launch_bounds__(256) void k_sym_same(
 // Opposite-spin part, accumulated: one workgroup per alpha string (irrep-sorted
 // index k), threads over the row's beta columns.
 // LDS: srcoff[sA] (int64, source row offset in the vector) | wro[sA] (int32,
-// pair row of W) | sg[sA] (T, sign) | ord[sA] (class-sorted entry) | cs[9].
-template <typename T>
+// pair row of W) | ord[sA] (class-sorted entry) | cls[sA] | cs[9] | sg[sA]
+// (T, sign); with WL also so2[sA] (srcoff in class order) and Ws[sA][npair]
+// (sign_e (pq_e|kl) in class order), so that the inner loop reads W from LDS.
+template <typename T, bool WL>
 __global__ __launch_bounds__(256) void k_sym_opp(
     SymArgs g, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ idxB, const int32_t *__restrict__ posA,
@@ -176,6 +178,18 @@ __global__ __launch_bounds__(256) void k_sym_opp(
     for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
   }
   __syncthreads();
+  const size_t o2 = ((((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * sizeof(T) + 7) & ~(size_t)7;
+  int64_t *so2 = reinterpret_cast<int64_t *>(smem + o2);
+  T *Ws = reinterpret_cast<T *>(so2 + sA);
+  if constexpr (WL) {
+    for (int i = threadIdx.x; i < sA; i += blockDim.x) so2[i] = srcoff[ord[i]];
+    for (int64_t x = threadIdx.x; x < (int64_t)sA * npair; x += blockDim.x) {
+      const int i = (int)(x / npair), kl = (int)(x - (int64_t)i * npair);
+      const int e = ord[i];
+      Ws[x] = sg[e] * W[wro[e] + kl];
+    }
+    __syncthreads();
+  }
   const T *__restrict__ cv = c + vo;
   T *__restrict__ row = out + vo + g.off[a] + r * nc;
   for (int64_t q = threadIdx.x; q < nc; q += blockDim.x) {
@@ -187,9 +201,13 @@ __global__ __launch_bounds__(256) void k_sym_opp(
       const int kl = pair_index(t.p, t.q);
       const int64_t jp = posB[t.J];
       T inner = 0;
-      for (int i = cs[x]; i < cs[x + 1]; ++i) {
-        const int e = ord[i];
-        inner += sg[e] * W[wro[e] + kl] * cv[srcoff[e] + jp];
+      if constexpr (WL) {
+        for (int i = cs[x]; i < cs[x + 1]; ++i) inner += Ws[i * npair + kl] * cv[so2[i] + jp];
+      } else {
+        for (int i = cs[x]; i < cs[x + 1]; ++i) {
+          const int e = ord[i];
+          inner += sg[e] * W[wro[e] + kl] * cv[srcoff[e] + jp];
+        }
       }
       acc += (T)t.sign * inner;
     }
@@ -197,9 +215,15 @@ __global__ __launch_bounds__(256) void k_sym_opp(
   }
 }
 
-size_t opp_lds_bytes(int sA, size_t tsize) {
-  return (((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * tsize;
+size_t opp_lds_bytes(int sA, size_t tsize, int npair, bool wl) {
+  size_t b = (((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * tsize;
+  if (wl) b = ((b + 7) & ~(size_t)7) + (size_t)sA * 8 + (size_t)sA * npair * tsize;
+  return b;
 }
+
+// LDS staging of the workgroup's integral rows up to this size (the blocked
+// rows of CAS(14,14) take 49 KB in FP64).
+constexpr size_t kSymOppLdsMax = 128 * 1024;
 
 SymArgs make_args(const SymInfo &S) {
   SymArgs g{};
@@ -381,13 +405,25 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (ev) SBCI_HIP(hipEventRecord(ev[1], ctx->stream));
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (A.s > 0 && B.s > 0) {
-    const size_t lds = opp_lds_bytes(A.s, sizeof(T));
-    if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");
     const T *W;
     if constexpr (dbl) W = ctx->W64; else W = ctx->W32;
-    k_sym_opp<T><<<dim3((unsigned)A.ns, (unsigned)nvec), 256, lds, ctx->stream>>>(
-        g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB, A.tab, A.s, B.tab, B.s, W,
-        ctx->npair, c, out);
+    const size_t lw = opp_lds_bytes(A.s, sizeof(T), ctx->npair, true);
+    const dim3 grid((unsigned)A.ns, (unsigned)nvec);
+    if (lw <= kSymOppLdsMax) {
+      static bool attr = false;
+      if (!attr) {
+        SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp<T, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr = true;
+      }
+      k_sym_opp<T, true><<<grid, 256, lw, ctx->stream>>>(g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB,
+                                                          A.tab, A.s, B.tab, B.s, W, ctx->npair, c, out);
+    } else {
+      const size_t lds = opp_lds_bytes(A.s, sizeof(T), ctx->npair, false);
+      if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");
+      k_sym_opp<T, false><<<grid, 256, lds, ctx->stream>>>(g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB,
+                                                           A.tab, A.s, B.tab, B.s, W, ctx->npair, c, out);
+    }
     SBCI_CHECK_LAUNCH();
   }
   if (ev)

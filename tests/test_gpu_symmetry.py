@@ -61,6 +61,22 @@ def test_layout_diag_and_sigma_f64(n, na, nb, orbsym):
         ctx.close()
 
 
+@pytest.mark.parametrize("g", [0, 5])
+def test_sigma_with_integral_rows_beyond_lds(g):
+    """30 orbitals, 2 + 2 electrons: the workgroup's integral rows (58 x 465 in
+    FP64, 216 KB) exceed the LDS budget, so the contraction reads them from
+    global memory instead of staging them."""
+    n, na, nb = 30, 2, 2
+    ctx, I, o = _ctx(n, na, nb, g, seed=4)
+    c = sigma_inputs(1, 2, ctx.ndet)
+    want = SY.sigma(n, na, nb, I.h1, I.eri, o, g, c)
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    got32 = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype="f32").cpu().numpy()
+    assert np.linalg.norm(got32 - want) / np.linalg.norm(want) < 2e-6
+    ctx.close()
+
+
 def test_bf16_and_bad_arguments_are_refused():
     import paper_2603_06101_amd as sb
     ctx, I, o = _ctx(6, 3, 3, 0)
