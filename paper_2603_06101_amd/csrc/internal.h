@@ -110,6 +110,13 @@ struct SymInfo {
   int32_t *colA = nullptr, *colB = nullptr;
   double *valA64 = nullptr, *valB64 = nullptr;
   float *valA32 = nullptr, *valB32 = nullptr;
+  // pair form of the opposite-spin part: beta pair codes with the target's
+  // rank inside its irrep, columns in irrep-sorted order [npair][nsb], and
+  // the orbital pairs sorted by class (orbsym[k] ^ orbsym[l]) with class starts
+  uint32_t *pairS = nullptr;
+  int32_t *plist = nullptr;
+  int pcs[9] = {};
+  int64_t maxcol = 0;                    // longest block row
 };
 
 }  // namespace sbci

@@ -127,13 +127,12 @@ __global__ __launch_bounds__(256) void k_sym_same(
   out[vo + d] = acc;
 }
 
-// Opposite-spin part, accumulated: one workgroup per alpha string (irrep-sorted
+// Opposite-spin part in gather form (used where the pair form below does not
+// fit in LDS), accumulated: one workgroup per alpha string (irrep-sorted
 // index k), threads over the row's beta columns.
 // LDS: srcoff[sA] (int64, source row offset in the vector) | wro[sA] (int32,
-// pair row of W) | ord[sA] (class-sorted entry) | cls[sA] | cs[9] | sg[sA]
-// (T, sign); with WL also so2[sA] (srcoff in class order) and Ws[sA][npair]
-// (sign_e (pq_e|kl) in class order), so that the inner loop reads W from LDS.
-template <typename T, bool WL>
+// pair row of W) | ord[sA] (class-sorted entry) | cls[sA] | cs[9] | sg[sA] (T, sign).
+template <typename T>
 __global__ __launch_bounds__(256) void k_sym_opp(
     SymArgs g, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ idxB, const int32_t *__restrict__ posA,
@@ -178,18 +177,6 @@ __global__ __launch_bounds__(256) void k_sym_opp(
     for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
   }
   __syncthreads();
-  const size_t o2 = ((((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * sizeof(T) + 7) & ~(size_t)7;
-  int64_t *so2 = reinterpret_cast<int64_t *>(smem + o2);
-  T *Ws = reinterpret_cast<T *>(so2 + sA);
-  if constexpr (WL) {
-    for (int i = threadIdx.x; i < sA; i += blockDim.x) so2[i] = srcoff[ord[i]];
-    for (int64_t x = threadIdx.x; x < (int64_t)sA * npair; x += blockDim.x) {
-      const int i = (int)(x / npair), kl = (int)(x - (int64_t)i * npair);
-      const int e = ord[i];
-      Ws[x] = sg[e] * W[wro[e] + kl];
-    }
-    __syncthreads();
-  }
   const T *__restrict__ cv = c + vo;
   T *__restrict__ row = out + vo + g.off[a] + r * nc;
   for (int64_t q = threadIdx.x; q < nc; q += blockDim.x) {
@@ -201,13 +188,9 @@ __global__ __launch_bounds__(256) void k_sym_opp(
       const int kl = pair_index(t.p, t.q);
       const int64_t jp = posB[t.J];
       T inner = 0;
-      if constexpr (WL) {
-        for (int i = cs[x]; i < cs[x + 1]; ++i) inner += Ws[i * npair + kl] * cv[so2[i] + jp];
-      } else {
-        for (int i = cs[x]; i < cs[x + 1]; ++i) {
-          const int e = ord[i];
-          inner += sg[e] * W[wro[e] + kl] * cv[srcoff[e] + jp];
-        }
+      for (int i = cs[x]; i < cs[x + 1]; ++i) {
+        const int e = ord[i];
+        inner += sg[e] * W[wro[e] + kl] * cv[srcoff[e] + jp];
       }
       acc += (T)t.sign * inner;
     }
@@ -215,15 +198,148 @@ __global__ __launch_bounds__(256) void k_sym_opp(
   }
 }
 
-size_t opp_lds_bytes(int sA, size_t tsize, int npair, bool wl) {
-  size_t b = (((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * tsize;
-  if (wl) b = ((b + 7) & ~(size_t)7) + (size_t)sA * 8 + (size_t)sA * npair * tsize;
-  return b;
+// Pair form of the opposite-spin part: one workgroup per alpha string Ia
+// (irrep-sorted index k, block a), the row of sigma accumulated in LDS.  For
+// each class x with alpha excitations e of Ia, the source block is a ^ x and
+// for each of its columns J (a beta string) and each orbital pair kl of class x
+//   M[kl][J] = sum_e sign_e (kl_e|kl) c[a ^ x](rank(J_e), J)
+// is formed in registers (8 pairs at a time) and scattered through the beta
+// pair code of (kl, J) to the row entry of E_kl J or E_lk J (the one that is
+// not zero), with that sign.  c is read along rows (coalesced), W from LDS.
+// LDS: acc[maxcol] (double) | srcoff, wro, ord, cls, cs | sg | so2 | Ws[sA][npair] | plist[npair]
+struct PairStarts {
+  int s[9];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_opp_pair(
+    SymArgs g, PairStarts pcs, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
+    const int32_t *__restrict__ posA, const Ent *__restrict__ tabA, int sA,
+    const uint32_t *__restrict__ pairS, int64_t nsb, const int32_t *__restrict__ plist_g,
+    const T *__restrict__ W, int npair, int64_t maxcol, const T *__restrict__ c,
+    T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *acc = reinterpret_cast<double *>(smem);
+  unsigned char *base = smem + (((size_t)maxcol * 8 + 15) & ~(size_t)15);
+  int64_t *srcoff = reinterpret_cast<int64_t *>(base);
+  int32_t *wro = reinterpret_cast<int32_t *>(srcoff + sA);
+  int32_t *ord = wro + sA;
+  int32_t *cls = ord + sA;
+  int32_t *cs = cls + sA;  // [9]
+  const size_t o1 = ((size_t)sA * 20 + 36 + 15) & ~(size_t)15;
+  T *sg = reinterpret_cast<T *>(base + o1);
+  const size_t o2 = (o1 + (size_t)sA * sizeof(T) + 7) & ~(size_t)7;
+  int64_t *so2 = reinterpret_cast<int64_t *>(base + o2);
+  T *Ws = reinterpret_cast<T *>(so2 + sA);
+  int32_t *plist = reinterpret_cast<int32_t *>(Ws + (size_t)sA * npair);
+
+  const int64_t k = blockIdx.x;
+  int a = 0;
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (g.startA[t] <= k) a = t;
+  const int64_t nc = g.ncol[a];
+  if (nc == 0) return;  // uniform over the workgroup
+  const int64_t r = k - g.startA[a];
+  const int64_t Ia = idxA[k];
+  const int64_t vo = (int64_t)blockIdx.y * g.off[8];
+  for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) acc[j] = 0.0;
+  for (int e = threadIdx.x; e < sA; e += blockDim.x) {
+    const Ent t = tabA[Ia * sA + e];
+    const int x = orbsym[t.p] ^ orbsym[t.q];
+    const int b = a ^ x;
+    cls[e] = x;
+    srcoff[e] = g.off[b] + (int64_t)posA[t.J] * g.ncol[b];
+    wro[e] = pair_index(t.p, t.q) * npair;
+    sg[e] = (T)t.sign;
+  }
+  for (int p = threadIdx.x; p < npair; p += blockDim.x) plist[p] = plist_g[p];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = 0; e < sA; ++e) ++n[cls[e]];
+    cs[0] = 0;
+    for (int x = 0; x < 8; ++x) cs[x + 1] = cs[x] + n[x];
+    int fill[8];
+    for (int x = 0; x < 8; ++x) fill[x] = cs[x];
+    for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < sA; i += blockDim.x) so2[i] = srcoff[ord[i]];
+  for (int64_t x = threadIdx.x; x < (int64_t)sA * npair; x += blockDim.x) {
+    const int i = (int)(x / npair), kl = (int)(x - (int64_t)i * npair);
+    const int e = ord[i];
+    Ws[x] = sg[e] * W[wro[e] + kl];
+  }
+  __syncthreads();
+  const T *__restrict__ cv = c + vo;
+  for (int x = 0; x < 8; ++x) {
+    const int i0 = cs[x], i1 = cs[x + 1];
+    const int p0 = pcs.s[x], p1 = pcs.s[x + 1];
+    if (i0 == i1 || p0 == p1) continue;  // uniform
+    const int b = a ^ x;
+    const int64_t nbc = g.ncol[b];
+    const int64_t col0 = g.startBc[b];  // irrep-sorted beta index of column 0 of block b
+    for (int64_t j = threadIdx.x; j < nbc; j += blockDim.x) {
+      for (int pp = p0; pp < p1; pp += 8) {
+        int kl[8];
+        T m[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          kl[t] = plist[pp + t < p1 ? pp + t : p0];
+          m[t] = 0;
+        }
+        for (int i = i0; i < i1; ++i) {
+          const T v = cv[so2[i] + j];
+          const T *wr = Ws + (size_t)i * npair;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) m[t] += wr[kl[t]] * v;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (pp + t < p1) {
+            const uint32_t cd = pairS[(int64_t)kl[t] * nsb + col0 + j];
+            if (cd != kInvalid) {
+              const double v = (double)m[t];
+              atomicAdd(&acc[cd >> 1], (cd & 1u) ? -v : v);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  T *__restrict__ row = out + vo + g.off[a] + r * nc;
+  for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) row[j] += (T)acc[j];
 }
 
-// LDS staging of the workgroup's integral rows up to this size (the blocked
-// rows of CAS(14,14) take 49 KB in FP64).
-constexpr size_t kSymOppLdsMax = 128 * 1024;
+size_t opp_pair_lds_bytes(int sA, size_t tsize, int npair, int64_t maxcol) {
+  size_t b = (((size_t)maxcol * 8 + 15) & ~(size_t)15);
+  size_t o1 = ((size_t)sA * 20 + 36 + 15) & ~(size_t)15;
+  size_t o2 = (o1 + (size_t)sA * tsize + 7) & ~(size_t)7;
+  return b + o2 + (size_t)sA * 8 + (size_t)sA * npair * tsize + (size_t)npair * 4;
+}
+
+// Beta pair codes re-addressed for the blocks: row kl, column = irrep-sorted
+// index of the source string, code = (rank of the target in its irrep << 1) | sign.
+__global__ void k_sym_pairs(const uint32_t *__restrict__ pair, int64_t ns_pad, int64_t nsb, int npair,
+                            const int32_t *__restrict__ irr, const int32_t *__restrict__ pos,
+                            const int64_t *__restrict__ start, uint32_t *__restrict__ out) {
+  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int kl = blockIdx.y;
+  if (J >= nsb || kl >= npair) return;
+  const uint32_t cd = pair[(int64_t)kl * ns_pad + J];
+  const uint32_t nc = cd == kInvalid ? kInvalid : (((uint32_t)pos[cd >> 1]) << 1) | (cd & 1u);
+  out[(int64_t)kl * nsb + start[irr[J]] + pos[J]] = nc;
+}
+
+size_t opp_lds_bytes(int sA, size_t tsize) {
+  return (((size_t)sA * 20 + 36 + 15) & ~(size_t)15) + (size_t)sA * tsize;
+}
+
+// The pair form (row of sigma and the integral rows in LDS) up to this size:
+// CAS(14,14) takes 53 KB in FP64, CAS(16,16) 93 KB.
+constexpr size_t kSymPairLdsMax = 160 * 1024;
 
 SymArgs make_args(const SymInfo &S) {
   SymArgs g{};
@@ -345,6 +461,31 @@ int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1
   SBCI_TRY(upload(&S->orbsym_d, os, st));
   SBCI_TRY(compact_lists(ctx, ctx->A, S->irrA, S->posA, &S->nfA, &S->colA, &S->valA64, &S->valA32));
   SBCI_TRY(compact_lists(ctx, ctx->B, S->irrB, S->posB, &S->nfB, &S->colB, &S->valB64, &S->valB32));
+  // pair form of the opposite-spin part: re-addressed beta pair codes and the
+  // orbital pairs sorted by class
+  {
+    const int np = ctx->npair;
+    std::vector<int32_t> pl;
+    for (int x = 0; x < 8; ++x) {
+      S->pcs[x] = (int)pl.size();
+      for (int kk = 0, kl = 0; kk < n; ++kk)
+        for (int l = 0; l <= kk; ++l, ++kl)
+          if ((orbsym[kk] ^ orbsym[l]) == x) pl.push_back(kl);
+    }
+    S->pcs[8] = (int)pl.size();
+    SBCI_TRY(upload(&S->plist, pl, st));
+    std::vector<int64_t> sb9(S->startB, S->startB + 9);
+    int64_t *sbd = nullptr;
+    SBCI_TRY(upload(&sbd, sb9, st));
+    const int64_t nsb = ctx->B.ns;
+    SBCI_HIP(hipMalloc(&S->pairS, sizeof(uint32_t) * (size_t)np * nsb));
+    k_sym_pairs<<<dim3((unsigned)((nsb + 255) / 256), (unsigned)np), 256, 0, st>>>(
+        ctx->B.pair, ctx->B.ns_pad, nsb, np, S->irrB, S->posB, sbd, S->pairS);
+    SBCI_CHECK_LAUNCH();
+    SBCI_HIP(hipStreamSynchronize(st));
+    hipFree(sbd);
+    for (int a = 0; a < 8; ++a) S->maxcol = std::max<int64_t>(S->maxcol, S->cntB[a]);
+  }
   // the diagonal in the blocked layout replaces the full-space one
   const SymArgs g = make_args(*S);
   const int64_t nd = S->off[8];
@@ -381,6 +522,8 @@ void free_symmetry(sbci_ctx *ctx) {
   hipFree(S->colB);
   hipFree(S->valB64);
   hipFree(S->valB32);
+  hipFree(S->pairS);
+  hipFree(S->plist);
   delete S;
   ctx->sym = nullptr;
 }
@@ -407,22 +550,25 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (A.s > 0 && B.s > 0) {
     const T *W;
     if constexpr (dbl) W = ctx->W64; else W = ctx->W32;
-    const size_t lw = opp_lds_bytes(A.s, sizeof(T), ctx->npair, true);
+    const size_t lp = opp_pair_lds_bytes(A.s, sizeof(T), ctx->npair, S.maxcol);
     const dim3 grid((unsigned)A.ns, (unsigned)nvec);
-    if (lw <= kSymOppLdsMax) {
-      static bool attr = false;
-      if (!attr) {
-        SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp<T, true>,
+    if (lp <= kSymPairLdsMax) {
+      static bool attrp = false;
+      if (!attrp) {
+        SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_pair<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr = true;
+        attrp = true;
       }
-      k_sym_opp<T, true><<<grid, 256, lw, ctx->stream>>>(g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB,
-                                                          A.tab, A.s, B.tab, B.s, W, ctx->npair, c, out);
+      PairStarts pcs;
+      for (int x = 0; x < 9; ++x) pcs.s[x] = S.pcs[x];
+      k_sym_opp_pair<T><<<grid, 256, lp, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, A.tab, A.s,
+                                                        S.pairS, B.ns, S.plist, W, ctx->npair,
+                                                        S.maxcol, c, out);
     } else {
-      const size_t lds = opp_lds_bytes(A.s, sizeof(T), ctx->npair, false);
+      const size_t lds = opp_lds_bytes(A.s, sizeof(T));
       if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");
-      k_sym_opp<T, false><<<grid, 256, lds, ctx->stream>>>(g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB,
-                                                           A.tab, A.s, B.tab, B.s, W, ctx->npair, c, out);
+      k_sym_opp<T><<<grid, 256, lds, ctx->stream>>>(g, S.orbsym_d, S.idxA, S.idxB, S.posA, S.posB,
+                                                    A.tab, A.s, B.tab, B.s, W, ctx->npair, c, out);
     }
     SBCI_CHECK_LAUNCH();
   }
