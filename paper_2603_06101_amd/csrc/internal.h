@@ -110,6 +110,10 @@ struct SymInfo {
   int32_t *colA = nullptr, *colB = nullptr;
   double *valA64 = nullptr, *valB64 = nullptr;
   float *valA32 = nullptr, *valB32 = nullptr;
+  // the beta lists transposed, [entry][irrep-sorted string index]
+  int32_t *colBT = nullptr;
+  double *valBT64 = nullptr;
+  float *valBT32 = nullptr;
   // pair form of the opposite-spin part: beta pair codes with the target's
   // rank inside its irrep, columns in irrep-sorted order [npair][nsb], and
   // the orbital pairs sorted by class (orbsym[k] ^ orbsym[l]) with class starts

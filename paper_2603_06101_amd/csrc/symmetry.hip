@@ -63,12 +63,18 @@ __global__ void k_sym_count(const int32_t *__restrict__ fcol, int nf, int64_t ns
   cnt[i] = k;
 }
 
+// With start (the first irrep-sorted index of each irrep) the lists are also
+// written transposed, [entry][irrep-sorted string index], so that the lanes of
+// a wave, which own consecutive strings of one irrep, read them coalesced.
 __global__ void k_sym_compact(const int32_t *__restrict__ fcol, const double *__restrict__ f64,
                               int nf, int64_t ns, const int32_t *__restrict__ irr,
                               const int32_t *__restrict__ pos, int nfs, int32_t *__restrict__ col,
-                              double *__restrict__ v64, float *__restrict__ v32) {
+                              double *__restrict__ v64, float *__restrict__ v32,
+                              const int64_t *__restrict__ start, int32_t *__restrict__ colT,
+                              double *__restrict__ t64, float *__restrict__ t32) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ns) return;
+  const int64_t is = start ? start[irr[i]] + pos[i] : 0;
   int k = 0;
   for (int e = 0; e < nf; ++e) {
     const int32_t J = fcol[i * nf + e];
@@ -76,12 +82,22 @@ __global__ void k_sym_compact(const int32_t *__restrict__ fcol, const double *__
     col[i * nfs + k] = pos[J];
     v64[i * nfs + k] = f64[i * nf + e];
     v32[i * nfs + k] = (float)f64[i * nf + e];
+    if (start) {
+      colT[(int64_t)k * ns + is] = pos[J];
+      t64[(int64_t)k * ns + is] = f64[i * nf + e];
+      t32[(int64_t)k * ns + is] = (float)f64[i * nf + e];
+    }
     ++k;
   }
   for (; k < nfs; ++k) {
     col[i * nfs + k] = pos[i];
     v64[i * nfs + k] = 0.0;
     v32[i * nfs + k] = 0.0f;
+    if (start) {
+      colT[(int64_t)k * ns + is] = pos[i];
+      t64[(int64_t)k * ns + is] = 0.0;
+      t32[(int64_t)k * ns + is] = 0.0f;
+    }
   }
 }
 
@@ -104,9 +120,9 @@ __global__ void k_sym_gather(SymArgs g, const int32_t *__restrict__ idxA,
 // One-electron and same-spin part, plain write.
 template <typename T, typename V>
 __global__ __launch_bounds__(256) void k_sym_same(
-    SymArgs g, const int32_t *__restrict__ idxA, const int32_t *__restrict__ idxB,
+    SymArgs g, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ colA, const V *__restrict__ valA, int nfA,
-    const int32_t *__restrict__ colB, const V *__restrict__ valB, int nfB,
+    const int32_t *__restrict__ colBT, const V *__restrict__ valBT, int nfB, int64_t nsb,
     const T *__restrict__ c, T *__restrict__ out) {
   const int64_t nd = g.off[8];
   const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -115,12 +131,12 @@ __global__ __launch_bounds__(256) void k_sym_same(
   const int a = find_block(g, d);
   const int64_t nc = g.ncol[a], rel = d - g.off[a];
   const int64_t r = rel / nc, q = rel - r * nc;
-  const int64_t Ia = idxA[g.startA[a] + r], Ib = idxB[g.startBc[a] + q];
+  const int64_t Ia = idxA[g.startA[a] + r], qs = g.startBc[a] + q;
   const T *__restrict__ blk = c + vo + g.off[a];
   T acc = 0;
-  const int32_t *cb = colB + Ib * nfB;
-  const V *vb = valB + Ib * nfB;
-  for (int e = 0; e < nfB; ++e) acc += (T)vb[e] * blk[r * nc + cb[e]];
+  // beta: in-row gather over the transposed lists (coalesced over q)
+  for (int e = 0; e < nfB; ++e)
+    acc += (T)valBT[(int64_t)e * nsb + qs] * blk[r * nc + colBT[(int64_t)e * nsb + qs]];
   const int32_t *ca = colA + Ia * nfA;
   const V *va = valA + Ia * nfA;
   for (int e = 0; e < nfA; ++e) acc += (T)va[e] * blk[(int64_t)ca[e] * nc + q];
@@ -387,7 +403,8 @@ int upload(T **dst, const std::vector<T> &v, hipStream_t st) {
 
 // Compacted same-spin lists of one spin (see k_sym_compact).
 int compact_lists(sbci_ctx *ctx, const SpinTables &T, const int32_t *irr, const int32_t *pos,
-                  int *nfs, int32_t **col, double **v64, float **v32) {
+                  int *nfs, int32_t **col, double **v64, float **v32, const int64_t *start = nullptr,
+                  int32_t **colT = nullptr, double **t64 = nullptr, float **t32 = nullptr) {
   const int64_t ns = T.ns;
   int32_t *cnt = nullptr;
   SBCI_HIP(hipMalloc(&cnt, sizeof(int32_t) * ns));
@@ -404,8 +421,14 @@ int compact_lists(sbci_ctx *ctx, const SpinTables &T, const int32_t *irr, const 
   SBCI_HIP(hipMalloc(col, sizeof(int32_t) * ns * m));
   SBCI_HIP(hipMalloc(v64, sizeof(double) * ns * m));
   SBCI_HIP(hipMalloc(v32, sizeof(float) * ns * m));
+  if (start) {
+    SBCI_HIP(hipMalloc(colT, sizeof(int32_t) * ns * m));
+    SBCI_HIP(hipMalloc(t64, sizeof(double) * ns * m));
+    SBCI_HIP(hipMalloc(t32, sizeof(float) * ns * m));
+  }
   k_sym_compact<<<nb, 256, 0, ctx->stream>>>(T.fcol, T.fval64, T.nf, ns, irr, pos, m, *col, *v64,
-                                             *v32);
+                                             *v32, start, start ? *colT : nullptr,
+                                             start ? *t64 : nullptr, start ? *t32 : nullptr);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -460,7 +483,17 @@ int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1
   std::vector<int32_t> os(orbsym, orbsym + n);
   SBCI_TRY(upload(&S->orbsym_d, os, st));
   SBCI_TRY(compact_lists(ctx, ctx->A, S->irrA, S->posA, &S->nfA, &S->colA, &S->valA64, &S->valA32));
-  SBCI_TRY(compact_lists(ctx, ctx->B, S->irrB, S->posB, &S->nfB, &S->colB, &S->valB64, &S->valB32));
+  std::vector<int64_t> sb9(S->startB, S->startB + 9);
+  int64_t *sbd = nullptr;
+  SBCI_TRY(upload(&sbd, sb9, st));
+  {
+    const int rc = compact_lists(ctx, ctx->B, S->irrB, S->posB, &S->nfB, &S->colB, &S->valB64,
+                                 &S->valB32, sbd, &S->colBT, &S->valBT64, &S->valBT32);
+    if (rc != SBCI_OK) {
+      hipFree(sbd);
+      return rc;
+    }
+  }
   // pair form of the opposite-spin part: re-addressed beta pair codes and the
   // orbital pairs sorted by class
   {
@@ -474,9 +507,6 @@ int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1
     }
     S->pcs[8] = (int)pl.size();
     SBCI_TRY(upload(&S->plist, pl, st));
-    std::vector<int64_t> sb9(S->startB, S->startB + 9);
-    int64_t *sbd = nullptr;
-    SBCI_TRY(upload(&sbd, sb9, st));
     const int64_t nsb = ctx->B.ns;
     SBCI_HIP(hipMalloc(&S->pairS, sizeof(uint32_t) * (size_t)np * nsb));
     k_sym_pairs<<<dim3((unsigned)((nsb + 255) / 256), (unsigned)np), 256, 0, st>>>(
@@ -524,6 +554,9 @@ void free_symmetry(sbci_ctx *ctx) {
   hipFree(S->valB32);
   hipFree(S->pairS);
   hipFree(S->plist);
+  hipFree(S->colBT);
+  hipFree(S->valBT64);
+  hipFree(S->valBT32);
   delete S;
   ctx->sym = nullptr;
 }
@@ -540,10 +573,10 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (nblk >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "blocked space too large");
   if constexpr (dbl)
     k_sym_same<double, double><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.idxA, S.idxB, S.colA, S.valA64, S.nfA, S.colB, S.valB64, S.nfB, c, out);
+        g, S.idxA, S.colA, S.valA64, S.nfA, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
   else
     k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.idxA, S.idxB, S.colA, S.valA32, S.nfA, S.colB, S.valB32, S.nfB, c, out);
+        g, S.idxA, S.colA, S.valA32, S.nfA, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
   SBCI_CHECK_LAUNCH();
   if (ev) SBCI_HIP(hipEventRecord(ev[1], ctx->stream));
   const SpinTables &A = ctx->A, &B = ctx->B;
