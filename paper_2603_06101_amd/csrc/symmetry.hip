@@ -221,8 +221,11 @@ __global__ __launch_bounds__(256) void k_sym_opp(
 //   M[kl][J] = sum_e sign_e (kl_e|kl) c[a ^ x](rank(J_e), J)
 // is formed in registers (8 pairs at a time) and scattered through the beta
 // pair code of (kl, J) to the row entry of E_kl J or E_lk J (the one that is
-// not zero), with that sign.  c is read along rows (coalesced), W from LDS.
-// LDS: acc[maxcol] (double) | srcoff, wro, ord, cls, cs | sg | so2 | Ws[sA][npair] | plist[npair]
+// not zero), with that sign.  c is read along rows (coalesced), W from LDS:
+// class x's integrals sign_e (kl_e|kl) are a K_x x P8_x block (rows padded
+// with zeros to whole tiles of 8 pairs), so a tile's 8 values are contiguous.
+// LDS: acc[maxcol] (double) | srcoff, wro, ord, cls, cs[9], woff[9] | sg | so2
+//      | Ws[<= sA * maxp8] | plist[npair]   (maxp8: the largest class, padded to 8)
 struct PairStarts {
   int s[9];
 };
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
     SymArgs g, PairStarts pcs, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ posA, const Ent *__restrict__ tabA, int sA,
     const uint32_t *__restrict__ pairS, int64_t nsb, const int32_t *__restrict__ plist_g,
-    const T *__restrict__ W, int npair, int64_t maxcol, const T *__restrict__ c,
+    const T *__restrict__ W, int npair, int64_t maxcol, int maxp8, const T *__restrict__ c,
     T *__restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *acc = reinterpret_cast<double *>(smem);
@@ -242,12 +245,14 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
   int32_t *ord = wro + sA;
   int32_t *cls = ord + sA;
   int32_t *cs = cls + sA;  // [9]
-  const size_t o1 = ((size_t)sA * 20 + 36 + 15) & ~(size_t)15;
+  int32_t *woff = cs + 9;  // [9]
+  const size_t o1 = ((size_t)sA * 20 + 72 + 15) & ~(size_t)15;
   T *sg = reinterpret_cast<T *>(base + o1);
   const size_t o2 = (o1 + (size_t)sA * sizeof(T) + 7) & ~(size_t)7;
   int64_t *so2 = reinterpret_cast<int64_t *>(base + o2);
-  T *Ws = reinterpret_cast<T *>(so2 + sA);
-  int32_t *plist = reinterpret_cast<int32_t *>(Ws + (size_t)sA * npair);
+  const size_t ow = (o2 + (size_t)sA * 8 + 15) & ~(size_t)15;
+  T *Ws = reinterpret_cast<T *>(base + ow);
+  int32_t *plist = reinterpret_cast<int32_t *>(Ws + (size_t)sA * maxp8);
 
   const int64_t k = blockIdx.x;
   int a = 0;
@@ -279,13 +284,20 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
     int fill[8];
     for (int x = 0; x < 8; ++x) fill[x] = cs[x];
     for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
+    woff[0] = 0;
+    for (int x = 0; x < 8; ++x)
+      woff[x + 1] = woff[x] + n[x] * ((pcs.s[x + 1] - pcs.s[x] + 7) & ~7);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < sA; i += blockDim.x) so2[i] = srcoff[ord[i]];
-  for (int64_t x = threadIdx.x; x < (int64_t)sA * npair; x += blockDim.x) {
-    const int i = (int)(x / npair), kl = (int)(x - (int64_t)i * npair);
-    const int e = ord[i];
-    Ws[x] = sg[e] * W[wro[e] + kl];
+  for (int x = 0; x < 8; ++x) {
+    const int np_ = pcs.s[x + 1] - pcs.s[x], p8 = (np_ + 7) & ~7;
+    const int nx = (cs[x + 1] - cs[x]) * p8;
+    for (int y = threadIdx.x; y < nx; y += blockDim.x) {
+      const int il = y / p8, pl = y - il * p8;
+      const int e = ord[cs[x] + il];
+      Ws[woff[x] + y] = pl < np_ ? sg[e] * W[wro[e] + plist[pcs.s[x] + pl]] : (T)0;
+    }
   }
   __syncthreads();
   const T *__restrict__ cv = c + vo;
@@ -296,6 +308,8 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
     const int b = a ^ x;
     const int64_t nbc = g.ncol[b];
     const int64_t col0 = g.startBc[b];  // irrep-sorted beta index of column 0 of block b
+    const int p8 = (p1 - p0 + 7) & ~7;
+    const T *__restrict__ wc = Ws + woff[x];
     for (int64_t j = threadIdx.x; j < nbc; j += blockDim.x) {
       for (int pp = p0; pp < p1; pp += 8) {
         int kl[8];
@@ -305,11 +319,12 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
           kl[t] = plist[pp + t < p1 ? pp + t : p0];
           m[t] = 0;
         }
+        const T *__restrict__ wt = wc + (pp - p0);
         for (int i = i0; i < i1; ++i) {
           const T v = cv[so2[i] + j];
-          const T *wr = Ws + (size_t)i * npair;
+          const T *wr = wt + (size_t)(i - i0) * p8;
 #pragma unroll
-          for (int t = 0; t < 8; ++t) m[t] += wr[kl[t]] * v;
+          for (int t = 0; t < 8; ++t) m[t] += wr[t] * v;
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -329,11 +344,12 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
   for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) row[j] += (T)acc[j];
 }
 
-size_t opp_pair_lds_bytes(int sA, size_t tsize, int npair, int64_t maxcol) {
+size_t opp_pair_lds_bytes(int sA, size_t tsize, int npair, int64_t maxcol, int maxp8) {
   size_t b = (((size_t)maxcol * 8 + 15) & ~(size_t)15);
-  size_t o1 = ((size_t)sA * 20 + 36 + 15) & ~(size_t)15;
+  size_t o1 = ((size_t)sA * 20 + 72 + 15) & ~(size_t)15;
   size_t o2 = (o1 + (size_t)sA * tsize + 7) & ~(size_t)7;
-  return b + o2 + (size_t)sA * 8 + (size_t)sA * npair * tsize + (size_t)npair * 4;
+  size_t ow = (o2 + (size_t)sA * 8 + 15) & ~(size_t)15;
+  return b + ow + (size_t)sA * maxp8 * tsize + (size_t)npair * 4;
 }
 
 // Beta pair codes re-addressed for the blocks: row kl, column = irrep-sorted
@@ -583,7 +599,9 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (A.s > 0 && B.s > 0) {
     const T *W;
     if constexpr (dbl) W = ctx->W64; else W = ctx->W32;
-    const size_t lp = opp_pair_lds_bytes(A.s, sizeof(T), ctx->npair, S.maxcol);
+    int maxp8 = 8;
+    for (int x = 0; x < 8; ++x) maxp8 = std::max(maxp8, (S.pcs[x + 1] - S.pcs[x] + 7) & ~7);
+    const size_t lp = opp_pair_lds_bytes(A.s, sizeof(T), ctx->npair, S.maxcol, maxp8);
     const dim3 grid((unsigned)A.ns, (unsigned)nvec);
     if (lp <= kSymPairLdsMax) {
       static bool attrp = false;
@@ -596,7 +614,7 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
       for (int x = 0; x < 9; ++x) pcs.s[x] = S.pcs[x];
       k_sym_opp_pair<T><<<grid, 256, lp, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, A.tab, A.s,
                                                         S.pairS, B.ns, S.plist, W, ctx->npair,
-                                                        S.maxcol, c, out);
+                                                        S.maxcol, maxp8, c, out);
     } else {
       const size_t lds = opp_lds_bytes(A.s, sizeof(T));
       if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");
