@@ -105,12 +105,12 @@ struct SymInfo {
   int32_t *irrA = nullptr, *posA = nullptr, *idxA = nullptr;  // [nsa] irrep, rank in irrep, sorted -> global
   int32_t *irrB = nullptr, *posB = nullptr, *idxB = nullptr;  // [nsb]
   int32_t *orbsym_d = nullptr;           // [norb]
-  // same-spin lists compacted to the string's own irrep: [ns][nf*] ranks and values
+  // same-spin lists compacted to the string's own irrep (ranks and values):
+  // alpha [irrep-sorted string][nfA], beta transposed [nfB][irrep-sorted string]
   int nfA = 0, nfB = 0;
-  int32_t *colA = nullptr, *colB = nullptr;
-  double *valA64 = nullptr, *valB64 = nullptr;
-  float *valA32 = nullptr, *valB32 = nullptr;
-  // the beta lists transposed, [entry][irrep-sorted string index]
+  int32_t *colA = nullptr;
+  double *valA64 = nullptr;
+  float *valA32 = nullptr;
   int32_t *colBT = nullptr;
   double *valBT64 = nullptr;
   float *valBT32 = nullptr;
@@ -207,6 +207,10 @@ void free_tables(sbci_ctx *ctx);
 // sigma = H c for nvec vectors of element type T (double or float).
 // mode: SBCI_F64 (T = double), SBCI_F32 or SBCI_BF16 (T = float).
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
+// dst[r][q] += sum_e fval[r][e] src[fcol[r][e]][q] for one R x C matrix (one
+// vector) with the L2-streaming list kernel; FP64 or FP32 (mode).
+int same_lists_block(sbci_ctx *ctx, const int32_t *fcol, const void *fval, int nf, int64_t R,
+                     int64_t C, const void *src, void *dst, int mode);
 // Same, with HIP events around its five parts; ms[0..4] = alpha lists,
 // opposite spin, transpose, beta lists, transposed add (milliseconds).
 int sigma_profile(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, float *ms);

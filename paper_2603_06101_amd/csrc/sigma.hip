@@ -1429,6 +1429,19 @@ int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
   return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
 }
 
+int same_lists_block(sbci_ctx *ctx, const int32_t *fcol, const void *fval, int nf, int64_t R,
+                     int64_t C, const void *src, void *dst, int mode) {
+  SpinTables P{};
+  P.fcol = const_cast<int32_t *>(fcol);
+  P.nf = nf;
+  if (mode == SBCI_F64)
+    return launch_same<double, double>(ctx, P, static_cast<const double *>(fval), R, C,
+                                       static_cast<const double *>(src), static_cast<double *>(dst),
+                                       1, 1);
+  return launch_same<float, float>(ctx, P, static_cast<const float *>(fval), R, C,
+                                   static_cast<const float *>(src), static_cast<float *>(dst), 1, 1);
+}
+
 int same_form(sbci_ctx *ctx, int spin, int dtype, int *form) {
   const SpinTables &S = spin == 0 ? ctx->A : ctx->B;
   const bool dense = dtype == SBCI_BF16 ? use_dense_bf16(ctx, S) : use_dense(ctx, S);

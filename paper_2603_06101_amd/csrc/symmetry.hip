@@ -63,41 +63,34 @@ __global__ void k_sym_count(const int32_t *__restrict__ fcol, int nf, int64_t ns
   cnt[i] = k;
 }
 
-// With start (the first irrep-sorted index of each irrep) the lists are also
-// written transposed, [entry][irrep-sorted string index], so that the lanes of
-// a wave, which own consecutive strings of one irrep, read them coalesced.
+// The compacted lists with rows in irrep-sorted order (start: first sorted
+// index of each irrep), row-major [sorted string][entry] or transposed
+// [entry][sorted string] (the lanes of a wave, which own consecutive strings of
+// one irrep, then read them coalesced).
 __global__ void k_sym_compact(const int32_t *__restrict__ fcol, const double *__restrict__ f64,
                               int nf, int64_t ns, const int32_t *__restrict__ irr,
-                              const int32_t *__restrict__ pos, int nfs, int32_t *__restrict__ col,
-                              double *__restrict__ v64, float *__restrict__ v32,
-                              const int64_t *__restrict__ start, int32_t *__restrict__ colT,
-                              double *__restrict__ t64, float *__restrict__ t32) {
+                              const int32_t *__restrict__ pos, int nfs,
+                              const int64_t *__restrict__ start, int transposed,
+                              int32_t *__restrict__ col, double *__restrict__ v64,
+                              float *__restrict__ v32) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ns) return;
-  const int64_t is = start ? start[irr[i]] + pos[i] : 0;
+  const int64_t is = start[irr[i]] + pos[i];
   int k = 0;
   for (int e = 0; e < nf; ++e) {
     const int32_t J = fcol[i * nf + e];
     if (irr[J] != irr[i]) continue;
-    col[i * nfs + k] = pos[J];
-    v64[i * nfs + k] = f64[i * nf + e];
-    v32[i * nfs + k] = (float)f64[i * nf + e];
-    if (start) {
-      colT[(int64_t)k * ns + is] = pos[J];
-      t64[(int64_t)k * ns + is] = f64[i * nf + e];
-      t32[(int64_t)k * ns + is] = (float)f64[i * nf + e];
-    }
+    const int64_t o = transposed ? (int64_t)k * ns + is : is * nfs + k;
+    col[o] = pos[J];
+    v64[o] = f64[i * nf + e];
+    v32[o] = (float)f64[i * nf + e];
     ++k;
   }
   for (; k < nfs; ++k) {
-    col[i * nfs + k] = pos[i];
-    v64[i * nfs + k] = 0.0;
-    v32[i * nfs + k] = 0.0f;
-    if (start) {
-      colT[(int64_t)k * ns + is] = pos[i];
-      t64[(int64_t)k * ns + is] = 0.0;
-      t32[(int64_t)k * ns + is] = 0.0f;
-    }
+    const int64_t o = transposed ? (int64_t)k * ns + is : is * nfs + k;
+    col[o] = pos[i];
+    v64[o] = 0.0;
+    v32[o] = 0.0f;
   }
 }
 
@@ -117,12 +110,11 @@ __global__ void k_sym_gather(SymArgs g, const int32_t *__restrict__ idxA,
   }
 }
 
-// One-electron and same-spin part, plain write.
+// Beta same-spin part (with the beta one-electron terms), plain write; the
+// alpha part follows block by block with the list kernel of the unblocked sigma.
 template <typename T, typename V>
 __global__ __launch_bounds__(256) void k_sym_same(
-    SymArgs g, const int32_t *__restrict__ idxA,
-    const int32_t *__restrict__ colA, const V *__restrict__ valA, int nfA,
-    const int32_t *__restrict__ colBT, const V *__restrict__ valBT, int nfB, int64_t nsb,
+    SymArgs g, const int32_t *__restrict__ colBT, const V *__restrict__ valBT, int nfB, int64_t nsb,
     const T *__restrict__ c, T *__restrict__ out) {
   const int64_t nd = g.off[8];
   const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -131,15 +123,12 @@ __global__ __launch_bounds__(256) void k_sym_same(
   const int a = find_block(g, d);
   const int64_t nc = g.ncol[a], rel = d - g.off[a];
   const int64_t r = rel / nc, q = rel - r * nc;
-  const int64_t Ia = idxA[g.startA[a] + r], qs = g.startBc[a] + q;
+  const int64_t qs = g.startBc[a] + q;
   const T *__restrict__ blk = c + vo + g.off[a];
   T acc = 0;
-  // beta: in-row gather over the transposed lists (coalesced over q)
+  // in-row gather over the transposed lists (coalesced over q)
   for (int e = 0; e < nfB; ++e)
     acc += (T)valBT[(int64_t)e * nsb + qs] * blk[r * nc + colBT[(int64_t)e * nsb + qs]];
-  const int32_t *ca = colA + Ia * nfA;
-  const V *va = valA + Ia * nfA;
-  for (int e = 0; e < nfA; ++e) acc += (T)va[e] * blk[(int64_t)ca[e] * nc + q];
   out[vo + d] = acc;
 }
 
@@ -419,8 +408,8 @@ int upload(T **dst, const std::vector<T> &v, hipStream_t st) {
 
 // Compacted same-spin lists of one spin (see k_sym_compact).
 int compact_lists(sbci_ctx *ctx, const SpinTables &T, const int32_t *irr, const int32_t *pos,
-                  int *nfs, int32_t **col, double **v64, float **v32, const int64_t *start = nullptr,
-                  int32_t **colT = nullptr, double **t64 = nullptr, float **t32 = nullptr) {
+                  const int64_t *start, int transposed, int *nfs, int32_t **col, double **v64,
+                  float **v32) {
   const int64_t ns = T.ns;
   int32_t *cnt = nullptr;
   SBCI_HIP(hipMalloc(&cnt, sizeof(int32_t) * ns));
@@ -437,14 +426,8 @@ int compact_lists(sbci_ctx *ctx, const SpinTables &T, const int32_t *irr, const 
   SBCI_HIP(hipMalloc(col, sizeof(int32_t) * ns * m));
   SBCI_HIP(hipMalloc(v64, sizeof(double) * ns * m));
   SBCI_HIP(hipMalloc(v32, sizeof(float) * ns * m));
-  if (start) {
-    SBCI_HIP(hipMalloc(colT, sizeof(int32_t) * ns * m));
-    SBCI_HIP(hipMalloc(t64, sizeof(double) * ns * m));
-    SBCI_HIP(hipMalloc(t32, sizeof(float) * ns * m));
-  }
-  k_sym_compact<<<nb, 256, 0, ctx->stream>>>(T.fcol, T.fval64, T.nf, ns, irr, pos, m, *col, *v64,
-                                             *v32, start, start ? *colT : nullptr,
-                                             start ? *t64 : nullptr, start ? *t32 : nullptr);
+  k_sym_compact<<<nb, 256, 0, ctx->stream>>>(T.fcol, T.fval64, T.nf, ns, irr, pos, m, start,
+                                             transposed, *col, *v64, *v32);
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
@@ -498,13 +481,20 @@ int setup_symmetry(sbci_ctx *ctx, const int *orbsym, int irrep, const double *h1
   SBCI_TRY(upload(&S->idxB, ixB, st));
   std::vector<int32_t> os(orbsym, orbsym + n);
   SBCI_TRY(upload(&S->orbsym_d, os, st));
-  SBCI_TRY(compact_lists(ctx, ctx->A, S->irrA, S->posA, &S->nfA, &S->colA, &S->valA64, &S->valA32));
-  std::vector<int64_t> sb9(S->startB, S->startB + 9);
-  int64_t *sbd = nullptr;
+  std::vector<int64_t> sa9(S->startA, S->startA + 9), sb9(S->startB, S->startB + 9);
+  int64_t *sad = nullptr, *sbd = nullptr;
+  SBCI_TRY(upload(&sad, sa9, st));
+  {
+    const int rc = compact_lists(ctx, ctx->A, S->irrA, S->posA, sad, 0, &S->nfA, &S->colA,
+                                 &S->valA64, &S->valA32);
+    SBCI_HIP(hipStreamSynchronize(st));
+    hipFree(sad);
+    if (rc != SBCI_OK) return rc;
+  }
   SBCI_TRY(upload(&sbd, sb9, st));
   {
-    const int rc = compact_lists(ctx, ctx->B, S->irrB, S->posB, &S->nfB, &S->colB, &S->valB64,
-                                 &S->valB32, sbd, &S->colBT, &S->valBT64, &S->valBT32);
+    const int rc = compact_lists(ctx, ctx->B, S->irrB, S->posB, sbd, 1, &S->nfB, &S->colBT,
+                                 &S->valBT64, &S->valBT32);
     if (rc != SBCI_OK) {
       hipFree(sbd);
       return rc;
@@ -565,9 +555,6 @@ void free_symmetry(sbci_ctx *ctx) {
   hipFree(S->colA);
   hipFree(S->valA64);
   hipFree(S->valA32);
-  hipFree(S->colB);
-  hipFree(S->valB64);
-  hipFree(S->valB32);
   hipFree(S->pairS);
   hipFree(S->plist);
   hipFree(S->colBT);
@@ -589,11 +576,22 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (nblk >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "blocked space too large");
   if constexpr (dbl)
     k_sym_same<double, double><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.idxA, S.colA, S.valA64, S.nfA, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
+        g, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
   else
     k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.idxA, S.colA, S.valA32, S.nfA, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
+        g, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
   SBCI_CHECK_LAUNCH();
+  // alpha same-spin part, block by block (rows of irrep a, lists in sorted order)
+  for (int v = 0; v < nvec; ++v)
+    for (int a = 0; a < 8; ++a) {
+      const int64_t R = S.cntA[a], C = g.ncol[a];
+      if (R == 0 || C == 0) continue;
+      const int64_t lo = S.startA[a] * S.nfA;
+      const void *vals;
+      if constexpr (dbl) vals = S.valA64 + lo; else vals = S.valA32 + lo;
+      SBCI_TRY(same_lists_block(ctx, S.colA + lo, vals, S.nfA, R, C, c + (int64_t)v * nd + S.off[a],
+                                out + (int64_t)v * nd + S.off[a], dbl ? SBCI_F64 : SBCI_F32));
+    }
   if (ev) SBCI_HIP(hipEventRecord(ev[1], ctx->stream));
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (A.s > 0 && B.s > 0) {
