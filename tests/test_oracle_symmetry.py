@@ -96,3 +96,24 @@ def test_generic_integrals_do_couple_blocks():
     mask = np.ones(Hd.shape[0], bool)
     mask[idx] = False
     assert np.abs(Hd[np.ix_(mask, idx)]).max() > 1e-3
+
+
+@pytest.mark.parametrize("n,na,nb,g", [(6, 3, 3, 0), (7, 3, 2, 5), (8, 4, 4, 3)])
+def test_bench_pair_count_matches_tables(n, na, nb, g):
+    """The multiply-add count bench.py reports for the blocked opposite-spin
+    part equals a count over the oracle's excitation tables: for every
+    determinant of the block, the pairs of alpha and beta excitations whose
+    classes orbsym[p] ^ orbsym[q] agree."""
+    import bench
+    o = orbital_irreps(n)
+    JA, PA, QA, _ = ST.excitation_table(n, na)
+    JB, PB, QB, _ = ST.excitation_table(n, nb)
+    idx, _ = SY.block_layout(n, na, nb, o, g)
+    nsb = len(ST.strings(n, nb))
+    total = 0
+    for d in idx:
+        ia, ib = divmod(int(d), nsb)
+        ca = np.bincount([o[p] ^ o[q] for p, q in zip(PA[ia], QA[ia])], minlength=8)
+        cb = np.bincount([o[p] ^ o[q] for p, q in zip(PB[ib], QB[ib])], minlength=8)
+        total += int(ca @ cb)
+    assert bench.sym_pair_count(n, na, nb, o, g) == total
