@@ -22,8 +22,12 @@
 //              cls(E_pq) = orbsym[p] ^ orbsym[q]; the integral vanishes when
 //              the classes differ, and when they agree the source
 //              determinant lies in block a ^ cls.
-// Both are gather kernels (one output element per thread); the opposite-spin
-// one keeps the workgroup's alpha excitations, sorted by class, in LDS.
+// Kernels: the beta same-spin part is an in-row gather (k_sym_same) over
+// transposed lists; the alpha same-spin part runs block by block through the
+// list kernel of the unblocked sigma; the opposite-spin part is the pair form
+// (k_sym_opp_pair: one alpha string per workgroup, the row of sigma and the
+// class blocks of integrals in LDS), or the gather form (k_sym_opp) where that
+// does not fit in LDS.
 #include <algorithm>
 #include <cmath>
 #include <vector>
