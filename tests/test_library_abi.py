@@ -74,3 +74,13 @@ def test_null_context_calls_fail_cleanly():
     assert L.sbci_step(None, None, None) == sb.SBCI_EINVAL
     assert L.sbci_ndet(None) == -1
     assert L.sbci_destroy(None) == sb.SBCI_OK
+
+
+def test_symmetry_entry_points_reject_null_arguments():
+    I = make_integrals(4, 8, 0)
+    out = ctypes.c_void_p()
+    rc = sb.lib().sbci_create_sym(4, 2, 2, I.h1.ctypes.data, I.eri.ctypes.data, None, 0,
+                                  ctypes.byref(out))
+    assert rc == sb.SBCI_EINVAL and not out.value and b"orbsym" in sb.lib().sbci_last_error()
+    blocks = np.zeros(24, dtype=np.int64)
+    assert sb.lib().sbci_sym_blocks(None, blocks.ctypes.data) == sb.SBCI_EINVAL
