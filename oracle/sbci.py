@@ -78,6 +78,25 @@ class Result:
     converged: bool = True
 
 
+def restart_reason(alpha, t, b, dE, xn, dz, o: Options) -> str:
+    """Section S1.5: why the segment restarts after step t of root alpha, or "".
+
+    b = b_t, dE = |E_{t+1} - E_t|, xn = |x_{t+1}| (= |k_t|), dz = |z'_{t+1}|.
+    Tested in the paper's order: Eq. S62a (excited roots only: a stalled b
+    with a settled energy), Eq. S62b (the norm left [x_th1, x_th2]), Eq. S62c
+    (a large residual, not on a segment's first step), then max_cycle steps
+    in the segment.  Comparisons are strict."""
+    if alpha > 0 and abs(b) < o.b_th and dE < o.eps1:
+        return "S62a"
+    if xn < o.x_th1 or xn > o.x_th2:
+        return "S62b"
+    if dz > o.r1 and t > 0:
+        return "S62c"
+    if t + 1 == o.max_cycle:
+        return "max_cycle"
+    return ""
+
+
 def start_vectors(op, diag, n):
     """Section S1.1: n lowest diagonal determinants, H diagonalised in their span."""
     ndet = diag.shape[0]
@@ -266,12 +285,7 @@ def sbci1(op, diag, nroots, opts: Options | None = None, x0=None, record=True, p
                     conv = True
                     reason = "converged"
                 else:
-                    s62a = alpha > 0 and abs(b) < o.b_th and dE < o.eps1
-                    s62b = xn < o.x_th1 or xn > o.x_th2
-                    s62c = dz > o.r1 and t > 0
-                    cap = t + 1 == o.max_cycle
-                    reason = ("S62a" if s62a else "S62b" if s62b else "S62c" if s62c
-                              else "max_cycle" if cap else "")
+                    reason = restart_reason(alpha, t, b, dE, xn, dz, o)
                 if record:
                     steps.append(StepRecord(alpha, seg, t, Enew, dE, dz, b, c, xn, reason))
                 E = Enew

@@ -74,6 +74,12 @@ class PairStep:
     dE: float
     dz: float
     reason: str
+    # the step's B_t diagonal and |k| (= |x_{t+1}|) of both states (NaN for
+    # a coefficient restart), recorded for the Section S2.5 tests
+    b00: float = float("nan")
+    b11: float = float("nan")
+    kn0: float = float("nan")
+    kn1: float = float("nan")
 
 
 def canonical_ritz(Smat, Hmat, lindep):
@@ -124,6 +130,30 @@ def coefficients_next(Vp, lindep):
         return None
     C = -np.linalg.solve(M, R)                     # S121
     return dict(k=(k0, k1), A=np.array([[0.0, a01], [a10, 0.0]]), B=B, C=C)
+
+
+def restart_reason_before_update(B, dE, kn, o: Options2) -> str:
+    """Section S2.5, the conditions fixed by the step's coefficients.
+
+    B: the 2x2 B_t of the step, dE = |E_{t+1}^alpha - E_t^alpha|, kn: the two
+    norms |x_{t+1}^alpha|, |x_{t+1}^alpha+1| (= |k|).  Eq. S130a: either
+    diagonal entry of B below b_th while state alpha's energy has settled;
+    Eq. S130b: either norm outside [x_th1, x_th2].  Strict comparisons."""
+    if (abs(B[0, 0]) < o.b_th or abs(B[1, 1]) < o.b_th) and dE < o.eps1:
+        return "S130a"
+    if (kn[0] < o.x_th1 or kn[1] < o.x_th1 or kn[0] > o.x_th2 or kn[1] > o.x_th2):
+        return "S130b"
+    return ""
+
+
+def restart_reason_after_update(t, dz, o: Options2) -> str:
+    """Section S2.5 after the update: Eq. S130c (|z'^alpha_{t+1}| above r1,
+    not on a segment's first step), then max_cycle (10) steps in the segment."""
+    if dz > o.r1 and t > 0:
+        return "S130c"
+    if t + 1 == o.max_cycle2:
+        return "max_cycle"
+    return ""
 
 
 @dataclass
@@ -234,9 +264,8 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                 # updated vectors are k times the two lowest Ritz vectors, which
                 # are orthonormal in the overlap metric, so |x_{t+1}| = |k|
                 kn = np.abs(np.array(cf["k"], dtype=float))
-                s130a = (abs(B[0, 0]) < o.b_th or abs(B[1, 1]) < o.b_th) and dE < o.eps1
-                s130b = (kn < o.x_th1).any() or (kn > o.x_th2).any()
-                if s130a or s130b:
+                early = restart_reason_before_update(B, dE, kn, o)
+                if early:
                     # restart (Section S2.5): x_{t+1}/|x_{t+1}| are the Ritz vectors
                     # themselves; take them from the basis, since the update
                     # reaches them through cancellation when |k| << 1
@@ -246,9 +275,10 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                     x, X = v / nv[:, None], V / nv[:, None]
                     dz = np.linalg.norm(X[0] - Enew[0] * x[0])
                     conv = dE < o.eps0 and dz < o.r0                              # S127
-                    reason = "converged" if conv else ("S130a" if s130a else "S130b")
+                    reason = "converged" if conv else early
                     if record:
-                        steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason))
+                        steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason,
+                                              B[0, 0], B[1, 1], kn[0], kn[1]))
                     E = Enew
                     if not conv:
                         seg += 1
@@ -273,11 +303,10 @@ def sbci2(op, diag, nroots, opts: Options2 | None = None, record=True):
                     conv = True
                     reason = "converged"
                 else:
-                    s130c = dz > o.r1 and t > 0
-                    cap = t + 1 == o.max_cycle2
-                    reason = "S130c" if s130c else "max_cycle" if cap else ""
+                    reason = restart_reason_after_update(t, dz, o)
                 if record:
-                    steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason))
+                    steps.append(PairStep(alpha, seg, t, Enew[0], Enew[1], dE, dz, reason,
+                                          B[0, 0], B[1, 1], kn[0], kn[1]))
                 E = Enew
                 if conv:
                     break
