@@ -147,9 +147,10 @@ int sbci_destroy(sbci_ctx *ctx);
 
 /* A context restricted to the determinants of one irreducible representation
  * of an abelian point group with irreps 0..7 multiplying by XOR (D2h and its
- * subgroups).  Every instance of the paper is solved inside one irrep
- * (Results, problem statement; the determinant counts of Section S3.1 are
- * per symmetry block).
+ * subgroups).  Every instance of the paper is solved inside one irrep (the
+ * IRep column of the Section S3.1 table); the determinant counts printed
+ * there are the full C(norb, nalpha) * C(norb, nbeta) products, not the
+ * size of that irrep's block.
  *   orbsym host [norb], irrep label 0..7 of each orbital;
  *   irrep  0..7, the irrep of the states sought.
  * A string's irrep is the XOR of its occupied orbitals' labels and |Ia, Ib>

@@ -17,10 +17,14 @@ Contents (each module cites the passage of the paper it follows):
                       application and the Slater-Condon rules; its diagonal D;
                       <S^2>.
 * ``sigma``        -- sigma = H c in the string basis, row by row from the
-                      Slater-Condon rules (plain C, ``csrc/sigma_ref.c``, with a
-                      NumPy fallback for tiny cases), plus sampled rows.
+                      Slater-Condon rules (plain C, ``csrc/sigma_ref.c``, built
+                      with gcc on first use), plus sampled rows.
 * ``sbci``         -- SBCI1 step by step (Algorithm 1 with Sections S1.1-S1.5)
                       and a block Davidson reference, both in FP64 NumPy.
+* ``sbci2``        -- SBCI2 step by step (Algorithm 2 with Sections S2.1-S2.5).
+* ``symmetry``     -- the irrep block layout of a point-group symmetric
+                      problem and the blocked sigma as the restriction of the
+                      full sigma.
 
 Pins: see ``tests/test_oracle_*.py``.  Functions whose results the paper does
 not fix and that no closed form or brute force checks are marked

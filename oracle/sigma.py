@@ -5,7 +5,7 @@ rules (see its header).  It is compiled with gcc by ``build()`` (called from
 ``__graft_entry__.build``) into ``oracle/liboracle_sigma.so``; nothing of the
 HIP library is involved.  Pins: equality with the two dense builders of
 ``hamiltonian`` on every size they reach, linearity, symmetry, transpose
-symmetry, and closed forms (tests/test_oracle_sigma.py).
+symmetry, and closed forms (tests/test_oracle_hamiltonian.py).
 """
 from __future__ import annotations
 

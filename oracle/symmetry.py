@@ -3,8 +3,9 @@ infrastructure, used only by the tests, the smoke check and the benchmark's
 CPU baseline).
 
 The paper solves each molecule inside one irreducible representation of its
-point group (Results, problem statement; the determinant counts of Section
-S3.1 are those of one symmetry block).  With an abelian group whose irreps
+point group (the IRep column of the Section S3.1 table; the determinant
+counts printed there are the full C(norb, na) * C(norb, nb) products, not
+the size of one irrep's block).  With an abelian group whose irreps
 are labelled 0..7 and multiply by XOR (D2h and its subgroups):
 
 * orbital p carries the irrep orbsym[p];

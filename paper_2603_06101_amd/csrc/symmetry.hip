@@ -1,8 +1,9 @@
 // Point-group symmetry blocking: sigma on the determinants of one irrep.
 //
 // Every molecule of the paper is solved inside one irreducible
-// representation of its point group (Results, problem statement; the
-// determinant counts of Section S3.1 are per symmetry block).  For an abelian
+// representation of its point group (the IRep column of the Section S3.1
+// table, whose determinant counts are the full C(norb, na) * C(norb, nb)
+// products, not the size of that irrep's block).  For an abelian
 // group with irreps 0..7 that multiply by XOR (D2h and its subgroups), a
 // string's irrep is the XOR of its occupied orbitals' irreps and |Ia, Ib> has
 // irrep irr(Ia) ^ irr(Ib).  Totally symmetric integrals make H block
