@@ -117,12 +117,25 @@ def test_solvers_reach_the_blocked_spectrum(n, na, nb, g):
     assert np.abs(np.sort(r2.energies) - w[:nroots]).max() < 1e-8
     rd = ctx.davidson(nroots, tol=1e-10)
     assert np.abs(np.sort(rd.energies) - w[:nroots]).max() < 1e-8
-    # The FP32 precision form is checked on the full-size block below, not on
-    # these few-hundred-determinant blocks: their lowest states lie within
-    # about 5e-5 Eh of single diagonal entries, and on two of them, (7, 3, 4,
-    # irrep 2) and (8, 4, 4, irrep 5), the FP32 form stopped with a non-finite
-    # reduction in some runs, depending on the rounding of the FP32 sigma (the
-    # FP64 solvers above never did).  Open until diagnosed.
+    ctx.close()
+
+
+@pytest.mark.skip(reason="FP32 precision form stopped with SBCI_ENUMERIC 'non-finite reduction in "
+                         "SBCI step' on (7, 3, 4, irrep 2) and (8, 4, 4, irrep 5); open until the "
+                         "restart paths are guarded")
+@pytest.mark.parametrize("n,na,nb,g", [(8, 4, 4, 0), (8, 4, 4, 5), (7, 3, 4, 2), (9, 4, 4, 1)])
+def test_fp32_form_reaches_the_blocked_spectrum(n, na, nb, g):
+    """The FP32 precision form (FP32 sigma and vectors, FP64 reductions and
+    refinement) on few-hundred-determinant blocks whose lowest states lie
+    within about 5e-5 Eh of single diagonal entries."""
+    ctx, I, o = _ctx(n, na, nb, g, seed=11)
+    idx, _ = SY.block_layout(n, na, nb, o, g)
+    Hd = H.dense_h_slater_condon(n, na, nb, I.h1, I.eri)[np.ix_(idx, idx)]
+    w = np.linalg.eigvalsh(Hd)
+    nroots = 3
+    rm = ctx.solve(nroots, tol=1e-10, opts=dict(precision="f32"))
+    assert rm.status == 0
+    assert np.abs(np.sort(rm.energies) - w[:nroots]).max() < 1e-8, (rm.energies, w[:nroots])
     ctx.close()
 
 
