@@ -128,7 +128,9 @@ typedef struct sbci_step_info {
   double seconds;             /* since the solve started                                */
   int reason;                 /* 0 none, 1 converged, 2 S62a, 3 S62b, 4 S62c,
                                  5 max_cycle, 6 rank guard, 7 coefficient guard,
-                                 8 switch to FP64 refinement                           */
+                                 8 hand-over to the next precision (FP64 refinement),
+                                 9 hand-over before a low-precision step whose new
+                                   iterate would have norm |k| < x_th1               */
 } sbci_step_info;
 
 void sbci_default_opts(sbci_opts *opt);

@@ -22,7 +22,7 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2, "orbital_windowed": 3}
 SAME_FORMS = {"auto": 0, "lists": 1, "dense": 2}
 REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
-           7: "coef", 8: "refine"}
+           7: "coef", 8: "refine", 9: "handover_k"}
 
 
 class SbciError(RuntimeError):

@@ -796,7 +796,21 @@ struct Solve {
     in2.p[0] = V(SXX);
     in2.p[1] = V(SYY);
     in2.p[2] = V(SZ);
+    // the Ritz vector goes to the free z slot; x and X stay intact until its
+    // norm is known to be usable
     wg_lincomb<T, NT>(I.ndet, V(SZB), in1, 0.0);
+    Pack<T> pv = pack<T>(1);
+    pv.p[0] = V(SZB);
+    wg_dots<T, NT>(I.ndet, V(SZB), pv, R);
+    const double nxx = R.out[0];
+    __syncthreads();
+    if (!(nxx > 0) || !isfinite(nxx)) {
+      if (C.phase == SBCI_BF16) return to_f32();
+      if (C.phase != SBCI_F64) return promote();
+      if (lane0()) C.status = SBCI_ENUMERIC;
+      __syncthreads();
+      return false;
+    }
     wg_lincomb<T, NT>(I.ndet, V(SYY), in2, 0.0);
     if (lane0()) {
       int *m = std::is_same<T, double>::value ? C.m64 : C.m32;
@@ -810,12 +824,6 @@ struct Solve {
       C.seg += 1;
       C.nrestarts += 1;
     }
-    __syncthreads();
-    const Vecs<T> V2 = vecs<T>(I, C);
-    Pack<T> p1 = pack<T>(1);
-    p1.p[0] = V2(SX);
-    wg_dots<T, NT>(I.ndet, V2(SX), p1, R);
-    const double nxx = R.out[0];
     __syncthreads();
     segment_start<T>(1.0 / sqrt(nxx));
     return true;
@@ -855,10 +863,16 @@ struct Solve {
       bool fin = true;
       for (int i = 0; i < 6; ++i) fin = fin && isfinite(N[i]) && isfinite(Hm[i]);
       // action: 0 update, 1 error, 2 finish (eigenvector at segment start),
-      // 3 promote, 4 new segment (rank), 5 restart from Ritz
+      // 3 promote, 4 new segment (rank), 5 restart from Ritz, 6 hand over to
+      // the next precision rung
       if (!fin) {
-        C.action = 1;
-        C.status = SBCI_ENUMERIC;
+        // a low-precision phase hands over (X = H x is recomputed from x)
+        if (C.phase != SBCI_F64) {
+          C.action = 6;
+        } else {
+          C.action = 1;
+          C.status = SBCI_ENUMERIC;
+        }
       } else {
         C.r = pod(C.seg_start ? ritz_first(N[0], N[2], N[5], Hm[0], Hm[2], Hm[5], P.lindep)
                               : ritz_next(N, Hm, P.lindep));
@@ -874,6 +888,13 @@ struct Solve {
               C.action = 1;
               C.status = SBCI_ENUMERIC;
             }
+          } else if (!(N[0] > 0)) {
+            if (C.phase != SBCI_F64) {
+              C.action = 6;
+            } else {
+              C.action = 1;
+              C.status = SBCI_ENUMERIC;
+            }
           } else {
             C.action = 4;
             C.nrestarts += 1;
@@ -882,6 +903,11 @@ struct Solve {
           }
         } else if (!C.r.coef_ok) {
           C.action = 5;
+        } else if (C.phase != SBCI_F64 && fabs(C.r.k) < P.x_th1) {
+          // |x_{t+1}| = |k_t|: the update would build x_{t+1} by heavy
+          // cancellation, which the low-precision images cannot follow; the
+          // phase hands over from the current, intact x
+          C.action = 6;
         } else {
           C.action = 0;
         }
@@ -901,6 +927,7 @@ struct Solve {
       return true;
     }
     if (act == 5) return restart_from_ritz<T>();
+    if (act == 6) return C.phase == SBCI_BF16 ? to_f32() : promote();
     const RitzS r = C.r;
     const double Enew = r.E[0];
     Upd a{};

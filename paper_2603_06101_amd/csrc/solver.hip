@@ -249,6 +249,8 @@ int to_f32(sbci_ctx *ctx, Solver &S) {
   double d[2];
   SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx->stream));
   SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  if (!(d[0] > 0) || !std::isfinite(d[0]) || !std::isfinite(d[1]))
+    return set_error(SBCI_ENUMERIC, "the BF16-phase iterate is not finite at the hand-over");
   S.E = d[1] / d[0];
   S.phase = SBCI_F32;
   const int steps = S.steps_root, seg = S.seg;
@@ -270,6 +272,8 @@ int promote(sbci_ctx *ctx, Solver &S) {
   double d[2];
   SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx->stream));
   SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  if (!(d[0] > 0) || !std::isfinite(d[0]) || !std::isfinite(d[1]))
+    return set_error(SBCI_ENUMERIC, "the low-precision iterate is not finite at the hand-over");
   S.E = d[1] / d[0];
   S.phase = SBCI_F64;
   int steps = S.steps_root;
@@ -278,6 +282,12 @@ int promote(sbci_ctx *ctx, Solver &S) {
   S.steps_root = steps;
   S.seg = seg + 1;
   return SBCI_OK;
+}
+
+// Hand-over from a low-precision phase to the next rung: BF16 -> FP32,
+// FP32 -> FP64.  Both recompute X = H x from x in the new precision.
+int next_rung(sbci_ctx *ctx, Solver &S) {
+  return S.phase == SBCI_BF16 ? to_f32(ctx, S) : promote(ctx, S);
 }
 
 // Finish root alpha in FP64 and prepare the next root's start vector from
@@ -336,7 +346,18 @@ int restart_from_ritz(sbci_ctx *ctx, Solver &S, const Ritz &r) {
   const T *in2[3] = {S.vec<T>(XX_), S.vec<T>(YY_), S.vec<T>(Z_)};
   // account for the pending scale of x
   cf[0] *= S.sx;
+  // the Ritz vector goes to the free z slot first; x and X stay intact until
+  // its norm is known to be usable
   SBCI_TRY(lincomb<T>(ctx, S.n, S.vec<T>(S.zn), in1, cf, 3, 0.0));
+  const T *vp[1] = {S.vec<T>(S.zn)};
+  SBCI_TRY(dots<T>(ctx, S.n, S.vec<T>(S.zn), vp, 1, S.red + 40));
+  double nxx;
+  SBCI_HIP(hipMemcpyAsync(&nxx, S.red + 40, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
+  if (!(nxx > 0) || !std::isfinite(nxx)) {
+    if (S.phase != SBCI_F64) return next_rung(ctx, S);
+    return set_error(SBCI_ENUMERIC, "SBCI: the Ritz vector of a restart vanished");
+  }
   SBCI_TRY(lincomb<T>(ctx, S.n, S.vec<T>(YY_), in2, cf, 3, 0.0));
   if (std::is_same<T, double>::value) {
     std::swap(S.v64[X_], S.v64[S.zn]);
@@ -348,11 +369,6 @@ int restart_from_ritz(sbci_ctx *ctx, Solver &S, const Ritz &r) {
   S.E = r.E[0];
   S.seg += 1;
   S.rep.nrestarts += 1;
-  const T *xp[1] = {S.vec<T>(X_)};
-  SBCI_TRY(dots<T>(ctx, S.n, S.vec<T>(X_), xp, 1, S.red + 40));
-  double nxx;
-  SBCI_HIP(hipMemcpyAsync(&nxx, S.red + 40, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  SBCI_HIP(hipStreamSynchronize(ctx->stream));
   return segment_start<T>(ctx, S, 1.0 / std::sqrt(nxx));
 }
 
@@ -386,9 +402,14 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
   Hm[2] = sx * S.h3[0];
   Hm[4] = S.h3[1];
   Hm[5] = S.h3[2];
-  for (int i = 0; i < 6; ++i)
-    if (!std::isfinite(N[i]) || !std::isfinite(Hm[i]))
-      return set_error(SBCI_ENUMERIC, "non-finite reduction in SBCI step");
+  bool finite = true;
+  for (int i = 0; i < 6; ++i) finite = finite && std::isfinite(N[i]) && std::isfinite(Hm[i]);
+  if (!finite) {
+    // a low-precision phase hands over (the next rung recomputes X = H x
+    // from x); in FP64 there is nothing to fall back to
+    if (S.phase != SBCI_F64) return next_rung(ctx, S);
+    return set_error(SBCI_ENUMERIC, "non-finite reduction in SBCI step");
+  }
   Ritz r = S.seg_start ? ritz_first(N[0], N[2], N[5], Hm[0], Hm[2], Hm[5], S.o.lindep)
                        : ritz_next(N, Hm, S.o.lindep);
   if (!r.rank_ok) {
@@ -405,6 +426,10 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
       if (S.phase != SBCI_F64) return promote(ctx, S);
       return set_error(SBCI_ENUMERIC, "SBCI: residual direction parallel to x at a segment start");
     }
+    if (!(N[0] > 0)) {
+      if (S.phase != SBCI_F64) return next_rung(ctx, S);
+      return set_error(SBCI_ENUMERIC, "SBCI: x vanished at a rank restart");
+    }
     record(ctx, S, S.E, NAN, NAN, NAN, NAN, NAN, std::sqrt(N[0]), 6);
     S.rep.nrestarts += 1;
     S.seg += 1;
@@ -415,6 +440,18 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
     record(ctx, S, r.E[0], NAN, NAN, NAN, NAN, NAN, NAN, 7);
     if (info) *info = ctx->trace.empty() ? sbci_step_info{} : ctx->trace.back();
     return restart_from_ritz<T>(ctx, S, r);
+  }
+  if (S.phase != SBCI_F64 && std::fabs(r.k) < S.o.x_th1) {
+    // |x_{t+1}| = |k_t| (the Ritz vector has unit norm and x_{t+1} is it
+    // divided by its x coefficient), so the update would build x_{t+1} by
+    // heavy cancellation.  In a low-precision phase the carried images then
+    // no longer match H x to the accuracy the small problem needs (its
+    // lowest value can fall below the spectrum and the iterate runs away to
+    // overflow), so the step is not taken: the phase hands over from the
+    // current x, which is still intact.
+    record(ctx, S, r.E[0], NAN, NAN, r.b, r.c, r.k, std::fabs(r.k), 9);
+    if (info) *info = ctx->trace.empty() ? sbci_step_info{} : ctx->trace.back();
+    return next_rung(ctx, S);
   }
   const double Enew = r.E[0];
   UpdateArgs a{};
@@ -473,7 +510,7 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
   if (info) *info = ctx->trace.empty() ? sbci_step_info{} : ctx->trace.back();
   S.E = Enew;
   if (conv) return finish_root(ctx, S, xn, true);
-  if (promote_now) return S.phase == SBCI_BF16 ? to_f32(ctx, S) : promote(ctx, S);
+  if (promote_now) return next_rung(ctx, S);
   if (S.steps_root >= S.o.max_steps) {
     S.any_noconv = true;
     if (low) return promote(ctx, S);
@@ -1379,6 +1416,17 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
                           dE < S.o.eps1;                                          // S130a
           const bool b_ = kn[0] < S.o.x_th1 || kn[1] < S.o.x_th1 || kn[0] > S.o.x_th2 ||
                           kn[1] > S.o.x_th2;                                      // S130b
+          if (phase != SBCI_F64 && (kn[0] < S.o.x_th1 || kn[1] < S.o.x_th1)) {
+            // a low-precision phase hands over from the current pair instead:
+            // its Ritz problem carries the low-precision images' error,
+            // amplified by the near-dependence that makes |k| small
+            record_pair(ctx, S, seg, t, Enew[0], dE, NAN, &cf, kn[0], 9);
+            SBCI_TRY(next_phase());  // normalises x, recomputes X and E
+            inv[0] = inv[1] = 1.0;
+            xn[0] = xn[1] = 1.0;
+            seg += 1;
+            break;
+          }
           if (a_ || b_) {
             for (int i = 0; i < 2; ++i) {
               double c1[6];
