@@ -205,6 +205,20 @@ int sbci_hdiag(sbci_ctx *ctx, double *dev_out);
  * overlap.  Asynchronous on the context stream. */
 int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype);
 
+/* sbci_sigma for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result, with the beta part's transposed operand and result in a
+ * 64 MiB device array inside the library (one per device, held until the
+ * process ends) instead of workspaces allocated on first use.  This call
+ * makes no hipMalloc, hipFree or other allocating call.  Limits, refused
+ * with SBCI_EINVAL before any launch: dtype SBCI_F64 or SBCI_F32;
+ * nvec * N_det * element size at most 32 MiB; the list same-spin form and
+ * the pair opposite-spin form (no dense or orbital forms, whose operands are
+ * built on first use); no symmetry blocking.  Every call on a device shares
+ * that device's array: calls that overlap on one device (several contexts or
+ * streams at once) race.  Asynchronous on the context stream. */
+int sbci_sigma_noalloc(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype);
+
 /* The same sigma, synchronously, with HIP events recorded on the context
  * stream around its five kernels; ms_parts (host [5]) receives the elapsed
  * milliseconds of: same-spin alpha lists, opposite-spin MFMA contraction,

@@ -122,6 +122,7 @@ SIGNATURES = [
     ("sbci_tables", _I, [_P, _I, _P, ctypes.POINTER(_I64)]),
     ("sbci_hdiag", _I, [_P, _P]),
     ("sbci_sigma", _I, [_P, _P, _P, _I, _I]),
+    ("sbci_sigma_noalloc", _I, [_P, _P, _P, _I, _I]),
     ("sbci_sigma_timed", _I, [_P, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
     ("sbci_set_opp_form", _I, [_P, _I]),
     ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),

@@ -250,6 +250,18 @@ int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int 
   return sigma(ctx, dev_c, dev_sigma, nvec, dtype);
 }
 
+int sbci_sigma_noalloc(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype) {
+  if (!ctx || !dev_c || !dev_sigma) return set_error(SBCI_EINVAL, "NULL argument");
+  if (nvec < 1 || nvec > 65535) return set_error(SBCI_EINVAL, "nvec must be in [1, 65535]");
+  if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
+    return set_error(SBCI_EINVAL, "unknown dtype");
+  const size_t es = dtype == SBCI_F64 ? 8 : 4;
+  const char *a = static_cast<const char *>(dev_c), *b = static_cast<const char *>(dev_sigma);
+  const size_t span = es * (size_t)ctx->ndet * nvec;
+  if (a < b + span && b < a + span) return set_error(SBCI_EINVAL, "c and sigma overlap");
+  return sigma_noalloc(ctx, dev_c, dev_sigma, nvec, dtype);
+}
+
 int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype,
                      float *ms_parts) {
   if (!ms_parts) return set_error(SBCI_EINVAL, "ms_parts is NULL");

@@ -207,6 +207,13 @@ void free_tables(sbci_ctx *ctx);
 // sigma = H c for nvec vectors of element type T (double or float).
 // mode: SBCI_F64 (T = double), SBCI_F32 or SBCI_BF16 (T = float).
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
+// The same sigma with its scratch in a file-scope device array instead of
+// allocated workspaces (no hipMalloc / hipFree): FP64 or FP32, list
+// same-spin and pair opposite-spin forms, nvec * ndet * element size at most
+// kNoAllocScratchBytes / 2; calls that overlap on one device race.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+int sigma_noalloc(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode);
 // dst[r][q] += sum_e fval[r][e] src[fcol[r][e]][q] for one R x C matrix (one
 // vector) with the L2-streaming list kernel; FP64 or FP32 (mode).
 int same_lists_block(sbci_ctx *ctx, const int32_t *fcol, const void *fval, int nf, int64_t R,

@@ -23,6 +23,8 @@
 #include "internal.h"
 #include "mfma.h"
 
+#include <mutex>
+
 namespace sbci {
 
 namespace {
@@ -1322,8 +1324,12 @@ int launch_gemm(sbci_ctx *ctx, int64_t Mr, int64_t N, int64_t K, const T *A, int
   return SBCI_OK;
 }
 
+// ct_fixed / st_fixed: caller-provided scratch for the beta part's transposed
+// operand and result (each nvec * ndet elements); nullptr takes the
+// context's workspaces, allocated on first use.
 template <typename T, typename M>
-int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullptr) {
+int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullptr,
+            T *ct_fixed = nullptr, T *st_fixed = nullptr) {
   SpinTables &A = ctx->A, &B = ctx->B;
   const int64_t na = A.ns, nb = B.ns, nd = ctx->ndet;
   const bool dbl = std::is_same<T, double>::value;
@@ -1387,11 +1393,14 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
     return SBCI_OK;
   }
   // beta part on C^T, added back transposed
-  const size_t vbytes = sizeof(T) * (size_t)nd * nvec;
-  SBCI_TRY(ensure(ctx->ws_t, vbytes));
-  SBCI_TRY(ensure(ctx->ws_s, vbytes));
-  T *ct = static_cast<T *>(ctx->ws_t.ptr);
-  T *st = static_cast<T *>(ctx->ws_s.ptr);
+  T *ct = ct_fixed, *st = st_fixed;
+  if (!ct || !st) {
+    const size_t vbytes = sizeof(T) * (size_t)nd * nvec;
+    SBCI_TRY(ensure(ctx->ws_t, vbytes));
+    SBCI_TRY(ensure(ctx->ws_s, vbytes));
+    ct = static_cast<T *>(ctx->ws_t.ptr);
+    st = static_cast<T *>(ctx->ws_s.ptr);
+  }
   SBCI_TRY(launch_transpose<T>(ctx, c, ct, na, nb, nvec, false));
   SBCI_TRY(rec(ctx, pe, 3));
   if (dbl)
@@ -1427,6 +1436,74 @@ int sigma_dispatch(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, 
 
 int sigma(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
   return sigma_dispatch(ctx, c, out, nvec, mode, nullptr);
+}
+
+}  // namespace sbci
+
+// Scratch of the allocation-free sigma: the beta part's transposed operand
+// and result.  Each device that loads the library holds one copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for that device.
+static __device__ __align__(256) unsigned char scratch[sbci::kNoAllocScratchBytes];
+
+namespace sbci {
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+int scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices)
+    return set_error(SBCI_EDEVICE, "allocation-free sigma: device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    SBCI_HIP(hipGetDevice(&cur));
+    if (cur != device) SBCI_HIP(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) SBCI_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return set_error(SBCI_EDEVICE, std::string("allocation-free sigma: hipGetSymbolAddress: ") +
+                                         hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return SBCI_OK;
+}
+}  // namespace
+
+int sigma_noalloc(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
+  if (ctx->sym)
+    return set_error(SBCI_EINVAL, "allocation-free sigma: symmetry-blocked contexts are not supported");
+  if (mode != SBCI_F64 && mode != SBCI_F32)
+    return set_error(SBCI_EINVAL, "allocation-free sigma: FP64 or FP32 only (the BF16 form builds "
+                                  "its operand copies on first use)");
+  if (use_dense(ctx, ctx->A) || use_dense(ctx, ctx->B))
+    return set_error(SBCI_EINVAL, "allocation-free sigma: the dense same-spin form is not "
+                                  "supported (its operator is built on first use)");
+  int form = 0;
+  SBCI_TRY(opp_form(ctx, mode, &form));
+  if (form != SBCI_OPP_PAIR)
+    return set_error(SBCI_EINVAL, "allocation-free sigma: only the pair opposite-spin form is "
+                                  "supported (the orbital form stages a copy of c)");
+  const size_t es = mode == SBCI_F64 ? 8 : 4;
+  const size_t half = (es * (size_t)ctx->ndet * (size_t)nvec + 255) / 256 * 256;
+  if (half > kNoAllocScratchBytes / 2)
+    return set_error(SBCI_EINVAL, "allocation-free sigma: nvec * ndet * element size must be at "
+                                  "most 32 MiB (the scratch holds two such operands in 64 MiB)");
+  void *p = nullptr;
+  SBCI_TRY(scratch_address(ctx->device, &p));
+  unsigned char *base = static_cast<unsigned char *>(p);
+  if (mode == SBCI_F64)
+    return sigma_t<double, MF64>(ctx, static_cast<const double *>(c), static_cast<double *>(out),
+                                 nvec, nullptr, reinterpret_cast<double *>(base),
+                                 reinterpret_cast<double *>(base + half));
+  return sigma_t<float, MF32>(ctx, static_cast<const float *>(c), static_cast<float *>(out), nvec,
+                              nullptr, reinterpret_cast<float *>(base),
+                              reinterpret_cast<float *>(base + half));
 }
 
 int same_lists_block(sbci_ctx *ctx, const int32_t *fcol, const void *fval, int nf, int64_t R,
