@@ -64,6 +64,18 @@ struct SpinTables {
   int32_t *fcolT = nullptr;
   double *fvalT64 = nullptr;
   float *fvalT32 = nullptr;
+  // block-binned lists of the LDS-blocked same-spin kernel (ns above the
+  // LDS-stripe range), built on first use: source rows in blocks of
+  // kSameBlkRows; for 64-row group g and block b, slots boff[g*nblk + b] ..
+  // boff[g*nblk + b + 1] - 1 hold one entry per row (lane) of the group:
+  // bcol = column - b * kSameBlkRows (16 bits), values in FP64 and FP32;
+  // rows with fewer entries in the block are padded with column 0, value 0.
+  int nblk = 0;
+  int64_t ngrp = 0;
+  int32_t *boff = nullptr;     // [ngrp * nblk + 1]
+  uint16_t *bcol = nullptr;    // [slots][64]
+  double *bval64 = nullptr;    // [slots][64]
+  float *bval32 = nullptr;     // [slots][64]
   // dense same-spin operator [ns][ns] (one-electron and same-spin parts),
   // built on first use by the dense form
   double *hd64 = nullptr;
@@ -80,6 +92,11 @@ struct SpinTables {
 // below ~1024 rows the register-streaming kernel is already latency-bound.
 constexpr int64_t kSameLdsMinRows = 1024;
 constexpr int64_t kSameLdsMaxRows = 3840;
+// LDS-blocked same-spin kernel above that range: source rows pass through
+// LDS in blocks of kSameBlkRows rows x 64 bytes (8 FP64 or 16 FP32 columns,
+// 128 KB); up to kSameBlkMaxBlocks blocks (block-local columns fit 16 bits).
+constexpr int kSameBlkRows = 2048;
+constexpr int kSameBlkMaxBlocks = 64;
 // Dense same-spin form: chosen automatically above the LDS range when the
 // lists hold at least a tenth of a row (there the MFMA product's extra flops
 // cost less than streaming 8 bytes of source per list entry from L2); the
@@ -201,6 +218,9 @@ int sym_blocks(const sbci_ctx *ctx, int64_t *out);
 
 // ---- tables.hip ----
 int build_tables(sbci_ctx *ctx, const double *h1_host, const double *eri_host);
+// block-binned same-spin lists of one spin (fields nblk .. bval32), from its
+// row lists; allocates on the context stream
+int build_blk_lists(sbci_ctx *ctx, SpinTables &T);
 void free_tables(sbci_ctx *ctx);
 
 // ---- sigma.hip ----

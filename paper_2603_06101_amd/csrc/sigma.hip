@@ -1108,6 +1108,132 @@ int launch_same_lds(sbci_ctx *ctx, const SpinTables &S, const V *fvalT, int64_t 
   return SBCI_OK;
 }
 
+// Same-spin part above the LDS-stripe range: the stripe of 64-byte source
+// rows (8 FP64 or 16 FP32 columns) no longer fits in LDS whole, so it passes
+// through LDS in blocks of rb rows.  One workgroup (16 waves) per (row panel,
+// stripe); wave w owns the 64-row groups w, w + 16, ... of its panel (RPT of
+// them, lane = row) and keeps their WC accumulators in registers across the
+// blocks.  For each block the workgroup stages the block's stripe, then each
+// wave walks its groups' block-binned lists: one 2-byte block-local column
+// and one value per lane per slot, coalesced, and four 16-byte LDS reads.
+// The 16-byte chunks of row j sit at chunk ^ ((j >> 2) & 3), so the reads of
+// 16 random rows spread over all LDS banks.  Work items are numbered
+// row-panel-major and dealt to the XCDs in contiguous ranges: the workgroups
+// of one XCD sweep the same panel's lists together.
+template <typename T, typename V, int RPT>
+__global__ __launch_bounds__(1024) void k_same_blk(
+    const uint16_t *__restrict__ bcol, const V *__restrict__ bval, const int32_t *__restrict__ boff,
+    int nblk, int rb, int64_t R, int64_t C, const T *__restrict__ src, T *__restrict__ dst,
+    int64_t nstripes, int64_t ngrp, int64_t per_xcd, int64_t total) {
+  constexpr int WC = 64 / sizeof(T);   // columns of a stripe
+  constexpr int CE = 16 / sizeof(T);   // elements of a 16-byte chunk
+  constexpr int NW = 16;               // waves per workgroup
+  using T16 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T16 *L = reinterpret_cast<T16 *>(smem);  // [rb][4] chunks, swizzled
+  const int64_t b = blockIdx.x;
+  const int64_t w = (b & 7) * per_xcd + (b >> 3);
+  if (w >= total) return;
+  const int64_t panel = w / nstripes, stripe = w - panel * nstripes;
+  const int64_t vo = (int64_t)blockIdx.z * R * C;
+  const int64_t c0 = stripe * WC;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g0 = panel * NW * RPT;
+  T acc[RPT][WC];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+#pragma unroll
+    for (int u = 0; u < WC; ++u) acc[k][u] = 0;
+  const bool full = c0 + WC <= C;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int64_t j0 = (int64_t)blk * rb;
+    const int rows = (int)(R - j0 < rb ? R - j0 : rb);
+    __syncthreads();  // the previous block's readers are done
+    for (int e = threadIdx.x; e < rows * 4; e += 1024) {
+      const int j = e >> 2, q = e & 3;
+      const T *g = src + vo + (j0 + j) * C + c0 + q * CE;
+      T16 v;
+      T *pv = reinterpret_cast<T *>(&v);
+      if (full) {
+#pragma unroll
+        for (int u = 0; u < CE; ++u) pv[u] = g[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < CE; ++u) pv[u] = c0 + q * CE + u < C ? g[u] : (T)0;
+      }
+      L[j * 4 + (q ^ ((j >> 2) & 3))] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int64_t grp = g0 + wave + NW * k;
+      if (grp < ngrp) {
+        const int s0 = boff[grp * nblk + blk], s1 = boff[grp * nblk + blk + 1];
+        auto apply = [&](int j, T v) {
+          const int sw = (j >> 2) & 3;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const T16 x = L[j * 4 + (q ^ sw)];
+            const T *px = reinterpret_cast<const T *>(&x);
+#pragma unroll
+            for (int u = 0; u < CE; ++u) acc[k][q * CE + u] += v * px[u];
+          }
+        };
+        constexpr int UN = sizeof(T) == 8 ? 4 : 8;
+        int sl = s0;
+        for (; sl + UN <= s1; sl += UN) {
+          int j[UN];
+          T v[UN];
+#pragma unroll
+          for (int i = 0; i < UN; ++i) {
+            j[i] = bcol[(int64_t)(sl + i) * 64 + lane];
+            v[i] = (T)bval[(int64_t)(sl + i) * 64 + lane];
+          }
+#pragma unroll
+          for (int i = 0; i < UN; ++i) apply(j[i], v[i]);
+        }
+        for (; sl < s1; ++sl) apply(bcol[(int64_t)sl * 64 + lane], (T)bval[(int64_t)sl * 64 + lane]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int64_t I = (g0 + wave + NW * k) * 64 + lane;
+    if (I < R) {
+      T *d = dst + vo + I * C + c0;
+#pragma unroll
+      for (int u = 0; u < WC; ++u)
+        if (c0 + u < C) d[u] = acc[k][u];
+    }
+  }
+}
+
+template <typename T, typename V>
+int launch_same_blk(sbci_ctx *ctx, const SpinTables &S, const V *bval, int64_t R, int64_t C,
+                    const T *src, T *dst, int nvec) {
+  constexpr int RPT = 4, NW = 16, WC = 64 / sizeof(T);
+  const size_t lds = (size_t)kSameBlkRows * 64;
+  static bool attr = false;
+  if (!attr) {
+    SBCI_HIP(hipFuncSetAttribute((const void *)k_same_blk<T, V, RPT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const int64_t nstripes = (C + WC - 1) / WC;
+  const int64_t rows_per_panel = (int64_t)NW * RPT * 64;
+  const int64_t npanels = (R + rows_per_panel - 1) / rows_per_panel;
+  const int64_t total = npanels * nstripes;
+  const int64_t per_xcd = (total + 7) / 8;
+  if (per_xcd * 8 >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "same-spin sigma: grid too large");
+  dim3 grid((unsigned)(per_xcd * 8), 1, (unsigned)nvec);
+  k_same_blk<T, V, RPT><<<grid, 1024, lds, ctx->stream>>>(S.bcol, bval, S.boff, S.nblk,
+                                                         kSameBlkRows, R, C, src, dst, nstripes,
+                                                         S.ngrp, per_xcd, total);
+  SBCI_CHECK_LAUNCH();
+  return SBCI_OK;
+}
+
 template <typename T, typename V, int VC>
 void launch_same_vc(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, int64_t C,
                     const T *src, T *dst, int nvec, int accumulate) {
@@ -1129,6 +1255,12 @@ int launch_same(sbci_ctx *ctx, const SpinTables &S, const V *fval, int64_t R, in
       return launch_same_lds<T, V>(ctx, S, S.fvalT64, R, C, src, dst, nvec);
     else
       return launch_same_lds<T, V>(ctx, S, S.fvalT32, R, C, src, dst, nvec);
+  }
+  if (!accumulate && S.bcol && R > kSameLdsMaxRows && R == S.ns) {
+    if constexpr (std::is_same<V, double>::value)
+      return launch_same_blk<T, V>(ctx, S, S.bval64, R, C, src, dst, nvec);
+    else
+      return launch_same_blk<T, V>(ctx, S, S.bval32, R, C, src, dst, nvec);
   }
   // widest column tile whose source rows (R x 64 VC elements) stay within
   // about half of one XCD's 4 MB L2
@@ -1306,6 +1438,28 @@ int dense_same(sbci_ctx *ctx, SpinTables &S, const T **out) {
   return SBCI_OK;
 }
 
+// The block-binned lists of a spin above the LDS-stripe range, built on
+// first use (in the owner of shared tables).  Without permission to
+// allocate, a spin whose lists are not built yet keeps the L2-streaming
+// kernel.
+int prepare_blk(sbci_ctx *ctx, SpinTables &S, bool may_alloc) {
+  SpinTables &O = S.shared ? ctx->A : S;
+  if (O.ns <= kSameLdsMaxRows || O.nf < 1) return SBCI_OK;
+  if (!O.bcol) {
+    if (!may_alloc) return SBCI_OK;
+    SBCI_TRY(build_blk_lists(ctx, O));
+  }
+  if (&O != &S) {
+    S.nblk = O.nblk;
+    S.ngrp = O.ngrp;
+    S.boff = O.boff;
+    S.bcol = O.bcol;
+    S.bval64 = O.bval64;
+    S.bval32 = O.bval32;
+  }
+  return SBCI_OK;
+}
+
 template <typename T>
 int launch_gemm(sbci_ctx *ctx, int64_t Mr, int64_t N, int64_t K, const T *A, int64_t lda,
                 int64_t sA, const T *B, int64_t ldb, int64_t sB, T *out, int64_t ldc, int64_t sC,
@@ -1336,6 +1490,9 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
   constexpr bool bf = std::is_same<M, MBF16>::value;
   const bool bfA = bf && use_dense_bf16(ctx, A), bfB = bf && use_dense_bf16(ctx, B);
   const bool denseA = !bfA && use_dense(ctx, A), denseB = !bfB && use_dense(ctx, B);
+  const bool may_alloc = !ct_fixed;
+  if (!bfA && !denseA) SBCI_TRY(prepare_blk(ctx, A, may_alloc));
+  if (!bfB && !denseB) SBCI_TRY(prepare_blk(ctx, B, may_alloc));
   // alpha part (plain write), then opposite-spin (accumulate)
   SBCI_TRY(rec(ctx, pe, 0));
   if constexpr (bf) {

@@ -194,6 +194,55 @@ __global__ void k_list_t(const T *__restrict__ src, T *__restrict__ dst, int64_t
   dst[f * ns + i] = src[e];
 }
 
+// Block-binned lists: per 64-row group (one wave, lane = row), the largest
+// number of entries any row of the group has in each source block.
+__global__ __launch_bounds__(64) void k_blk_count(const int32_t *__restrict__ fcol, int nf,
+                                                  int64_t ns, int nblk, int rb,
+                                                  int32_t *__restrict__ kmax) {
+  __shared__ int cnt[kSameBlkMaxBlocks][64];
+  const int lane = threadIdx.x;
+  const int64_t g = blockIdx.x, I = g * 64 + lane;
+  for (int b = 0; b < nblk; ++b) cnt[b][lane] = 0;
+  if (I < ns)
+    for (int e = 0; e < nf; ++e) cnt[fcol[I * nf + e] / rb][lane] += 1;
+  __syncthreads();
+  for (int b = lane; b < nblk; b += 64) {
+    int m = 0;
+    for (int l = 0; l < 64; ++l) m = max(m, cnt[b][l]);
+    kmax[g * nblk + b] = m;
+  }
+}
+
+// Fill the block-binned lists (entries in list order within each block),
+// then pad every row's block segment to the group's length.
+__global__ __launch_bounds__(64) void k_blk_fill(const int32_t *__restrict__ fcol,
+                                                 const double *__restrict__ f64,
+                                                 const float *__restrict__ f32, int nf, int64_t ns,
+                                                 int nblk, int rb, const int32_t *__restrict__ boff,
+                                                 uint16_t *__restrict__ bcol,
+                                                 double *__restrict__ b64, float *__restrict__ b32) {
+  __shared__ int cnt[kSameBlkMaxBlocks][64];
+  const int lane = threadIdx.x;
+  const int64_t g = blockIdx.x, I = g * 64 + lane;
+  for (int b = 0; b < nblk; ++b) cnt[b][lane] = 0;
+  if (I < ns)
+    for (int e = 0; e < nf; ++e) {
+      const int col = fcol[I * nf + e];
+      const int b = col / rb;
+      const int64_t slot = (int64_t)boff[g * nblk + b] + cnt[b][lane]++;
+      bcol[slot * 64 + lane] = (uint16_t)(col - b * rb);
+      b64[slot * 64 + lane] = f64[I * nf + e];
+      b32[slot * 64 + lane] = f32[I * nf + e];
+    }
+  for (int b = 0; b < nblk; ++b)
+    for (int64_t slot = (int64_t)boff[g * nblk + b] + cnt[b][lane]; slot < boff[g * nblk + b + 1];
+         ++slot) {
+      bcol[slot * 64 + lane] = 0;
+      b64[slot * 64 + lane] = 0.0;
+      b32[slot * 64 + lane] = 0.0f;
+    }
+}
+
 __device__ __forceinline__ double G4(const double *__restrict__ g, int n, int p, int q, int r, int s) {
   return g[((p * n + q) * n + r) * n + s];
 }
@@ -386,6 +435,52 @@ int build_spin(sbci_ctx *ctx, SpinTables &T, int m) {
   return SBCI_OK;
 }
 
+}  // namespace
+
+int build_blk_lists(sbci_ctx *ctx, SpinTables &T) {
+  if (T.bcol) return SBCI_OK;
+  const int rb = kSameBlkRows;
+  const int nblk = (int)((T.ns + rb - 1) / rb);
+  if (nblk > kSameBlkMaxBlocks || T.nf < 1)
+    return set_error(SBCI_EINVAL, "same-spin sigma: too many strings for the blocked LDS form");
+  const int64_t ngrp = (T.ns + 63) / 64;
+  hipStream_t st = ctx->stream;
+  int32_t *kmax = nullptr;
+  SBCI_HIP(hipMalloc(&kmax, sizeof(int32_t) * ngrp * nblk));
+  struct Free {
+    void *p;
+    ~Free() { hipFree(p); }
+  } guard{kmax};
+  k_blk_count<<<(unsigned)ngrp, 64, 0, st>>>(T.fcol, T.nf, T.ns, nblk, rb, kmax);
+  SBCI_CHECK_LAUNCH();
+  std::vector<int32_t> k((size_t)(ngrp * nblk)), off((size_t)(ngrp * nblk + 1));
+  SBCI_HIP(hipMemcpyAsync(k.data(), kmax, sizeof(int32_t) * k.size(), hipMemcpyDeviceToHost, st));
+  SBCI_HIP(hipStreamSynchronize(st));
+  int64_t acc = 0;
+  for (size_t i = 0; i < k.size(); ++i) {
+    off[i] = (int32_t)acc;
+    acc += k[i];
+  }
+  off[k.size()] = (int32_t)acc;
+  if (acc >= ((int64_t)1 << 31) / 64)
+    return set_error(SBCI_EINVAL, "same-spin sigma: blocked lists too large");
+  const int64_t slots = acc > 0 ? acc : 1;
+  SBCI_HIP(hipMalloc(&T.boff, sizeof(int32_t) * off.size()));
+  SBCI_HIP(hipMalloc(&T.bcol, sizeof(uint16_t) * slots * 64));
+  SBCI_HIP(hipMalloc(&T.bval64, sizeof(double) * slots * 64));
+  SBCI_HIP(hipMalloc(&T.bval32, sizeof(float) * slots * 64));
+  SBCI_HIP(hipMemcpyAsync(T.boff, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st));
+  k_blk_fill<<<(unsigned)ngrp, 64, 0, st>>>(T.fcol, T.fval64, T.fval32, T.nf, T.ns, nblk, rb, T.boff,
+                                           T.bcol, T.bval64, T.bval32);
+  SBCI_CHECK_LAUNCH();
+  SBCI_HIP(hipStreamSynchronize(st));  // off[] and kmax stay valid until here
+  T.nblk = nblk;
+  T.ngrp = ngrp;
+  return SBCI_OK;
+}
+
+namespace {
+
 void free_spin(SpinTables &T) {
   if (T.shared) {
     T = SpinTables();
@@ -410,6 +505,10 @@ void free_spin(SpinTables &T) {
   hipFree(T.fcolT);
   hipFree(T.fvalT64);
   hipFree(T.fvalT32);
+  hipFree(T.boff);
+  hipFree(T.bcol);
+  hipFree(T.bval64);
+  hipFree(T.bval32);
   T = SpinTables();
 }
 

@@ -48,10 +48,13 @@ def test_hdiag(n, na, nb):
 
 
 # (13, 5, 5) and (13, 6, 5): 1287 / 1716 strings per spin, the row range of
-# the LDS-staged same-spin kernel (both spins, square and rectangular C)
+# the LDS-staged same-spin kernel (both spins, square and rectangular C);
+# (15, 7, 2), (15, 2, 7) and (16, 8, 1): 6435 / 12870 strings in one spin,
+# the LDS-blocked kernel (4 and 7 source blocks, a partial last 64-row group,
+# stripes narrower than 8 columns at the end of a 105- or 16-column C)
 SIGMA_CASES = [(1, 1, 0), (2, 1, 1), (4, 0, 2), (4, 2, 2), (5, 5, 5), (5, 2, 3), (6, 3, 3),
                (7, 4, 2), (8, 4, 4), (9, 4, 5), (10, 5, 5), (11, 3, 4), (12, 6, 6), (13, 5, 5),
-               (13, 6, 5)]
+               (13, 6, 5), (15, 7, 2), (15, 2, 7), (16, 8, 1)]
 
 
 @pytest.mark.parametrize("n,na,nb", SIGMA_CASES)
@@ -67,7 +70,8 @@ def test_sigma_f64_parity(n, na, nb):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("bf16", 2e-2)])
-@pytest.mark.parametrize("n,na,nb", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (9, 4, 5), (13, 6, 5)])
+@pytest.mark.parametrize("n,na,nb", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (9, 4, 5), (13, 6, 5),
+                                     (15, 7, 2), (15, 2, 7)])
 def test_sigma_low_precision_error(n, na, nb, dtype, tol):
     ctx, I = _ctx(n, na, nb, seed=2)
     c = sigma_inputs(4, 1, ctx.ndet)
