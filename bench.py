@@ -1,35 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the SBCI sigma/solve hot path on one MI355X.
 
-One step = one pass of the whole path on the workload: build the context
-(strings, excitation and pair tables, same-spin lists, diagonal) from the
-integrals already on the host, then solve the lowest nroots states with
-SBCI1 in the precision form (low-precision sigma phase + FP64 refinement) to
-the paper's thresholds (eps0 = 1e-10, r0 = 1e-5), so every root is within
-1e-8 Eh of the FP64 solution.
+One step = one pass of the whole path on the workload, in the paper's
+precision: build the context (strings, excitation tables, same-spin lists,
+diagonal) from the integrals already on the host, then solve the lowest
+nroots states with FP64 SBCI1 to the paper's thresholds (eps0 = 1e-10,
+r0 = 1e-5), so every root is within 1e-8 Eh.  The default workload is
+CAS(16e,16o), 165,636,900 determinants, ground state.
 
 Reported (one JSON line):
-  value        sigma determinant-applications per second over the whole step
-               (sum over sigma calls of N_det, divided by the step time), Gdet/s;
-  ms_per_step  time to |dE| < 1e-8 for all roots (mixed form), including the
-               context build;
-  fp64         the same solve with FP64 sigma only (reference form), timed
-               once outside the timed region, and its agreement with the
-               mixed energies;
-  sigma        per-precision sigma throughput (Gdet/s per root) and the
-               per-kernel durations measured with HIP events on the
-               library's stream;
-  roofline     the dominant kernel of the step against the MI355X peak;
-  batch        the batching form on its own workload (512 instances of
-               CAS(6..10), 1-3 roots each): autotuned persistent-kernel
-               graph launch, makespan FP64 vs mixed, per-instance span;
-  cas6, cas10, cas16  the other workloads: launch latency (CAS(6,6)),
-               SBCI1 vs Davidson over 10 seeds (CAS(10,10)), and the
-               165.6 M-determinant ground state, mixed vs FP64 (CAS(16,16));
-  dilute45     CAS(6e,45o), 201.4 M determinants (few electrons in many
-               orbitals): sigma forms and rates, ground state mixed vs FP64;
-  cpu_baseline the CPU oracle's plain FP64 string sigma on the host cores,
-               on a bounded sample of determinant rows.
+  value          FP64 sigma determinant-applications per second over the
+                 whole timed step (N_det x sigma calls / step time), Gdet/s
+                 per root (one vector per sigma call);
+  ms_per_step    time of one step: FP64 time to |dE| < 1e-8 Eh;
+  time_to_1e8_s  FP64 (median of the timed steps) against the precision
+                 forms (BF16 ladder, FP32 ladder; median of 3 each, same step);
+  sigma          per-dtype sigma throughput and per-kernel durations, HIP
+                 events on the library's stream;
+  roofline       the step's dominant kernel against the MI355X peak;
+  roofline_same  the same-spin list kernel (ALU and LDS figures);
+  cas14          CAS(14e,14o), 5 roots: FP64, both precision forms and SBCI2,
+                 each root's energy against the oracle's (tests/golden);
+  batch, cas6, cas10, dilute45, symmetry   the other workloads;
+  cpu_baseline   the CPU oracle's FP64 string sigma on the host cores, on a
+                 bounded sample of determinant rows;
+  oracle_checks  from the same oracle rows: the GPU sigma's relative error per
+                 dtype, and the GPU ground state's residual on sampled rows.
 """
 from __future__ import annotations
 
@@ -43,17 +39,17 @@ from math import comb
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {  # MI355X published dense peaks
-    "f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
+PEAK = {  # MI355X published dense peaks; LDS: 128 B/clk/CU x 256 CUs x 2.4 GHz
+    "f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12, "lds": 78.6e12,
 }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cas14",
+    ap.add_argument("--workload", default="cas16",
                     choices=["cas6", "cas10", "cas14", "cas16", "dilute45", "cas14_sym", "cas16_sym"])
     ap.add_argument("--precision", default="bf16", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -105,6 +101,11 @@ def roofline(cfg, ndet, kname, kdt, k_ms):
         vpk = PEAK["f64"] if kdt == "f64" else PEAK["f32"]
         r = {"bound": "alu", "achieved": 2.0 * nf * ndet / t / 1e12, "peak": vpk / 1e12,
              "unit": "TFLOP/s"}
+        # the list kernels read one source element from LDS per list entry
+        # and column: nf * element bytes per determinant
+        r["lds_achieved_TBps"] = nf * esz * ndet / t / 1e12
+        r["lds_peak_TBps"] = PEAK["lds"] / 1e12
+        r["lds_frac"] = r["lds_achieved_TBps"] / r["lds_peak_TBps"]
     else:
         passes = 3.0 if kname == "add_t" else 2.0
         r = {"bound": "hbm", "achieved": passes * esz * ndet / t / 1e9, "peak": PEAK["hbm"] / 1e9,
@@ -202,10 +203,15 @@ def small_sections(sb, stream):
     us_sigma = (time.perf_counter() - t) / 200 * 1e6
     ctx.solve(1, tol=1e-10, x0=x0, want_vectors=False)
     r = ctx.solve(1, tol=1e-10, x0=x0, want_vectors=False)
+    ref = refs_section("cas6", I.digest())
     out["cas6"] = {"ndet": ctx.ndet, "us_per_sigma": round(us_sigma, 1),
                    "solve_ms": round(r.report["seconds"] * 1e3, 2), "steps": r.report["nsteps"],
                    "us_per_step": round(r.report["seconds"] / max(1, r.report["nsteps"]) * 1e6, 1),
-                   "energy": float(r.energies[0])}
+                   "energy": float(r.energies[0]),
+                   # the start e_0 + noise is spin-flip symmetric: SBCI1 reaches
+                   # the lowest singlet, which lies above a triplet here
+                   "oracle_sbci1_energy": (ref.get("sbci1") or [None])[0],
+                   "oracle_eigh_lowest": (ref.get("eigh") or [None])[0]}
     ctx.close()
     rows = []
     for seed in range(10):
@@ -543,27 +549,127 @@ def batch_section(sb, precision):
     return out
 
 
-def cpu_baseline(cfg, I, ndet, seconds):
+def refs_section(name, digest):
+    """Stored oracle values for a workload (tests/golden/refs.json, written by
+    tests/golden/make_refs.py from the oracle only), if their integral digest
+    matches; {} otherwise."""
+    path = os.path.join(ROOT, "tests", "golden", "refs.json")
+    try:
+        sec = json.load(open(path)).get(name, {})
+    except (OSError, ValueError):
+        return {}
+    return sec if sec.get("digest") == digest else {}
+
+
+def vs_oracle(energies, ref):
+    """|E - E_oracle| per root (both sorted ascending)."""
     import numpy as np
+    e, r = np.sort(np.asarray(energies)), np.sort(np.asarray(ref))
+    k = min(len(e), len(r))
+    return [float(v) for v in np.abs(e[:k] - r[:k])]
+
+
+def cas14_section(sb, stream, reps):
+    """cas14 (11,778,624 determinants), 5 roots: FP64 SBCI1 and both precision
+    forms (time to 1e-8 Eh, median of reps runs), SBCI2, and each root's
+    energy against the oracle's SBCI1 and eigsh values (tests/golden/refs.json)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from workloads import CONFIGS, make_integrals
+    cf = CONFIGS["cas14"]
+    I = make_integrals(cf["norb"], cf["rank"], cf["seed"])
+    ref = refs_section("cas14", I.digest())
+    ctx = sb.Context(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri, stream=stream)
+    out = {"ndet": ctx.ndet, "nroots": cf["nroots"], "forms": {}}
+    for name, fn in (
+            ("sbci1_f64", lambda: ctx.solve(cf["nroots"], tol=1e-10, opts=dict(precision="f64"),
+                                            want_vectors=False)),
+            ("sbci1_bf16_ladder", lambda: ctx.solve(cf["nroots"], tol=1e-10,
+                                                    opts=dict(precision="bf16"), want_vectors=False)),
+            ("sbci1_f32_ladder", lambda: ctx.solve(cf["nroots"], tol=1e-10,
+                                                   opts=dict(precision="f32"), want_vectors=False)),
+            ("sbci2_f64", lambda: ctx.solve2(cf["nroots"], tol=1e-10, want_vectors=False)),
+            ("sbci2_f32_ladder", lambda: ctx.solve2(cf["nroots"], tol=1e-10,
+                                                    opts=dict(precision="f32"), want_vectors=False))):
+        times, r = [], None
+        for _ in range(reps if name.startswith("sbci1") else 1):
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        sec = {"time_to_1e8_s": round(statistics.median(times), 4), "runs": len(times),
+               "nsigma": {"f64": r.report["nsigma_f64"], "low": r.report.get("nsigma_low", 0),
+                          "bf16": r.report.get("nsigma_bf16", 0)},
+               "energies": [float(e) for e in r.energies],
+               "residuals": [float(v) for v in r.report.get("resid", [])[:cf["nroots"]]]}
+        if ref.get("sbci1"):
+            sec["abs_dE_vs_oracle_sbci1"] = vs_oracle(r.energies, ref["sbci1"])
+        out["forms"][name] = sec
+    ctx.close()
+    if ref.get("eigsh"):
+        out["oracle_eigsh_lowest"] = ref["eigsh"][:cf["nroots"] + 1]
+    if ref.get("sbci1"):
+        out["oracle_sbci1"] = ref["sbci1"]
+    f = out["forms"]
+    out["speedup_vs_fp64"] = {k: round(f["sbci1_f64"]["time_to_1e8_s"] / f[k]["time_to_1e8_s"], 3)
+                              for k in ("sbci1_bf16_ladder", "sbci1_f32_ladder")}
+    return out
+
+
+def oracle_checks(cfg, I, ndet, sb, stream, seconds, xE=None):
+    """The CPU-baseline leg: the oracle's FP64 string sigma on a bounded sample
+    of determinant rows, timed on the host cores; the same oracle rows then
+    check the GPU sigma of that vector in each dtype (relative error on the
+    sample) and, if given, the GPU ground state (x, E): max |(H x)[J] - E x[J]|
+    over sampled rows J, against max |E x[J]|."""
+    import numpy as np
+    import torch
 
     from oracle import sigma as OS
     from workloads import sigma_inputs
     c = sigma_inputs(0, 1, ndet)[0]
     rng = np.random.default_rng(11)
-    n = 2000
-    rows = rng.integers(0, ndet, n)
+    # calibration: the rate of a 2000-row and a 50000-row call (the oracle
+    # lists every string's excitations once per call, a fixed cost)
+    ts = []
+    for n in (2000, 50000):
+        rows = rng.integers(0, ndet, n)
+        t = time.perf_counter()
+        OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
+        ts.append(time.perf_counter() - t)
+    per_row = max((ts[1] - ts[0]) / 48000, 1e-9)
+    n2 = int(max(2000, min(2e7, seconds / per_row)))
+    rows = np.sort(rng.integers(0, ndet, n2))
     t = time.perf_counter()
-    OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
-    dt = time.perf_counter() - t
-    n2 = int(max(2000, min(5e6, n * seconds / max(dt, 1e-6))))
-    rows = rng.integers(0, ndet, n2)
-    t = time.perf_counter()
-    OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
+    want = OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, c, rows)
     dt = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n2 / dt / 1e9, "unit": "Gdet/s", "cores": cores, "kind": "oracle",
+    base = {"value": n2 / dt / 1e9, "unit": "Gdet/s", "cores": cores, "kind": "oracle",
             "sample": f"{n2} random determinant rows of the FP64 string sigma "
                       f"({cfg['norb']} orbitals, {ndet} determinants), {dt:.1f} s"}
+    checks = {"rows": n2, "sigma_rel_err": {}}
+    ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+    cg = torch.from_numpy(c).cuda()
+    idx = torch.from_numpy(rows).cuda()
+    for dt_ in ("f64", "f32", "bf16"):
+        x = cg if dt_ == "f64" else cg.float()
+        got = ctx.sigma(x, dt_)[idx].double().cpu().numpy()
+        checks["sigma_rel_err"][dt_] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        del got, x
+    ctx.close()
+    del cg
+    if xE is not None:
+        x, E = xE
+        xr = x[idx].cpu().numpy()
+        hx = OS.sigma_rows(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, x.cpu().numpy(), rows)
+        checks["ground_state_residual"] = {"max_abs": float(np.abs(hx - E * xr).max()),
+                                           "scale_max_abs_Ex": float(np.abs(E * xr).max()),
+                                           "rows": n2}
+    torch.cuda.empty_cache()
+    return base, checks
 
 
 def main():
@@ -572,6 +678,8 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
+    import statistics
+
     import numpy as np
     import torch
 
@@ -637,50 +745,54 @@ def main():
         ctx.close()
         return
 
-    def step(prec):
-        ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
-        r = ctx.solve(nroots, tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+    # ---- the timed step: one FP64 SBCI1 solve (the paper's form), context
+    # build included, to |dE| < 1e-8 Eh for every root
+    def step(prec, want_vectors=False):
+        ctx = context()
+        r = ctx.solve(nroots, tol=1e-10, opts=dict(precision=prec), want_vectors=want_vectors)
         ctx.close()
         return r
 
     for _ in range(a.warmup):
-        step(a.precision)
+        step("f64")
     torch.cuda.synchronize()
+    times, res = [], []
     t0 = time.perf_counter()
-    res = [step(a.precision) for _ in range(a.steps)]
-    torch.cuda.synchronize()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        res.append(step("f64"))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
     t1 = time.perf_counter()
     ms = (t1 - t0) / a.steps * 1e3
     last = res[-1]
-    ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
+    ctx = context()
     ndet = ctx.ndet
-    nsig_f64 = sum(r.report["nsigma_f64"] for r in res) / a.steps
-    nsig_low = sum(r.report["nsigma_low"] for r in res) / a.steps
-    nsig_bf16 = sum(r.report["nsigma_bf16"] for r in res) / a.steps
-    value = ndet * (nsig_f64 + nsig_low) / (ms / 1e3) / 1e9
+    ctx.close()
+    nsig = sum(r.report["nsigma_f64"] for r in res) / a.steps
+    value = ndet * nsig / (ms / 1e3) / 1e9
 
-    # reference form: FP64 sigma throughout (outside the timed region)
-    t = time.perf_counter()
-    ref = ctx.solve(nroots, tol=1e-10, opts=dict(precision="f64"), want_vectors=False)
-    torch.cuda.synchronize()
-    t_f64 = time.perf_counter() - t
-    # SBCI2 (pairs of states, FP64), outside the timed region
-    t = time.perf_counter()
-    r2 = ctx.solve2(nroots, tol=1e-10, want_vectors=False)
-    torch.cuda.synchronize()
-    sbci2 = {"fp64_s": round(time.perf_counter() - t, 4), "nsigma": r2.report["nsigma_f64"],
-             "energies": [float(e) for e in r2.energies]}
-    t = time.perf_counter()
-    r2m = ctx.solve2(nroots, tol=1e-10, opts=dict(precision="f32"), want_vectors=False)
-    torch.cuda.synchronize()
-    sbci2["f32_ladder_s"] = round(time.perf_counter() - t, 4)
-    sbci2["f32_ladder_nsigma"] = {"f64": r2m.report["nsigma_f64"], "low": r2m.report["nsigma_low"]}
-    sbci2["f32_ladder_max_abs_dE"] = float(np.abs(np.sort(r2m.energies) - np.sort(r2.energies)).max())
-    dE = float(np.max(np.abs(np.sort(ref.energies) - np.sort(last.energies))))
+    # ---- outside the timed region: the precision forms (median of 3 solves
+    # each, context build included, like the timed step)
+    mixed = {}
+    for prec in ("bf16", "f32"):
+        tt, rr = [], None
+        for _ in range(3):
+            ts = time.perf_counter()
+            rr = step(prec)
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - ts)
+        mixed[prec] = {"time_to_1e8_s": round(statistics.median(tt), 4), "runs": 3,
+                       "nsigma": {"f64": rr.report["nsigma_f64"], "low": rr.report["nsigma_low"],
+                                  "bf16": rr.report["nsigma_bf16"]},
+                       "max_abs_dE_vs_fp64": float(np.abs(np.sort(rr.energies) -
+                                                          np.sort(last.energies)).max())}
+    t64 = statistics.median(times)
 
-    # sigma per precision, per kernel (HIP events on the library stream)
+    # ---- sigma per dtype, per kernel (HIP events on the library stream)
     parts = ["same_alpha", "opp_mfma", "transpose", "same_beta", "add_t"]
     sig = {}
+    ctx = context()
     c64 = torch.from_numpy(sigma_inputs(0, 1, ndet)[0]).cuda()
     for dt in ["f64", "f32", "bf16"]:
         c = c64 if dt == "f64" else c64.float()
@@ -689,15 +801,16 @@ def main():
         med = np.median(np.array(runs), axis=0)
         sig[dt] = {"gdet_per_s": ndet / (med.sum() / 1e3) / 1e9, "ms": float(med.sum()),
                    "kernels_ms": dict(zip(parts, [round(float(v), 4) for v in med]))}
-    del c64, out
+        del out, c
+    forms = {"same_spin": ctx.same_form(0), "opposite_spin": ctx.opp_form("f64")}
+    del c64
     ctx.close()
+    torch.cuda.empty_cache()
 
-    # dominant kernel of the step: sigma calls per dtype x per-kernel time
-    counts = {"f64": nsig_f64, "f32": nsig_low - nsig_bf16, "bf16": nsig_bf16}
-    share = {(p, dt): cnt * sig[dt]["kernels_ms"][p] for dt, cnt in counts.items() for p in parts
-             if cnt > 0}
-    (kname, kdt), _ = max(share.items(), key=lambda kv: kv[1])
+    # dominant kernel of the FP64 step: the largest per-kernel share of sigma
+    (kname, kdt) = max(((p, "f64") for p in parts), key=lambda k: sig["f64"]["kernels_ms"][k[0]])
     roof = roofline(cfg, ndet, kname, kdt, sig[kdt]["kernels_ms"][kname])
+    roof_same = roofline(cfg, ndet, "same_alpha", "f64", sig["f64"]["kernels_ms"]["same_alpha"])
 
     line = {
         "metric": "sigma=H.c Gdet/s per root; time to |dE|<1e-8 Eh, mixed vs FP64 SBCI",
@@ -710,30 +823,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16": "bf16+f32+f64"}[a.precision],
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "norb": cfg["norb"], "nalpha": cfg["na"],
                    "nbeta": cfg["nb"], "ndet": ndet, "nroots": nroots, "eri_rank": cfg["rank"],
-                   "seed": cfg["seed"], "precision": a.precision, "parallelism": "1 GPU"},
-        "time_to_1e8_s": {"mixed": round(ms / 1e3, 4), "fp64": round(t_f64, 4),
-                          "speedup": round(t_f64 / (ms / 1e3), 3),
-                          "fp64_nsigma": ref.report["nsigma_f64"]},
+                   "seed": cfg["seed"], "step": "context build + FP64 SBCI1 solve to 1e-8 Eh",
+                   "parallelism": "1 GPU"},
+        "time_to_1e8_s": {"fp64": round(t64, 4), "fp64_runs": a.steps,
+                          "fp64_min_max": [round(min(times), 4), round(max(times), 4)],
+                          "mixed_bf16": mixed["bf16"]["time_to_1e8_s"],
+                          "mixed_f32": mixed["f32"]["time_to_1e8_s"],
+                          "speedup_bf16": round(t64 / mixed["bf16"]["time_to_1e8_s"], 3),
+                          "speedup_f32": round(t64 / mixed["f32"]["time_to_1e8_s"], 3)},
+        "fp64_nsigma": nsig,
         "energies": [float(e) for e in last.energies],
-        "max_abs_dE_vs_fp64": dE,
-        "sbci2": sbci2,
-        "nsigma": {"f64": nsig_f64, "f32": nsig_low - nsig_bf16, "bf16": nsig_bf16},
+        "mixed": mixed,
+        "forms": forms,
         "sigma": sig,
         "roofline": roof,
+        "roofline_same": roof_same,
     }
+    if a.workload == "cas16" and not a.no_configs:
+        line["cas14"] = cas14_section(sb, stream, 3)
     if not a.no_batch:
         line["batch"] = batch_section(sb, a.precision)
     if not a.no_configs:
         line.update(small_sections(sb, stream))
-        line["cas16"] = cas16_section(sb, stream, a.precision)
+        if a.workload != "cas16":
+            line["cas16"] = cas16_section(sb, stream, a.precision)
         line["dilute45"] = dilute45_section(sb, stream, a.precision)
         line["symmetry"] = sym_section(sb, stream)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, I, ndet, a.cpu_seconds)
+        xE = None
+        if not a.no_configs:
+            r = step("f64", want_vectors=True)
+            xE = (r.vectors[0], float(r.energies[0]))
+        base, checks = oracle_checks(cfg, I, ndet, sb, stream, a.cpu_seconds, xE)
+        line["cpu_baseline"] = base
+        line["oracle_checks"] = checks
+        del xE
     print(json.dumps(line))
 
 
