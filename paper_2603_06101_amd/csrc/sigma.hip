@@ -393,7 +393,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
     int64_t nsa, int64_t nsb, int64_t nsb_pad, int s, int npair, int ngroups, int nkc,
     const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
     const uint4 *__restrict__ quads, const TC *__restrict__ c, int64_t ldc,
-    T *__restrict__ sigma) {
+    T *__restrict__ sigma, int64_t per_xcd) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
@@ -402,7 +402,11 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
   constexpr int GROWS = MG * 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ia = blockIdx.x;
+  // rows are dealt to the 8 XCDs in contiguous ranges (workgroup b runs on
+  // XCD b % 8): neighbouring alpha strings share most of their excited
+  // strings J_e, so the workgroups of one XCD find the same C rows in its L2
+  const int64_t ia = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (ia >= nsa) return;
   const int64_t vo = (int64_t)blockIdx.y * nsa * nsb;
   const int MROWS = ngroups * GROWS;
   const int ktot = nkc * KW;
@@ -553,35 +557,30 @@ int plan_opp(sbci_ctx *ctx, const int *mg_options, int nmg, const int *ks_option
              OppPlan &p) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   const int Mt = (ctx->npair + 15) / 16;
-  // M tiles per group: the smallest option covering all of Mt, else the one
-  // with the least padding (ties: fewer groups)
-  p.MG = 0;
-  for (int i = 0; i < nmg; ++i)
-    if (mg_options[i] >= Mt && (p.MG == 0 || mg_options[i] < p.MG)) p.MG = mg_options[i];
-  if (p.MG == 0) {
-    int best = 1 << 30;
-    for (int i = 0; i < nmg; ++i) {
-      const int m = mg_options[i], cost = (Mt + m - 1) / m * m;
-      if (cost < best || (cost == best && m > p.MG)) {
-        best = cost;
-        p.MG = m;
-      }
-    }
-  }
-  p.ngroups = (Mt + p.MG - 1) / p.MG;
-  if (p.ngroups * p.MG * 16 > ctx->npair_pad)
-    return set_error(SBCI_EINVAL, "pair table padding too small");
   const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
   const size_t cap = 160 * 1024;
-  // fewest K chunks that fit, then the smallest K tile
-  p.KS = 0;
-  for (int i = 0; i < nks; ++i) {
-    const int ks = ks_options[i];
-    const int nkc = (kst + ks - 1) / ks;
-    if (opp_lds<M>(B.ns, p.MG, ks, p.ngroups, nkc) > cap) continue;
-    if (p.KS == 0 || (nkc < p.nkc) || (nkc == p.nkc && ks < p.KS)) {
-      p.KS = ks;
-      p.nkc = nkc;
+  // (M tiles per group, k-steps per chunk) with the least padded MFMA work
+  // per column tile, ngroups * MG * nkc * KS, among those that fit in LDS;
+  // ties: fewer K chunks (fewer barriers), then fewer groups
+  p.MG = p.KS = 0;
+  int64_t best = -1;
+  for (int i = 0; i < nmg; ++i) {
+    const int mg = mg_options[i], ng = (Mt + mg - 1) / mg;
+    if (ng * mg * 16 > ctx->npair_pad) continue;
+    for (int j = 0; j < nks; ++j) {
+      const int ks = ks_options[j], nkc = (kst + ks - 1) / ks;
+      if (opp_lds<M>(B.ns, mg, ks, ng, nkc) > cap) continue;
+      // the FP64 tile of 9 x 14 needs more than 256 VGPRs (spills)
+      if (std::is_same<typename M::A, double>::value && mg * ks > 100) continue;
+      const int64_t work = (int64_t)ng * mg * nkc * ks;
+      if (best < 0 || work < best || (work == best && nkc < p.nkc) ||
+          (work == best && nkc == p.nkc && ng < p.ngroups)) {
+        best = work;
+        p.MG = mg;
+        p.KS = ks;
+        p.nkc = nkc;
+        p.ngroups = ng;
+      }
     }
   }
   if (p.KS == 0)
@@ -597,7 +596,8 @@ void launch_opp_k(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, c
   constexpr int NW = 8;
   k_opp<M, T, TC, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
       A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab,
-      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, ldc, out);
+      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, ldc, out,
+      (int64_t)(grid.x / 8));
 }
 
 template <typename M, typename T, int MG, typename TC>
@@ -619,7 +619,9 @@ void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, co
   } else {
     if constexpr (std::is_same<typename M::A, double>::value) {
       if (p.KS == 4) launch_opp_k<M, T, MG, 4, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else if (p.KS == 6) launch_opp_k<M, T, MG, 6, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
       else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
       else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     } else {
       if (p.KS == 8) launch_opp_k<M, T, MG, 8, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
@@ -635,11 +637,13 @@ int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const TC *c, int64_t ldc, T
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
-  dim3 grid((unsigned)A.ns, (unsigned)nvec);
+  const int64_t per_xcd = (A.ns + 7) / 8;
+  dim3 grid((unsigned)(per_xcd * 8), (unsigned)nvec);
   if constexpr (std::is_same<typename M::A, double>::value) {
     if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     else if (p.MG == 5) dispatch_ks<M, T, 5, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
   } else {
     if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
     else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
@@ -960,14 +964,14 @@ int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
   {
     // K tiles (k-steps per chunk) offered to the pair planner; the register
     // budget of two waves per SIMD bounds them (B fragments double-buffered)
-    static const int ks_d[3] = {4, 7, 14};
+    static const int ks_d[5] = {4, 6, 7, 9, 14};
     static const int ks_f[3] = {8, 9, 14};
     static const int ks_b[3] = {1, 2, 3};
-    static const int mg_d[3] = {4, 5, 7};
+    static const int mg_d[4] = {4, 5, 7, 9};
     static const int mg_f[3] = {4, 7, 9};
     int rc;
     if (M::KPL == 8) rc = plan_opp<M>(ctx, mg_f, 3, ks_b, 3, pp);
-    else if (std::is_same<typename M::A, double>::value) rc = plan_opp<M>(ctx, mg_d, 3, ks_d, 3, pp);
+    else if (std::is_same<typename M::A, double>::value) rc = plan_opp<M>(ctx, mg_d, 4, ks_d, 5, pp);
     else rc = plan_opp<M>(ctx, mg_f, 3, ks_f, 3, pp);
     pok = rc == SBCI_OK;
   }
