@@ -13,9 +13,14 @@ Contents (all FP64, electronic energies, Eh):
 
   sbci2  oracle SBCI2 (Algorithm 2) energies: CAS(10,10) seeds 0..2 with 3
          roots, rank 20.
+  cas14  CAS(14e,14o), seed 0, rank 28 (11,778,624 determinants): oracle
+         SBCI1 with 5 roots (Section S1.1 start, Section S1.4 sequencing;
+         eps0 = 1e-10, r0 = 1e-5) and the lowest 6 eigenvalues from Lanczos
+         eigsh on the oracle sigma (tol 1e-12).  About 400 oracle sigma calls
+         (roughly 2.5 h on 8 cores); the section is written after each part.
 
-"python tests/golden/make_refs.py batch" (or "sbci2") recomputes only that
-section.
+"python tests/golden/make_refs.py batch" (or "sbci2", "cas14") recomputes
+only that section.
 """
 import json
 import os
@@ -70,16 +75,51 @@ def sbci2_section():
     return sec
 
 
+def cas14_section(save):
+    """CAS(14,14): oracle SBCI1 (5 roots), then eigsh; save(sec) after each."""
+    n, na, nb, K, nroots = 14, 7, 7, 28, 5
+    I = make_integrals(n, K, 0)
+    op = S.Operator(n, na, nb, I.h1, I.eri)
+    sec = {"norb": n, "nalpha": na, "nbeta": nb, "rank": K, "seed": 0, "nroots": nroots,
+           "digest": I.digest()}
+    t = time.time()
+    rs = sbci.sbci1(op, op.diag(), nroots)
+    sec.update({"sbci1": rs.energies.tolist(), "sbci1_nsigma": rs.nsigma,
+                "sbci1_converged": bool(rs.converged),
+                "sbci1_resid": [float(s.dz) for s in rs.steps if s.reason == "converged"],
+                "sbci1_seconds": round(time.time() - t, 1)})
+    print("cas14 sbci1", rs.energies, rs.nsigma, f"{time.time() - t:.0f}s", flush=True)
+    save(sec)
+    t = time.time()
+    cnt = [0]
+
+    def mv(v):
+        cnt[0] += 1
+        return S.sigma(n, na, nb, I.h1, I.eri, v)
+    L = LinearOperator((op.ndet, op.ndet), matvec=mv, dtype=np.float64)
+    ev = np.sort(eigsh(L, k=6, which="SA", tol=1e-12, ncv=24)[0])
+    sec.update({"eigsh": ev.tolist(), "eigsh_nsigma": cnt[0],
+                "eigsh_seconds": round(time.time() - t, 1)})
+    print("cas14 eigsh", ev, cnt[0], f"{time.time() - t:.0f}s", flush=True)
+    save(sec)
+    return sec
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("batch", "sbci2"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("batch", "sbci2", "cas14"):
         with open(REFS) as f:
             out = json.load(f)
+
+        def save(sec):
+            out[sys.argv[1]] = sec
+            with open(REFS, "w") as f:
+                json.dump(out, f, indent=1)
         if sys.argv[1] == "batch":
-            out["batch512"] = batch_section()
+            save(batch_section())
+        elif sys.argv[1] == "sbci2":
+            save(sbci2_section())
         else:
-            out["sbci2"] = sbci2_section()
-        with open(REFS, "w") as f:
-            json.dump(out, f, indent=1)
+            cas14_section(save)
         return
     out = {"generator": "tests/golden/make_refs.py", "cas6": {}, "cas10": {}}
     n, na, nb, K = 6, 3, 3, 12

@@ -17,6 +17,10 @@ orbital counts and the same 8-fold symmetric structure):
          L_k[p, q] = L_k[q, p] = 0.1 * v * exp(-|p - q| / 4)
   5. (pq|rs) = sum_k L_k[p, q] * L_k[r, s]        (PSD as an N^2 x N^2 matrix)
 
+Every step gives the same bits on every host: the normal draws are PCG64's,
+exp(-d/4) is correctly rounded from decimal arithmetic, and the sum in step 5
+runs over k in order, one elementwise product and add at a time (no BLAS).
+
 Point-group symmetric variant (``make_sym_integrals``): orbital p carries the
 D2h-like irrep label orbsym[p] (``orbital_irreps``: p mod 8); after the same
 draws, h[p, q] is kept only where orbsym[p] == orbsym[q], and L_k only on the
@@ -26,6 +30,7 @@ integrals) and stays PSD.
 """
 from __future__ import annotations
 
+import decimal
 import hashlib
 from dataclasses import dataclass
 
@@ -67,7 +72,7 @@ def _draw(norb: int, rank: int, rng: np.random.Generator, orbsym=None):
     h[iu] = 0.05 * u
     h[(iu[1], iu[0])] = 0.05 * u
     it = np.triu_indices(n)
-    damp = np.exp(-np.abs(it[0] - it[1]) / 4.0)
+    damp = _damping(n)[np.abs(it[0] - it[1])]
     L = np.zeros((rank, n, n))
     for k in range(rank):
         v = rng.standard_normal(len(it[0]))
@@ -79,9 +84,21 @@ def _draw(norb: int, rank: int, rng: np.random.Generator, orbsym=None):
         h = np.where(pair == 0, h, 0.0)
         for k in range(rank):
             L[k] = np.where(pair == (k % 8), L[k], 0.0)
+    # sum over k in order, one elementwise product and add per k: the same
+    # bits on every host (a BLAS product would sum in a host-dependent order)
     Lm = L.reshape(rank, n * n)
-    eri = (Lm.T @ Lm).reshape(n, n, n, n)
-    return h, eri
+    eri = np.zeros((n * n, n * n))
+    for k in range(rank):
+        eri += np.multiply.outer(Lm[k], Lm[k])
+    return h, eri.reshape(n, n, n, n)
+
+
+def _damping(n: int) -> np.ndarray:
+    """exp(-d / 4) for d = 0 .. n-1, correctly rounded (40-digit decimal
+    arithmetic, then the nearest double), so the value does not depend on
+    the host's exp implementation."""
+    ctx = decimal.Context(prec=40)
+    return np.array([float(ctx.exp(decimal.Decimal(-d) / 4)) for d in range(n)])
 
 
 def make_integrals(norb: int, rank: int, seed: int) -> Integrals:
