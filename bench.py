@@ -802,6 +802,16 @@ def main():
         sig[dt] = {"gdet_per_s": ndet / (med.sum() / 1e3) / 1e9, "ms": float(med.sum()),
                    "kernels_ms": dict(zip(parts, [round(float(v), 4) for v in med]))}
         del out, c
+    # the FP64 sigma with its opposite-spin scatter in FP64 atomics (not
+    # reproducible bit for bit) instead of the default fixed point
+    ctx.set_deterministic(False)
+    out, _ = ctx.sigma_timed(c64, "f64")
+    runs = [ctx.sigma_timed(c64, "f64", out=out)[1] for _ in range(a.sigma_reps)]
+    med = np.median(np.array(runs), axis=0)
+    sig["f64_atomics"] = {"gdet_per_s": ndet / (med.sum() / 1e3) / 1e9, "ms": float(med.sum()),
+                          "kernels_ms": dict(zip(parts, [round(float(v), 4) for v in med]))}
+    ctx.set_deterministic(True)
+    del out
     forms = {"same_spin": ctx.same_form(0), "opposite_spin": ctx.opp_form("f64")}
     del c64
     ctx.close()

@@ -205,6 +205,16 @@ int sbci_hdiag(sbci_ctx *ctx, double *dev_out);
  * overlap.  Asynchronous on the context stream. */
 int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int dtype);
 
+/* FP64 sigma reproducibility.  on = 1 (the default): the FP64 opposite-spin
+ * part accumulates each row of sigma in 64-bit fixed point with integer
+ * atomics, under a power-of-two scale set per row from a bound on its
+ * partial sums (max |C| over the rows it reads times s_beta times the
+ * largest row sum of |(kl|k'l')|), so an FP64 sigma is the same to the last
+ * bit on every call; every other part sums in a fixed order.  on = 0: FP64
+ * atomics (the order of additions varies, about 10% faster).  FP32 and BF16
+ * sigma are not covered.  SBCI_EINVAL unless on is 0 or 1. */
+int sbci_set_deterministic(sbci_ctx *ctx, int on);
+
 /* sbci_sigma for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same result, with the beta part's transposed operand and result in a
@@ -212,7 +222,9 @@ int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int 
  * process ends) instead of workspaces allocated on first use.  This call
  * makes no hipMalloc, hipFree or other allocating call.  Limits, refused
  * with SBCI_EINVAL before any launch: dtype SBCI_F64 or SBCI_F32;
- * nvec * N_det * element size at most 32 MiB; the list same-spin form and
+ * 2 * nvec * N_det * element size (plus, in FP64, 8 * nvec * N_alpha bytes
+ * of row maxima; each part rounded up to 256 bytes) at most 64 MiB, so
+ * nvec * N_det * element size up to just under 32 MiB; the list same-spin form and
  * the pair opposite-spin form (no dense or orbital forms, whose operands are
  * built on first use); no symmetry blocking.  Every call on a device shares
  * that device's array: calls that overlap on one device (several contexts or

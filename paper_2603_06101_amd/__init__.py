@@ -124,6 +124,7 @@ SIGNATURES = [
     ("sbci_sigma", _I, [_P, _P, _P, _I, _I]),
     ("sbci_sigma_noalloc", _I, [_P, _P, _P, _I, _I]),
     ("sbci_sigma_timed", _I, [_P, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
+    ("sbci_set_deterministic", _I, [_P, _I]),
     ("sbci_set_opp_form", _I, [_P, _I]),
     ("sbci_get_opp_form", _I, [_P, _I, ctypes.POINTER(_I)]),
     ("sbci_set_same_form", _I, [_P, _I]),
@@ -278,6 +279,10 @@ class Context:
         _check(lib().sbci_sigma(self.h, ctypes.c_void_p(c.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), nvec, code))
         return out
+
+    def set_deterministic(self, on=True):
+        """FP64 sigma the same to the last bit on every call (default) or, off, FP64 atomics."""
+        _check(lib().sbci_set_deterministic(self.h, 1 if on else 0))
 
     def set_opp_form(self, form):
         """Force the opposite-spin form ("auto", "pair" or "orbital") of later sigma calls."""

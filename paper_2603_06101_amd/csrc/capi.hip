@@ -185,6 +185,7 @@ int sbci_destroy(sbci_ctx *ctx) {
   hipFree(ctx->ws_s.ptr);
   hipFree(ctx->ws_red.ptr);
   hipFree(ctx->ws_q.ptr);
+  hipFree(ctx->ws_rmax.ptr);
   if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
   delete ctx;
   return SBCI_OK;
@@ -270,6 +271,13 @@ int sbci_sigma_timed(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec
   if (dtype != SBCI_F64 && dtype != SBCI_F32 && dtype != SBCI_BF16)
     return set_error(SBCI_EINVAL, "unknown dtype");
   return sigma_profile(ctx, dev_c, dev_sigma, nvec, dtype, ms_parts);
+}
+
+int sbci_set_deterministic(sbci_ctx *ctx, int on) {
+  if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
+  if (on != 0 && on != 1) return set_error(SBCI_EINVAL, "on must be 0 or 1");
+  ctx->deterministic = on != 0;
+  return SBCI_OK;
 }
 
 int sbci_set_opp_form(sbci_ctx *ctx, int form) {

@@ -155,6 +155,11 @@ struct sbci_ctx {
   double *h1 = nullptr;           // device [N][N]
   double *eri = nullptr;          // device [N^4]
   double *W64 = nullptr;          // device [npair][npair] (kl|k'l')
+  // s_beta * max_kl sum_k'l' |(kl|k'l')|: with max |C| over the rows an
+  // output row gathers, a bound on every partial sum of the FP64
+  // opposite-spin scatter (which accumulates in 64-bit fixed point)
+  double opp_wbound = 0;
+  bool deterministic = true;      // FP64 opposite-spin scatter in fixed point (sbci_set_deterministic)
   float *W32 = nullptr;
   __hip_bfloat16 *Wbf = nullptr;
   double *hdiag = nullptr;        // device [ndet]
@@ -162,6 +167,7 @@ struct sbci_ctx {
   sbci::Workspace ws_t, ws_s;     // transposed input / output scratch of sigma
   sbci::Workspace ws_red;         // reduction partials + results
   sbci::Workspace ws_q;           // orbital-grouped copy of c (opposite-spin, dilute form)
+  sbci::Workspace ws_rmax;        // max |C[J][.]| per alpha row and vector (FP64 opposite spin)
   int opp_form = 0;               // SBCI_OPP_AUTO / _PAIR / _ORBITAL
   int same_form = 0;              // SBCI_SAME_AUTO / _LISTS / _DENSE
   sbci::Solver *solver = nullptr;

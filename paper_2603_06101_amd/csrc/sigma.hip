@@ -368,6 +368,73 @@ __global__ __launch_bounds__(64 * WAVES) void k_same(
   }
 }
 
+// Fixed-point scale of the FP64 opposite-spin scatter for output row ia:
+// every partial sum of sigma's row is at most wbound * max_e max |C[J_e][.]|
+// (s_beta contributions per element, each at most max_kl sum |W[kl][.]| times
+// the largest C entry the row gathers); the power-of-two scale puts that
+// bound below 2^62.  bad: a non-finite C row (the result becomes NaN).
+// Called by every thread of the workgroup (it holds a barrier).
+template <int NW>
+__device__ inline void fix_scale(const double *__restrict__ rowmax, const Ent *__restrict__ taba,
+                                 int64_t ia, int s, int64_t nsa, double wbound, double *wmax,
+                                 double &scale, double &inv, bool &bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double m = 0.0;
+  for (int e = tid; e < s; e += 64 * NW) {
+    const double r = rowmax[(int64_t)blockIdx.y * nsa + taba[ia * s + e].J];
+    m = (r > m || r != r) ? r : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double r = __shfl_xor(m, o);
+    m = (r > m || r != r) ? r : m;
+  }
+  if (lane == 0) wmax[wave] = m;
+  __syncthreads();
+  m = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+  const double bnd = wbound * m;
+  bad = !(bnd < INFINITY);
+  scale = inv = 1.0;
+  if (bnd > 0 && !bad) {
+    int x = 0;
+    frexp(bnd, &x);  // bnd < 2^x
+    int ex = 62 - x;
+    ex = ex > 1000 ? 1000 : (ex < -1000 ? -1000 : ex);
+    scale = ldexp(1.0, ex);
+    inv = ldexp(1.0, -ex);
+  }
+}
+
+// Scatter one contribution into sigma's row: FP64 in 64-bit fixed point
+// (exact integer adds, so the row does not depend on the scatter order),
+// the other flavours with FP64 atomics.
+template <bool FIX>
+__device__ __forceinline__ void scatter_add(double *slot, double v, double scale) {
+  if constexpr (FIX) {
+    const long long q = __double2ll_rn(v * scale);
+    atomicAdd(reinterpret_cast<unsigned long long *>(slot), (unsigned long long)q);
+  } else {
+    atomicAdd(slot, v);
+  }
+}
+
+// Row write-back: sigma += the row (fixed point scaled back, or NaN).
+template <bool FIX, typename T>
+__device__ __forceinline__ T row_value(const double *acc, int64_t j, double inv, bool bad) {
+  if constexpr (FIX) {
+    const long long q = (long long)reinterpret_cast<const unsigned long long *>(acc)[j];
+    return bad ? (T)NAN : (T)((double)q * inv);
+  } else {
+    return (T)acc[j];
+  }
+}
+
+// Dynamic LDS of the opposite-spin kernels: 160 KB less the static
+// per-wave scale slots of the FP64 fixed-point scatter (NW doubles).
+constexpr size_t kOppLdsCap = 160 * 1024 - 256;
+
 constexpr int32_t kPadEntry = -1;  // K padding: zero column of A
 
 // Opposite-spin contraction, one output row Ia (of one vector) per
@@ -388,19 +455,24 @@ constexpr int32_t kPadEntry = -1;  // K padding: zero column of A
 // checks; no workgroup barrier sits inside the column loop.  c (type TC,
 // row stride ldc) is the vector itself, or for the BF16 flavour its BF16
 // copy, which halves the bytes of the gathers.
-template <typename M, typename T, typename TC, int MG, int KS, bool AREG, int NW>
+template <typename M, typename T, typename TC, int MG, int KS, bool AREG, int NW, bool FIXT>
 __global__ __launch_bounds__(64 * NW) void k_opp(
     int64_t nsa, int64_t nsb, int64_t nsb_pad, int s, int npair, int ngroups, int nkc,
     const float *__restrict__ Wf, const double *__restrict__ Wd, const Ent *__restrict__ taba,
     const uint4 *__restrict__ quads, const TC *__restrict__ c, int64_t ldc,
-    T *__restrict__ sigma, int64_t per_xcd) {
+    T *__restrict__ sigma, int64_t per_xcd, const double *__restrict__ rowmax, double wbound) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
   constexpr int KW = KS * M::KSTEP;
   constexpr int LDW = KW + M::PAD;
   constexpr int GROWS = MG * 16;
+  // FIXT (FP64, the default): sigma's row accumulates in 64-bit fixed point
+  // (integer LDS atomics, exact and order-independent), so the result does
+  // not depend on the order in which waves scatter
+  constexpr bool FIX = FIXT && std::is_same<M, MF64>::value;
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double wmax[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // rows are dealt to the 8 XCDs in contiguous ranges (workgroup b runs on
   // XCD b % 8): neighbouring alpha strings share most of their excited
@@ -430,6 +502,9 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
     }
   }
   for (int64_t j = tid; j < nsb + 64; j += 64 * NW) acc[j] = (Acc)0;
+  double fscale = 1.0, finv = 1.0;
+  bool fbad = false;
+  if constexpr (FIX) fix_scale<NW>(rowmax, taba, ia, s, nsa, wbound, wmax, fscale, finv, fbad);
 
   const TC *__restrict__ cv = c + (int64_t)blockIdx.y * nsa * ldc;
   const uint32_t nsb32 = (uint32_t)nsb;
@@ -526,7 +601,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
             if (cd != kInvalid) {
               Acc v = (Acc)out[u][r];
               if (cd & 1u) v = -v;
-              atomicAdd(&acc[cd >> 1], v);
+              scatter_add<FIX>(&acc[cd >> 1], v, fscale);
             }
           }
         }
@@ -535,7 +610,33 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
   }
   __syncthreads();
   T *__restrict__ sv = sigma + vo + ia * nsb;
-  for (int64_t j = tid; j < nsb; j += 64 * NW) sv[j] += (T)acc[j];
+  for (int64_t j = tid; j < nsb; j += 64 * NW) sv[j] += row_value<FIX, T>(acc, j, finv, fbad);
+}
+
+// max |C[J][.]| of every alpha row J (and vector): the fixed-point scale of
+// the FP64 opposite-spin scatter; NaN if the row holds a NaN
+__global__ __launch_bounds__(256) void k_rowmax(const double *__restrict__ c, int64_t nsa,
+                                                int64_t nsb, double *__restrict__ out) {
+  __shared__ double red[4];
+  const int64_t J = blockIdx.x;
+  const double *row = c + ((int64_t)blockIdx.y * nsa + J) * nsb;
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < nsb; j += 256) {
+    const double a = fabs(row[j]);
+    m = (a > m || a != a) ? a : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double r = __shfl_xor(m, o);
+    m = (r > m || r != r) ? r : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < 4; ++w) r = (red[w] > r || red[w] != red[w]) ? red[w] : r;
+    out[(int64_t)blockIdx.y * nsa + J] = r;
+  }
 }
 
 struct OppPlan {
@@ -558,7 +659,7 @@ int plan_opp(sbci_ctx *ctx, const int *mg_options, int nmg, const int *ks_option
   const SpinTables &A = ctx->A, &B = ctx->B;
   const int Mt = (ctx->npair + 15) / 16;
   const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
-  const size_t cap = 160 * 1024;
+  const size_t cap = kOppLdsCap;
   // (M tiles per group, k-steps per chunk) with the least padded MFMA work
   // per column tile, ngroups * MG * nkc * KS, among those that fit in LDS;
   // ties: fewer K chunks (fewer barriers), then fewer groups
@@ -591,63 +692,83 @@ int plan_opp(sbci_ctx *ctx, const int *mg_options, int nmg, const int *ks_option
 
 template <typename M, typename T, int MG, int KS, bool AREG, typename TC>
 void launch_opp_k(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
-                  const TC *c, int64_t ldc, T *out) {
+                  const TC *c, int64_t ldc, T *out, const double *rowmax) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   constexpr int NW = 8;
-  k_opp<M, T, TC, MG, KS, AREG, NW><<<grid, 64 * NW, p.lds, ctx->stream>>>(
-      A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab,
-      std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, ldc, out,
-      (int64_t)(grid.x / 8));
+  auto launch = [&](auto kern) {
+    static bool attr = false;
+    if (!attr) {
+      hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kOppLdsCap);
+      attr = true;
+    }
+    kern<<<grid, 64 * NW, p.lds, ctx->stream>>>(
+        A.ns, B.ns, B.ns_pad, A.s, ctx->npair, p.ngroups, p.nkc, Wf, Wd, A.tab,
+        std::is_same<typename M::A, double>::value ? B.quad_s : B.quad_r, c, ldc, out,
+        (int64_t)(grid.x / 8), rowmax, ctx->opp_wbound);
+  };
+  if (std::is_same<M, MF64>::value && ctx->deterministic)
+    launch(k_opp<M, T, TC, MG, KS, AREG, NW, std::is_same<M, MF64>::value>);
+  else
+    launch(k_opp<M, T, TC, MG, KS, AREG, NW, false>);
 }
 
 template <typename M, typename T, int MG, typename TC>
 void dispatch_ks(sbci_ctx *ctx, const OppPlan &p, dim3 grid, const float *Wf, const double *Wd,
-                 const TC *c, int64_t ldc, T *out) {
+                 const TC *c, int64_t ldc, T *out, const double *rowmax) {
   if constexpr (M::KPL == 8) {
     // A fragments in registers when they are few enough (MG * KS <= 18)
     const bool areg = p.ngroups == 1 && MG * p.KS <= 18;
     if (p.KS == 1) {
-      if (areg) launch_opp_k<M, T, MG, 1, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else launch_opp_k<M, T, MG, 1, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      if (areg) launch_opp_k<M, T, MG, 1, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else launch_opp_k<M, T, MG, 1, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
     } else if (p.KS == 2) {
-      if (areg) launch_opp_k<M, T, MG, 2, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else launch_opp_k<M, T, MG, 2, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      if (areg) launch_opp_k<M, T, MG, 2, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else launch_opp_k<M, T, MG, 2, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
     } else {
-      if (areg) launch_opp_k<M, T, MG, 3, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else launch_opp_k<M, T, MG, 3, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      if (areg) launch_opp_k<M, T, MG, 3, true, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else launch_opp_k<M, T, MG, 3, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
     }
   } else {
     if constexpr (std::is_same<typename M::A, double>::value) {
-      if (p.KS == 4) launch_opp_k<M, T, MG, 4, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else if (p.KS == 6) launch_opp_k<M, T, MG, 6, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      if (p.KS == 4) launch_opp_k<M, T, MG, 4, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else if (p.KS == 6) launch_opp_k<M, T, MG, 6, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else if (p.KS == 7) launch_opp_k<M, T, MG, 7, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
     } else {
-      if (p.KS == 8) launch_opp_k<M, T, MG, 8, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+      if (p.KS == 8) launch_opp_k<M, T, MG, 8, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else if (p.KS == 9) launch_opp_k<M, T, MG, 9, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
+      else launch_opp_k<M, T, MG, 14, false, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rowmax);
     }
   }
 }
 
 template <typename M, typename T, typename TC>
-int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const TC *c, int64_t ldc, T *out, int nvec) {
+int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const TC *c, int64_t ldc, T *out, int nvec,
+                    double *rmax) {
   const SpinTables &A = ctx->A;
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
   const int64_t per_xcd = (A.ns + 7) / 8;
   dim3 grid((unsigned)(per_xcd * 8), (unsigned)nvec);
+  if constexpr (std::is_same<M, MF64>::value) {
+    if (ctx->deterministic) {
+      k_rowmax<<<dim3((unsigned)A.ns, (unsigned)nvec), 256, 0, ctx->stream>>>(
+          reinterpret_cast<const double *>(c), A.ns, ldc, rmax);
+      SBCI_CHECK_LAUNCH();
+    }
+  }
   if constexpr (std::is_same<typename M::A, double>::value) {
-    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else if (p.MG == 5) dispatch_ks<M, T, 5, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
+    else if (p.MG == 5) dispatch_ks<M, T, 5, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
+    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
+    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
   } else {
-    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
-    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out);
+    if (p.MG == 4) dispatch_ks<M, T, 4, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
+    else if (p.MG == 7) dispatch_ks<M, T, 7, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
+    else dispatch_ks<M, T, 9, TC>(ctx, p, grid, Wf, Wd, c, ldc, out, rmax);
   }
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
@@ -670,19 +791,21 @@ int launch_opp_pair(sbci_ctx *ctx, const OppPlan &p, const TC *c, int64_t ldc, T
 // target strings: the workgroup computes every M_q but scatters only the
 // targets in its window (nwin windows cost nwin times the MFMA work).
 // LDS (dynamic): acc[win + 64] | Ws[MT*16][KW + PAD] | eoff[nkc*KW] | eW[nkc*KW]
-template <typename M, typename T, int MT, int KS, int NW>
+template <typename M, typename T, int MT, int KS, int NW, bool FIXT>
 __global__ __launch_bounds__(64 * NW) void k_opp_q(
     int64_t nsa, int64_t nsb, int norb, int64_t nq, int64_t nq_pad, int s, int npair, int nkc,
     int64_t per_xcd, int64_t win, const float *__restrict__ Wf, const double *__restrict__ Wd,
     const Ent *__restrict__ taba, const uint4 *__restrict__ quads, const T *__restrict__ cq,
-    T *__restrict__ sigma) {
+    T *__restrict__ sigma, const double *__restrict__ rowmax, double wbound) {
   using A = typename M::A;
   using Acc = typename M::Acc;
   using Frag = typename M::Frag;
   constexpr int KW = KS * M::KSTEP;
   constexpr int LDW = KW + M::PAD;
   constexpr int ROWS = MT * 16;
+  constexpr bool FIX = FIXT && std::is_same<M, MF64>::value;  // fixed-point FP64 scatter (see k_opp)
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double wmax[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ia = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (ia >= nsa) return;  // uniform over the workgroup
@@ -712,6 +835,9 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
     }
   }
   for (int64_t j = tid; j < win + 64; j += 64 * NW) acc[j] = (Acc)0;
+  double fscale = 1.0, finv = 1.0;
+  bool fbad = false;
+  if constexpr (FIX) fix_scale<NW>(rowmax, taba, ia, s, nsa, wbound, wmax, fscale, finv, fbad);
 
   const int njt = (int)(nq_pad / 16);
   const int g = lane >> 4;
@@ -813,7 +939,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
             if (cd != kInvalid && tw < tlen32) {
               Acc v = (Acc)out[u][r];
               if (cd & 1u) v = -v;
-              atomicAdd(&acc[tw], v);
+              scatter_add<FIX>(&acc[tw], v, fscale);
             }
           }
         }
@@ -822,7 +948,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
   }
   __syncthreads();
   T *__restrict__ sv = sigma + vo + ia * nsb + t0;
-  for (int64_t j = tid; j < tlen; j += 64 * NW) sv[j] += (T)acc[j];
+  for (int64_t j = tid; j < tlen; j += 64 * NW) sv[j] += row_value<FIX, T>(acc, j, finv, fbad);
 }
 
 // cq[v][q][Ia][j] = c[v][Ia][colq[q][j]]; blocks of one row Ia are adjacent
@@ -867,7 +993,7 @@ bool plan_opp_q(const sbci_ctx *ctx, OppQPlan &p, int64_t min_win) {
   static const int ks_b[3] = {1, 3, 5};
   const int *opts = M::KPL == 8 ? ks_b : ks_w;
   const int kst = (A.s + M::KSTEP - 1) / M::KSTEP;
-  const size_t cap = 160 * 1024;
+  const size_t cap = kOppLdsCap;
   p = OppQPlan();
   int64_t best = -1;
   for (int i = 0; i < 3; ++i) {
@@ -894,41 +1020,47 @@ bool plan_opp_q(const sbci_ctx *ctx, OppQPlan &p, int64_t min_win) {
 
 template <typename M, typename T, int MT, int KS>
 int launch_opp_q_k(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const double *Wd,
-                   const T *cq, T *out, int nvec) {
+                   const T *cq, T *out, int nvec, const double *rmax) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   constexpr int NW = 8;
-  auto kern = k_opp_q<M, T, MT, KS, NW>;
-  static bool attr = false;
-  if (!attr) {
-    SBCI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 160 * 1024));
-    attr = true;
-  }
   const uint4 *quads = std::is_same<typename M::A, double>::value ? B.qquad_s : B.qquad_r;
   const int64_t per_xcd = (A.ns + 7) / 8;
-  kern<<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec, (unsigned)p.nwin), 64 * NW, p.lds,
-         ctx->stream>>>(A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, per_xcd, p.win,
-                        Wf, Wd, A.tab, quads, cq, out);
+  auto launch = [&](auto kern) -> int {
+    static bool attr = false;
+    if (!attr) {
+      SBCI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kOppLdsCap));
+      attr = true;
+    }
+    kern<<<dim3((unsigned)(per_xcd * 8), (unsigned)nvec, (unsigned)p.nwin), 64 * NW, p.lds,
+           ctx->stream>>>(A.ns, B.ns, ctx->norb, B.nq, B.nq_pad, A.s, ctx->npair, p.nkc, per_xcd,
+                          p.win, Wf, Wd, A.tab, quads, cq, out, rmax, ctx->opp_wbound);
+    return SBCI_OK;
+  };
+  if (std::is_same<M, MF64>::value && ctx->deterministic)
+    SBCI_TRY(launch(k_opp_q<M, T, MT, KS, NW, std::is_same<M, MF64>::value>));
+  else
+    SBCI_TRY(launch(k_opp_q<M, T, MT, KS, NW, false>));
   SBCI_CHECK_LAUNCH();
   return SBCI_OK;
 }
 
 template <typename M, typename T, int MT>
 int dispatch_q_ks(sbci_ctx *ctx, const OppQPlan &p, const float *Wf, const double *Wd, const T *cq,
-                  T *out, int nvec) {
+                  T *out, int nvec, const double *rmax) {
   if constexpr (M::KPL == 8) {
-    if (p.KS == 1) return launch_opp_q_k<M, T, MT, 1>(ctx, p, Wf, Wd, cq, out, nvec);
-    if (p.KS == 3) return launch_opp_q_k<M, T, MT, 3>(ctx, p, Wf, Wd, cq, out, nvec);
-    return launch_opp_q_k<M, T, MT, 5>(ctx, p, Wf, Wd, cq, out, nvec);
+    if (p.KS == 1) return launch_opp_q_k<M, T, MT, 1>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    if (p.KS == 3) return launch_opp_q_k<M, T, MT, 3>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    return launch_opp_q_k<M, T, MT, 5>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
   } else {
-    if (p.KS == 9) return launch_opp_q_k<M, T, MT, 9>(ctx, p, Wf, Wd, cq, out, nvec);
-    if (p.KS == 12) return launch_opp_q_k<M, T, MT, 12>(ctx, p, Wf, Wd, cq, out, nvec);
-    return launch_opp_q_k<M, T, MT, 17>(ctx, p, Wf, Wd, cq, out, nvec);
+    if (p.KS == 9) return launch_opp_q_k<M, T, MT, 9>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    if (p.KS == 12) return launch_opp_q_k<M, T, MT, 12>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    return launch_opp_q_k<M, T, MT, 17>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
   }
 }
 
 template <typename M, typename T>
-int launch_opp_q(sbci_ctx *ctx, const OppQPlan &p, const T *c, T *out, int nvec) {
+int launch_opp_q(sbci_ctx *ctx, const OppQPlan &p, const T *c, T *out, int nvec, double *rmax) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   const int n = ctx->norb;
   const size_t bytes = sizeof(T) * (size_t)nvec * n * A.ns * B.nq;
@@ -943,11 +1075,18 @@ int launch_opp_q(sbci_ctx *ctx, const OppQPlan &p, const T *c, T *out, int nvec)
   const float *Wf = nullptr;
   const double *Wd = nullptr;
   if constexpr (std::is_same<typename M::A, double>::value) Wd = ctx->W64; else Wf = ctx->W32;
+  if constexpr (std::is_same<M, MF64>::value) {
+    if (ctx->deterministic) {
+      k_rowmax<<<dim3((unsigned)A.ns, (unsigned)nvec), 256, 0, ctx->stream>>>(
+          reinterpret_cast<const double *>(c), A.ns, B.ns, rmax);
+      SBCI_CHECK_LAUNCH();
+    }
+  }
   switch (B.mt) {
-    case 1: return dispatch_q_ks<M, T, 1>(ctx, p, Wf, Wd, cq, out, nvec);
-    case 2: return dispatch_q_ks<M, T, 2>(ctx, p, Wf, Wd, cq, out, nvec);
-    case 3: return dispatch_q_ks<M, T, 3>(ctx, p, Wf, Wd, cq, out, nvec);
-    default: return dispatch_q_ks<M, T, 4>(ctx, p, Wf, Wd, cq, out, nvec);
+    case 1: return dispatch_q_ks<M, T, 1>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    case 2: return dispatch_q_ks<M, T, 2>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    case 3: return dispatch_q_ks<M, T, 3>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
+    default: return dispatch_q_ks<M, T, 4>(ctx, p, Wf, Wd, cq, out, nvec, rmax);
   }
 }
 
@@ -998,7 +1137,7 @@ int choose_opp(sbci_ctx *ctx, int &form, OppPlan &pp, OppQPlan &pq) {
 
 template <typename M, typename T>
 int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec, const __bf16 *cb = nullptr,
-               int64_t ldcb = 0) {
+               int64_t ldcb = 0, double *rmax_fixed = nullptr) {
   const SpinTables &A = ctx->A, &B = ctx->B;
   if (A.s == 0 || B.m == 0) return SBCI_OK;
   if (ctx->ndet >= ((int64_t)1 << 31))
@@ -1007,15 +1146,22 @@ int launch_opp(sbci_ctx *ctx, const T *c, T *out, int nvec, const __bf16 *cb = n
   OppPlan pp{};
   OppQPlan pq{};
   SBCI_TRY(choose_opp<M>(ctx, form, pp, pq));
-  if (form == SBCI_OPP_ORBITAL) return launch_opp_q<M, T>(ctx, pq, c, out, nvec);
+  double *rmax = rmax_fixed;
+  if constexpr (std::is_same<M, MF64>::value) {
+    if (!rmax) {
+      SBCI_TRY(ensure(ctx->ws_rmax, sizeof(double) * (size_t)A.ns * nvec));
+      rmax = static_cast<double *>(ctx->ws_rmax.ptr);
+    }
+  }
+  if (form == SBCI_OPP_ORBITAL) return launch_opp_q<M, T>(ctx, pq, c, out, nvec, rmax);
   if constexpr (std::is_same<M, MBF16>::value) {
     if (cb) {
       if ((uint64_t)A.ns * (uint64_t)ldcb >= (1ull << 32))
         return set_error(SBCI_EINVAL, "opposite-spin sigma: BF16 copy too large for 32-bit offsets");
-      return launch_opp_pair<M, T, __bf16>(ctx, pp, cb, ldcb, out, nvec);
+      return launch_opp_pair<M, T, __bf16>(ctx, pp, cb, ldcb, out, nvec, nullptr);
     }
   }
-  return launch_opp_pair<M, T, T>(ctx, pp, c, B.ns, out, nvec);
+  return launch_opp_pair<M, T, T>(ctx, pp, c, B.ns, out, nvec, rmax);
 }
 
 // Same-spin part with the source stripe in LDS: one workgroup per (column
@@ -1487,7 +1633,7 @@ int launch_gemm(sbci_ctx *ctx, int64_t Mr, int64_t N, int64_t K, const T *A, int
 // context's workspaces, allocated on first use.
 template <typename T, typename M>
 int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullptr,
-            T *ct_fixed = nullptr, T *st_fixed = nullptr) {
+            T *ct_fixed = nullptr, T *st_fixed = nullptr, double *rmax_fixed = nullptr) {
   SpinTables &A = ctx->A, &B = ctx->B;
   const int64_t na = A.ns, nb = B.ns, nd = ctx->ndet;
   const bool dbl = std::is_same<T, double>::value;
@@ -1528,7 +1674,7 @@ int sigma_t(sbci_ctx *ctx, const T *c, T *out, int nvec, PartEvents *pe = nullpt
     if (bfB) SBCI_TRY(bf16_copy(ctx, 1, c, nvec, &cbeta));
   }
   SBCI_TRY(rec(ctx, pe, 1));
-  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec, cbeta, cbeta ? pad64(nb) : 0)));
+  SBCI_TRY((launch_opp<M, T>(ctx, c, out, nvec, cbeta, cbeta ? pad64(nb) : 0, rmax_fixed)));
   SBCI_TRY(rec(ctx, pe, 2));
   if constexpr (bf) {
     if (bfB) {
@@ -1652,16 +1798,19 @@ int sigma_noalloc(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode) {
                                   "supported (the orbital form stages a copy of c)");
   const size_t es = mode == SBCI_F64 ? 8 : 4;
   const size_t half = (es * (size_t)ctx->ndet * (size_t)nvec + 255) / 256 * 256;
-  if (half > kNoAllocScratchBytes / 2)
-    return set_error(SBCI_EINVAL, "allocation-free sigma: nvec * ndet * element size must be at "
-                                  "most 32 MiB (the scratch holds two such operands in 64 MiB)");
+  const size_t rtail = mode == SBCI_F64 ? (8 * (size_t)ctx->A.ns * (size_t)nvec + 255) / 256 * 256 : 0;
+  if (2 * half + rtail > kNoAllocScratchBytes)
+    return set_error(SBCI_EINVAL, "allocation-free sigma: needs two operands of nvec * ndet "
+                                  "elements (and, in FP64, nvec * N_alpha row maxima) within the "
+                                  "64 MiB scratch");
   void *p = nullptr;
   SBCI_TRY(scratch_address(ctx->device, &p));
   unsigned char *base = static_cast<unsigned char *>(p);
   if (mode == SBCI_F64)
     return sigma_t<double, MF64>(ctx, static_cast<const double *>(c), static_cast<double *>(out),
                                  nvec, nullptr, reinterpret_cast<double *>(base),
-                                 reinterpret_cast<double *>(base + half));
+                                 reinterpret_cast<double *>(base + half),
+                                 reinterpret_cast<double *>(base + 2 * half));
   return sigma_t<float, MF32>(ctx, static_cast<const float *>(c), static_cast<float *>(out), nvec,
                               nullptr, reinterpret_cast<float *>(base),
                               reinterpret_cast<float *>(base + half));

@@ -553,6 +553,16 @@ int build_tables(sbci_ctx *ctx, const double *h1, const double *eri) {
   SBCI_HIP(hipMemcpyAsync(ctx->W32, W32.data(), sizeof(float) * np * np, hipMemcpyHostToDevice, st));
   SBCI_HIP(hipMemcpyAsync(ctx->Wbf, Wbf.data(), sizeof(__hip_bfloat16) * np * np,
                           hipMemcpyHostToDevice, st));
+  {
+    double rmax = 0;
+    for (int a = 0; a < np; ++a) {
+      double r = 0;
+      for (int b = 0; b < np; ++b) r += std::fabs(W[(size_t)a * np + b]);
+      rmax = std::fmax(rmax, r);
+    }
+    const int mb = ctx->nb;
+    ctx->opp_wbound = (double)(mb * (n - mb + 1)) * rmax;
+  }
   SBCI_TRY(build_spin(ctx, ctx->A, ctx->na));
   if (ctx->nb == ctx->na) {
     ctx->B = ctx->A;

@@ -129,3 +129,29 @@ def test_sigma_full_size_cas16_sampled(dtype):
     del s, ct
     ctx.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,na,nb,form", [(10, 5, 5, "auto"), (13, 6, 5, "auto"), (15, 7, 2, "auto"),
+                                          (12, 2, 3, "orbital"), (9, 4, 5, "pair")])
+def test_sigma_f64_bitwise_reproducible(n, na, nb, form):
+    """The FP64 sigma is the same to the last bit from call to call: its
+    opposite-spin scatter accumulates in 64-bit fixed point (integer LDS
+    atomics), so the order in which waves add does not matter; every other
+    part sums in a fixed order.  Calls of other sizes in between change how
+    the waves interleave."""
+    ctx, I = _ctx(n, na, nb, seed=5)
+    ctx.set_opp_form(form)
+    c = torch.from_numpy(sigma_inputs(6, 2, ctx.ndet)).cuda()
+    ref = ctx.sigma(c).clone()
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c.cpu().numpy())
+    r = ref.cpu().numpy()
+    assert np.abs(r - want).max() <= 1e-12 * np.abs(want).max()
+    for _ in range(4):
+        ctx.sigma(c[:1].contiguous())
+        got = ctx.sigma(c)
+        assert torch.equal(got.view(torch.int64), ref.view(torch.int64))
+    # the FP64-atomic scatter (reproducibility off) meets the same bar
+    ctx.set_deterministic(False)
+    r = ctx.sigma(c).cpu().numpy()
+    assert np.abs(r - want).max() <= 1e-12 * np.abs(want).max()
+    ctx.close()

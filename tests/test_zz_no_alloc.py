@@ -67,7 +67,7 @@ def test_noalloc_sigma_refuses_what_it_cannot_hold():
     c = torch.zeros(nvec * ctx.ndet, dtype=torch.float64, device="cuda")
     out = torch.zeros_like(c)
     rc = _noalloc()(ctx.h, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()), nvec, sb.F64)
-    assert rc == sb.SBCI_EINVAL and b"32 MiB" in sb.lib().sbci_last_error()
+    assert rc == sb.SBCI_EINVAL and b"64 MiB" in sb.lib().sbci_last_error()
     c32 = torch.zeros(ctx.ndet, dtype=torch.float32, device="cuda")
     o32 = torch.zeros_like(c32)
     rc = _noalloc()(ctx.h, ctypes.c_void_p(c32.data_ptr()), ctypes.c_void_p(o32.data_ptr()), 1, sb.BF16)
