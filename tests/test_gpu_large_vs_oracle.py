@@ -1,0 +1,77 @@
+"""The two large workloads against the oracle.
+
+CAS(14e,14o), 11,778,624 determinants, 5 roots: every form's energies against
+the oracle's FP64 SBCI1 energies (tests/golden/refs.json, written by
+tests/golden/make_refs.py from the oracle only; Algorithm 1, Section S1.4 for
+the excited roots).
+
+CAS(16e,16o), 165,636,900 determinants, ground state: too large for an oracle
+solve, so the GPU eigenvector is checked row by row on sampled determinants:
+the oracle's (H x)[J] - E x[J] is an element of the residual, whose norm the
+convergence test bounds by r0 = 1e-5 (Eq. S61)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sigma as OS  # noqa: E402
+from workloads import CONFIGS, make_integrals  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REFS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "refs.json")))
+
+
+def _ctx(name):
+    import paper_2603_06101_amd as sb
+    cf = CONFIGS[name]
+    I = make_integrals(cf["norb"], cf["rank"], cf["seed"])
+    return sb.Context(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri), I, cf
+
+
+def test_cas14_five_roots_match_the_oracle():
+    ref = REFS["cas14"]
+    ctx, I, cf = _ctx("cas14")
+    assert ref["digest"] == I.digest()
+    want = np.sort(np.array(ref["sbci1"]))
+    # the FP64 sigma at full size is the same to the last bit on a second call
+    c = torch.randn(ctx.ndet, dtype=torch.float64, device="cuda")
+    s1 = ctx.sigma(c).clone()
+    s2 = ctx.sigma(c)
+    assert torch.equal(s1.view(torch.int64), s2.view(torch.int64))
+    del c, s1, s2
+    print("cas14: 5 roots, FP64 / BF16 ladder / FP32 ladder / SBCI2", flush=True)
+    for name, fn in (
+            ("sbci1 f64", lambda: ctx.solve(5, tol=1e-10, opts=dict(precision="f64"), want_vectors=False)),
+            ("sbci1 bf16", lambda: ctx.solve(5, tol=1e-10, opts=dict(precision="bf16"), want_vectors=False)),
+            ("sbci1 f32", lambda: ctx.solve(5, tol=1e-10, opts=dict(precision="f32"), want_vectors=False)),
+            ("sbci2 f64", lambda: ctx.solve2(5, tol=1e-10, want_vectors=False))):
+        r = fn()
+        assert r.status == 0, name
+        got = np.sort(np.asarray(r.energies))
+        assert np.abs(got - want).max() < 1e-8, (name, got - want)
+        assert max(r.report["resid"][:5]) < 1e-5, name
+    ctx.close()
+
+
+def test_cas16_ground_state_on_sampled_oracle_rows():
+    ctx, I, cf = _ctx("cas16")
+    print("cas16: BF16 ladder ground state, then 2000 oracle rows", flush=True)
+    r = ctx.solve(1, tol=1e-10, opts=dict(precision="bf16"))
+    assert r.status == 0 and r.report["nsigma_bf16"] > 0
+    E = float(r.energies[0])
+    x = r.vectors[0].cpu().numpy()
+    ctx.close()
+    assert abs(np.linalg.norm(x) - 1.0) < 1e-10
+    rows = np.sort(np.random.default_rng(16).choice(x.size, 2000, replace=False))
+    hx = OS.sigma_rows(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri, x, rows)
+    res = hx - E * x[rows]
+    # each residual element is bounded by the residual norm (< r0 = 1e-5)
+    assert np.abs(res).max() < 1e-5, np.abs(res).max()
+    # the largest amplitudes are resolved: their rows are checked too
+    top = np.argsort(np.abs(x))[-64:]
+    hx_top = OS.sigma_rows(cf["norb"], cf["na"], cf["nb"], I.h1, I.eri, x, top)
+    assert np.abs(hx_top - E * x[top]).max() < 1e-5
