@@ -536,18 +536,101 @@ int step_t(sbci_ctx *ctx, Solver &S, sbci_step_info *info) {
   return SBCI_OK;
 }
 
-// Section S1.1: the nroots lowest diagonal determinants (ties: lower index).
+// Lexicographic (value, index) order of diagonal entries: the order of
+// Section S1.1's "lowest diagonal elements" with ties broken by lower index.
+__device__ __forceinline__ bool lex_less(double v, int64_t i, double w, int64_t j) {
+  return v < w || (v == w && i < j);
+}
+
+__device__ __forceinline__ void lex_min_into(double &v, int64_t &i, double w, int64_t j) {
+  if (lex_less(w, j, v, i)) {
+    v = w;
+    i = j;
+  }
+}
+
+// Per block: the smallest entry of D, in (value, index) order, among those
+// above the previous pick (*pv, *pi) (all entries when has_prev = 0).  NaN
+// entries are never picked; the sentinel index n means "none".
+__global__ __launch_bounds__(256) void k_argmin_above(const double *__restrict__ D, int64_t n,
+                                                      const double *__restrict__ pv,
+                                                      const int64_t *__restrict__ pi, int has_prev,
+                                                      double *__restrict__ bv, int64_t *__restrict__ bi) {
+  __shared__ double sv[4];
+  __shared__ int64_t si[4];
+  const double v0 = has_prev ? *pv : 0.0;
+  const int64_t i0 = has_prev ? *pi : -1;
+  double best = INFINITY;
+  int64_t bidx = n;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = D[i];
+    if (v == v && (!has_prev || lex_less(v0, i0, v, i))) lex_min_into(best, bidx, v, i);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(best, o);
+    const int64_t j = __shfl_xor(bidx, o);
+    lex_min_into(best, bidx, w, j);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sv[threadIdx.x >> 6] = best;
+    si[threadIdx.x >> 6] = bidx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) lex_min_into(best, bidx, sv[w], si[w]);
+    bv[blockIdx.x] = best;
+    bi[blockIdx.x] = bidx;
+  }
+}
+
+// The pick: the smallest of nb block results, written to (*ov, *oi).
+__global__ __launch_bounds__(64) void k_argmin_final(const double *__restrict__ bv,
+                                                     const int64_t *__restrict__ bi, int nb,
+                                                     int64_t n, double *__restrict__ ov,
+                                                     int64_t *__restrict__ oi) {
+  double best = INFINITY;
+  int64_t bidx = n;
+  for (int b = threadIdx.x; b < nb; b += 64) lex_min_into(best, bidx, bv[b], bi[b]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(best, o);
+    const int64_t j = __shfl_xor(bidx, o);
+    lex_min_into(best, bidx, w, j);
+  }
+  if (threadIdx.x == 0) {
+    *ov = best;
+    *oi = bidx;
+  }
+}
+
+// Section S1.1: the nroots lowest diagonal determinants (ties: lower index),
+// found on the device: pick j is the smallest entry above pick j - 1 in
+// (value, index) order, one read of D per pick, one host copy at the end.
 int lowest_diagonal(sbci_ctx *ctx, int k, std::vector<int64_t> &idx) {
-  std::vector<double> D((size_t)ctx->ndet);
-  SBCI_HIP(hipMemcpyAsync(D.data(), ctx->hdiag, sizeof(double) * ctx->ndet, hipMemcpyDeviceToHost,
-                          ctx->stream));
+  const int64_t n = ctx->ndet;
+  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  double *buf = nullptr;
+  SBCI_HIP(hipMalloc(&buf, sizeof(double) * (2 * (size_t)nb + 2 * (size_t)k)));
+  struct Free {
+    void *p;
+    ~Free() { hipFree(p); }
+  } guard{buf};
+  double *bv = buf, *ov = buf + nb;
+  int64_t *bi = reinterpret_cast<int64_t *>(buf + nb + k);
+  int64_t *oi = bi + nb;
+  for (int j = 0; j < k; ++j) {
+    k_argmin_above<<<nb, 256, 0, ctx->stream>>>(ctx->hdiag, n, j > 0 ? ov + j - 1 : ov,
+                                                j > 0 ? oi + j - 1 : oi, j > 0 ? 1 : 0, bv, bi);
+    k_argmin_final<<<1, 64, 0, ctx->stream>>>(bv, bi, nb, n, ov + j, oi + j);
+    SBCI_CHECK_LAUNCH();
+  }
+  idx.assign((size_t)k, 0);
+  SBCI_HIP(hipMemcpyAsync(idx.data(), oi, sizeof(int64_t) * k, hipMemcpyDeviceToHost, ctx->stream));
   SBCI_HIP(hipStreamSynchronize(ctx->stream));
-  std::vector<int64_t> order((size_t)ctx->ndet);
-  for (int64_t i = 0; i < ctx->ndet; ++i) order[i] = i;
-  std::partial_sort(order.begin(), order.begin() + k, order.end(), [&](int64_t a, int64_t b) {
-    return D[a] < D[b] || (D[a] == D[b] && a < b);
-  });
-  idx.assign(order.begin(), order.begin() + k);
+  for (int j = 0; j < k; ++j)
+    if (idx[j] < 0 || idx[j] >= n)
+      return set_error(SBCI_ENUMERIC, "start vectors: fewer than nroots finite diagonal entries");
   return SBCI_OK;
 }
 
