@@ -44,6 +44,11 @@ PEAK = {  # MI355X published dense peaks; LDS: 128 B/clk/CU x 256 CUs x 2.4 GHz
 }
 
 
+def note(msg):
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +398,7 @@ def dilute45_section(sb, stream, precision):
     ctx = sb.Context(n, m, cf["nb"], I.h1, I.eri, stream=stream)
     torch.cuda.synchronize()
     ns, s = comb(n, m), m * (n - m + 1)
+    nf = 1 + m * (n - m) + comb(m, 2) * comb(n - m, 2)
     out = {"ndet": ctx.ndet, "create_s": round(time.perf_counter() - t, 3),
            "forms": {"same_spin": ctx.same_form(0), "opposite_spin": ctx.opp_form("f64")},
            "sigma": {}}
@@ -406,10 +412,11 @@ def dilute45_section(sb, stream, precision):
             "gdet_per_s": round(ctx.ndet / (sum(ms) / 1e3) / 1e9, 3),
             "kernels_ms": dict(zip(parts, [round(v, 3) for v in ms])),
             # algorithmic rates: 2 s^2 flops per determinant for the opposite-
-            # spin contraction, 2 N_s per determinant and spin for the dense
-            # same-spin product
+            # spin contraction, 2 F (list entries of a string) per determinant
+            # and spin for the same-spin part; the dense product issues 2 N_s
             "opp_tflops": round(2 * s * s * ctx.ndet / (ms[1] / 1e3) / 1e12, 1),
-            "same_dense_tflops": round(2 * ns * ctx.ndet / (ms[0] / 1e3) / 1e12, 1),
+            "same_tflops": round(2 * nf * ctx.ndet / (ms[0] / 1e3) / 1e12, 1),
+            "same_dense_issue_tflops": round(2 * ns * ctx.ndet / (ms[0] / 1e3) / 1e12, 1),
         }
         del o, x
     del c
@@ -417,13 +424,17 @@ def dilute45_section(sb, stream, precision):
     # committed summaries while the kernels' text is unchanged)
     cfgd = dict(cf, name="dilute45")
     ms64 = out["sigma"]["f64"]["kernels_ms"]
-    for key, kname, flops, t_ms in (
-            ("roofline_opp_orbital", "opp_orbital", 2 * s * s * ctx.ndet, ms64["opp_mfma"]),
-            ("roofline_same_dense", "same_dense", 2 * ns * ctx.ndet, ms64["same_alpha"])):
+    # achieved = the method's flops (2 s^2; 2 F for the same-spin part);
+    # issue_frac = what the kernel issues (2 N m s; the dense product's 2 N_s)
+    for key, kname, flops, issued, t_ms in (
+            ("roofline_opp_orbital", "opp_orbital", 2 * s * s * ctx.ndet, 2 * n * cf["nb"] * s * ctx.ndet,
+             ms64["opp_mfma"]),
+            ("roofline_same_dense", "same_dense", 2 * nf * ctx.ndet, 2 * ns * ctx.ndet, ms64["same_alpha"])):
         ach = flops / (t_ms / 1e3) / 1e12
         meas = measured(kname, "f64", cfgd)
         out[key] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f64"] / 1e12,
                     "unit": "TFLOP/s", "frac": round(ach / (PEAK["f64"] / 1e12), 4),
+                    "issue_frac": round(issued / (t_ms / 1e3) / PEAK["f64"], 4),
                     "traffic": meas.get("traffic_bytes_per_launch"),
                     "mfma_busy": meas.get("mfma_busy"), "ms_per_launch": t_ms}
     res = {}
@@ -619,6 +630,58 @@ def cas14_section(sb, stream, reps):
     return out
 
 
+def cpu_legs():
+    """The other CPU-baseline legs, the oracle as it stands on the host cores:
+    SBCI1 and LAPACK eigh at CAS(6,6) (1 root), SBCI1 and Davidson at
+    CAS(10,10) seed 0 (3 roots), each timed once (median of 3 for the
+    sub-second ones); and the stored CAS(14,14) 5-root oracle SBCI1 run
+    (tests/golden/refs.json, timed when the reference was written, on the
+    host that wrote it)."""
+    import statistics
+
+    import numpy as np
+
+    from oracle import hamiltonian as H
+    from oracle import sbci as OSB
+    from oracle import sigma as OS
+    from workloads import make_integrals, start_noise
+    out = {}
+    I = make_integrals(6, 12, 0)
+    op = OS.Operator(6, 3, 3, I.h1, I.eri)
+    x0 = np.zeros(op.ndet)
+    x0[0] = 1.0
+    x0 = x0 + 1e-3 * start_noise(6, 12, 0, op.ndet)
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        r = OSB.sbci1(op, op.diag(), 1, x0=x0, record=False)
+        ts.append(time.perf_counter() - t)
+    out["cas6_sbci1_s"] = round(statistics.median(ts), 4)
+    Hd = H.dense_h_slater_condon(6, 3, 3, I.h1, I.eri)
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        np.linalg.eigvalsh(Hd)
+        ts.append(time.perf_counter() - t)
+    out["cas6_eigh_s"] = round(statistics.median(ts), 5)
+    I = make_integrals(10, 20, 0)
+    op = OS.Operator(10, 5, 5, I.h1, I.eri)
+    d = op.diag()
+    t = time.perf_counter()
+    r = OSB.sbci1(op, d, 3, record=False)
+    out["cas10_sbci1_s"] = round(time.perf_counter() - t, 3)
+    out["cas10_sbci1_nsigma"] = r.nsigma
+    t = time.perf_counter()
+    r = OSB.davidson(op, d, 3)
+    out["cas10_davidson_s"] = round(time.perf_counter() - t, 3)
+    out["cas10_davidson_nsigma"] = r.nsigma
+    ref = refs_section("cas14", make_integrals(14, 28, 0).digest())
+    if ref.get("sbci1_seconds"):
+        out["cas14_sbci1_s_stored"] = ref["sbci1_seconds"]
+        out["cas14_sbci1_nsigma_stored"] = ref.get("sbci1_nsigma")
+    return out
+
+
 def oracle_checks(cfg, I, ndet, sb, stream, seconds, xE=None):
     """The CPU-baseline leg: the oracle's FP64 string sigma on a bounded sample
     of determinant rows, timed on the host cores; the same oracle rows then
@@ -651,6 +714,7 @@ def oracle_checks(cfg, I, ndet, sb, stream, seconds, xE=None):
             "sample": f"{n2} random determinant rows of the FP64 string sigma "
                       f"({cfg['norb']} orbitals, {ndet} determinants), {dt:.1f} s"}
     checks = {"rows": n2, "sigma_rel_err": {}}
+    base["legs"] = cpu_legs()
     ctx = sb.Context(cfg["norb"], cfg["na"], cfg["nb"], I.h1, I.eri, stream=stream)
     cg = torch.from_numpy(c).cuda()
     idx = torch.from_numpy(rows).cuda()
@@ -753,16 +817,19 @@ def main():
         ctx.close()
         return r
 
-    for _ in range(a.warmup):
+    for w in range(a.warmup):
         step("f64")
+        note(f"warm-up step {w + 1}/{a.warmup} done")
     torch.cuda.synchronize()
     times, res = [], []
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for k in range(a.steps):
         ts = time.perf_counter()
         res.append(step("f64"))
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
+        if (k + 1) % 4 == 0 or k + 1 == a.steps:
+            note(f"timed step {k + 1}/{a.steps}: {times[-1]:.3f} s")
     t1 = time.perf_counter()
     ms = (t1 - t0) / a.steps * 1e3
     last = res[-1]
@@ -776,6 +843,7 @@ def main():
     # each, context build included, like the timed step)
     mixed = {}
     for prec in ("bf16", "f32"):
+        note(f"precision form {prec}")
         tt, rr = [], None
         for _ in range(3):
             ts = time.perf_counter()
@@ -854,16 +922,22 @@ def main():
         "roofline_same": roof_same,
     }
     if a.workload == "cas16" and not a.no_configs:
+        note("section cas14")
         line["cas14"] = cas14_section(sb, stream, 3)
     if not a.no_batch:
+        note("section batch")
         line["batch"] = batch_section(sb, a.precision)
     if not a.no_configs:
+        note("sections cas6, cas10")
         line.update(small_sections(sb, stream))
         if a.workload != "cas16":
             line["cas16"] = cas16_section(sb, stream, a.precision)
+        note("section dilute45")
         line["dilute45"] = dilute45_section(sb, stream, a.precision)
+        note("section symmetry")
         line["symmetry"] = sym_section(sb, stream)
     if not a.no_cpu_baseline:
+        note("cpu baseline and oracle checks")
         xE = None
         if not a.no_configs:
             r = step("f64", want_vectors=True)
