@@ -105,6 +105,11 @@ typedef struct sbci_opts {
   double bf16_eps0, bf16_r0;  /* SBCI_BF16: BF16 phase hands over to FP32 at these   */
   int max_cycle2;             /* SBCI2 steps per segment before a forced restart (10,
                                  Section S2.5)                                          */
+  int s78_printed;            /* SBCI2: 1 projects the images off the converged roots
+                                 with E_c x_c, as Eq. S78 is printed; 0 (default) with
+                                 the image H x_c carried to each root's acceptance
+                                 (an accepted x_c keeps a residual, which E_c x_c
+                                 would leave in the images)                             */
 } sbci_opts;
 
 typedef struct sbci_report {

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
         ("max_space", ctypes.c_int),
         ("x0", ctypes.POINTER(ctypes.c_double)),
         ("bf16_eps0", ctypes.c_double), ("bf16_r0", ctypes.c_double),
-        ("max_cycle2", ctypes.c_int),
+        ("max_cycle2", ctypes.c_int), ("s78_printed", ctypes.c_int),
     ]
 
 

@@ -106,6 +106,7 @@ void sbci_default_opts(sbci_opts *o) {
   o->bf16_eps0 = 1e-5;
   o->bf16_r0 = 1e-2;
   o->max_cycle2 = 10;
+  o->s78_printed = 0;
 }
 
 const char *sbci_last_error(void) { return g_err.c_str(); }

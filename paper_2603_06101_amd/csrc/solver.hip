@@ -54,6 +54,10 @@ struct Solver {
   float *v32[NV] = {};
   std::vector<double *> xc64;
   std::vector<float *> xc32;
+  // converged-root storage allocated when a solve begins, taken as roots
+  // converge (no allocation inside the step loop)
+  std::vector<double *> pool64;
+  std::vector<float *> pool32;
   // H x_c of the first Hxc64.size() converged roots (SBCI2 keeps them); where
   // present they replace E_c x_c in the projections of X (Eqs. S5, S78)
   std::vector<double *> Hxc64;
@@ -294,16 +298,26 @@ int next_rung(sbci_ctx *ctx, Solver &S) {
 // the second Ritz vector of the converging step (Section S1.4).
 int finish_root(sbci_ctx *ctx, Solver &S, double xn, bool second_ok) {
   double *xc = nullptr;
-  SBCI_HIP(hipMalloc(&xc, sizeof(double) * S.n));
-  S.alloc_bytes += sizeof(double) * S.n;
-  SBCI_TRY((convert<double, double>(ctx, S.n, xc, S.v64[X_], 1.0 / xn)));
+  if (!S.pool64.empty()) {
+    xc = S.pool64.back();
+    S.pool64.pop_back();
+  } else {
+    SBCI_HIP(hipMalloc(&xc, sizeof(double) * S.n));
+    S.alloc_bytes += sizeof(double) * S.n;
+  }
   S.xc64.push_back(xc);
+  SBCI_TRY((convert<double, double>(ctx, S.n, xc, S.v64[X_], 1.0 / xn)));
   if (S.o.precision != SBCI_F64) {
     float *x32 = nullptr;
-    SBCI_HIP(hipMalloc(&x32, sizeof(float) * S.n));
-    S.alloc_bytes += sizeof(float) * S.n;
-    SBCI_TRY((convert<float, double>(ctx, S.n, x32, xc, 1.0)));
+    if (!S.pool32.empty()) {
+      x32 = S.pool32.back();
+      S.pool32.pop_back();
+    } else {
+      SBCI_HIP(hipMalloc(&x32, sizeof(float) * S.n));
+      S.alloc_bytes += sizeof(float) * S.n;
+    }
     S.xc32.push_back(x32);
+    SBCI_TRY((convert<float, double>(ctx, S.n, x32, xc, 1.0)));
   }
   const double Enew = S.E;
   S.Ec.push_back(Enew);
@@ -758,9 +772,13 @@ void free_solver(Solver &S) {
   for (auto p : S.xc64) hipFree(p);
   for (auto p : S.xc32) hipFree(p);
   for (auto p : S.Hxc64) hipFree(p);
+  for (auto p : S.pool64) hipFree(p);
+  for (auto p : S.pool32) hipFree(p);
   S.xc64.clear();
   S.xc32.clear();
   S.Hxc64.clear();
+  S.pool64.clear();
+  S.pool32.clear();
   hipFree(S.red);
   S.red = nullptr;
 }
@@ -777,6 +795,7 @@ int resolve_opts(const sbci_opts *opt, double tol, int nroots, int64_t ndet, sbc
   if (o.precision != SBCI_F64 && o.precision != SBCI_F32 && o.precision != SBCI_BF16)
     return set_error(SBCI_EINVAL, "unknown precision");
   if (o.max_cycle < 1 || o.max_steps < 1) return set_error(SBCI_EINVAL, "max_cycle, max_steps >= 1");
+  if (o.s78_printed != 0 && o.s78_printed != 1) return set_error(SBCI_EINVAL, "s78_printed must be 0 or 1");
   return SBCI_OK;
 }
 
@@ -796,6 +815,18 @@ int solver_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {
   S->t0 = now_s();
   ctx->trace.clear();
   SBCI_TRY(alloc_solver(ctx, *S, S->o.precision != SBCI_F64));
+  for (int i = 0; i < nroots; ++i) {
+    double *p = nullptr;
+    SBCI_HIP(hipMalloc(&p, sizeof(double) * S->n));
+    S->pool64.push_back(p);
+    S->alloc_bytes += sizeof(double) * S->n;
+    if (S->o.precision != SBCI_F64) {
+      float *q = nullptr;
+      SBCI_HIP(hipMalloc(&q, sizeof(float) * S->n));
+      S->pool32.push_back(q);
+      S->alloc_bytes += sizeof(float) * S->n;
+    }
+  }
   SBCI_TRY(initial_vector(ctx, *S));
   if (S->o.precision != SBCI_F64) {
     SBCI_TRY((convert<float, double>(ctx, S->n, S->v32[X_], S->v64[X_], 1.0)));
@@ -1169,18 +1200,28 @@ int pair_start_vectors(sbci_ctx *ctx, Solver &S, Pair &P, int k) {
 // exact eigenvector; an accepted x_c^j keeps a residual, and E_c x_c would
 // leave it in V for the rest of the run, shifting the later Ritz energies at
 // first order.  The image carried to acceptance is H x_c^j up to rounding.
+// With opts.s78_printed the images are projected with E_c^j x_c^j as printed.
 int project_off(sbci_ctx *ctx, Solver &S, Pair &P, double *v, double *V) {
   const int nc = (int)S.Ec.size();
   if (nc == 0) return SBCI_OK;
-  if ((int)S.Hxc64.size() != nc) return set_error(SBCI_ENUMERIC, "SBCI2: internal: a converged root has no image");
+  const bool printed = S.o.s78_printed != 0;
+  if (!printed && (int)S.Hxc64.size() != nc)
+    return set_error(SBCI_ENUMERIC, "SBCI2: internal: a converged root has no image");
   std::vector<const double *> xcp(S.xc64.begin(), S.xc64.end());
-  std::vector<const double *> hcp(S.Hxc64.begin(), S.Hxc64.end());
   double d[16];
   SBCI_TRY(dots_h(ctx, P, S.n, v, xcp.data(), nc, d));
-  double cx[16];
-  for (int j = 0; j < nc; ++j) cx[j] = -d[j];
+  double cx[16], cE[16];
+  for (int j = 0; j < nc; ++j) {
+    cx[j] = -d[j];
+    cE[j] = -S.Ec[j] * d[j];
+  }
   SBCI_TRY(lincomb<double>(ctx, S.n, v, xcp.data(), cx, nc, 1.0));
-  SBCI_TRY(lincomb<double>(ctx, S.n, V, hcp.data(), cx, nc, 1.0));
+  if (printed) {
+    SBCI_TRY(lincomb<double>(ctx, S.n, V, xcp.data(), cE, nc, 1.0));
+  } else {
+    std::vector<const double *> hcp(S.Hxc64.begin(), S.Hxc64.end());
+    SBCI_TRY(lincomb<double>(ctx, S.n, V, hcp.data(), cx, nc, 1.0));
+  }
   return SBCI_OK;
 }
 
@@ -1647,11 +1688,13 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
       SBCI_TRY((convert<float, double>(ctx, n, x32, xc, 1.0)));
       S.xc32.push_back(x32);
     }
-    double *hxc = nullptr;
-    SBCI_HIP(hipMalloc(&hxc, sizeof(double) * n));
-    S.alloc_bytes += sizeof(double) * n;
-    S.Hxc64.push_back(hxc);
-    SBCI_TRY((convert<double, double>(ctx, n, hxc, P.X[0], 1.0 / xn[0])));
+    if (!S.o.s78_printed) {  // the carried image of the accepted root (Eq. S78 reading)
+      double *hxc = nullptr;
+      SBCI_HIP(hipMalloc(&hxc, sizeof(double) * n));
+      S.alloc_bytes += sizeof(double) * n;
+      S.Hxc64.push_back(hxc);
+      SBCI_TRY((convert<double, double>(ctx, n, hxc, P.X[0], 1.0 / xn[0])));
+    }
     S.Ec.push_back(E[0]);
     S.rep.t_converged[std::min(alpha, 15)] = now_s() - S.t0;
     S.rep.resid[std::min(alpha, 15)] = std::sqrt(dz2[0]);

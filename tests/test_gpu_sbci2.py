@@ -146,3 +146,16 @@ def test_sbci2_precision_ladder_cas10(seed, precision):
     assert any(s["reason"] == "refine" for s in r.trace)
     _check_eigenpairs(10, 5, 5, I20, r.energies, r.vectors.cpu().numpy())
     ctx.close()
+
+
+@pytest.mark.parametrize("n,na,nb,nroots,seed", [(6, 3, 3, 3, 0), (7, 3, 4, 3, 3), (8, 4, 4, 3, 5)])
+def test_sbci2_printed_s78_matches_oracle(n, na, nb, nroots, seed):
+    """Eq. S78 as printed (opts.s78_printed = 1: the images are projected with
+    E_c x_c): the GPU against the oracle's printed form, root by root."""
+    ctx, I = _ctx(n, na, nb, seed)
+    op = OS.Operator(n, na, nb, I.h1, I.eri)
+    ref = OS2.sbci2(op, op.diag(), nroots, OS2.Options2(s78_images=False))
+    r = ctx.solve2(nroots, tol=1e-10, opts=dict(s78_printed=1))
+    assert r.status == 0
+    assert np.abs(np.asarray(r.energies) - ref.energies).max() < 1e-8, (r.energies, ref.energies)
+    ctx.close()
