@@ -401,20 +401,26 @@ __device__ inline void fix_scale(const double *__restrict__ rowmax, const Ent *_
     int x = 0;
     frexp(bnd, &x);  // bnd < 2^x
     int ex = 62 - x;
-    ex = ex > 1000 ? 1000 : (ex < -1000 ? -1000 : ex);
+    ex = ex > 900 ? 900 : (ex < -900 ? -900 : ex);
     scale = ldexp(1.0, ex);
     inv = ldexp(1.0, -ex);
   }
 }
 
-// Scatter one contribution into sigma's row: FP64 in 64-bit fixed point
-// (exact integer adds, so the row does not depend on the scatter order),
-// the other flavours with FP64 atomics.
+// Scatter one contribution into sigma's row.  FP64 in 64-bit fixed point
+// (exact integer adds, so the row does not depend on the scatter order): v
+// is already in fixed-point units (|v| < 2^62, the scale is folded into the
+// A tile) and is taken to floor(v) by a split at 2^32, hi = floor(v / 2^32),
+// lo = v - hi 2^32 in [0, 2^32), both exact; the other flavours add with
+// FP64 atomics.
 template <bool FIX>
-__device__ __forceinline__ void scatter_add(double *slot, double v, double scale) {
+__device__ __forceinline__ void scatter_add(double *slot, double v) {
   if constexpr (FIX) {
-    const long long q = __double2ll_rn(v * scale);
-    atomicAdd(reinterpret_cast<unsigned long long *>(slot), (unsigned long long)q);
+    const double hi = floor(v * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, v);
+    const unsigned long long q =
+        ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+    atomicAdd(reinterpret_cast<unsigned long long *>(slot), q);
   } else {
     atomicAdd(slot, v);
   }
@@ -521,7 +527,8 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
       A v = M::cvt(0.0f);
       if (w != kPadEntry && row < npair) {
         const int kl = w & 0x7fffffff;
-        const double x = Wd ? Wd[(int64_t)row * npair + kl] : (double)Wf[(int64_t)row * npair + kl];
+        double x = Wd ? Wd[(int64_t)row * npair + kl] : (double)Wf[(int64_t)row * npair + kl];
+        if constexpr (FIX) x *= fscale;  // a power of two: exact; M comes out in fixed-point units
         v = M::cvt(w < 0 ? -x : x);
       }
       Ws[row * LDW + k] = v;
@@ -601,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
             if (cd != kInvalid) {
               Acc v = (Acc)out[u][r];
               if (cd & 1u) v = -v;
-              scatter_add<FIX>(&acc[cd >> 1], v, fscale);
+              scatter_add<FIX>(&acc[cd >> 1], v);
             }
           }
         }
@@ -858,7 +865,8 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
         if (w != kPadEntry && p < norb) {
           const int kl = w & 0x7fffffff;
           const int64_t pq = pair_index(p, q);
-          const double x = Wd ? Wd[pq * npair + kl] : (double)Wf[pq * npair + kl];
+          double x = Wd ? Wd[pq * npair + kl] : (double)Wf[pq * npair + kl];
+          if constexpr (FIX) x *= fscale;  // exact: M in fixed-point units
           v = M::cvt(w < 0 ? -x : x);
         }
       }
@@ -939,7 +947,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
             if (cd != kInvalid && tw < tlen32) {
               Acc v = (Acc)out[u][r];
               if (cd & 1u) v = -v;
-              scatter_add<FIX>(&acc[tw], v, fscale);
+              scatter_add<FIX>(&acc[tw], v);
             }
           }
         }
