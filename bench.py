@@ -739,8 +739,8 @@ def oracle_checks(cfg, I, ndet, sb, stream, seconds, xE=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the multi-GPU sharding is described, not built)", file=sys.stderr)
+        print("bench.py: the path runs on one GPU; --gpus must be 1 "
+              "(sharding over several GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
     import statistics
 
