@@ -1,7 +1,8 @@
 """The two large workloads against the oracle.
 
 CAS(14e,14o), 11,778,624 determinants, 5 roots: every form's energies against
-the oracle's FP64 SBCI1 energies (tests/golden/refs.json, written by
+the oracle's FP64 SBCI1 energies and the five lowest Lanczos eigenvalues of
+the oracle's sigma (tests/golden/refs.json, written by
 tests/golden/make_refs.py from the oracle only; Algorithm 1, Section S1.4 for
 the excited roots).
 
@@ -37,6 +38,7 @@ def test_cas14_five_roots_match_the_oracle():
     ctx, I, cf = _ctx("cas14")
     assert ref["digest"] == I.digest()
     want = np.sort(np.array(ref["sbci1"]))
+    lanczos = np.array(ref["eigsh"][:5])
     # the FP64 sigma at full size is the same to the last bit on a second call
     c = torch.randn(ctx.ndet, dtype=torch.float64, device="cuda")
     s1 = ctx.sigma(c).clone()
@@ -53,6 +55,7 @@ def test_cas14_five_roots_match_the_oracle():
         assert r.status == 0, name
         got = np.sort(np.asarray(r.energies))
         assert np.abs(got - want).max() < 1e-8, (name, got - want)
+        assert np.abs(got - lanczos).max() < 1e-8, (name, got - lanczos)
         assert max(r.report["resid"][:5]) < 1e-5, name
     ctx.close()
 

@@ -138,3 +138,19 @@ def test_start_vectors_section_S1_1():
     sub = Hs[np.ix_(order, order)]
     assert np.abs(np.sort(E) - np.linalg.eigvalsh(sub)).max() < 1e-13
     assert np.abs(X0 - x0 @ Hs).max() < 1e-13
+
+
+def test_stored_cas14_roots_are_the_lowest_lanczos_values():
+    """The stored CAS(14,14) run (tests/golden/make_refs.py, oracle only): the
+    five SBCI1 roots (Algorithm 1 with the deflated excited roots of Section
+    S1.4) are the five lowest eigenvalues that an independent Lanczos solver
+    (scipy eigsh on the oracle's sigma) finds, below a sixth one."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "refs.json")))["cas14"]
+    assert ref["digest"] == make_integrals(14, 28, 0).digest()
+    e = np.sort(np.array(ref["sbci1"]))
+    lan = np.array(ref["eigsh"])
+    assert len(lan) == 6 and ref["sbci1_converged"]
+    assert np.abs(e - lan[:5]).max() < 1e-9
+    assert lan[5] - e[-1] > 1e-3
