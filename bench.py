@@ -546,6 +546,7 @@ def batch_section(sb, precision):
                                   "span_s": round(float(spans[crit]), 4),
                                   "steps": r.instances[crit]["nsteps"]},
             "median_instance_span_s": round(float(np.median(spans)), 5),
+            "teams": {"instances": r.report["nteams"], "workgroups": r.report["team_workgroups"]},
         }
     # the faster mixed form against FP64
     best = min(("f32", "bf16"), key=lambda p: res[p].report["seconds"])

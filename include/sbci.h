@@ -329,8 +329,13 @@ int sbci_solve2(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
  * whole SBCI1 state machine of one instance (Algorithm 1 with Sections
  * S1.1-S1.5: start vectors, steps, restarts, deflation against the lower
  * roots, the precision hand-overs of sbci_solve); workgroups take instances
- * from a device queue.  Limits per instance: 1 <= norb <= 10 (at most 252
- * strings per spin), 1 <= nroots <= min(4, N_det).
+ * from a device queue.  An instance whose estimated work exceeds the
+ * balanced share of one workgroup runs on a team of up to max_team
+ * co-resident workgroups that split its rows and meet at bounded barriers
+ * (the device should not be shared with other work during the solve: a team
+ * that waits longer than one second ends its instance with SBCI_EDEVICE).
+ * Limits per instance: 1 <= norb <= 10 (at most 252 strings per spin),
+ * 1 <= nroots <= min(4, N_det).
  */
 typedef struct sbci_batch sbci_batch;
 
@@ -340,6 +345,7 @@ typedef struct sbci_batch_config {
   int wg_per_cu;  /* persistent workgroups per compute unit: 1..4              */
   int order;      /* queue order: 0 = largest estimated work first, 1 = input  */
   int k_panel;    /* K panel of the same-spin MFMA products in LDS: 8 or 16    */
+  int max_team;   /* workgroups per instance at most: 1 (no teams) .. 4; 0 = 4 */
 } sbci_batch_config;
 
 typedef struct sbci_batch_report {
@@ -351,7 +357,9 @@ typedef struct sbci_batch_report {
   int64_t det_sigma;         /* sum over instances of N_det x sigma applications */
   int64_t nsteps, nrestarts; /* summed over instances                           */
   int ninst_converged;       /* instances with status SBCI_OK                   */
-  int threads, wg_per_cu, order, k_panel;   /* the launch shape used           */
+  int threads, wg_per_cu, order, k_panel, max_team;  /* the launch shape used  */
+  int nteams;                /* instances run by a team of workgroups          */
+  int team_workgroups;       /* workgroups in those teams                       */
 } sbci_batch_report;
 
 /* Per-instance outcome of a batch solve (times from the device real-time

@@ -82,7 +82,7 @@ _P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int6
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I)]
+    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -100,7 +100,8 @@ class BatchReport(ctypes.Structure):
     _fields_ = [
         ("seconds", _D), ("span_seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
         ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
-        ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I),
+        ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I),
+        ("nteams", _I), ("team_workgroups", _I),
     ]
 
     def as_dict(self):

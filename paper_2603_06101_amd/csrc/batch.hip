@@ -12,6 +12,16 @@
 //     (or input order), so uneven sizes balance across the 256 CUs.  Every
 //     workgroup leaves when the queue is exhausted; every instance ends after
 //     at most max_steps steps per root.
+//   * Teams: an instance whose estimated work exceeds the balanced share of
+//     one workgroup runs on a team of 2-4 workgroups (the lowest block
+//     indices, dispatched first and co-resident).  Each member owns a range
+//     of 16-row alpha tiles: its rows of sigma and of every vector pass.
+//     The members run the same state machine on the same reduced values (the
+//     team sums the members' partials in member order), so they take the same
+//     decisions; a barrier (agent-scope release / acquire around a counter)
+//     sits in every reduction and before every sigma, whose input spans all
+//     members' rows.  Every wait is bounded: past one second the team aborts
+//     the instance with SBCI_EDEVICE.
 //   * sigma inside a workgroup: the one-electron and same-spin parts as two
 //     dense MFMA products C * H_beta + H_alpha * C (for norb <= 10 these
 //     operators are 50-95 % dense) with LDS-staged K panels; the
@@ -44,6 +54,7 @@ constexpr int BMAX_NS = 252; // strings per spin, C(10, 5)
 constexpr int BMAX_S = 30;   // single excitations per string, 5 * 6
 constexpr int BMAX_NP = 64;  // pair rows (55 for norb = 10), padded to 16
 constexpr int NVW = 7;       // work vectors: x, X, y, Y, za, zb, Z
+constexpr int BMAX_TEAM = 4; // workgroups per instance
 enum { SX = 0, SXX = 1, SY = 2, SYY = 3, SZA = 4, SZB = 5, SZ = 6 };
 
 struct BInst {
@@ -83,13 +94,84 @@ template <int NT>
 struct Red {
   double w[NT / 64][16];
   double out[16];
+  unsigned gen;  // team barriers passed by this member
+  unsigned red;  // team reductions done (selects the partials buffer)
+  int abort;     // the team gave up waiting
 };
 
-// Sum v[0..q) over the workgroup; the result lands in r.out (all threads
-// read it after the trailing barrier).  Fixed order: lanes by xor tree,
-// waves in index order.
+// Team state in global memory, one per team instance (zeroed by the reset
+// kernel before every solve).
+struct TeamSync {
+  unsigned cnt;    // arrivals, monotonic over the solve
+  unsigned abort;  // set by the first member that times out
+  unsigned pad[62];
+  double part[2][BMAX_TEAM][16];  // partial sums, double-buffered by reduction
+};
+
+// The rows a workgroup owns: all of an instance (T = 1), or member m's range
+// of 16-row alpha tiles.
+struct Team {
+  TeamSync *ts;
+  int T, m;
+  int t0, t1;        // alpha tiles
+  int a0, a1;        // alpha rows
+  int64_t r0, r1;    // determinant rows
+};
+
+__device__ inline Team make_team(int nsa, int64_t nsb, TeamSync *ts, int T, int m) {
+  Team t;
+  t.ts = ts;
+  t.T = T;
+  t.m = m;
+  const int tiles = (nsa + 15) / 16;
+  t.t0 = m * tiles / T;
+  t.t1 = (m + 1) * tiles / T;
+  t.a0 = t.t0 * 16 < nsa ? t.t0 * 16 : nsa;
+  t.a1 = t.t1 * 16 < nsa ? t.t1 * 16 : nsa;
+  t.r0 = (int64_t)t.a0 * nsb;
+  t.r1 = (int64_t)t.a1 * nsb;
+  return t;
+}
+
+constexpr uint64_t kTeamWaitTicks = 100000000ull;  // 1 s of the 100 MHz real-time counter
+
+// Team barrier: every member's prior global writes become visible to every
+// member.  Each thread releases at agent scope, thread 0 arrives and waits
+// (bounded) for all members, each thread acquires.  A lone workgroup only
+// synchronises its threads.
+template <int NT>
+__device__ void team_sync(const Team &tm, Red<NT> &R) {
+  if (tm.T <= 1) {
+    __syncthreads();
+    return;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0 && !R.abort) {
+    const unsigned target = (R.gen + 1u) * (unsigned)tm.T;
+    __hip_atomic_fetch_add(&tm.ts->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      if (__hip_atomic_load(&tm.ts->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(&tm.ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          __builtin_amdgcn_s_memrealtime() - t0 > kTeamWaitTicks) {
+        __hip_atomic_store(&tm.ts->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R.abort = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    R.gen += 1u;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Sum v[0..q) over the workgroup, then over the team; the result lands in
+// r.out (all threads read it after the trailing barrier).  Fixed order:
+// lanes by xor tree, waves in index order, members in index order.
 template <int NT, int Q>
-__device__ void wg_sum(double (&v)[Q], int q, Red<NT> &r) {
+__device__ void wg_sum(double (&v)[Q], int q, Red<NT> &r, const Team &tm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -108,6 +190,19 @@ __device__ void wg_sum(double (&v)[Q], int q, Red<NT> &r) {
     r.out[threadIdx.x] = s;
   }
   __syncthreads();
+  if (tm.T > 1) {
+    const int buf = (int)(r.red & 1u);
+    if ((int)threadIdx.x < q) tm.ts->part[buf][tm.m][threadIdx.x] = r.out[threadIdx.x];
+    team_sync<NT>(tm, r);
+    if ((int)threadIdx.x < q) {
+      double s = 0;
+      for (int mm = 0; mm < tm.T; ++mm) s += tm.ts->part[buf][mm][threadIdx.x];
+      r.out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) r.red += 1u;
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ control state
@@ -163,13 +258,14 @@ struct DenseH<float> {
 
 // One-electron and same-spin part as two dense products on MFMA:
 //   out = C * H_beta + H_alpha * C       (C is [ns_a][ns_b]; H_s symmetric)
-// For norb <= 10 the same-spin operators are 50-95 % dense, so the dense
-// form does little extra work and runs at matrix-core rate.  K panels of
-// both operands are staged in LDS; each wavefront owns whole 16-row tile
-// rows and a block of CB column tiles per pass.
+// for the output tile rows [tr0, tr1) (16 alpha rows each).  For norb <= 10
+// the same-spin operators are 50-95 % dense, so the dense form does little
+// extra work and runs at matrix-core rate.  K panels of both operands are
+// staged in LDS; each wavefront owns whole 16-row tile rows and a block of
+// CB column tiles per pass.
 template <typename T, typename M, int NT>
 __device__ void wg_same_dense(const BInst &I, const T *__restrict__ c, T *__restrict__ out,
-                              int kp, char *lds) {
+                              int kp, char *lds, int tr0, int tr1) {
   static_assert(M::KPL == 1 && M::KSTEP == 4, "dense same-spin GEMM uses 16x16x4 MFMA");
   using Frag = typename M::Frag;
   using Out = typename M::Out;
@@ -178,8 +274,9 @@ __device__ void wg_same_dense(const BInst &I, const T *__restrict__ c, T *__rest
   constexpr int RW = (TMMAX + NW - 1) / NW;          // tile rows per wave
   constexpr int CB = RW >= 8 ? 1 : 8 / RW;           // column tiles per wave and pass
   const int nsa = I.ns_a, nsb = I.ns_b;
-  const int tm = (nsa + 15) / 16, tn = (nsb + 15) / 16;
+  const int tm = tr1 - tr0, tn = (nsb + 15) / 16;  // tm <= TMMAX
   const int mp = tm * 16;
+  const int row0 = tr0 * 16;
   const int lda = kp + 1, ldb = CB * 16 + 1;
   T *Ap = reinterpret_cast<T *>(lds);                 // [mp][lda]
   T *Bp = Ap + (size_t)(TMMAX * 16) * lda;            // [kp][ldb]
@@ -195,11 +292,12 @@ __device__ void wg_same_dense(const BInst &I, const T *__restrict__ c, T *__rest
     for (int prod = 0; prod < 2; ++prod) {
       const int K = prod == 0 ? nsb : nsa;
       for (int k0 = 0; k0 < K; k0 += kp) {
-        // A panel: rows of C (prod 0) or H_alpha (prod 1), columns k0..k0+kp
+        // A panel: this range's rows of C (prod 0) or H_alpha (prod 1),
+        // columns k0..k0+kp
         for (int e = tid; e < mp * kp; e += NT) {
-          const int r = e / kp, k = e - r * kp, kk = k0 + k;
+          const int r = e / kp, k = e - r * kp, kk = k0 + k, rr = row0 + r;
           T v = (T)0;
-          if (r < nsa && kk < K) v = prod == 0 ? c[(int64_t)r * nsb + kk] : Ha[(int64_t)r * nsa + kk];
+          if (rr < nsa && kk < K) v = prod == 0 ? c[(int64_t)rr * nsb + kk] : Ha[(int64_t)rr * nsa + kk];
           Ap[r * lda + k] = v;
         }
         // B panel: rows k0..k0+kp of H_beta (prod 0) or C (prod 1), CB column tiles
@@ -237,9 +335,92 @@ __device__ void wg_same_dense(const BInst &I, const T *__restrict__ c, T *__rest
           const int col = (n0 + v) * 16 + li;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = tr * 16 + M::orow(g, r);
+            const int row = row0 + tr * 16 + M::orow(g, r);
             if (row < nsa && col < nsb) out[(int64_t)row * nsb + col] = (T)acc[u][v][r];
           }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Team form of the same dense products.  A member owns few tile rows
+// (5-8 of 16 at norb = 10), so a fixed rows-per-wave split would idle most
+// waves; here each pass spans up to kPairCB column tiles and its (tile row,
+// column tile) pairs are dealt to all waves, up to PW per wave.  Both
+// fragments of every MFMA come from LDS.
+constexpr int kPairCB = 8;
+
+template <typename T, typename M, int NT>
+__device__ void wg_same_pairs(const BInst &I, const T *__restrict__ c, T *__restrict__ out, int kp,
+                              char *lds, int tr0, int tr1) {
+  static_assert(M::KPL == 1 && M::KSTEP == 4, "dense same-spin GEMM uses 16x16x4 MFMA");
+  using Frag = typename M::Frag;
+  using Out = typename M::Out;
+  constexpr int NW = NT / 64;
+  constexpr int PW = 8;
+  constexpr int TMMAX = (BMAX_NS + 15) / 16;
+  const int nsa = I.ns_a, nsb = I.ns_b;
+  const int tm = tr1 - tr0, tn = (nsb + 15) / 16;
+  const int mp = tm * 16, row0 = tr0 * 16;
+  int cbp = (NW * PW) / (tm > 0 ? tm : 1);
+  cbp = cbp > kPairCB ? kPairCB : cbp;
+  cbp = cbp > tn ? tn : cbp;
+  cbp = cbp < 1 ? 1 : cbp;
+  const int lda = kp + 1, ldb = cbp * 16 + 1;
+  T *Ap = reinterpret_cast<T *>(lds);                 // [mp][lda]
+  T *Bp = Ap + (size_t)(TMMAX * 16) * lda;            // [kp][ldb]
+  const T *Ha = DenseH<T>::a(I), *Hb = DenseH<T>::b(I);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, g = lane >> 4;
+  for (int n0 = 0; n0 < tn && tm > 0; n0 += cbp) {
+    const int ncb = tn - n0 < cbp ? tn - n0 : cbp;
+    const int np = tm * ncb;
+    Out acc[PW];
+#pragma unroll
+    for (int j = 0; j < PW; ++j) acc[j] = Out{0, 0, 0, 0};
+    for (int prod = 0; prod < 2; ++prod) {
+      const int K = prod == 0 ? nsb : nsa;
+      for (int k0 = 0; k0 < K; k0 += kp) {
+        for (int e = tid; e < mp * kp; e += NT) {
+          const int r = e / kp, k = e - r * kp, kk = k0 + k, rr = row0 + r;
+          T v = (T)0;
+          if (rr < nsa && kk < K) v = prod == 0 ? c[(int64_t)rr * nsb + kk] : Ha[(int64_t)rr * nsa + kk];
+          Ap[r * lda + k] = v;
+        }
+        for (int e = tid; e < kp * ncb * 16; e += NT) {
+          const int k = e / (ncb * 16), j = e - k * (ncb * 16), kk = k0 + k, col = n0 * 16 + j;
+          T v = (T)0;
+          if (kk < K && col < nsb)
+            v = prod == 0 ? Hb[(int64_t)kk * nsb + col] : c[(int64_t)kk * nsb + col];
+          Bp[k * ldb + j] = v;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kp / 4; ++ks) {
+#pragma unroll
+          for (int j = 0; j < PW; ++j) {
+            const int p = wv + NW * j;
+            if (p < np) {
+              const int tr = p % tm, cv = p / tm;
+              const Frag a = Ap[(tr * 16 + li) * lda + ks * 4 + g];
+              const Frag b = Bp[(ks * 4 + g) * ldb + cv * 16 + li];
+              acc[j] = M::mma(a, b, acc[j]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      const int p = wv + NW * j;
+      if (p < np) {
+        const int tr = p % tm, cv = p / tm;
+        const int col = (n0 + cv) * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + tr * 16 + M::orow(g, r);
+          if (row < nsa && col < nsb) out[(int64_t)row * nsb + col] = (T)acc[j][r];
         }
       }
     }
@@ -266,17 +447,26 @@ constexpr size_t kWBytes = sizeof(double) * BMAX_NP * BMAX_NP;  // LDS copy of t
 
 // out = H c for one vector of instance I (T = double: FP64 everywhere;
 // T = float: FP32 same-spin part, MFMA flavour M for the opposite spin).
+// Rows [tm.a0, tm.a1) of out = H c for one vector of instance I (c: all
+// rows, complete before the call).
 template <typename T, typename M, int NT>
 __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__ c,
-                         T *__restrict__ out, char *lds, uint64_t *tick) {
+                         T *__restrict__ out, char *lds, uint64_t *tick, const Team &tm) {
   uint64_t tk = __builtin_amdgcn_s_memrealtime();
   const int tid = threadIdx.x;
   const int nsa = I.ns_a, nsb = I.ns_b;
   // (1) one-electron and same-spin parts of both spins (dense MFMA products)
-  if constexpr (std::is_same<T, double>::value)
-    wg_same_dense<double, MF64, NT>(I, c, out, P.kp, lds);
-  else
-    wg_same_dense<float, MF32, NT>(I, c, out, P.kp, lds);
+  if (tm.T > 1) {
+    if constexpr (std::is_same<T, double>::value)
+      wg_same_pairs<double, MF64, NT>(I, c, out, P.kp, lds, tm.t0, tm.t1);
+    else
+      wg_same_pairs<float, MF32, NT>(I, c, out, P.kp, lds, tm.t0, tm.t1);
+  } else {
+    if constexpr (std::is_same<T, double>::value)
+      wg_same_dense<double, MF64, NT>(I, c, out, P.kp, lds, 0, (I.ns_a + 15) / 16);
+    else
+      wg_same_dense<float, MF32, NT>(I, c, out, P.kp, lds, 0, (I.ns_a + 15) / 16);
+  }
   if (threadIdx.x == 0) {
     const uint64_t t = __builtin_amdgcn_s_memrealtime();
     tick[0] += t - tk;
@@ -309,7 +499,7 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
   // The K and pair-tile loops run at the largest shape (the norb = 10
   // instances that bound the makespan use all of it): padded K slots carry
   // zero ERI fragments and padded pair rows carry invalid scatter codes.
-  for (int ia = wv; ia < nsa && sa > 0; ia += NW) {
+  for (int ia = tm.a0 + wv; ia < tm.a1 && sa > 0; ia += NW) {
     const Ent *te = I.tab_a + (int64_t)ia * sa;
     uint32_t boff[KSMAX][M::KPL];
     Frag af[NPT][KSMAX];
@@ -422,7 +612,8 @@ struct Upd {
 // Fused SBCI update (Eqs. S56-S60 with Eq. S31's preconditioner), the same
 // per-element arithmetic as the full-size k_update.  Results in C.h1.
 template <typename T, int NT>
-__device__ void wg_update(const BInst &I, Ctl &C, Red<NT> &R, const Upd &a, int zslot, int wslot) {
+__device__ void wg_update(const BInst &I, Ctl &C, Red<NT> &R, const Team &tm, const Upd &a, int zslot,
+                          int wslot) {
   const Vecs<T> V = vecs<T>(I, C);
   T *x = V(SX), *X = V(SXX), *y = V(SY), *Y = V(SYY), *w = V(wslot);
   const T *zz = V(zslot);
@@ -431,7 +622,7 @@ __device__ void wg_update(const BInst &I, Ctl &C, Red<NT> &R, const Upd &a, int 
   double v[10 + BMAXR];
 #pragma unroll
   for (int q = 0; q < 10 + BMAXR; ++q) v[q] = 0;
-  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
     double zi = 0, Zi = 0, yi = 0, Yi = 0;
     if (a.read_z) {
       zi = (double)zz[i];
@@ -470,14 +661,14 @@ __device__ void wg_update(const BInst &I, Ctl &C, Red<NT> &R, const Upd &a, int 
     for (int j = 0; j < BMAXR; ++j)
       if (j < a.nconv) v[10 + j] += ws * (double)V.xc(j)[i];
   }
-  wg_sum<NT>(v, 10 + a.nconv, R);
+  wg_sum<NT>(v, 10 + a.nconv, R, tm);
   if ((int)threadIdx.x < 10 + a.nconv) C.h1[threadIdx.x] = R.out[threadIdx.x];
   __syncthreads();
 }
 
 // z = w - sum_j d_j xc_j in place (Eq. S31), d_j = C.h1[10 + j]; x.z, y.z, z.z -> C.h2
 template <typename T, int NT>
-__device__ void wg_deflate(const BInst &I, Ctl &C, Red<NT> &R, int wslot) {
+__device__ void wg_deflate(const BInst &I, Ctl &C, Red<NT> &R, const Team &tm, int wslot) {
   const Vecs<T> V = vecs<T>(I, C);
   T *w = V(wslot);
   const T *x = V(SX), *y = V(SY);
@@ -485,7 +676,7 @@ __device__ void wg_deflate(const BInst &I, Ctl &C, Red<NT> &R, int wslot) {
 #pragma unroll
   for (int j = 0; j < BMAXR; ++j) dj[j] = j < C.nconv ? C.h1[10 + j] : 0.0;
   double v[3] = {0, 0, 0};
-  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
     double zi = (double)w[i];
 #pragma unroll
     for (int j = 0; j < BMAXR; ++j)
@@ -497,24 +688,24 @@ __device__ void wg_deflate(const BInst &I, Ctl &C, Red<NT> &R, int wslot) {
     v[1] += (double)y[i] * zs;
     v[2] += zs * zs;
   }
-  wg_sum<NT>(v, 3, R);
+  wg_sum<NT>(v, 3, R, tm);
   if (threadIdx.x < 3) C.h2[threadIdx.x] = R.out[threadIdx.x];
   __syncthreads();
 }
 
 // x.Z, y.Z, z.Z -> C.h3
 template <typename T, int NT>
-__device__ void wg_dots_xyz(const BInst &I, Ctl &C, Red<NT> &R, int zslot) {
+__device__ void wg_dots_xyz(const BInst &I, Ctl &C, Red<NT> &R, const Team &tm, int zslot) {
   const Vecs<T> V = vecs<T>(I, C);
   const T *x = V(SX), *y = V(SY), *z = V(zslot), *Z = V(SZ);
   double v[3] = {0, 0, 0};
-  for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
     const double Zi = (double)Z[i];
     v[0] += (double)x[i] * Zi;
     v[1] += (double)y[i] * Zi;
     v[2] += (double)z[i] * Zi;
   }
-  wg_sum<NT>(v, 3, R);
+  wg_sum<NT>(v, 3, R, tm);
   if (threadIdx.x < 3) C.h3[threadIdx.x] = R.out[threadIdx.x];
   __syncthreads();
 }
@@ -528,25 +719,26 @@ struct Pack {
   int n;
 };
 
-// dot products a . b_j -> R.out[j]
+// dot products a . b_j over all rows -> R.out[j]
 template <typename T, int NT>
-__device__ void wg_dots(int64_t n, const T *a, const Pack<T> bs, Red<NT> &R) {
+__device__ void wg_dots(const Team &tm, const T *a, const Pack<T> bs, Red<NT> &R) {
   double v[BMAXR + 1];
 #pragma unroll
   for (int j = 0; j < BMAXR + 1; ++j) v[j] = 0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
     const double ai = (double)a[i];
 #pragma unroll
     for (int j = 0; j < BMAXR + 1; ++j)
       if (j < bs.n) v[j] += ai * (double)bs.p[j][i];
   }
-  wg_sum<NT>(v, bs.n, R);
+  wg_sum<NT>(v, bs.n, R, tm);
 }
 
-// out = beta * out + sum_q c_q * x_q (elementwise; out may alias one of x_q)
+// out = beta * out + sum_q c_q * x_q (elementwise over this workgroup's rows;
+// out may alias one of x_q)
 template <typename T, int NT>
-__device__ void wg_lincomb(int64_t n, T *out, const Pack<T> xs, double beta) {
-  for (int64_t i = threadIdx.x; i < n; i += NT) {
+__device__ void wg_lincomb(const Team &tm, T *out, const Pack<T> xs, double beta) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
     double s = beta == 0.0 ? 0.0 : beta * (double)out[i];
 #pragma unroll
     for (int q = 0; q < BMAXR + 1; ++q)
@@ -569,8 +761,8 @@ __device__ Pack<T> pack(int n) {
 }
 
 template <typename Td, typename Ts, int NT>
-__device__ void wg_convert(int64_t n, Td *dst, const Ts *src, double scale) {
-  for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = (Td)(scale * (double)src[i]);
+__device__ void wg_convert(const Team &tm, Td *dst, const Ts *src, double scale) {
+  for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) dst[i] = (Td)(scale * (double)src[i]);
   __syncthreads();
 }
 
@@ -582,19 +774,23 @@ struct Solve {
   Ctl &C;
   Red<NT> &R;
   char *lds;
+  Team tm;
 
   __device__ bool lane0() const { return threadIdx.x == 0; }
+  // lane 0 of member 0 writes the instance's outputs
+  __device__ bool writer() const { return threadIdx.x == 0 && tm.m == 0; }
 
   template <typename T>
   __device__ void sigma_phase(const T *c, T *o, int mode) {
+    if (tm.T > 1) team_sync<NT>(tm, R);  // every member's rows of c are written
     if constexpr (std::is_same<T, double>::value) {
-      wg_sigma<double, MF64, NT>(I, P, c, o, lds, C.tsig);
+      wg_sigma<double, MF64, NT>(I, P, c, o, lds, C.tsig, tm);
       if (lane0()) C.nsig64 += 1;
     } else {
       if (mode == SBCI_BF16)
-        wg_sigma<float, MBF16, NT>(I, P, c, o, lds, C.tsig);
+        wg_sigma<float, MBF16, NT>(I, P, c, o, lds, C.tsig, tm);
       else
-        wg_sigma<float, MF32, NT>(I, P, c, o, lds, C.tsig);
+        wg_sigma<float, MF32, NT>(I, P, c, o, lds, C.tsig, tm);
       if (lane0()) C.nsiglow += 1;
     }
     __syncthreads();
@@ -617,8 +813,8 @@ struct Solve {
     a.nconv = C.nconv;
     a.want_zdots = C.nconv == 0;
     // the preconditioned residual goes to the current z slot (za)
-    wg_update<T, NT>(I, C, R, a, SZB, SZA);
-    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, SZA);
+    wg_update<T, NT>(I, C, R, tm, a, SZB, SZA);
+    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, tm, SZA);
     if (lane0()) {
       C.sx = 1.0;
       C.seg_start = 1;
@@ -639,7 +835,7 @@ struct Solve {
       for (int j = 0; j < BMAXR; ++j) {
         px.p[j] = pX.p[j] = V.xc(j);
       }
-      wg_dots<T, NT>(I.ndet, x, px, R);
+      wg_dots<T, NT>(tm, x, px, R);
 #pragma unroll
       for (int j = 0; j < BMAXR; ++j) {
         if (j < nc) {
@@ -648,12 +844,12 @@ struct Solve {
         }
       }
       __syncthreads();
-      wg_lincomb<T, NT>(I.ndet, x, px, 1.0);   // Eq. S4
-      wg_lincomb<T, NT>(I.ndet, X, pX, 1.0);   // Eq. S5
+      wg_lincomb<T, NT>(tm, x, px, 1.0);   // Eq. S4
+      wg_lincomb<T, NT>(tm, X, pX, 1.0);   // Eq. S5
     }
     Pack<T> p1 = pack<T>(1);
     p1.p[0] = x;
-    wg_dots<T, NT>(I.ndet, x, p1, R);
+    wg_dots<T, NT>(tm, x, p1, R);
     const double nxx = R.out[0];
     __syncthreads();
     if (!(nxx > 0) || !isfinite(nxx)) return false;
@@ -675,7 +871,7 @@ struct Solve {
     Pack<T> bs = pack<T>(2);
     bs.p[0] = V(SX);
     bs.p[1] = V(SXX);
-    wg_dots<T, NT>(I.ndet, V(SX), bs, R);
+    wg_dots<T, NT>(tm, V(SX), bs, R);
     const double e = R.out[1] / R.out[0];
     __syncthreads();
     return e;
@@ -703,7 +899,7 @@ struct Solve {
   __device__ bool promote() {
     const Vecs<double> V = vecs<double>(I, C);
     const Vecs<float> F = vecs<float>(I, C);
-    wg_convert<double, float, NT>(I.ndet, V(SX), F(SX), 1.0);
+    wg_convert<double, float, NT>(tm, V(SX), F(SX), 1.0);
     sigma_phase<double>(V(SX), V(SXX), SBCI_F64);
     const double e = rayleigh<double>();
     const int steps = C.steps_root, seg = C.seg;
@@ -726,10 +922,10 @@ struct Solve {
   __device__ bool finish_root(double xn, bool second_ok) {
     const Vecs<double> V = vecs<double>(I, C);
     const int j = C.nconv;
-    wg_convert<double, double, NT>(I.ndet, V.xc(j), V(SX), 1.0 / xn);
+    wg_convert<double, double, NT>(tm, V.xc(j), V(SX), 1.0 / xn);
     if (P.precision != SBCI_F64) {
       const Vecs<float> F = vecs<float>(I, C);
-      wg_convert<float, double, NT>(I.ndet, F.xc(j), V.xc(j), 1.0);
+      wg_convert<float, double, NT>(tm, F.xc(j), V.xc(j), 1.0);
     }
     if (lane0()) {
       C.Ec[j] = C.E;
@@ -755,8 +951,8 @@ struct Solve {
     in2.p[0] = V(SXX);
     in2.p[1] = V(SYY);
     in2.p[2] = V(SZ);
-    wg_lincomb<double, NT>(I.ndet, V(SZB), in1, 0.0);
-    wg_lincomb<double, NT>(I.ndet, V(SYY), in2, 0.0);
+    wg_lincomb<double, NT>(tm, V(SZB), in1, 0.0);
+    wg_lincomb<double, NT>(tm, V(SYY), in2, 0.0);
     if (lane0()) {
       int t = C.m64[SX];
       C.m64[SX] = C.m64[SZB];
@@ -771,8 +967,8 @@ struct Solve {
     if (P.precision != SBCI_F64) {
       const Vecs<double> V2 = vecs<double>(I, C);
       const Vecs<float> F = vecs<float>(I, C);
-      wg_convert<float, double, NT>(I.ndet, F(SX), V2(SX), 1.0);
-      wg_convert<float, double, NT>(I.ndet, F(SXX), V2(SXX), 1.0);
+      wg_convert<float, double, NT>(tm, F(SX), V2(SX), 1.0);
+      wg_convert<float, double, NT>(tm, F(SXX), V2(SXX), 1.0);
       if (lane0()) C.phase = P.precision;
       __syncthreads();
       return start_root<float>();
@@ -798,10 +994,10 @@ struct Solve {
     in2.p[2] = V(SZ);
     // the Ritz vector goes to the free z slot; x and X stay intact until its
     // norm is known to be usable
-    wg_lincomb<T, NT>(I.ndet, V(SZB), in1, 0.0);
+    wg_lincomb<T, NT>(tm, V(SZB), in1, 0.0);
     Pack<T> pv = pack<T>(1);
     pv.p[0] = V(SZB);
-    wg_dots<T, NT>(I.ndet, V(SZB), pv, R);
+    wg_dots<T, NT>(tm, V(SZB), pv, R);
     const double nxx = R.out[0];
     __syncthreads();
     if (!(nxx > 0) || !isfinite(nxx)) {
@@ -811,7 +1007,7 @@ struct Solve {
       __syncthreads();
       return false;
     }
-    wg_lincomb<T, NT>(I.ndet, V(SYY), in2, 0.0);
+    wg_lincomb<T, NT>(tm, V(SYY), in2, 0.0);
     if (lane0()) {
       int *m = std::is_same<T, double>::value ? C.m64 : C.m32;
       int t = m[SX];
@@ -836,7 +1032,7 @@ struct Solve {
     const Vecs<T> V = vecs<T>(I, C);
     const int mode = C.phase;
     sigma_phase<T>(V(SZA), V(SZ), mode);                       // Eq. S32
-    wg_dots_xyz<T, NT>(I, C, R, SZA);
+    wg_dots_xyz<T, NT>(I, C, R, tm, SZA);
     if (lane0()) {
       C.steps_root += 1;
       C.nsteps += 1;
@@ -942,7 +1138,7 @@ struct Solve {
     a.read_z = 1;
     a.nconv = C.nconv;
     a.want_zdots = C.nconv == 0;
-    wg_update<T, NT>(I, C, R, a, SZA, SZB);
+    wg_update<T, NT>(I, C, R, tm, a, SZA, SZB);
     // decisions (lane 0), then the follow-up passes
     if (lane0()) {
       C.last = r;
@@ -1017,7 +1213,7 @@ struct Solve {
       if (C.phase != SBCI_F64) return promote();
       return finish_root(xn, true);
     }
-    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, SZB);
+    if (C.nconv > 0) wg_deflate<T, NT>(I, C, R, tm, SZB);
     if (lane0()) {
       int *m = std::is_same<T, double>::value ? C.m64 : C.m32;
       const int t = m[SZA];
@@ -1030,7 +1226,9 @@ struct Solve {
 
   // Section S1.1: the k lowest diagonal determinants (ties: lower index),
   // sigma on their unit vectors, k x k eigenproblem; x, X from its lowest
-  // eigenvector.  He_i are kept in the y, Y, za, zb slots (k <= 4).
+  // eigenvector.  He_i are kept in the y, Y, za, zb slots (k <= 4).  Every
+  // team member scans the whole diagonal (the same picks everywhere); the
+  // entries (He_q)[idx_i] come from their owners through a team sum.
   __device__ bool initial_vector() {
     const Vecs<double> V = vecs<double>(I, C);
     const int k = (int)(I.nroots < I.ndet ? I.nroots : I.ndet);
@@ -1080,10 +1278,17 @@ struct Solve {
     const int hs[4] = {SY, SYY, SZA, SZB};
     double *x = V(SX);
     for (int q = 0; q < k; ++q) {
-      for (int64_t i = threadIdx.x; i < I.ndet; i += NT) x[i] = i == C.idx[q] ? 1.0 : 0.0;
+      for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) x[i] = i == C.idx[q] ? 1.0 : 0.0;
       __syncthreads();
       sigma_phase<double>(x, V(hs[q]), SBCI_F64);              // Eq. S1
-      if ((int)threadIdx.x < k) C.Hs[threadIdx.x * k + q] = V(hs[q])[C.idx[threadIdx.x]];
+      double hv[BMAXR];
+#pragma unroll
+      for (int i = 0; i < BMAXR; ++i) {
+        const int64_t r = i < k ? C.idx[i] : -1;
+        hv[i] = (threadIdx.x == 0 && r >= tm.r0 && r < tm.r1) ? V(hs[q])[r] : 0.0;
+      }
+      wg_sum<NT>(hv, k, R, tm);
+      if ((int)threadIdx.x < k) C.Hs[threadIdx.x * k + q] = R.out[threadIdx.x];
       __syncthreads();
     }
     if (lane0()) {
@@ -1095,7 +1300,7 @@ struct Solve {
     }
     __syncthreads();
     // x = sum_i U[i][0] e_idx_i (Eq. S2), X = sum_i U[i][0] He_i (Eq. S3)
-    for (int64_t i = threadIdx.x; i < I.ndet; i += NT) {
+    for (int64_t i = tm.r0 + threadIdx.x; i < tm.r1; i += NT) {
       double s = 0;
       for (int q = 0; q < k; ++q)
         if (C.idx[q] == i) s += C.U[q * k + 0];
@@ -1107,12 +1312,15 @@ struct Solve {
       hp.p[q] = V(hs[q]);
       hp.c[q] = q < k ? C.U[q * k + 0] : 0.0;
     }
-    wg_lincomb<double, NT>(I.ndet, V(SXX), hp, 0.0);
+    wg_lincomb<double, NT>(tm, V(SXX), hp, 0.0);
     return true;
   }
 
   __device__ void run(BOut &out) {
     if (lane0()) {
+      R.gen = 0u;
+      R.red = 0u;
+      R.abort = 0;
       C.alpha = 0;
       C.seg = 0;
       C.t = 0;
@@ -1143,8 +1351,8 @@ struct Solve {
       if (P.precision != SBCI_F64) {
         const Vecs<double> V = vecs<double>(I, C);
         const Vecs<float> F = vecs<float>(I, C);
-        wg_convert<float, double, NT>(I.ndet, F(SX), V(SX), 1.0);
-        wg_convert<float, double, NT>(I.ndet, F(SXX), V(SXX), 1.0);
+        wg_convert<float, double, NT>(tm, F(SX), V(SX), 1.0);
+        wg_convert<float, double, NT>(tm, F(SXX), V(SXX), 1.0);
         if (lane0()) C.phase = P.precision;
         __syncthreads();
         ok = start_root<float>();
@@ -1158,14 +1366,14 @@ struct Solve {
     const int cap = I.nroots * (P.max_steps + 8) + 8;
     int guard = 0;
     int last_nconv = 0;
-    while (ok && !C.done && guard < cap) {
+    while (ok && !C.done && !R.abort && guard < cap) {
       ++guard;
       ok = C.phase == SBCI_F64 ? step<double>() : step<float>();
-      if (lane0() && C.nconv > last_nconv) out.dz[C.nconv - 1] = C.dzroot;
+      if (writer() && C.nconv > last_nconv) out.dz[C.nconv - 1] = C.dzroot;
       last_nconv = C.nconv;
       __syncthreads();
     }
-    if (lane0()) {
+    if (writer()) {
       for (int i = 0; i < BMAXR; ++i) out.E[i] = C.Ec[i];
       out.nconv = C.nconv;
       out.nsteps = C.nsteps;
@@ -1174,31 +1382,52 @@ struct Solve {
       out.nsiglow = C.nsiglow;
       for (int q = 0; q < 2; ++q) out.tsig[q] = C.tsig[q];
       int st = C.status;
-      if (st == SBCI_OK && (!C.done || C.any_noconv)) st = SBCI_ENOCONV;
+      if (R.abort) st = SBCI_EDEVICE;  // a team member stopped arriving
+      else if (st == SBCI_OK && (!C.done || C.any_noconv)) st = SBCI_ENOCONV;
       out.status = st;
     }
     __syncthreads();
   }
 };
 
+// Blocks [0, ntw) are team members: team_blk[b] = (instance, T, member,
+// team).  They run their team's instance first (they are dispatched first,
+// and ntw never exceeds the resident capacity, so every member of a team is
+// resident at once), then join the queue.  The queue holds the other
+// instances (order[0 .. nqueue)), each run by one workgroup.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
-                                              const int *__restrict__ order, int ninst,
+                                              const int *__restrict__ order, int nqueue,
                                               unsigned *queue, BOut *out,
-                                              const BParams *__restrict__ prm) {
+                                              const BParams *__restrict__ prm,
+                                              const int4 *__restrict__ team_blk, int ntw,
+                                              TeamSync *tsync) {
   extern __shared__ __align__(16) char lds[];
   __shared__ Ctl C;
   __shared__ Red<NT> R;
   __shared__ int item;
+  if ((int)blockIdx.x < ntw) {
+    const int4 tb = team_blk[blockIdx.x];
+    const BInst &I = inst[tb.x];
+    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, tsync + tb.w, tb.y, tb.z)};
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    S.run(out[tb.x]);
+    if (threadIdx.x == 0 && tb.z == 0) {
+      out[tb.x].t0 = t0;
+      out[tb.x].t1 = __builtin_amdgcn_s_memrealtime();
+    }
+    __syncthreads();
+  }
   for (;;) {
     if (threadIdx.x == 0) item = (int)atomicAdd(queue, 1u);
     __syncthreads();
     const int it = item;
     __syncthreads();
-    if (it >= ninst) break;
+    if (it >= nqueue) break;
     const int id = order[it];
     // descriptors and parameters stay in global memory (uniform loads)
-    Solve<NT> S{inst[id], *prm, C, R, lds};
+    const BInst &I = inst[id];
+    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, nullptr, 1, 0)};
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     S.run(out[id]);
     if (threadIdx.x == 0) {
@@ -1208,9 +1437,15 @@ __global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
   }
 }
 
-// Graph-safe reset of the work queue (a kernel, not a memset node).
-__global__ void k_batch_reset(unsigned *queue) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) queue[0] = 0u;
+// Graph-safe reset of the work queue and of the team barriers (a kernel, not
+// a memset node).
+__global__ void k_batch_reset(unsigned *queue, TeamSync *tsync, int nteam) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) queue[0] = 0u;
+  if (t < nteam) {
+    tsync[t].cnt = 0u;
+    tsync[t].abort = 0u;
+  }
 }
 
 // Dense same-spin operator from its lists: H[i][col(i,f)] = F[i][f]
@@ -1230,7 +1465,7 @@ size_t lds_bytes(int kp, int threads) {
   const int rw = ((BMAX_NS + 15) / 16 + nw - 1) / nw;
   const int cb = rw >= 8 ? 1 : 8 / rw;
   const size_t same = sizeof(double) * ((size_t)((BMAX_NS + 15) / 16 * 16) * (kp + 1) +
-                                        (size_t)kp * (cb * 16 + 1));
+                                        (size_t)kp * (std::max(cb, kPairCB) * 16 + 1));
   const size_t opp = kWBytes + sizeof(double) * BMAX_NS * (size_t)nw;
   return std::max(same, opp);
 }
@@ -1258,6 +1493,8 @@ struct sbci_batch {
   BParams *d_params = nullptr;
   int *d_order = nullptr;
   unsigned *d_queue = nullptr;
+  int4 *d_team_blk = nullptr;   // [ninst * BMAX_TEAM]
+  TeamSync *d_tsync = nullptr;  // [ninst]
   BOut *d_out = nullptr;
   double *arena64 = nullptr;
   float *arena32 = nullptr;
@@ -1295,17 +1532,36 @@ int build_dense(sbci_batch *b, int i) {
   return SBCI_OK;
 }
 
+// Workgroups of k_batch<NT> resident at once on the device.
 template <int NT>
-int instantiate(sbci_batch *b, const sbci_batch_config &cfg, size_t lds, BParams P,
-                hipGraphExec_t *exec_out, hipGraph_t *graph_out) {
+int resident_blocks(sbci_batch *b, size_t lds, int *out) {
   SBCI_HIP(hipFuncSetAttribute((const void *)k_batch<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-  const unsigned grid = (unsigned)std::max(1, std::min(b->ncu * cfg.wg_per_cu, b->ninst));
+  int per_cu = 0;
+  SBCI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch<NT>, NT, lds));
+  *out = per_cu * b->ncu;
+  return SBCI_OK;
+}
+
+struct Plan {
+  int ntw = 0;     // team workgroups (the first blocks)
+  int nteam = 0;
+  int nqueue = 0;  // instances in the queue
+  int grid = 1;
+};
+
+template <int NT>
+int instantiate(sbci_batch *b, const Plan &pl, size_t lds, hipGraphExec_t *exec_out,
+                hipGraph_t *graph_out) {
+  SBCI_HIP(hipFuncSetAttribute((const void *)k_batch<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  const unsigned grid = (unsigned)pl.grid;
   hipGraph_t g = nullptr;
   SBCI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue);
-  k_batch<NT><<<grid, NT, lds, b->stream>>>(b->d_inst, b->d_order, b->ninst, b->d_queue, b->d_out,
-                                            b->d_params);
+  k_batch_reset<<<(unsigned)((pl.nteam + 255) / 256 + 1), 256, 0, b->stream>>>(b->d_queue, b->d_tsync,
+                                                                              pl.nteam);
+  k_batch<NT><<<grid, NT, lds, b->stream>>>(b->d_inst, b->d_order, pl.nqueue, b->d_queue, b->d_out,
+                                            b->d_params, b->d_team_blk, pl.ntw, b->d_tsync);
   hipError_t le = hipGetLastError();
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (le != hipSuccess) return batch_error(SBCI_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
@@ -1329,6 +1585,8 @@ int check_config(const sbci_batch_config &c) {
   if (c.order != 0 && c.order != 1) return batch_error(SBCI_EINVAL, "batch config: order must be 0 or 1");
   if (c.k_panel != 8 && c.k_panel != 16)
     return batch_error(SBCI_EINVAL, "batch config: k_panel must be 8 or 16");
+  if (c.max_team < 0 || c.max_team > BMAX_TEAM)
+    return batch_error(SBCI_EINVAL, "batch config: max_team must be in 0..4");
   return SBCI_OK;
 }
 
@@ -1431,25 +1689,97 @@ int prepare(sbci_batch *b, const int *nroots, int precision) {
   return SBCI_OK;
 }
 
-int set_order(sbci_batch *b, int order) {
-  std::vector<int> ord(b->ninst);
-  for (int i = 0; i < b->ninst; ++i) ord[i] = i;
-  if (order == 0) {
-    // longest first: work ~ N_det * (F list + opposite-spin pair rows) * roots
-    auto work = [&](int i) {
-      const BInst &I = b->h_inst[i];
-      return (double)I.ndet * (double)(I.nf_a + I.nf_b + I.npair * I.s_a / 2 + 24) * I.nroots;
-    };
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work(x) > work(y); });
+constexpr double kTeamMargin = 1.25;
+
+// Estimated work of an instance: N_det x (F lists + opposite-spin pair rows) x roots.
+double inst_work(const BInst &I) {
+  return (double)I.ndet * (double)(I.nf_a + I.nf_b + I.npair * I.s_a / 2 + 24) * I.nroots;
+}
+
+// Launch plan: team sizes, the team block table and the queue order.
+// Balanced share M = max(total work / workgroup slots, largest work /
+// max_team); an instance of work w gets T = ceil(w / M) workgroups (at most
+// max_team), largest first, while the team workgroups fit in the slots that
+// are resident at once.  The other instances form the queue, largest first
+// (order 0) or in input order (order 1).
+int plan_launch(sbci_batch *b, const sbci_batch_config &cfg, int resident, Plan &pl) {
+  const int n = b->ninst;
+  const int slots = std::max(1, std::min(b->ncu * cfg.wg_per_cu, resident));
+  const int maxT = cfg.max_team == 0 ? BMAX_TEAM : cfg.max_team;
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::vector<double> w(n);
+  double total = 0, wmax = 0;
+  for (int i = 0; i < n; ++i) {
+    w[i] = inst_work(b->h_inst[i]);
+    total += w[i];
+    wmax = std::max(wmax, w[i]);
   }
-  SBCI_HIP(hipMemcpyAsync(b->d_order, ord.data(), sizeof(int) * b->ninst, hipMemcpyHostToDevice,
-                          b->stream));
+  std::vector<int> by_work = ord;
+  std::stable_sort(by_work.begin(), by_work.end(), [&](int x, int y) { return w[x] > w[y]; });
+  std::vector<char> in_team(n, 0);
+  std::vector<int4> blk;
+  if (maxT > 1 && n > 1) {
+    // T_i = ceil(kTeamMargin w_i / M), at most max_team and the instance's
+    // alpha tiles (a member needs one); M grows from the balanced share until
+    // the teams leave an eighth of the slots to the queue.  The margin covers
+    // the spread of step counts that the work estimate does not see.
+    auto team_size = [&](int i, double M) {
+      int T = (int)std::ceil(kTeamMargin * w[i] / M - 1e-9);
+      T = std::min(T, maxT);
+      return std::min(T, (b->h_inst[i].ns_a + 15) / 16);
+    };
+    const int budget = slots - slots / 8;
+    double M = std::max(total / slots, wmax / maxT);
+    for (int it = 0; it < 200; ++it, M *= 1.05) {
+      int used = 0;
+      for (int i : by_work) {
+        const int T = team_size(i, M);
+        if (T < 2) break;
+        used += T;
+      }
+      if (used <= budget) break;
+    }
+    for (int i : by_work) {
+      const int T = team_size(i, M);
+      if (T < 2 || (int)blk.size() + T > budget) break;
+      for (int m = 0; m < T; ++m) blk.push_back(make_int4(i, T, m, pl.nteam));
+      in_team[i] = 1;
+      pl.nteam += 1;
+    }
+  }
+  pl.ntw = (int)blk.size();
+  std::vector<int> q;
+  for (int i : (cfg.order == 0 ? by_work : ord))
+    if (!in_team[i]) q.push_back(i);
+  pl.nqueue = (int)q.size();
+  pl.grid = std::max(1, std::max(pl.ntw, std::min(b->ncu * cfg.wg_per_cu, pl.ntw + pl.nqueue)));
+  if (!q.empty())
+    SBCI_HIP(hipMemcpyAsync(b->d_order, q.data(), sizeof(int) * q.size(), hipMemcpyHostToDevice,
+                            b->stream));
+  if (!blk.empty())
+    SBCI_HIP(hipMemcpyAsync(b->d_team_blk, blk.data(), sizeof(int4) * blk.size(),
+                            hipMemcpyHostToDevice, b->stream));
+  // the host vectors must outlive the copies
+  SBCI_HIP(hipStreamSynchronize(b->stream));
   return SBCI_OK;
 }
 
-int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, double *ms) {
+int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, double *ms,
+              Plan *plan_out = nullptr) {
   size_t lds = 0;
   lds = lds_bytes(cfg.k_panel, cfg.threads);
+  int resident = 0;
+  if (cfg.threads == 256)
+    SBCI_TRY(resident_blocks<256>(b, lds, &resident));
+  else if (cfg.threads == 512)
+    SBCI_TRY(resident_blocks<512>(b, lds, &resident));
+  else
+    SBCI_TRY(resident_blocks<1024>(b, lds, &resident));
+  if (resident < 1) return batch_error(SBCI_EDEVICE, "batch kernel: no workgroup fits on a compute unit");
+  Plan pl;
+  SBCI_TRY(plan_launch(b, cfg, resident, pl));
+  if (plan_out) *plan_out = pl;
   // The solve parameters are baked into the captured launch, so every call
   // captures a fresh graph (a few microseconds next to the solve).
   hipGraph_t g = nullptr;
@@ -1459,11 +1789,11 @@ int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, dou
   SBCI_HIP(hipMemcpyAsync(b->d_params, &Pc, sizeof(BParams), hipMemcpyHostToDevice, b->stream));
   int rc = SBCI_OK;
   if (cfg.threads == 256)
-    rc = instantiate<256>(b, cfg, lds, Pc, &x, &g);
+    rc = instantiate<256>(b, pl, lds, &x, &g);
   else if (cfg.threads == 512)
-    rc = instantiate<512>(b, cfg, lds, Pc, &x, &g);
+    rc = instantiate<512>(b, pl, lds, &x, &g);
   else
-    rc = instantiate<1024>(b, cfg, lds, Pc, &x, &g);
+    rc = instantiate<1024>(b, pl, lds, &x, &g);
   if (rc != SBCI_OK) return rc;
   hipEvent_t e0, e1;
   SBCI_HIP(hipEventCreate(&e0));
@@ -1490,6 +1820,7 @@ sbci_batch_config default_config() {
   c.wg_per_cu = 2;
   c.order = 0;
   c.k_panel = 16;
+  c.max_team = 0;
   return c;
 }
 
@@ -1540,6 +1871,8 @@ int sbci_batch_create(int ninst, const int *norb, const int *nalpha, const int *
   if (e2 == hipSuccess) e2 = hipMalloc(&b->d_order, sizeof(int) * ninst);
   if (e2 == hipSuccess) e2 = hipMalloc(&b->d_queue, 256);
   if (e2 == hipSuccess) e2 = hipMalloc(&b->d_out, sizeof(BOut) * ninst);
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_team_blk, sizeof(int4) * (size_t)ninst * BMAX_TEAM);
+  if (e2 == hipSuccess) e2 = hipMalloc(&b->d_tsync, sizeof(TeamSync) * (size_t)ninst);
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
   if (e2 != hipSuccess) {
     sbci_batch_destroy(b);
@@ -1567,6 +1900,8 @@ int sbci_batch_destroy(sbci_batch *b) {
   hipFree(b->d_order);
   hipFree(b->d_queue);
   hipFree(b->d_out);
+  hipFree(b->d_team_blk);
+  hipFree(b->d_tsync);
   hipFree(b->arena64);
   hipFree(b->arena32);
   if (b->stream) hipStreamDestroy(b->stream);
@@ -1589,9 +1924,9 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   sbci_batch_config cfg = cfg_in ? *cfg_in : (b->have_tuned ? b->tuned : default_config());
   SBCI_TRY(check_config(cfg));
   SBCI_TRY(prepare(b, nroots, precision));
-  SBCI_TRY(set_order(b, cfg.order));
   double ms = 0;
-  SBCI_TRY(run_graph(b, cfg, P, &ms));
+  Plan pl;
+  SBCI_TRY(run_graph(b, cfg, P, &ms, &pl));
   b->solved_precision = precision;
   std::vector<BOut> o(b->ninst);
   SBCI_HIP(hipMemcpy(o.data(), b->d_out, sizeof(BOut) * b->ninst, hipMemcpyDeviceToHost));
@@ -1637,6 +1972,9 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   r.wg_per_cu = cfg.wg_per_cu;
   r.order = cfg.order;
   r.k_panel = cfg.k_panel;
+  r.max_team = cfg.max_team;
+  r.nteams = pl.nteam;
+  r.team_workgroups = pl.ntw;
   if (rep) *rep = r;
   if (worst != SBCI_OK)
     return batch_error(worst, worst == SBCI_ENOCONV ? "some batch instances did not converge"
@@ -1657,7 +1995,6 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
   std::vector<sbci_batch_config> tried;
   std::vector<double> times;
   auto trial = [&](const sbci_batch_config &c) -> int {
-    SBCI_TRY(set_order(b, c.order));
     double ms = 0;
     SBCI_TRY(run_graph(b, c, P, &ms));
     tried.push_back(c);
@@ -1671,6 +2008,7 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
       c.wg_per_cu = w;
       c.order = 0;
       c.k_panel = 16;
+      c.max_team = 0;
       SBCI_TRY(trial(c));
     }
   size_t bi = std::min_element(times.begin(), times.end()) - times.begin();

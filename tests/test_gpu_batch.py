@@ -3,7 +3,8 @@
 Every instance's result is checked against the oracle: root 0 against the
 oracle's SBCI1 from the same (Section S1.1) start, every root as an
 eigenpair of H through the oracle's sigma, and, for the small instances,
-every energy against the dense Slater-Condon spectrum.
+every energy against the dense Slater-Condon spectrum.  Instances on teams
+of workgroups are checked against the one-workgroup solve.
 """
 import json
 import os
@@ -111,6 +112,27 @@ def test_launch_shapes_agree(small_batch, cfg):
         assert abs(a[0] - b[0]) < 1e-9
 
 
+def test_teams_agree_with_lone_workgroups(small_batch):
+    """The largest instances run on teams of workgroups that split their rows
+    and meet at barriers; the energies match the one-workgroup solve to
+    rounding, and the vectors are eigenpairs."""
+    nroots = [t[3] for t in SMALL]
+    cfg = dict(threads=512, wg_per_cu=1, order=0, k_panel=16)
+    lone = small_batch.solve(nroots, tol=1e-10, config=dict(cfg, max_team=1))
+    assert lone.report["nteams"] == 0 and lone.report["team_workgroups"] == 0
+    for mt in (2, 4):
+        team = small_batch.solve(nroots, tol=1e-10, config=dict(cfg, max_team=mt))
+        assert (team.status == 0).all(), team.status
+        assert team.report["nteams"] >= 1
+        assert 2 * team.report["nteams"] <= team.report["team_workgroups"] <= mt * team.report["nteams"]
+        for a, b in zip(lone.energies, team.energies):
+            assert np.abs(np.asarray(a) - np.asarray(b)).max() < 1e-9
+        for i, (n, na, nb, k, seed) in enumerate(SMALL):
+            if n >= 8:
+                I = make_integrals(n, 2 * n, seed)
+                _check_eigenpairs(n, na, nb, I, team.energies[i], small_batch.vectors(i).cpu().numpy())
+
+
 def test_autotuner_picks_a_measured_candidate(small_batch):
     nroots = [t[3] for t in SMALL]
     best, cands = small_batch.tune(nroots, tol=1e-10)
@@ -160,6 +182,7 @@ def test_full_batch_512_fp64_and_mixed(full_batch):
     nroots = [t[2] for t in inst]
     r64 = b.solve(nroots, tol=1e-10)
     assert (r64.status == 0).all(), np.nonzero(r64.status)[0]
+    assert r64.report["nteams"] > 0   # the largest instances run on teams
     ref = REFS["batch512"]
     for key, rr in ref.items():
         i = int(key)
