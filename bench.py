@@ -328,8 +328,10 @@ def sym_pair_count(norb, na, nb, orbsym, irrep):
 def sym_section(sb, stream):
     """Point-group blocked workloads (irrep 0 of orbital labels p mod 8, totally
     symmetric integrals): CAS(14e,14o) with 5 roots and CAS(16e,16o) with the
-    ground state.  Blocked sigma per dtype and the time to 1e-8 Eh in FP64 and
-    in the FP32 precision form (the blocked sigma has no BF16 form)."""
+    ground state.  Blocked sigma per dtype (the opposite-spin part in the
+    vector pair form, BF16 on MFMA; "f64_class_mfma": the MFMA form in FP64)
+    and the time to 1e-8 Eh in FP64 and in the FP32 and BF16 precision
+    forms."""
     import statistics
 
     import numpy as np
@@ -349,12 +351,13 @@ def sym_section(sb, stream):
                "sigma": {}}
         pairs = sym_pair_count(cf["norb"], cf["na"], cf["nb"], o, cf["irrep"])
         c = torch.from_numpy(sigma_inputs(0, 1, ctx.ndet)[0]).cuda()
-        for dt in ("f32", "f64"):
-            x = c if dt == "f64" else c.float()
-            y, _ = ctx.sigma_timed(x, dt)
+        for dt in ("bf16", "f32", "f64", "f64_class_mfma"):
+            ctx.set_opp_form("class_mfma" if dt == "f64_class_mfma" else "auto")
+            x = c if dt.startswith("f64") else c.float()
+            y, _ = ctx.sigma_timed(x, dt[:3] if dt != "bf16" else dt)
             runs = []
             for _ in range(5):
-                y, ms = ctx.sigma_timed(x, dt, out=y)
+                y, ms = ctx.sigma_timed(x, dt[:3] if dt != "bf16" else dt, out=y)
                 runs.append(ms)
             same = statistics.median(r[0] for r in runs)
             opp = statistics.median(r[1] for r in runs)
@@ -362,23 +365,26 @@ def sym_section(sb, stream):
                                 "kernels_ms": {"same": round(same, 4), "opp": round(opp, 4)},
                                 "opp_gflops": round(2 * pairs / (opp / 1e3) / 1e9, 1)}
             del y, x
+        ctx.set_opp_form("auto")
         sec["opp_pairs_per_det"] = round(pairs / ctx.ndet, 1)
         del c
         res = {}
-        for prec in ("f32", "f64"):
+        for prec in ("bf16", "f32", "f64"):
             t = time.perf_counter()
             r = ctx.solve(cf["nroots"], tol=1e-10, opts=dict(precision=prec), want_vectors=False)
             torch.cuda.synchronize()
             res[prec] = (time.perf_counter() - t, r)
         ctx.close()
         tm, rm = res["f32"]
+        tb, rb = res["bf16"]
         t64, r64 = res["f64"]
-        sec["time_to_1e8_s"] = {"mixed_f32": round(tm, 3), "fp64": round(t64, 3),
-                                "speedup": round(t64 / tm, 3)}
+        sec["time_to_1e8_s"] = {"mixed_bf16": round(tb, 3), "mixed_f32": round(tm, 3), "fp64": round(t64, 3),
+                                "speedup_bf16": round(t64 / tb, 3), "speedup_f32": round(t64 / tm, 3)}
         sec["energies"] = [float(e) for e in r64.energies]
-        sec["max_abs_dE_mixed_vs_fp64"] = float(np.abs(np.sort(rm.energies) - np.sort(r64.energies)).max())
-        sec["nsigma"] = {"fp64_form": r64.report["nsigma_f64"], "mixed_f64": rm.report["nsigma_f64"],
-                         "mixed_f32": rm.report["nsigma_low"]}
+        sec["max_abs_dE_mixed_vs_fp64"] = {
+            p: float(np.abs(np.sort(res[p][1].energies) - np.sort(r64.energies)).max()) for p in ("bf16", "f32")}
+        sec["nsigma"] = {"fp64_form": r64.report["nsigma_f64"], "f32_form": [rm.report["nsigma_f64"], rm.report["nsigma_low"]],
+                         "bf16_form": [rb.report["nsigma_f64"], rb.report["nsigma_low"]]}
         out[name] = sec
     return out
 

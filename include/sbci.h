@@ -65,7 +65,8 @@ typedef enum sbci_opp_form {
   SBCI_OPP_AUTO = 0,
   SBCI_OPP_PAIR = 1,
   SBCI_OPP_ORBITAL = 2,
-  SBCI_OPP_ORBITAL_WINDOWED = 3
+  SBCI_OPP_ORBITAL_WINDOWED = 3,
+  SBCI_OPP_CLASS_MFMA = 4  /* symmetry-blocked contexts only: see sbci_create_sym */
 } sbci_opp_form;
 
 /* Form of the one-electron and same-spin parts H_alpha + H_beta:
@@ -169,8 +170,14 @@ int sbci_destroy(sbci_ctx *ctx);
  * block after another; sbci_sym_blocks reports the block shapes.  The
  * integrals must be totally symmetric: entries that break the symmetry must
  * be below 1e-10 of the largest entry (they are left out).  sigma runs in
- * FP64 and FP32; the BF16 dtype is refused (SBCI_EINVAL), and with it the
- * BF16 precision form.  The caller keeps ownership of every host array.
+ * FP64, FP32 and BF16.  The opposite-spin part contracts per class of
+ * orbital pairs (the irrep of E_pq).  SBCI_OPP_AUTO picks the vector pair
+ * form in FP64 and FP32, the faster one at these class sizes, and the MFMA
+ * form in BF16.  SBCI_OPP_PAIR forces the vector form (FP64 and FP32), and
+ * SBCI_OPP_CLASS_MFMA forces the MFMA form (all three dtypes).  The MFMA
+ * form needs every class to hold at most 64 pairs, otherwise SBCI_EINVAL
+ * (and with it no BF16 precision form).  The orbital forms are refused by
+ * sbci_set_opp_form.  The caller keeps ownership of every host array.
  * Errors: as sbci_create, plus SBCI_EINVAL for labels out of range,
  * integrals that are not totally symmetric, or an irrep with no
  * determinant. */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsbci.so")
 SBCI_OK, SBCI_EINVAL, SBCI_ENOMEM, SBCI_EDEVICE, SBCI_ENOCONV, SBCI_ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
-OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2, "orbital_windowed": 3}
+OPP_FORMS = {"auto": 0, "pair": 1, "orbital": 2, "orbital_windowed": 3, "class_mfma": 4}
 SAME_FORMS = {"auto": 0, "lists": 1, "dense": 2}
 REASONS = {0: "", 1: "converged", 2: "S62a", 3: "S62b", 4: "S62c", 5: "max_cycle", 6: "rank",
            7: "coef", 8: "refine", 9: "handover_k"}
@@ -286,7 +286,8 @@ class Context:
         _check(lib().sbci_set_deterministic(self.h, 1 if on else 0))
 
     def set_opp_form(self, form):
-        """Force the opposite-spin form ("auto", "pair" or "orbital") of later sigma calls."""
+        """Force the opposite-spin form ("auto", "pair", "orbital", "orbital_windowed";
+        "class_mfma" on symmetry-blocked contexts) of later sigma calls."""
         _check(lib().sbci_set_opp_form(self.h, OPP_FORMS[form]))
 
     def opp_form(self, dtype="f64"):

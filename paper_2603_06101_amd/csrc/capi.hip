@@ -284,8 +284,12 @@ int sbci_set_deterministic(sbci_ctx *ctx, int on) {
 int sbci_set_opp_form(sbci_ctx *ctx, int form) {
   if (!ctx) return set_error(SBCI_EINVAL, "ctx is NULL");
   if (form != SBCI_OPP_AUTO && form != SBCI_OPP_PAIR && form != SBCI_OPP_ORBITAL &&
-      form != SBCI_OPP_ORBITAL_WINDOWED)
+      form != SBCI_OPP_ORBITAL_WINDOWED && form != SBCI_OPP_CLASS_MFMA)
     return set_error(SBCI_EINVAL, "unknown opposite-spin form");
+  if (form == SBCI_OPP_CLASS_MFMA && !ctx->sym)
+    return set_error(SBCI_EINVAL, "the class MFMA form is for symmetry-blocked contexts");
+  if ((form == SBCI_OPP_ORBITAL || form == SBCI_OPP_ORBITAL_WINDOWED) && ctx->sym)
+    return set_error(SBCI_EINVAL, "symmetry-blocked contexts have no orbital form");
   ctx->opp_form = form;
   return SBCI_OK;
 }

@@ -338,6 +338,160 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
   for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) row[j] += (T)acc[j];
 }
 
+// MFMA form of the pair contraction above, the same sums: for each class x
+// with alpha excitations e of Ia and pairs kl of class x, the product
+//   M[kl][J] = sum_e A_x[kl][e] c[a ^ x](rank(J_e), J),
+//   A_x[kl][e] = sign_e (kl_e|kl)
+// runs as 16 x 16 MFMA tiles: A_x (its pairs padded to whole 16-row tiles,
+// its excitations to whole k-steps, zeros in the padding) sits in LDS, and
+// each wave takes 16-column tiles J of the source block, gathers the B
+// fragments c[a ^ x](rank(J_e), J) from the vector and scatters M through
+// the beta pair codes, as the pair form does.  Flavour M: FP64, FP32, or BF16
+// operands with FP32 accumulation (T = float).  Classes with more than
+// kSymMmaRows pairs use the pair form.
+// LDS: acc[maxcol] (double) | A tile [kSymMmaRows][lda] (16-byte aligned)
+//      | so2[sA] (uint32) | ord, cls[sA] | cs[9] | wro[sA] | sg[sA] (double)
+//      | plist[npair] | srcoff[sA] (uint32)
+constexpr int kSymMmaRows = 64;
+
+template <typename M, typename T>
+__global__ __launch_bounds__(256) void k_sym_opp_mma(
+    SymArgs g, PairStarts pcs, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
+    const int32_t *__restrict__ posA, const Ent *__restrict__ tabA, int sA,
+    const uint32_t *__restrict__ pairS, int64_t nsb, const int32_t *__restrict__ plist_g,
+    const T *__restrict__ W, int npair, int64_t maxcol, const T *__restrict__ c, T *__restrict__ out) {
+  using A = typename M::A;
+  using Frag = typename M::Frag;
+  using Out = typename M::Out;
+  constexpr int NW = 4;
+  constexpr int MTMAX = kSymMmaRows / 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ksmax = (sA + M::KSTEP - 1) / M::KSTEP;
+  const int lda = ksmax * M::KSTEP + M::PAD;
+  double *acc = reinterpret_cast<double *>(smem);
+  A *At = reinterpret_cast<A *>(smem + (((size_t)maxcol * 8 + 15) & ~(size_t)15));
+  unsigned char *base = reinterpret_cast<unsigned char *>(At) +
+                        ((((size_t)kSymMmaRows * lda * sizeof(A)) + 15) & ~(size_t)15);
+  uint32_t *so2 = reinterpret_cast<uint32_t *>(base);
+  int32_t *ord = reinterpret_cast<int32_t *>(so2 + sA);
+  int32_t *cls = ord + sA;
+  int32_t *cs = cls + sA;  // [9]
+  int32_t *wro = cs + 9;
+  double *sg = reinterpret_cast<double *>(base + ((((size_t)sA * 16 + 36) + 15) & ~(size_t)15));
+  int32_t *plist = reinterpret_cast<int32_t *>(sg + sA);
+  uint32_t *srcoff = reinterpret_cast<uint32_t *>(plist + npair);
+
+  const int64_t k = blockIdx.x;
+  int a = 0;
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (g.startA[t] <= k) a = t;
+  const int64_t nc = g.ncol[a];
+  if (nc == 0) return;  // uniform over the workgroup
+  const int64_t r = k - g.startA[a];
+  const int64_t Ia = idxA[k];
+  const int64_t vo = (int64_t)blockIdx.y * g.off[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, gq = lane >> 4;
+  for (int64_t j = tid; j < nc; j += 64 * NW) acc[j] = 0.0;
+  for (int e = tid; e < sA; e += 64 * NW) {
+    const Ent t = tabA[Ia * sA + e];
+    const int x = orbsym[t.p] ^ orbsym[t.q];
+    const int b = a ^ x;
+    cls[e] = x;
+    srcoff[e] = (uint32_t)(g.off[b] + (int64_t)posA[t.J] * g.ncol[b]);
+    wro[e] = pair_index(t.p, t.q) * npair;
+    sg[e] = (double)t.sign;
+  }
+  for (int p = tid; p < npair; p += 64 * NW) plist[p] = plist_g[p];
+  __syncthreads();
+  if (tid == 0) {
+    int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = 0; e < sA; ++e) ++n[cls[e]];
+    cs[0] = 0;
+    for (int x = 0; x < 8; ++x) cs[x + 1] = cs[x] + n[x];
+    int fill[8];
+    for (int x = 0; x < 8; ++x) fill[x] = cs[x];
+    for (int e = 0; e < sA; ++e) ord[fill[cls[e]]++] = e;
+  }
+  __syncthreads();
+  for (int i = tid; i < sA; i += 64 * NW) so2[i] = srcoff[ord[i]];
+  __syncthreads();
+  const T *__restrict__ cv = c + vo;
+  for (int x = 0; x < 8; ++x) {
+    const int i0 = cs[x], nx = cs[x + 1] - cs[x];
+    const int p0 = pcs.s[x], np_ = pcs.s[x + 1] - pcs.s[x];
+    if (nx == 0 || np_ == 0) continue;  // uniform
+    const int b = a ^ x;
+    const int64_t nbc = g.ncol[b];
+    const int64_t col0 = g.startBc[b];
+    const int mt = (np_ + 15) / 16;   // <= MTMAX (checked on the host)
+    const int ks = (nx + M::KSTEP - 1) / M::KSTEP;
+    // A_x: rows = pairs of class x, columns = its excitations (class order)
+    for (int y = tid; y < mt * 16 * ks * M::KSTEP; y += 64 * NW) {
+      const int row = y / (ks * M::KSTEP), kk = y - row * (ks * M::KSTEP);
+      double v = 0.0;
+      if (row < np_ && kk < nx) {
+        const int e = ord[i0 + kk];
+        v = sg[e] * (double)W[wro[e] + plist[p0 + row]];
+      }
+      At[row * lda + kk] = M::cvt(v);
+    }
+    __syncthreads();
+    const int njt = (int)((nbc + 15) / 16);
+    for (int jt = wave; jt < njt; jt += NW) {
+      const int64_t col = (int64_t)jt * 16 + li;
+      const uint32_t jc = (uint32_t)(col < nbc ? col : nbc - 1);
+      Out o[MTMAX];
+#pragma unroll
+      for (int u = 0; u < MTMAX; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[u][q] = 0;
+      for (int s = 0; s < ks; ++s) {
+        uint32_t off[M::KPL];
+#pragma unroll
+        for (int t = 0; t < M::KPL; ++t) {
+          const int kk = s * M::KSTEP + gq * M::KPL + t;
+          off[t] = so2[i0 + (kk < nx ? kk : 0)];  // padded K: any row of the class (A is zero there)
+        }
+        const Frag bf = M::load_b(cv, off, jc);
+#pragma unroll
+        for (int u = 0; u < MTMAX; ++u)
+          if (u < mt) o[u] = M::mma(M::load_a(&At[(u * 16 + li) * lda + s * M::KSTEP + gq * M::KPL]), bf, o[u]);
+      }
+      if (col < nbc) {
+#pragma unroll
+        for (int u = 0; u < MTMAX; ++u) {
+          if (u < mt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = u * 16 + M::orow(gq, q);
+              if (row < np_) {
+                const uint32_t cd = pairS[(int64_t)plist[p0 + row] * nsb + col0 + col];
+                if (cd != kInvalid) {
+                  const double v = (double)o[u][q];
+                  atomicAdd(&acc[cd >> 1], (cd & 1u) ? -v : v);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // the next class rebuilds the A tile
+  }
+  T *__restrict__ row = out + vo + g.off[a] + r * nc;
+  for (int64_t j = tid; j < nc; j += 64 * NW) row[j] += (T)acc[j];
+}
+
+size_t opp_mma_lds_bytes(int sA, int kstep, int pad, size_t asize, int npair, int64_t maxcol) {
+  const int lda = (sA + kstep - 1) / kstep * kstep + pad;
+  size_t b = (((size_t)maxcol * 8 + 15) & ~(size_t)15);
+  b += (((size_t)kSymMmaRows * lda * asize) + 15) & ~(size_t)15;
+  b += (((size_t)sA * 16 + 36) + 15) & ~(size_t)15;
+  b += (size_t)sA * 8 + (size_t)npair * 4 + (size_t)sA * 4;
+  return b;
+}
+
 size_t opp_pair_lds_bytes(int sA, size_t tsize, int npair, int64_t maxcol, int maxp8) {
   size_t b = (((size_t)maxcol * 8 + 15) & ~(size_t)15);
   size_t o1 = ((size_t)sA * 20 + 72 + 15) & ~(size_t)15;
@@ -570,8 +724,25 @@ void free_symmetry(sbci_ctx *ctx) {
 }
 
 namespace {
+template <typename M, typename T>
+int launch_sym_mma(sbci_ctx *ctx, const SymArgs &g, const PairStarts &pcs, const T *W, size_t lds,
+                   dim3 grid, const T *c, T *out) {
+  const SymInfo &S = *ctx->sym;
+  static bool attr = false;
+  if (!attr) {
+    SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_mma<M, T>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr = true;
+  }
+  k_sym_opp_mma<M, T><<<grid, 256, lds, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, ctx->A.tab,
+                                                       ctx->A.s, S.pairS, ctx->B.ns, S.plist, W,
+                                                       ctx->npair, S.maxcol, c, out);
+  return SBCI_OK;
+}
+
+// bf16: the opposite-spin part on BF16 MFMA (T = float; the other parts in FP32)
 template <typename T>
-int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
+int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, bool bf16) {
   const SymInfo &S = *ctx->sym;
   const SymArgs g = make_args(S);
   const int64_t nd = S.off[8];
@@ -602,19 +773,49 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev) {
   if (A.s > 0 && B.s > 0) {
     const T *W;
     if constexpr (dbl) W = ctx->W64; else W = ctx->W32;
-    int maxp8 = 8;
-    for (int x = 0; x < 8; ++x) maxp8 = std::max(maxp8, (S.pcs[x + 1] - S.pcs[x] + 7) & ~7);
+    int maxp8 = 8, maxp = 0;
+    for (int x = 0; x < 8; ++x) {
+      maxp8 = std::max(maxp8, (S.pcs[x + 1] - S.pcs[x] + 7) & ~7);
+      maxp = std::max(maxp, S.pcs[x + 1] - S.pcs[x]);
+    }
     const size_t lp = opp_pair_lds_bytes(A.s, sizeof(T), ctx->npair, S.maxcol, maxp8);
     const dim3 grid((unsigned)A.ns, (unsigned)nvec);
-    if (lp <= kSymPairLdsMax) {
+    PairStarts pcs;
+    for (int x = 0; x < 9; ++x) pcs.s[x] = S.pcs[x];
+    // the MFMA form: classes of at most kSymMmaRows pairs, the block offsets
+    // in 32 bits, its LDS within a CU's.  AUTO takes it for BF16 only: in
+    // FP64 and FP32 the vector pair form below is faster at the measured
+    // class sizes (CAS(14,14) irrep 0: 0.38 against 0.51 ms), the sums being
+    // bound by the scatter, not the multiply-adds
+    const int kstep = bf16 ? MBF16::KSTEP : dbl ? MF64::KSTEP : MF32::KSTEP;
+    const int pad = bf16 ? MBF16::PAD : dbl ? MF64::PAD : MF32::PAD;
+    const size_t asz = bf16 ? 2 : sizeof(T);
+    const size_t lm = opp_mma_lds_bytes(A.s, kstep, pad, asz, ctx->npair, S.maxcol);
+    const bool mma_ok = maxp <= kSymMmaRows && nd < ((int64_t)1 << 32) && lm <= 160 * 1024;
+    if (bf16 && !mma_ok)
+      return set_error(SBCI_EINVAL, "blocked sigma: the BF16 form needs at most 64 pairs per class");
+    if (bf16 && ctx->opp_form == SBCI_OPP_PAIR)
+      return set_error(SBCI_EINVAL, "blocked sigma: the pair form has FP64 and FP32 flavours only");
+    if (ctx->opp_form == SBCI_OPP_ORBITAL || ctx->opp_form == SBCI_OPP_ORBITAL_WINDOWED)
+      return set_error(SBCI_EINVAL, "blocked sigma: the orbital form is not offered");
+    if (ctx->opp_form == SBCI_OPP_CLASS_MFMA && !mma_ok)
+      return set_error(SBCI_EINVAL, "blocked sigma: the MFMA form needs at most 64 pairs per class");
+    if (bf16 || ctx->opp_form == SBCI_OPP_CLASS_MFMA) {
+      if constexpr (dbl) {
+        SBCI_TRY((launch_sym_mma<MF64, double>(ctx, g, pcs, ctx->W64, lm, grid, c, out)));
+      } else {
+        if (bf16)
+          SBCI_TRY((launch_sym_mma<MBF16, float>(ctx, g, pcs, ctx->W32, lm, grid, c, out)));
+        else
+          SBCI_TRY((launch_sym_mma<MF32, float>(ctx, g, pcs, ctx->W32, lm, grid, c, out)));
+      }
+    } else if (lp <= kSymPairLdsMax) {
       static bool attrp = false;
       if (!attrp) {
         SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_pair<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attrp = true;
       }
-      PairStarts pcs;
-      for (int x = 0; x < 9; ++x) pcs.s[x] = S.pcs[x];
       k_sym_opp_pair<T><<<grid, 256, lp, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, A.tab, A.s,
                                                         S.pairS, B.ns, S.plist, W, ctx->npair,
                                                         S.maxcol, maxp8, c, out);
@@ -636,12 +837,13 @@ int sigma_sym(sbci_ctx *ctx, const void *c, void *out, int nvec, int mode, hipEv
   switch (mode) {
     case SBCI_F64:
       return sigma_sym_t<double>(ctx, static_cast<const double *>(c), static_cast<double *>(out),
-                                 nvec, ev);
+                                 nvec, ev, false);
     case SBCI_F32:
       return sigma_sym_t<float>(ctx, static_cast<const float *>(c), static_cast<float *>(out),
-                                nvec, ev);
+                                nvec, ev, false);
     case SBCI_BF16:
-      return set_error(SBCI_EINVAL, "the symmetry-blocked sigma has FP64 and FP32 forms only");
+      return sigma_sym_t<float>(ctx, static_cast<const float *>(c), static_cast<float *>(out),
+                                nvec, ev, true);
     default:
       return set_error(SBCI_EINVAL, "unknown sigma dtype");
   }

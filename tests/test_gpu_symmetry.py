@@ -1,5 +1,6 @@
 """Point-group blocked contexts (sbci_create_sym) against the symmetry-blocked
-oracle: block layout, diagonal, sigma in FP64 and FP32, and the solvers'
+oracle: block layout, diagonal, sigma in FP64, FP32 and BF16 (the
+opposite-spin part on MFMA, and in the vector pair form), and the solvers'
 energies against the spectrum of the blocked Hamiltonian."""
 import numpy as np
 import pytest
@@ -55,9 +56,22 @@ def test_layout_diag_and_sigma_f64(n, na, nb, orbsym):
         got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
         scale = np.abs(want).max()
         assert np.abs(got - want).max() <= 1e-12 * scale, (g, np.abs(got - want).max() / scale)
-        got32 = ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype="f32").cpu().numpy()
+        c32 = torch.from_numpy(c.astype(np.float32)).cuda()
+        got32 = ctx.sigma(c32, dtype="f32").cpu().numpy()
         rel = np.linalg.norm(got32 - want) / np.linalg.norm(want)
         assert rel < 2e-6, (g, rel)
+        # BF16 operands in the opposite-spin MFMA (8-bit mantissa), FP32 elsewhere
+        gotb = ctx.sigma(c32, dtype="bf16").cpu().numpy()
+        relb = np.linalg.norm(gotb - want) / np.linalg.norm(want)
+        assert relb < 1e-2, (g, relb)
+        # the class MFMA form in FP64 and FP32 (the default there is the vector form)
+        ctx.set_opp_form("class_mfma")
+        gotm = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+        assert np.abs(gotm - want).max() <= 1e-12 * scale, (g, np.abs(gotm - want).max() / scale)
+        gotm32 = ctx.sigma(c32, dtype="f32").cpu().numpy()
+        assert np.linalg.norm(gotm32 - want) / np.linalg.norm(want) < 2e-6
+        gotmb = ctx.sigma(c32, dtype="bf16").cpu().numpy()
+        assert np.array_equal(gotmb, gotb) or np.linalg.norm(gotmb - gotb) / np.linalg.norm(want) < 1e-6
         ctx.close()
 
 
@@ -77,12 +91,15 @@ def test_sigma_with_integral_rows_beyond_lds(g):
     ctx.close()
 
 
-def test_bf16_and_bad_arguments_are_refused():
+def test_bad_forms_and_arguments_are_refused():
     import paper_2603_06101_amd as sb
     ctx, I, o = _ctx(6, 3, 3, 0)
     c = torch.zeros(ctx.ndet, dtype=torch.float32, device="cuda")
+    ctx.set_opp_form("pair")
     with pytest.raises(sb.SbciError):
-        ctx.sigma(c, dtype="bf16")
+        ctx.sigma(c, dtype="bf16")       # the vector pair form has no BF16 flavour
+    with pytest.raises(sb.SbciError):
+        ctx.set_opp_form("orbital")      # no orbital form on blocked contexts
     ctx.close()
     # integrals that break the symmetry
     J = make_integrals(6, 12, 0)
@@ -94,10 +111,12 @@ def test_bf16_and_bad_arguments_are_refused():
         sb.Context(2, 1, 1, K.h1, K.eri, orbsym=[0, 1], irrep=2)
     with pytest.raises(sb.SbciError):
         sb.Context(2, 1, 1, K.h1, K.eri, orbsym=[0, 9], irrep=0)
-    # an unblocked context has no blocks
+    # an unblocked context has no blocks and no class MFMA form
     U = sb.Context(6, 3, 3, J.h1, J.eri)
     with pytest.raises(sb.SbciError):
         U.sym_blocks()
+    with pytest.raises(sb.SbciError):
+        U.set_opp_form("class_mfma")
     U.close()
 
 
@@ -120,10 +139,12 @@ def test_solvers_reach_the_blocked_spectrum(n, na, nb, g):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("n,na,nb,g", [(8, 4, 4, 0), (8, 4, 4, 5), (7, 3, 4, 2), (9, 4, 4, 1)])
-def test_fp32_form_reaches_the_blocked_spectrum(n, na, nb, g):
-    """The FP32 precision form (FP32 sigma and vectors, FP64 reductions and
-    refinement) on few-hundred-determinant blocks whose lowest states lie
+def test_precision_forms_reach_the_blocked_spectrum(n, na, nb, g, prec):
+    """The FP32 and BF16 precision forms (low-precision sigma and FP32
+    vectors, FP64 reductions and refinement) on few-hundred-determinant
+    blocks whose lowest states lie
     within about 5e-5 Eh of single diagonal entries.  (7,3,4, irrep 2) and
     (8,4,4, irrep 5) once stopped with a non-finite reduction: a step whose
     new iterate has norm |k| << 1 amplified the FP32 images' error until the
@@ -134,7 +155,7 @@ def test_fp32_form_reaches_the_blocked_spectrum(n, na, nb, g):
     Hd = H.dense_h_slater_condon(n, na, nb, I.h1, I.eri)[np.ix_(idx, idx)]
     w = np.linalg.eigvalsh(Hd)
     nroots = 3
-    rm = ctx.solve(nroots, tol=1e-10, opts=dict(precision="f32"))
+    rm = ctx.solve(nroots, tol=1e-10, opts=dict(precision=prec))
     assert rm.status == 0
     assert np.abs(np.sort(rm.energies) - w[:nroots]).max() < 1e-8, (rm.energies, w[:nroots])
     ctx.close()
@@ -167,8 +188,10 @@ def test_full_size_cas14_sym_sampled_and_solved():
     assert np.abs(rq - r.energies).max() < 1e-9
     assert res.max() < 3e-5
     assert np.abs((X @ X.T).cpu().numpy() - np.eye(5)).max() < 1e-8
-    rm = ctx.solve(5, tol=1e-10, opts=dict(precision="f32"), want_vectors=False)
-    assert np.abs(np.sort(rm.energies) - np.sort(r.energies)).max() < 1e-8
+    for prec in ("f32", "bf16"):
+        rm = ctx.solve(5, tol=1e-10, opts=dict(precision=prec), want_vectors=False)
+        assert rm.status == 0, prec
+        assert np.abs(np.sort(rm.energies) - np.sort(r.energies)).max() < 1e-8, prec
     r2 = ctx.solve2(5, tol=1e-10, want_vectors=False)
     assert np.abs(np.sort(r2.energies) - np.sort(r.energies)).max() < 1e-8
     ctx.close()
