@@ -340,7 +340,8 @@ int sbci_solve2(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt,
  * balanced share of one workgroup runs on a team of up to max_team
  * co-resident workgroups that split its rows and meet at bounded barriers
  * (the device should not be shared with other work during the solve: a team
- * that waits longer than one second ends its instance with SBCI_EDEVICE).
+ * that waits longer than config.team_wait_us, one second by default, ends its
+ * instance with SBCI_EDEVICE).
  * Limits per instance: 1 <= norb <= 10 (at most 252 strings per spin),
  * 1 <= nroots <= min(4, N_det).
  */
@@ -353,6 +354,9 @@ typedef struct sbci_batch_config {
   int order;      /* queue order: 0 = largest estimated work first, 1 = input  */
   int k_panel;    /* K panel of the same-spin MFMA products in LDS: 8 or 16    */
   int max_team;   /* workgroups per instance at most: 1 (no teams) .. 4; 0 = 4 */
+  int team_wait_us; /* bound of a team barrier wait in microseconds; 0 = 1 s.
+                       A team whose wait exceeds it ends its instance with
+                       SBCI_EDEVICE                                             */
 } sbci_batch_config;
 
 typedef struct sbci_batch_report {
@@ -364,9 +368,12 @@ typedef struct sbci_batch_report {
   int64_t det_sigma;         /* sum over instances of N_det x sigma applications */
   int64_t nsteps, nrestarts; /* summed over instances                           */
   int ninst_converged;       /* instances with status SBCI_OK                   */
-  int threads, wg_per_cu, order, k_panel, max_team;  /* the launch shape used  */
+  int threads, wg_per_cu, order, k_panel, max_team, team_wait_us;  /* the shape used */
   int nteams;                /* instances run by a team of workgroups          */
   int team_workgroups;       /* workgroups in those teams                       */
+  int team_timeouts;         /* team instances ended by the wait bound
+                                (status SBCI_EDEVICE; the call then returns
+                                SBCI_EDEVICE with every output written)         */
 } sbci_batch_report;
 
 /* Per-instance outcome of a batch solve (times from the device real-time

@@ -82,7 +82,8 @@ _P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int6
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I)]
+    _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I),
+                ("team_wait_us", _I)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,7 +102,7 @@ class BatchReport(ctypes.Structure):
         ("seconds", _D), ("span_seconds", _D), ("nsigma_f64", _I64), ("nsigma_low", _I64), ("det_sigma", _I64),
         ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
         ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I),
-        ("nteams", _I), ("team_workgroups", _I),
+        ("team_wait_us", _I), ("nteams", _I), ("team_workgroups", _I), ("team_timeouts", _I),
     ]
 
     def as_dict(self):
@@ -459,7 +460,8 @@ class Batch:
         rc = lib().sbci_batch_solve(self.h, r.ctypes.data, tol, ctypes.byref(o),
                                     ctypes.byref(cfg) if cfg is not None else None,
                                     e.ctypes.data, info, ctypes.byref(rep))
-        _check(rc, allow=(SBCI_ENOCONV, SBCI_ENUMERIC))
+        # SBCI_EDEVICE with team timeouts counted: per-instance outcomes, outputs written
+        _check(rc, allow=(SBCI_ENOCONV, SBCI_ENUMERIC) + ((SBCI_EDEVICE,) if rep.team_timeouts > 0 else ()))
         self._nroots = r
         parts = np.split(e, np.cumsum(r)[:-1])
         inst = []

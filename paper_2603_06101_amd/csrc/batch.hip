@@ -20,8 +20,8 @@
 //     team sums the members' partials in member order), so they take the same
 //     decisions; a barrier (agent-scope release / acquire around a counter)
 //     sits in every reduction and before every sigma, whose input spans all
-//     members' rows.  Every wait is bounded: past one second the team aborts
-//     the instance with SBCI_EDEVICE.
+//     members' rows.  Every wait is bounded (one second by default): past the
+//     bound the team aborts the instance with SBCI_EDEVICE.
 //   * sigma inside a workgroup: the one-electron and same-spin parts as two
 //     dense MFMA products C * H_beta + H_alpha * C (for norb <= 10 these
 //     operators are 50-95 % dense) with LDS-staged K panels; the
@@ -86,6 +86,7 @@ struct BParams {
   double eps0, r0, b_th, eps1, x_th1, x_th2, r1, mix_eps0, mix_r0, bf16_eps0, bf16_r0, floor,
       lindep;
   int max_cycle, max_steps, precision, mix_stall;
+  uint64_t team_wait;  // bound of a team barrier wait, real-time counter ticks
   int kp;  // K panel of the same-spin GEMMs: 8 or 16
 };
 
@@ -112,15 +113,17 @@ struct TeamSync {
 // of 16-row alpha tiles.
 struct Team {
   TeamSync *ts;
+  uint64_t wait;     // bound of a barrier wait (ticks)
   int T, m;
   int t0, t1;        // alpha tiles
   int a0, a1;        // alpha rows
   int64_t r0, r1;    // determinant rows
 };
 
-__device__ inline Team make_team(int nsa, int64_t nsb, TeamSync *ts, int T, int m) {
+__device__ inline Team make_team(int nsa, int64_t nsb, TeamSync *ts, int T, int m, uint64_t wait) {
   Team t;
   t.ts = ts;
+  t.wait = wait;
   t.T = T;
   t.m = m;
   const int tiles = (nsa + 15) / 16;
@@ -133,7 +136,8 @@ __device__ inline Team make_team(int nsa, int64_t nsb, TeamSync *ts, int T, int 
   return t;
 }
 
-constexpr uint64_t kTeamWaitTicks = 100000000ull;  // 1 s of the 100 MHz real-time counter
+constexpr uint64_t kTeamWaitTicks = 100000000ull;  // default bound: 1 s of the 100 MHz real-time counter
+constexpr uint64_t kTicksPerUs = 100;
 
 // Team barrier: every member's prior global writes become visible to every
 // member.  Each thread releases at agent scope, thread 0 arrives and waits
@@ -154,7 +158,7 @@ __device__ void team_sync(const Team &tm, Red<NT> &R) {
     for (;;) {
       if (__hip_atomic_load(&tm.ts->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
       if (__hip_atomic_load(&tm.ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          __builtin_amdgcn_s_memrealtime() - t0 > kTeamWaitTicks) {
+          __builtin_amdgcn_s_memrealtime() - t0 > tm.wait) {
         __hip_atomic_store(&tm.ts->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         R.abort = 1;
         break;
@@ -1409,7 +1413,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
   if ((int)blockIdx.x < ntw) {
     const int4 tb = team_blk[blockIdx.x];
     const BInst &I = inst[tb.x];
-    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, tsync + tb.w, tb.y, tb.z)};
+    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, tsync + tb.w, tb.y, tb.z, prm->team_wait)};
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     S.run(out[tb.x]);
     if (threadIdx.x == 0 && tb.z == 0) {
@@ -1427,7 +1431,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BInst *__restrict__ inst,
     const int id = order[it];
     // descriptors and parameters stay in global memory (uniform loads)
     const BInst &I = inst[id];
-    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, nullptr, 1, 0)};
+    Solve<NT> S{I, *prm, C, R, lds, make_team(I.ns_a, I.ns_b, nullptr, 1, 0, 0)};
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     S.run(out[id]);
     if (threadIdx.x == 0) {
@@ -1587,6 +1591,7 @@ int check_config(const sbci_batch_config &c) {
     return batch_error(SBCI_EINVAL, "batch config: k_panel must be 8 or 16");
   if (c.max_team < 0 || c.max_team > BMAX_TEAM)
     return batch_error(SBCI_EINVAL, "batch config: max_team must be in 0..4");
+  if (c.team_wait_us < 0) return batch_error(SBCI_EINVAL, "batch config: team_wait_us must be >= 0");
   return SBCI_OK;
 }
 
@@ -1786,6 +1791,7 @@ int run_graph(sbci_batch *b, const sbci_batch_config &cfg, const BParams &P, dou
   hipGraphExec_t x = nullptr;
   BParams Pc = P;
   Pc.kp = cfg.k_panel;
+  Pc.team_wait = cfg.team_wait_us == 0 ? kTeamWaitTicks : (uint64_t)cfg.team_wait_us * kTicksPerUs;
   SBCI_HIP(hipMemcpyAsync(b->d_params, &Pc, sizeof(BParams), hipMemcpyHostToDevice, b->stream));
   int rc = SBCI_OK;
   if (cfg.threads == 256)
@@ -1821,6 +1827,7 @@ sbci_batch_config default_config() {
   c.order = 0;
   c.k_panel = 16;
   c.max_team = 0;
+  c.team_wait_us = 0;
   return c;
 }
 
@@ -1960,7 +1967,8 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
       f.t_opp = (double)q.tsig[1] / kRealtimeHz;
     }
     if (q.status == SBCI_OK) r.ninst_converged += 1;
-    else if (worst == SBCI_OK || q.status == SBCI_ENUMERIC) worst = q.status;
+    else if (worst == SBCI_OK || q.status == SBCI_ENUMERIC || q.status == SBCI_EDEVICE) worst = q.status;
+    if (q.status == SBCI_EDEVICE) r.team_timeouts += 1;
     r.nsigma_f64 += q.nsig64;
     r.nsigma_low += q.nsiglow;
     r.det_sigma += (int64_t)b->ctx[i]->ndet * (q.nsig64 + q.nsiglow);
@@ -1973,12 +1981,14 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   r.order = cfg.order;
   r.k_panel = cfg.k_panel;
   r.max_team = cfg.max_team;
+  r.team_wait_us = cfg.team_wait_us;
   r.nteams = pl.nteam;
   r.team_workgroups = pl.ntw;
   if (rep) *rep = r;
   if (worst != SBCI_OK)
-    return batch_error(worst, worst == SBCI_ENOCONV ? "some batch instances did not converge"
-                                                    : "numerical failure in a batch instance");
+    return batch_error(worst, worst == SBCI_ENOCONV   ? "some batch instances did not converge"
+                              : worst == SBCI_EDEVICE ? "a team of workgroups exceeded its wait bound"
+                                                      : "numerical failure in a batch instance");
   return SBCI_OK;
 }
 

@@ -133,6 +133,31 @@ def test_teams_agree_with_lone_workgroups(small_batch):
                 _check_eigenpairs(n, na, nb, I, team.energies[i], small_batch.vectors(i).cpu().numpy())
 
 
+def test_team_wait_bound_ends_team_instances():
+    """The failure path of the team barrier, forced from the host: with a
+    1 microsecond bound on each wait, the members of a team stop waiting for
+    each other and the team's instances end with SBCI_EDEVICE, while every
+    wait still ends, the kernel returns and the lone-workgroup instances
+    converge.  The next solve, at the default bound, is unaffected."""
+    import paper_2603_06101_amd as sb
+    inst = [(9, 4, 4, 3, 0), (9, 4, 4, 2, 1), (6, 3, 3, 1, 2), (7, 3, 3, 1, 3), (5, 2, 2, 1, 4)]
+    b = sb.Batch(_instances(inst))
+    nroots = [t[3] for t in inst]
+    cfg = dict(threads=512, wg_per_cu=1, order=0, k_panel=16, max_team=4)
+    r = b.solve(nroots, tol=1e-10, config=dict(cfg, team_wait_us=1))
+    assert r.report["nteams"] >= 1
+    st = np.asarray(r.status)
+    assert (st == sb.SBCI_EDEVICE).sum() >= 1, st
+    assert r.report["team_timeouts"] == (st == sb.SBCI_EDEVICE).sum()
+    assert r.rc == sb.SBCI_EDEVICE
+    assert set(np.unique(st).tolist()) <= {0, sb.SBCI_EDEVICE}, st
+    lone = [i for i in range(len(inst)) if inst[i][0] <= 7]
+    assert (st[lone] == 0).all(), st
+    ok = b.solve(nroots, tol=1e-10, config=cfg)
+    assert (np.asarray(ok.status) == 0).all(), ok.status
+    b.close()
+
+
 def test_autotuner_picks_a_measured_candidate(small_batch):
     nroots = [t[3] for t in SMALL]
     best, cands = small_batch.tune(nroots, tol=1e-10)
