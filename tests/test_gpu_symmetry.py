@@ -120,6 +120,26 @@ def test_bad_forms_and_arguments_are_refused():
     U.close()
 
 
+def test_class_of_more_than_64_pairs_uses_the_vector_form():
+    """Labels that put 12 of 13 orbitals in irrep 0 make pair class 0 hold 79
+    pairs (more than an MFMA class tile takes): FP64 still runs (the vector
+    pair form); the MFMA form, and with it BF16, is refused."""
+    import paper_2603_06101_amd as sb
+    o = [0] * 12 + [3]
+    ctx, I, _ = _ctx(13, 3, 2, 0, orbsym=o, seed=2)
+    c = sigma_inputs(5, 1, ctx.ndet)[0]
+    idx, _ = SY.block_layout(13, 3, 2, np.asarray(o), 0)
+    want = SY.sigma(13, 3, 2, I.h1, I.eri, np.asarray(o), 0, c[None])[0]
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    with pytest.raises(sb.SbciError):
+        ctx.sigma(torch.from_numpy(c.astype(np.float32)).cuda(), dtype="bf16")
+    ctx.set_opp_form("class_mfma")
+    with pytest.raises(sb.SbciError):
+        ctx.sigma(torch.from_numpy(c).cuda())
+    ctx.close()
+
+
 @pytest.mark.parametrize("n,na,nb,g", [(8, 4, 4, 0), (8, 4, 4, 5), (7, 3, 4, 2), (9, 4, 4, 1)])
 def test_solvers_reach_the_blocked_spectrum(n, na, nb, g):
     ctx, I, o = _ctx(n, na, nb, g, seed=11)
