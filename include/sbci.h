@@ -111,6 +111,22 @@ typedef struct sbci_opts {
                                  the image H x_c carried to each root's acceptance
                                  (an accepted x_c keeps a residual, which E_c x_c
                                  would leave in the images)                             */
+  /* Resume (sbci_solve and sbci_begin only; SBCI2, Davidson and the batch
+   * form refuse nconv0 != 0).  The solver's state between roots is the set
+   * {x_c, E_c} of converged roots (Algorithm 1 deflates against nothing
+   * else), so a solve stopped after k roots continues from them: pass the
+   * k vectors (e.g. rows of an earlier dev_vecs, copied to the host) and
+   * optionally their energies, and root k starts from x0 when given (an
+   * earlier iterate) or else from the Section S1.1 start block's vector k,
+   * projected off the given roots (Eqs. S4-S5).  The given vectors are
+   * orthonormalised in order (Gram-Schmidt, FP64); SBCI_EINVAL if one is
+   * zero, not finite or (to lindep) dependent on the earlier ones.
+   * energies / dev_vecs / the report count the given roots as roots 0..k-1
+   * (their t_converged and resid read 0). */
+  int nconv0;                 /* roots already converged, in [0, nroots); 0 = none      */
+  const double *xc0;          /* host [nconv0][N_det] FP64 converged vectors, row-major */
+  const double *ec0;          /* host [nconv0] their energies, or NULL: the Rayleigh
+                                 quotients x_c^T H x_c (one FP64 sigma each)            */
 } sbci_opts;
 
 typedef struct sbci_report {

@@ -46,6 +46,8 @@ class Opts(ctypes.Structure):
         ("x0", ctypes.POINTER(ctypes.c_double)),
         ("bf16_eps0", ctypes.c_double), ("bf16_r0", ctypes.c_double),
         ("max_cycle2", ctypes.c_int), ("s78_printed", ctypes.c_int),
+        ("nconv0", ctypes.c_int),
+        ("xc0", ctypes.POINTER(ctypes.c_double)), ("ec0", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -343,12 +345,34 @@ class Context:
         _check(rc, allow=(SBCI_ENOCONV,))
         return SolveResult(e, vec, _report_dict(rep, nroots), self.trace(), rc)
 
-    def solve(self, nroots, tol=1e-10, opts=None, want_vectors=True, x0=None):
-        """SBCI1 for the lowest nroots states; x0: optional host start vector (numpy)."""
+    @staticmethod
+    def _resume(o, xc, ec):
+        """Point opts at converged roots xc [k, N_det] (numpy or a torch tensor,
+        copied to the host) and energies ec [k] (or None); returns the host
+        arrays, which must outlive the call."""
+        if xc is None:
+            return ()
+        if hasattr(xc, "detach"):
+            xc = xc.detach().to("cpu").numpy()
+        xc = np.ascontiguousarray(np.atleast_2d(xc), dtype=np.float64)
+        o.nconv0 = xc.shape[0]
+        o.xc0 = xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if ec is not None:
+            ec = np.ascontiguousarray(ec, dtype=np.float64)
+            if ec.shape != (xc.shape[0],):
+                raise ValueError("ec must hold one energy per row of xc")
+            o.ec0 = ec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return (xc, ec)
+
+    def solve(self, nroots, tol=1e-10, opts=None, want_vectors=True, x0=None, xc=None, ec=None):
+        """SBCI1 for the lowest nroots states; x0: optional host start vector (numpy).
+        xc / ec: resume after len(xc) converged roots (their vectors and, optionally,
+        energies); the result holds all nroots roots."""
         o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
         if x0 is not None:
             x0 = np.ascontiguousarray(x0, dtype=np.float64)
             o.x0 = x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep = self._resume(o, xc, ec)  # noqa: F841 (kept alive across the call)
         return self._run(lib().sbci_solve, nroots, tol, o, want_vectors)
 
     def davidson(self, nroots, tol=1e-10, opts=None, want_vectors=True):
@@ -358,11 +382,12 @@ class Context:
         """SBCI2 (pairs of states; FP64) for the lowest nroots states."""
         return self._run(lib().sbci_solve2, nroots, tol, opts, want_vectors)
 
-    def begin(self, nroots, tol=1e-10, opts=None, x0=None):
+    def begin(self, nroots, tol=1e-10, opts=None, x0=None, xc=None, ec=None):
         o = opts if isinstance(opts, Opts) else default_opts(**(opts or {}))
         if x0 is not None:
             self._x0 = np.ascontiguousarray(x0, dtype=np.float64)
             o.x0 = self._x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._resume_keep = self._resume(o, xc, ec)
         self._opts = o
         _check(lib().sbci_begin(self.h, nroots, tol, ctypes.byref(o)))
         self._nroots = nroots

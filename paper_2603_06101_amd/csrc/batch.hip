@@ -1607,6 +1607,7 @@ int params_from(const sbci_opts *opt, double tol, BParams &P, int &precision) {
     return batch_error(SBCI_EINVAL, "unknown precision");
   if (o.max_cycle < 1 || o.max_steps < 1) return batch_error(SBCI_EINVAL, "max_cycle, max_steps >= 1");
   if (o.x0) return batch_error(SBCI_EINVAL, "batch solve: opts.x0 must be NULL");
+  if (o.nconv0 != 0) return batch_error(SBCI_EINVAL, "batch solve: opts.nconv0 must be 0");
   P.eps0 = o.eps0;
   P.r0 = o.r0;
   P.b_th = o.b_th;

@@ -751,14 +751,82 @@ int initial_vector(sbci_ctx *ctx, Solver &S) {
     return SBCI_OK;
   }
   const int k = (int)std::min<int64_t>(S.nroots, n);
+  // a resumed solve starts root alpha from the start block's vector alpha
+  // (the lower ones are projected off by the root start)
+  const int a = (int)S.Ec.size();
   std::vector<int64_t> idx;
   std::vector<double> w, U;
   // the solver's y and Y slots are free until the first step
   SBCI_TRY(start_block(ctx, k, S.v64[Y_], S.v64[YY_], idx, w, U, S.rep.nsigma_f64));
   SBCI_HIP(hipMemsetAsync(S.v64[Y_], 0, sizeof(double) * n, ctx->stream));
   SBCI_HIP(hipMemsetAsync(S.v64[YY_], 0, sizeof(double) * n, ctx->stream));
-  SBCI_TRY(start_vector(ctx, k, idx, U, 0, x, X, S.rep.nsigma_f64));         // Eqs. S2-S3
-  S.E = w[0];
+  SBCI_TRY(start_vector(ctx, k, idx, U, a, x, X, S.rep.nsigma_f64));         // Eqs. S2-S3
+  S.E = w[a];
+  return SBCI_OK;
+}
+
+// Resume: the caller's nconv0 converged roots become x_c (orthonormalised in
+// the given order by Gram-Schmidt, in FP64) with energies E_c (given, or the
+// Rayleigh quotients x_c^T H x_c), exactly as if this solve had converged
+// them; the state the solver deflates against is nothing more than {x_c, E_c}.
+int resume_roots(sbci_ctx *ctx, Solver &S) {
+  const int64_t n = S.n;
+  double *X = S.v64[XX_];
+  for (int i = 0; i < S.o.nconv0; ++i) {
+    double *xc = S.pool64.back();
+    S.pool64.pop_back();
+    SBCI_HIP(hipMemcpyAsync(xc, S.o.xc0 + (int64_t)i * n, sizeof(double) * n, hipMemcpyHostToDevice,
+                            ctx->stream));
+    const double *self[1] = {xc};
+    double d[16];
+    SBCI_TRY(dots<double>(ctx, n, xc, self, 1, S.red + 40));
+    SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SBCI_HIP(hipStreamSynchronize(ctx->stream));
+    const double n0 = d[0];
+    if (!(n0 > 0) || !std::isfinite(n0)) {
+      hipFree(xc);
+      return set_error(SBCI_EINVAL, "resume: a converged vector is zero or not finite");
+    }
+    S.xc64.push_back(xc);
+    if (i > 0) {
+      std::vector<const double *> xcp(S.xc64.begin(), S.xc64.end() - 1);
+      double cf[16];
+      for (int pass = 0; pass < 2; ++pass) {   // two passes: orthogonal to rounding
+        SBCI_TRY(dots<double>(ctx, n, xc, xcp.data(), i, S.red + 40));
+        SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double) * i, hipMemcpyDeviceToHost, ctx->stream));
+        SBCI_HIP(hipStreamSynchronize(ctx->stream));
+        for (int j = 0; j < i; ++j) cf[j] = -d[j];
+        SBCI_TRY(lincomb<double>(ctx, n, xc, xcp.data(), cf, i, 1.0));
+      }
+    }
+    SBCI_TRY(dots<double>(ctx, n, xc, self, 1, S.red + 40));
+    SBCI_HIP(hipMemcpyAsync(d, S.red + 40, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SBCI_HIP(hipStreamSynchronize(ctx->stream));
+    if (!(d[0] > S.o.lindep * n0))
+      return set_error(SBCI_EINVAL, "resume: the converged vectors are linearly dependent");
+    SBCI_TRY((convert<double, double>(ctx, n, xc, xc, 1.0 / std::sqrt(d[0]))));
+    double E;
+    if (S.o.ec0) {
+      E = S.o.ec0[i];
+      if (!std::isfinite(E)) return set_error(SBCI_EINVAL, "resume: a converged energy is not finite");
+    } else {
+      SBCI_TRY(sigma(ctx, xc, X, 1, SBCI_F64));
+      S.rep.nsigma_f64 += 1;
+      const double *Xp[1] = {X};
+      SBCI_TRY(dots<double>(ctx, n, xc, Xp, 1, S.red + 40));
+      SBCI_HIP(hipMemcpyAsync(&E, S.red + 40, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      SBCI_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    if (S.o.precision != SBCI_F64) {
+      float *x32 = S.pool32.back();
+      S.pool32.pop_back();
+      S.xc32.push_back(x32);
+      SBCI_TRY((convert<float, double>(ctx, n, x32, xc, 1.0)));
+    }
+    S.Ec.push_back(E);
+  }
+  S.alpha = S.o.nconv0;
+  S.rep.nroots_converged = S.o.nconv0;
   return SBCI_OK;
 }
 
@@ -796,6 +864,9 @@ int resolve_opts(const sbci_opts *opt, double tol, int nroots, int64_t ndet, sbc
     return set_error(SBCI_EINVAL, "unknown precision");
   if (o.max_cycle < 1 || o.max_steps < 1) return set_error(SBCI_EINVAL, "max_cycle, max_steps >= 1");
   if (o.s78_printed != 0 && o.s78_printed != 1) return set_error(SBCI_EINVAL, "s78_printed must be 0 or 1");
+  if (o.nconv0 < 0 || o.nconv0 >= nroots)
+    return set_error(SBCI_EINVAL, "nconv0 must be in [0, nroots)");
+  if (o.nconv0 > 0 && !o.xc0) return set_error(SBCI_EINVAL, "nconv0 > 0 needs xc0");
   return SBCI_OK;
 }
 
@@ -827,6 +898,7 @@ int solver_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {
       S->alloc_bytes += sizeof(float) * S->n;
     }
   }
+  SBCI_TRY(resume_roots(ctx, *S));
   SBCI_TRY(initial_vector(ctx, *S));
   if (S->o.precision != SBCI_F64) {
     SBCI_TRY((convert<float, double>(ctx, S->n, S->v32[X_], S->v64[X_], 1.0)));
@@ -921,6 +993,7 @@ int davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double
              double *dev_vecs, sbci_report *rep_out) {
   sbci_opts o;
   SBCI_TRY(resolve_opts(opt, tol, nroots, ctx->ndet, o));
+  if (o.nconv0 != 0) return set_error(SBCI_EINVAL, "sbci_davidson does not resume (nconv0 must be 0)");
   const int64_t n = ctx->ndet;
   const int maxs = o.max_space > 0 ? o.max_space : 12 + nroots;
   if (maxs < 2 * nroots) return set_error(SBCI_EINVAL, "max_space must be >= 2 * nroots");
@@ -1366,6 +1439,7 @@ int sbci2_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, dou
   ctx->solver = Sp;
   Solver &S = *Sp;
   SBCI_TRY(resolve_opts(opt, tol, nroots, ctx->ndet, S.o));
+  if (S.o.nconv0 != 0) return set_error(SBCI_EINVAL, "sbci_solve2 does not resume (nconv0 must be 0)");
   const int first_phase = S.o.precision;  // each pair starts here and ends in FP64
   S.nroots = nroots;
   S.n = ctx->ndet;

@@ -65,6 +65,24 @@ static void run_ctx(sbci_ctx *ctx, int nroots) {
   sbci_step_info info;
   while (!done && guard++ < 5000) CHECK(sbci_step(ctx, &info, &done));
   CHECK(sbci_finish(ctx, e.data(), vec, &rep));
+  if (nroots >= 2) {
+    // resume after nroots - 1 converged roots, with and without their energies,
+    // in FP64 and FP32 (host Gram-Schmidt and the root pools)
+    std::vector<double> hv(nd * (nroots - 1));
+    hipMemcpy(hv.data(), vec, 8 * nd * (nroots - 1), hipMemcpyDeviceToHost);
+    std::vector<double> ek(e.begin(), e.end() - 1);
+    o.nconv0 = nroots - 1;
+    o.xc0 = hv.data();
+    for (int prec : {SBCI_F64, SBCI_F32}) {
+      o.precision = prec;
+      o.ec0 = prec == SBCI_F64 ? ek.data() : nullptr;
+      CHECK(sbci_solve(ctx, nroots, 1e-10, &o, e.data(), vec, &rep));
+    }
+    if (sbci_davidson(ctx, nroots, 1e-10, &o, e.data(), vec, &rep) == 0) { std::printf("FAIL resume refusal\n"); std::exit(1); }
+    o.nconv0 = 0;
+    o.xc0 = o.ec0 = nullptr;
+    o.precision = SBCI_F64;
+  }
   std::vector<sbci_step_info> tr(64);
   if (sbci_trace(ctx, tr.data(), 64) < 0) { std::printf("FAIL trace\n"); std::exit(1); }
   // refusals: bad dtype, aliasing, nroots out of range

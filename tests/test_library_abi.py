@@ -84,3 +84,32 @@ def test_symmetry_entry_points_reject_null_arguments():
     assert rc == sb.SBCI_EINVAL and not out.value and b"orbsym" in sb.lib().sbci_last_error()
     blocks = np.zeros(24, dtype=np.int64)
     assert sb.lib().sbci_sym_blocks(None, blocks.ctypes.data) == sb.SBCI_EINVAL
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the structure of the same name in sbci.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("sbci_opts", sb.Opts), ("sbci_report", sb.Report), ("sbci_step_info", sb.StepInfo),
+             ("sbci_batch_config", sb.BatchConfig), ("sbci_batch_inst", sb.BatchInst),
+             ("sbci_batch_report", sb.BatchReport)]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sbci.h"', "int main(void) {"]
+    want = []
+    for cname, py in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(py))
+        for f in py._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            want.append(getattr(py, f[0]).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want
