@@ -238,9 +238,12 @@ int sbci_sigma(sbci_ctx *ctx, const void *dev_c, void *dev_sigma, int nvec, int 
  * atomics, under a power-of-two scale set per row from a bound on its
  * partial sums (max |C| over the rows it reads times s_beta times the
  * largest row sum of |(kl|k'l')|), so an FP64 sigma is the same to the last
- * bit on every call; every other part sums in a fixed order.  on = 0: FP64
- * atomics (the order of additions varies, about 10% faster).  FP32 and BF16
- * sigma are not covered.  SBCI_EINVAL unless on is 0 or 1. */
+ * bit on every call; every other part sums in a fixed order.  This holds for
+ * unblocked and point-group blocked contexts, in every opposite-spin form.
+ * A row whose scale bound is not finite (a NaN or Inf in a row of c it
+ * reads) becomes NaN.  on = 0: FP64 atomics (the order of additions varies;
+ * about 10% faster unblocked, 2-3% blocked).  FP32 and BF16 sigma are not
+ * covered.  SBCI_EINVAL unless on is 0 or 1. */
 int sbci_set_deterministic(sbci_ctx *ctx, int on);
 
 /* sbci_sigma for callers that cannot allocate device memory (code under HIP

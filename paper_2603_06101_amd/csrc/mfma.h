@@ -81,5 +81,53 @@ __device__ __forceinline__ int pair_index(int p, int q) {
   return k * (k + 1) / 2 + l;
 }
 
+// Reproducible FP64 scatter of the opposite-spin kernels.  A row of sigma
+// accumulates in 64-bit fixed point: integer additions are exact, so the row
+// does not depend on the order in which waves add.  The scale is a power of
+// two chosen per row from a bound bnd on every partial sum (bnd < 2^62 after
+// scaling); bad (a non-finite bound) makes the row NaN.
+__device__ __forceinline__ void fix_scale_from_bound(double bnd, double &scale, double &inv,
+                                                     bool &bad) {
+  bad = !(bnd < INFINITY);
+  scale = inv = 1.0;
+  if (bnd > 0 && !bad) {
+    int x = 0;
+    frexp(bnd, &x);  // bnd < 2^x
+    int ex = 62 - x;
+    ex = ex > 900 ? 900 : (ex < -900 ? -900 : ex);
+    scale = ldexp(1.0, ex);
+    inv = ldexp(1.0, -ex);
+  }
+}
+
+// Add one contribution to a row slot: in fixed point (FIX) v is already in
+// fixed-point units (|v| < 2^62, the scale folded into the operands) and is
+// taken to floor(v) by a split at 2^32, hi = floor(v / 2^32), lo = v - hi 2^32
+// in [0, 2^32), both exact; otherwise an FP64 atomic add.
+template <bool FIX>
+__device__ __forceinline__ void scatter_add(double *slot, double v) {
+  if constexpr (FIX) {
+    const double hi = floor(v * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, v);
+    const unsigned long long q =
+        ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+    atomicAdd(reinterpret_cast<unsigned long long *>(slot), q);
+  } else {
+    atomicAdd(slot, v);
+  }
+}
+
+// Row write-back value of slot j: fixed point scaled back (or NaN), or the
+// FP64 sum.
+template <bool FIX, typename T>
+__device__ __forceinline__ T row_value(const double *acc, int64_t j, double inv, bool bad) {
+  if constexpr (FIX) {
+    const long long q = (long long)reinterpret_cast<const unsigned long long *>(acc)[j];
+    return bad ? (T)NAN : (T)((double)q * inv);
+  } else {
+    return (T)acc[j];
+  }
+}
+
 }  // namespace
 }  // namespace sbci

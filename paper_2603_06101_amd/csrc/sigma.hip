@@ -394,47 +394,7 @@ __device__ inline void fix_scale(const double *__restrict__ rowmax, const Ent *_
   m = 0.0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-  const double bnd = wbound * m;
-  bad = !(bnd < INFINITY);
-  scale = inv = 1.0;
-  if (bnd > 0 && !bad) {
-    int x = 0;
-    frexp(bnd, &x);  // bnd < 2^x
-    int ex = 62 - x;
-    ex = ex > 900 ? 900 : (ex < -900 ? -900 : ex);
-    scale = ldexp(1.0, ex);
-    inv = ldexp(1.0, -ex);
-  }
-}
-
-// Scatter one contribution into sigma's row.  FP64 in 64-bit fixed point
-// (exact integer adds, so the row does not depend on the scatter order): v
-// is already in fixed-point units (|v| < 2^62, the scale is folded into the
-// A tile) and is taken to floor(v) by a split at 2^32, hi = floor(v / 2^32),
-// lo = v - hi 2^32 in [0, 2^32), both exact; the other flavours add with
-// FP64 atomics.
-template <bool FIX>
-__device__ __forceinline__ void scatter_add(double *slot, double v) {
-  if constexpr (FIX) {
-    const double hi = floor(v * 0x1p-32);
-    const double lo = fma(hi, -0x1p32, v);
-    const unsigned long long q =
-        ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
-    atomicAdd(reinterpret_cast<unsigned long long *>(slot), q);
-  } else {
-    atomicAdd(slot, v);
-  }
-}
-
-// Row write-back: sigma += the row (fixed point scaled back, or NaN).
-template <bool FIX, typename T>
-__device__ __forceinline__ T row_value(const double *acc, int64_t j, double inv, bool bad) {
-  if constexpr (FIX) {
-    const long long q = (long long)reinterpret_cast<const unsigned long long *>(acc)[j];
-    return bad ? (T)NAN : (T)((double)q * inv);
-  } else {
-    return (T)acc[j];
-  }
+  fix_scale_from_bound(wbound * m, scale, inv, bad);
 }
 
 // Dynamic LDS of the opposite-spin kernels: 160 KB less the static
@@ -503,7 +463,9 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
       int kl = pair_index(t.p, t.q);
       eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
     } else {
-      eoff[e] = (uint32_t)ia * (uint32_t)ldc;  // any valid row: its A column is zero
+      // the row's own string (its diagonal excitation is in the list, so a
+      // non-finite value there already makes the row NaN); its A column is zero
+      eoff[e] = (uint32_t)ia * (uint32_t)ldc;
       eW[e] = kPadEntry;
     }
   }
@@ -837,7 +799,10 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
       int kl = pair_index(t.p, t.q);
       eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
     } else {
-      eoff[e] = 0;  // row 0 of Cq: a valid address; its A column is zero
+      // the row's own string (its diagonal excitation is in the list, so a
+      // non-finite value there already makes the row NaN); its A column is
+      // zero.  Another row could carry a NaN or Inf into M through 0 * NaN.
+      eoff[e] = (uint32_t)ia * nq32;
       eW[e] = kPadEntry;
     }
   }

@@ -28,7 +28,10 @@
 // list kernel of the unblocked sigma; the opposite-spin part is the pair form
 // (k_sym_opp_pair: one alpha string per workgroup, the row of sigma and the
 // class blocks of integrals in LDS), or the gather form (k_sym_opp) where that
-// does not fit in LDS.
+// does not fit in LDS.  In FP64 the pair and MFMA forms scatter in 64-bit
+// fixed point as the unblocked sigma does (k_sym_rowmax gives each row's
+// scale), so the blocked FP64 sigma too is the same to the last bit from call
+// to call; the gather form sums each output in a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -208,6 +211,58 @@ __global__ __launch_bounds__(256) void k_sym_opp(
   }
 }
 
+// max |c| of every block row (irrep-sorted alpha index k, vector blockIdx.y):
+// the fixed-point scale of the FP64 opposite-spin scatter; NaN if the row
+// holds a NaN
+__global__ __launch_bounds__(256) void k_sym_rowmax(SymArgs g, const double *__restrict__ c,
+                                                    int64_t nsa, double *__restrict__ out) {
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
+  int a = 0;
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (g.startA[t] <= k) a = t;
+  const int64_t n = g.ncol[a];
+  const double *row = c + (int64_t)blockIdx.y * g.off[8] + g.off[a] + (k - g.startA[a]) * n;
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    const double v = fabs(row[j]);
+    m = (v > m || v != v) ? v : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double r = __shfl_xor(m, o);
+    m = (r > m || r != r) ? r : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < 4; ++w) r = (red[w] > r || red[w] != red[w]) ? red[w] : r;
+    out[(int64_t)blockIdx.y * nsa + k] = r;
+  }
+}
+
+// Largest (NaN-propagating) m over a 256-thread workgroup; every thread
+// calls it (it holds a barrier) and receives the result.
+__device__ inline double wg_max256(double m, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double r = __shfl_xor(m, o);
+    m = (r > m || r != r) ? r : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = 0.0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+  return m;
+}
+
+// Dynamic LDS of the blocked opposite-spin kernels: a CU's 160 KB less the
+// static slots of the fixed-point scale reduction.
+constexpr size_t kSymLdsCap = 160 * 1024 - 256;
+
 // Pair form of the opposite-spin part: one workgroup per alpha string Ia
 // (irrep-sorted index k, block a), the row of sigma accumulated in LDS.  For
 // each class x with alpha excitations e of Ia, the source block is a ^ x and
@@ -220,18 +275,24 @@ __global__ __launch_bounds__(256) void k_sym_opp(
 // with zeros to whole tiles of 8 pairs), so a tile's 8 values are contiguous.
 // LDS: acc[maxcol] (double) | srcoff, wro, ord, cls, cs[9], woff[9] | sg | so2
 //      | Ws[<= sA * maxp8] | plist[npair]   (maxp8: the largest class, padded to 8)
+// FIX (FP64): acc holds 64-bit fixed point; the row's scale comes from the
+// largest |c| over the source rows its excitations gather (rowmax) times
+// wbound, a bound on every partial sum of a row per unit of |c| (as in the
+// unblocked sigma; the blocked sums are a subset of its terms).
 struct PairStarts {
   int s[9];
 };
 
-template <typename T>
+template <typename T, bool FIXT>
 __global__ __launch_bounds__(256) void k_sym_opp_pair(
     SymArgs g, PairStarts pcs, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ posA, const Ent *__restrict__ tabA, int sA,
     const uint32_t *__restrict__ pairS, int64_t nsb, const int32_t *__restrict__ plist_g,
     const T *__restrict__ W, int npair, int64_t maxcol, int maxp8, const T *__restrict__ c,
-    T *__restrict__ out) {
+    T *__restrict__ out, const double *__restrict__ rowmax, double wbound) {
+  constexpr bool FIX = FIXT && std::is_same<T, double>::value;
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double wmax[4];
   double *acc = reinterpret_cast<double *>(smem);
   unsigned char *base = smem + (((size_t)maxcol * 8 + 15) & ~(size_t)15);
   int64_t *srcoff = reinterpret_cast<int64_t *>(base);
@@ -259,6 +320,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
   const int64_t Ia = idxA[k];
   const int64_t vo = (int64_t)blockIdx.y * g.off[8];
   for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) acc[j] = 0.0;
+  double rm = 0.0;
   for (int e = threadIdx.x; e < sA; e += blockDim.x) {
     const Ent t = tabA[Ia * sA + e];
     const int x = orbsym[t.p] ^ orbsym[t.q];
@@ -267,8 +329,15 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
     srcoff[e] = g.off[b] + (int64_t)posA[t.J] * g.ncol[b];
     wro[e] = pair_index(t.p, t.q) * npair;
     sg[e] = (T)t.sign;
+    if constexpr (FIX) {
+      const double v = rowmax[(int64_t)blockIdx.y * g.startA[8] + g.startA[b] + posA[t.J]];
+      rm = (v > rm || v != v) ? v : rm;
+    }
   }
   for (int p = threadIdx.x; p < npair; p += blockDim.x) plist[p] = plist_g[p];
+  double fscale = 1.0, finv = 1.0;
+  bool fbad = false;
+  if constexpr (FIX) fix_scale_from_bound(wbound * wg_max256(rm, wmax), fscale, finv, fbad);
   __syncthreads();
   if (threadIdx.x == 0) {
     int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -290,7 +359,8 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
     for (int y = threadIdx.x; y < nx; y += blockDim.x) {
       const int il = y / p8, pl = y - il * p8;
       const int e = ord[cs[x] + il];
-      Ws[woff[x] + y] = pl < np_ ? sg[e] * W[wro[e] + plist[pcs.s[x] + pl]] : (T)0;
+      // FIX: the power-of-two scale folded in (exact); M comes out in fixed-point units
+      Ws[woff[x] + y] = pl < np_ ? sg[e] * W[wro[e] + plist[pcs.s[x] + pl]] * (T)fscale : (T)0;
     }
   }
   __syncthreads();
@@ -326,7 +396,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
             const uint32_t cd = pairS[(int64_t)kl[t] * nsb + col0 + j];
             if (cd != kInvalid) {
               const double v = (double)m[t];
-              atomicAdd(&acc[cd >> 1], (cd & 1u) ? -v : v);
+              scatter_add<FIX>(&acc[cd >> 1], (cd & 1u) ? -v : v);
             }
           }
         }
@@ -335,7 +405,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
   }
   __syncthreads();
   T *__restrict__ row = out + vo + g.off[a] + r * nc;
-  for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) row[j] += (T)acc[j];
+  for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) row[j] += row_value<FIX, T>(acc, j, finv, fbad);
 }
 
 // MFMA form of the pair contraction above, the same sums: for each class x
@@ -354,12 +424,16 @@ __global__ __launch_bounds__(256) void k_sym_opp_pair(
 //      | plist[npair] | srcoff[sA] (uint32)
 constexpr int kSymMmaRows = 64;
 
-template <typename M, typename T>
+template <typename M, typename T, bool FIXT>
 __global__ __launch_bounds__(256) void k_sym_opp_mma(
     SymArgs g, PairStarts pcs, const int32_t *__restrict__ orbsym, const int32_t *__restrict__ idxA,
     const int32_t *__restrict__ posA, const Ent *__restrict__ tabA, int sA,
     const uint32_t *__restrict__ pairS, int64_t nsb, const int32_t *__restrict__ plist_g,
-    const T *__restrict__ W, int npair, int64_t maxcol, const T *__restrict__ c, T *__restrict__ out) {
+    const T *__restrict__ W, int npair, int64_t maxcol, const T *__restrict__ c, T *__restrict__ out,
+    const double *__restrict__ rowmax, double wbound) {
+  // FIX (FP64): fixed-point scatter, as in the pair form
+  constexpr bool FIX = FIXT && std::is_same<M, MF64>::value;
+  __shared__ double wmax[4];
   using A = typename M::A;
   using Frag = typename M::Frag;
   using Out = typename M::Out;
@@ -393,6 +467,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
   const int64_t vo = (int64_t)blockIdx.y * g.off[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, gq = lane >> 4;
   for (int64_t j = tid; j < nc; j += 64 * NW) acc[j] = 0.0;
+  double rm = 0.0;
   for (int e = tid; e < sA; e += 64 * NW) {
     const Ent t = tabA[Ia * sA + e];
     const int x = orbsym[t.p] ^ orbsym[t.q];
@@ -401,8 +476,15 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
     srcoff[e] = (uint32_t)(g.off[b] + (int64_t)posA[t.J] * g.ncol[b]);
     wro[e] = pair_index(t.p, t.q) * npair;
     sg[e] = (double)t.sign;
+    if constexpr (FIX) {
+      const double v = rowmax[(int64_t)blockIdx.y * g.startA[8] + g.startA[b] + posA[t.J]];
+      rm = (v > rm || v != v) ? v : rm;
+    }
   }
   for (int p = tid; p < npair; p += 64 * NW) plist[p] = plist_g[p];
+  double fscale = 1.0, finv = 1.0;
+  bool fbad = false;
+  if constexpr (FIX) fix_scale_from_bound(wbound * wg_max256(rm, wmax), fscale, finv, fbad);
   __syncthreads();
   if (tid == 0) {
     int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -432,7 +514,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
       double v = 0.0;
       if (row < np_ && kk < nx) {
         const int e = ord[i0 + kk];
-        v = sg[e] * (double)W[wro[e] + plist[p0 + row]];
+        v = sg[e] * (double)W[wro[e] + plist[p0 + row]] * fscale;  // FIX: exact power of two
       }
       At[row * lda + kk] = M::cvt(v);
     }
@@ -451,7 +533,10 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
 #pragma unroll
         for (int t = 0; t < M::KPL; ++t) {
           const int kk = s * M::KSTEP + gq * M::KPL + t;
-          off[t] = so2[i0 + (kk < nx ? kk : 0)];  // padded K: any row of the class (A is zero there)
+          // padded K: a source row of the class (A is zero there; the row is
+          // one this row gathers, so a non-finite value in it already makes
+          // the row NaN)
+          off[t] = so2[i0 + (kk < nx ? kk : 0)];
         }
         const Frag bf = M::load_b(cv, off, jc);
 #pragma unroll
@@ -469,7 +554,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
                 const uint32_t cd = pairS[(int64_t)plist[p0 + row] * nsb + col0 + col];
                 if (cd != kInvalid) {
                   const double v = (double)o[u][q];
-                  atomicAdd(&acc[cd >> 1], (cd & 1u) ? -v : v);
+                  scatter_add<FIX>(&acc[cd >> 1], (cd & 1u) ? -v : v);
                 }
               }
             }
@@ -480,7 +565,7 @@ __global__ __launch_bounds__(256) void k_sym_opp_mma(
     __syncthreads();  // the next class rebuilds the A tile
   }
   T *__restrict__ row = out + vo + g.off[a] + r * nc;
-  for (int64_t j = tid; j < nc; j += 64 * NW) row[j] += (T)acc[j];
+  for (int64_t j = tid; j < nc; j += 64 * NW) row[j] += row_value<FIX, T>(acc, j, finv, fbad);
 }
 
 size_t opp_mma_lds_bytes(int sA, int kstep, int pad, size_t asize, int npair, int64_t maxcol) {
@@ -519,7 +604,7 @@ size_t opp_lds_bytes(int sA, size_t tsize) {
 
 // The pair form (row of sigma and the integral rows in LDS) up to this size:
 // CAS(14,14) takes 53 KB in FP64, CAS(16,16) 93 KB.
-constexpr size_t kSymPairLdsMax = 160 * 1024;
+constexpr size_t kSymPairLdsMax = kSymLdsCap;
 
 SymArgs make_args(const SymInfo &S) {
   SymArgs g{};
@@ -724,19 +809,35 @@ void free_symmetry(sbci_ctx *ctx) {
 }
 
 namespace {
-template <typename M, typename T>
+template <typename M, typename T, bool FIX>
 int launch_sym_mma(sbci_ctx *ctx, const SymArgs &g, const PairStarts &pcs, const T *W, size_t lds,
-                   dim3 grid, const T *c, T *out) {
+                   dim3 grid, const T *c, T *out, const double *rowmax) {
   const SymInfo &S = *ctx->sym;
   static bool attr = false;
   if (!attr) {
-    SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_mma<M, T>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_mma<M, T, FIX>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSymLdsCap));
     attr = true;
   }
-  k_sym_opp_mma<M, T><<<grid, 256, lds, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, ctx->A.tab,
-                                                       ctx->A.s, S.pairS, ctx->B.ns, S.plist, W,
-                                                       ctx->npair, S.maxcol, c, out);
+  k_sym_opp_mma<M, T, FIX><<<grid, 256, lds, ctx->stream>>>(
+      g, pcs, S.orbsym_d, S.idxA, S.posA, ctx->A.tab, ctx->A.s, S.pairS, ctx->B.ns, S.plist, W,
+      ctx->npair, S.maxcol, c, out, rowmax, ctx->opp_wbound);
+  return SBCI_OK;
+}
+
+template <typename T, bool FIX>
+int launch_sym_pair(sbci_ctx *ctx, const SymArgs &g, const PairStarts &pcs, const T *W, size_t lds,
+                    dim3 grid, int maxp8, const T *c, T *out, const double *rowmax) {
+  const SymInfo &S = *ctx->sym;
+  static bool attr = false;
+  if (!attr) {
+    SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_pair<T, FIX>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSymLdsCap));
+    attr = true;
+  }
+  k_sym_opp_pair<T, FIX><<<grid, 256, lds, ctx->stream>>>(
+      g, pcs, S.orbsym_d, S.idxA, S.posA, ctx->A.tab, ctx->A.s, S.pairS, ctx->B.ns, S.plist, W,
+      ctx->npair, S.maxcol, maxp8, c, out, rowmax, ctx->opp_wbound);
   return SBCI_OK;
 }
 
@@ -791,7 +892,7 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, boo
     const int pad = bf16 ? MBF16::PAD : dbl ? MF64::PAD : MF32::PAD;
     const size_t asz = bf16 ? 2 : sizeof(T);
     const size_t lm = opp_mma_lds_bytes(A.s, kstep, pad, asz, ctx->npair, S.maxcol);
-    const bool mma_ok = maxp <= kSymMmaRows && nd < ((int64_t)1 << 32) && lm <= 160 * 1024;
+    const bool mma_ok = maxp <= kSymMmaRows && nd < ((int64_t)1 << 32) && lm <= kSymLdsCap;
     if (bf16 && !mma_ok)
       return set_error(SBCI_EINVAL, "blocked sigma: the BF16 form needs at most 64 pairs per class");
     if (bf16 && ctx->opp_form == SBCI_OPP_PAIR)
@@ -800,25 +901,30 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, boo
       return set_error(SBCI_EINVAL, "blocked sigma: the orbital form is not offered");
     if (ctx->opp_form == SBCI_OPP_CLASS_MFMA && !mma_ok)
       return set_error(SBCI_EINVAL, "blocked sigma: the MFMA form needs at most 64 pairs per class");
-    if (bf16 || ctx->opp_form == SBCI_OPP_CLASS_MFMA) {
+    const bool use_mma = bf16 || ctx->opp_form == SBCI_OPP_CLASS_MFMA;
+    // FP64 in the pair and MFMA forms: each row's fixed-point scale needs
+    // the largest |c| of every block row
+    const bool fix = dbl && ctx->deterministic && (use_mma || lp <= kSymPairLdsMax);
+    double *rmax = nullptr;
+    if (fix) {
+      SBCI_TRY(ensure(ctx->ws_rmax, sizeof(double) * (size_t)A.ns * nvec));
+      rmax = static_cast<double *>(ctx->ws_rmax.ptr);
+      k_sym_rowmax<<<grid, 256, 0, ctx->stream>>>(g, reinterpret_cast<const double *>(c), A.ns, rmax);
+      SBCI_CHECK_LAUNCH();
+    }
+    if (use_mma) {
       if constexpr (dbl) {
-        SBCI_TRY((launch_sym_mma<MF64, double>(ctx, g, pcs, ctx->W64, lm, grid, c, out)));
+        if (fix) SBCI_TRY((launch_sym_mma<MF64, double, true>(ctx, g, pcs, ctx->W64, lm, grid, c, out, rmax)));
+        else SBCI_TRY((launch_sym_mma<MF64, double, false>(ctx, g, pcs, ctx->W64, lm, grid, c, out, rmax)));
       } else {
         if (bf16)
-          SBCI_TRY((launch_sym_mma<MBF16, float>(ctx, g, pcs, ctx->W32, lm, grid, c, out)));
+          SBCI_TRY((launch_sym_mma<MBF16, float, false>(ctx, g, pcs, ctx->W32, lm, grid, c, out, rmax)));
         else
-          SBCI_TRY((launch_sym_mma<MF32, float>(ctx, g, pcs, ctx->W32, lm, grid, c, out)));
+          SBCI_TRY((launch_sym_mma<MF32, float, false>(ctx, g, pcs, ctx->W32, lm, grid, c, out, rmax)));
       }
     } else if (lp <= kSymPairLdsMax) {
-      static bool attrp = false;
-      if (!attrp) {
-        SBCI_HIP(hipFuncSetAttribute((const void *)k_sym_opp_pair<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attrp = true;
-      }
-      k_sym_opp_pair<T><<<grid, 256, lp, ctx->stream>>>(g, pcs, S.orbsym_d, S.idxA, S.posA, A.tab, A.s,
-                                                        S.pairS, B.ns, S.plist, W, ctx->npair,
-                                                        S.maxcol, maxp8, c, out);
+      if (fix) SBCI_TRY((launch_sym_pair<T, true>(ctx, g, pcs, W, lp, grid, maxp8, c, out, rmax)));
+      else SBCI_TRY((launch_sym_pair<T, false>(ctx, g, pcs, W, lp, grid, maxp8, c, out, rmax)));
     } else {
       const size_t lds = opp_lds_bytes(A.s, sizeof(T));
       if (lds > 64 * 1024) return set_error(SBCI_EINVAL, "blocked sigma: too many alpha excitations");

@@ -155,3 +155,26 @@ def test_sigma_f64_bitwise_reproducible(n, na, nb, form):
     r = ctx.sigma(c).cpu().numpy()
     assert np.abs(r - want).max() <= 1e-12 * np.abs(want).max()
     ctx.close()
+
+
+@pytest.mark.parametrize("det", [True, False])
+@pytest.mark.parametrize("form", ["pair", "orbital"])
+def test_sigma_f64_carries_a_nan(det, form):
+    """A NaN in c reaches sigma (the solvers stop on non-finite reductions):
+    the NaN's own entry is NaN, and every entry that stays finite equals the
+    oracle's.  The fixed-point scatter turns every row that gathers the NaN's
+    row into NaN (its scale is not finite); the FP64 atomics only the entries
+    it reaches."""
+    n, na, nb = 9, 4, 3
+    ctx, I = _ctx(n, na, nb, seed=3)
+    ctx.set_deterministic(det)
+    ctx.set_opp_form(form)
+    c = sigma_inputs(2, 1, ctx.ndet)
+    c[0, 40] = np.nan
+    want = OS.sigma(n, na, nb, I.h1, I.eri, c)
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    assert np.isnan(got[0, 40])
+    both = np.isfinite(got) & np.isfinite(want)
+    assert both.sum() > 0
+    assert np.abs(got[both] - want[both]).max() <= 1e-12 * np.abs(want[both]).max()
+    ctx.close()

@@ -120,6 +120,53 @@ def test_bad_forms_and_arguments_are_refused():
     U.close()
 
 
+@pytest.mark.parametrize("form", ["auto", "class_mfma"])
+@pytest.mark.parametrize("n,na,nb,g", [(8, 4, 4, 0), (9, 4, 5, 3), (7, 3, 2, 1), (12, 2, 3, 6)])
+def test_blocked_sigma_f64_bitwise_reproducible(n, na, nb, g, form):
+    """The blocked FP64 sigma is the same to the last bit from call to call:
+    its opposite-spin scatter (pair and MFMA forms) accumulates in 64-bit
+    fixed point, the other parts sum in a fixed order.  Calls of another size
+    in between change how the waves interleave; the FP64-atomic scatter
+    (reproducibility off) meets the same parity bar."""
+    ctx, I, o = _ctx(n, na, nb, g, seed=g)
+    ctx.set_opp_form(form)
+    c = torch.from_numpy(sigma_inputs(g, 2, ctx.ndet)).cuda()
+    want = SY.sigma(n, na, nb, I.h1, I.eri, o, g, c.cpu().numpy())
+    scale = np.abs(want).max()
+    ref = ctx.sigma(c).clone()
+    assert np.abs(ref.cpu().numpy() - want).max() <= 1e-12 * scale
+    for _ in range(4):
+        ctx.sigma(c[:1].contiguous())
+        got = ctx.sigma(c)
+        assert torch.equal(got.view(torch.int64), ref.view(torch.int64))
+    ctx.set_deterministic(False)
+    r = ctx.sigma(c).cpu().numpy()
+    assert np.abs(r - want).max() <= 1e-12 * scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("det", [True, False])
+@pytest.mark.parametrize("form", ["auto", "class_mfma"])
+def test_blocked_sigma_f64_carries_a_nan(det, form):
+    """A NaN in c reaches sigma (the solvers stop on non-finite reductions):
+    the NaN's own entry is NaN, and every entry that stays finite equals the
+    oracle's.  The fixed-point scatter turns every row that gathers the NaN's
+    row into NaN; the FP64 atomics only the entries it reaches."""
+    n, na, nb, g = 8, 4, 4, 0
+    ctx, I, o = _ctx(n, na, nb, g, seed=1)
+    ctx.set_deterministic(det)
+    ctx.set_opp_form(form)
+    c = sigma_inputs(1, 1, ctx.ndet)
+    c[0, 11] = np.nan
+    want = SY.sigma(n, na, nb, I.h1, I.eri, o, g, c)
+    got = ctx.sigma(torch.from_numpy(c).cuda()).cpu().numpy()
+    assert np.isnan(got[0, 11])
+    both = np.isfinite(got) & np.isfinite(want)
+    assert both.sum() > 0
+    assert np.abs(got[both] - want[both]).max() <= 1e-12 * np.abs(want[both]).max()
+    ctx.close()
+
+
 def test_class_of_more_than_64_pairs_uses_the_vector_form():
     """Labels that put 12 of 13 orbitals in irrep 0 make pair class 0 hold 79
     pairs (more than an MFMA class tile takes): FP64 still runs (the vector
