@@ -514,9 +514,9 @@ __device__ void wg_sigma(const BInst &I, const BParams &P, const T *__restrict__
         const int e = ks * M::KSTEP + g * M::KPL + t;
         const Ent en = te[e < sa ? e : sa - 1];
         const bool ok = e < sa;
-        // padded K: the row's own string (in its list as the diagonal
-        // excitation), so that 0 * (a non-finite value) reaches no other row
-        boff[ks][t] = (uint32_t)(ok ? en.J : ia) * (uint32_t)nsb;
+        // padded K: the last entry's row (one this row gathers), so that
+        // 0 * (a non-finite value) reaches no row that does not gather it
+        boff[ks][t] = (uint32_t)en.J * (uint32_t)nsb;
         const int pk = pair_index(en.p, en.q);
         const double sg = !ok ? 0.0 : en.sign < 0 ? -1.0 : 1.0;
 #pragma unroll

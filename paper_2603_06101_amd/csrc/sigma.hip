@@ -412,7 +412,9 @@ constexpr int32_t kPadEntry = -1;  // K padding: zero column of A
 //   acc  sigma's row Ia; the 64 extra slots absorb the lanes whose pair
 //        code is invalid, so the scatter needs no branch
 //   Ws   A tile of one K chunk: sign_e (kl|kl_e), zero for padded rows / K
-//   eoff row offset J_e * nsb of the C row feeding K element e
+//   eoff row offset J_e * nsb of the C row feeding K element e; padded K
+//        elements point at row Ia itself (in its own list as the diagonal
+//        excitation, so a non-finite value there makes the row NaN anyway)
 // Each wave owns 16-column tiles J0 = 16 (wave + NW i).  It gathers the B
 // fragment C[J_e][J0 + li] straight from global memory into registers (the
 // next tile's fragment is fetched before the current tile's MFMAs), runs all
@@ -463,9 +465,7 @@ __global__ __launch_bounds__(64 * NW) void k_opp(
       int kl = pair_index(t.p, t.q);
       eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
     } else {
-      // the row's own string (its diagonal excitation is in the list, so a
-      // non-finite value there already makes the row NaN); its A column is zero
-      eoff[e] = (uint32_t)ia * (uint32_t)ldc;
+      eoff[e] = (uint32_t)ia * (uint32_t)ldc;  // any valid row: its A column is zero
       eW[e] = kPadEntry;
     }
   }
@@ -799,10 +799,13 @@ __global__ __launch_bounds__(64 * NW) void k_opp_q(
       int kl = pair_index(t.p, t.q);
       eW[e] = t.sign < 0 ? (kl | (int32_t)0x80000000) : kl;
     } else {
-      // the row's own string (its diagonal excitation is in the list, so a
-      // non-finite value there already makes the row NaN); its A column is
-      // zero.  Another row could carry a NaN or Inf into M through 0 * NaN.
-      eoff[e] = (uint32_t)ia * nq32;
+      // the row of the first entry of this K chunk (a row this row gathers,
+      // in the same loads: a non-finite value there already makes the row
+      // NaN); its A column is zero.  A row outside the list could carry a
+      // NaN or Inf into M through 0 * NaN.  Every chunk starts with a real
+      // entry, since the chunks cover s entries with less than one chunk of
+      // padding.
+      eoff[e] = (uint32_t)taba[ia * s + (e / KW) * KW].J * nq32;
       eW[e] = kPadEntry;
     }
   }
