@@ -42,6 +42,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <utility>
+#include <vector>
 
 struct sbci_batch;
 
@@ -1698,6 +1700,10 @@ int prepare(sbci_batch *b, const int *nroots, int precision) {
 }
 
 constexpr double kTeamMargin = 1.25;
+// The teams take at most slots - slots / kQueueReserve of the resident
+// workgroup slots; the rest start on the queue at once (the team members
+// join it after their instance).
+constexpr int kQueueReserve = 16;
 
 // Estimated work of an instance: N_det x (F lists + opposite-spin pair rows) x roots.
 double inst_work(const BInst &I) {
@@ -1708,8 +1714,9 @@ double inst_work(const BInst &I) {
 // Balanced share M = max(total work / workgroup slots, largest work /
 // max_team); an instance of work w gets T = ceil(w / M) workgroups (at most
 // max_team), largest first, while the team workgroups fit in the slots that
-// are resident at once.  The other instances form the queue, largest first
-// (order 0) or in input order (order 1).
+// are resident at once; slots the rounding leaves unused go to the teams
+// with the most work per member.  The other instances form the queue,
+// largest first (order 0) or in input order (order 1).
 int plan_launch(sbci_batch *b, const sbci_batch_config &cfg, int resident, Plan &pl) {
   const int n = b->ninst;
   const int slots = std::max(1, std::min(b->ncu * cfg.wg_per_cu, resident));
@@ -1730,14 +1737,14 @@ int plan_launch(sbci_batch *b, const sbci_batch_config &cfg, int resident, Plan 
   if (maxT > 1 && n > 1) {
     // T_i = ceil(kTeamMargin w_i / M), at most max_team and the instance's
     // alpha tiles (a member needs one); M grows from the balanced share until
-    // the teams leave an eighth of the slots to the queue.  The margin covers
-    // the spread of step counts that the work estimate does not see.
+    // the teams leave 1/kQueueReserve of the slots to the queue.  The margin
+    // covers the spread of step counts that the work estimate does not see.
     auto team_size = [&](int i, double M) {
       int T = (int)std::ceil(kTeamMargin * w[i] / M - 1e-9);
       T = std::min(T, maxT);
       return std::min(T, (b->h_inst[i].ns_a + 15) / 16);
     };
-    const int budget = slots - slots / 8;
+    const int budget = slots - slots / kQueueReserve;
     double M = std::max(total / slots, wmax / maxT);
     for (int it = 0; it < 200; ++it, M *= 1.05) {
       int used = 0;
@@ -1748,11 +1755,37 @@ int plan_launch(sbci_batch *b, const sbci_batch_config &cfg, int resident, Plan 
       }
       if (used <= budget) break;
     }
+    std::vector<std::pair<int, int>> teams;  // (instance, members)
+    int used = 0;
     for (int i : by_work) {
       const int T = team_size(i, M);
-      if (T < 2 || (int)blk.size() + T > budget) break;
-      for (int m = 0; m < T; ++m) blk.push_back(make_int4(i, T, m, pl.nteam));
-      in_team[i] = 1;
+      if (T < 2 || used + T > budget) break;
+      teams.push_back({i, T});
+      used += T;
+    }
+    // The rounding of T leaves slots of the budget unused: give them one at
+    // a time to the team with the most work per member.  On a tie the smaller
+    // team gains (a 2-root team of 2 ties with a 3-root team of 3, and a
+    // member added to the smaller team shortens it more).
+    while (used < budget) {
+      int best = -1;
+      double bw = 0;
+      for (int k = 0; k < (int)teams.size(); ++k) {
+        const int i = teams[k].first, T = teams[k].second;
+        if (T >= maxT || T >= (b->h_inst[i].ns_a + 15) / 16) continue;
+        const double v = w[i] / T;
+        if (best < 0 || v > bw * (1 + 1e-9) || (v > bw * (1 - 1e-9) && T < teams[best].second)) {
+          bw = v;
+          best = k;
+        }
+      }
+      if (best < 0) break;
+      teams[best].second += 1;
+      used += 1;
+    }
+    for (const auto &t : teams) {
+      for (int m = 0; m < t.second; ++m) blk.push_back(make_int4(t.first, t.second, m, pl.nteam));
+      in_team[t.first] = 1;
       pl.nteam += 1;
     }
   }
