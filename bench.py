@@ -546,8 +546,8 @@ def batch_section(sb, precision):
             "steps": r.report["nsteps"],
             "tuned": best,
             "tuned_vs_default": round(rd.report["seconds"] / r.report["seconds"], 3),
-            "candidates_ms": [[c["threads"], c["wg_per_cu"], c["order"], c["k_panel"], round(ms, 1)]
-                              for c, ms in cands],
+            "candidates_ms": [[c["threads"], c["wg_per_cu"], c["order"], c["k_panel"], c["queue_reserve"],
+                               round(ms, 1)] for c, ms in cands],
             "critical_instance": {"id": crit, "norb": inst[crit][0], "nroots": inst[crit][2],
                                   "span_s": round(float(spans[crit]), 4),
                                   "steps": r.instances[crit]["nsteps"]},

@@ -376,6 +376,9 @@ typedef struct sbci_batch_config {
   int team_wait_us; /* bound of a team barrier wait in microseconds; 0 = 1 s.
                        A team whose wait exceeds it ends its instance with
                        SBCI_EDEVICE                                             */
+  int queue_reserve; /* teams take at most slots - slots / queue_reserve of the
+                        resident workgroup slots, the rest start on the queue:
+                        2..64; 0 = 16                                           */
 } sbci_batch_config;
 
 typedef struct sbci_batch_report {
@@ -393,6 +396,7 @@ typedef struct sbci_batch_report {
   int team_timeouts;         /* team instances ended by the wait bound
                                 (status SBCI_EDEVICE; the call then returns
                                 SBCI_EDEVICE with every output written)         */
+  int queue_reserve;         /* the shape used (continued)                      */
 } sbci_batch_report;
 
 /* Per-instance outcome of a batch solve (times from the device real-time

@@ -85,7 +85,7 @@ _P, _D, _I, _I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int6
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I),
-                ("team_wait_us", _I)]
+                ("team_wait_us", _I), ("queue_reserve", _I)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -105,6 +105,7 @@ class BatchReport(ctypes.Structure):
         ("nsteps", _I64), ("nrestarts", _I64), ("ninst_converged", _I),
         ("threads", _I), ("wg_per_cu", _I), ("order", _I), ("k_panel", _I), ("max_team", _I),
         ("team_wait_us", _I), ("nteams", _I), ("team_workgroups", _I), ("team_timeouts", _I),
+        ("queue_reserve", _I),
     ]
 
     def as_dict(self):

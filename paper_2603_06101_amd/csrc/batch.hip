@@ -1596,6 +1596,8 @@ int check_config(const sbci_batch_config &c) {
   if (c.max_team < 0 || c.max_team > BMAX_TEAM)
     return batch_error(SBCI_EINVAL, "batch config: max_team must be in 0..4");
   if (c.team_wait_us < 0) return batch_error(SBCI_EINVAL, "batch config: team_wait_us must be >= 0");
+  if (c.queue_reserve != 0 && (c.queue_reserve < 2 || c.queue_reserve > 64))
+    return batch_error(SBCI_EINVAL, "batch config: queue_reserve must be 0 or in 2..64");
   return SBCI_OK;
 }
 
@@ -1700,9 +1702,13 @@ int prepare(sbci_batch *b, const int *nroots, int precision) {
 }
 
 constexpr double kTeamMargin = 1.25;
-// The teams take at most slots - slots / kQueueReserve of the resident
-// workgroup slots; the rest start on the queue at once (the team members
-// join it after their instance).
+// The teams take at most slots - slots / queue_reserve of the resident
+// workgroup slots (16 by default); the rest start on the queue at once (the
+// team members join it after their instance).  Fewer reserved slots let
+// the teams grow; more let the queue of small instances finish sooner.
+// Which bounds the makespan depends on the form (measured on the
+// 512-instance workload: FP64 gains from 16, the FP32 ladder from 8), so
+// the autotuner tries both.
 constexpr int kQueueReserve = 16;
 
 // Estimated work of an instance: N_det x (F lists + opposite-spin pair rows) x roots.
@@ -1744,7 +1750,7 @@ int plan_launch(sbci_batch *b, const sbci_batch_config &cfg, int resident, Plan 
       T = std::min(T, maxT);
       return std::min(T, (b->h_inst[i].ns_a + 15) / 16);
     };
-    const int budget = slots - slots / kQueueReserve;
+    const int budget = slots - slots / (cfg.queue_reserve == 0 ? kQueueReserve : cfg.queue_reserve);
     double M = std::max(total / slots, wmax / maxT);
     for (int it = 0; it < 200; ++it, M *= 1.05) {
       int used = 0;
@@ -1864,6 +1870,7 @@ sbci_batch_config default_config() {
   c.k_panel = 16;
   c.max_team = 0;
   c.team_wait_us = 0;
+  c.queue_reserve = 0;
   return c;
 }
 
@@ -2018,6 +2025,7 @@ int sbci_batch_solve(sbci_batch *b, const int *nroots, double tol, const sbci_op
   r.k_panel = cfg.k_panel;
   r.max_team = cfg.max_team;
   r.team_wait_us = cfg.team_wait_us;
+  r.queue_reserve = cfg.queue_reserve;
   r.nteams = pl.nteam;
   r.team_workgroups = pl.ntw;
   if (rep) *rep = r;
@@ -2037,7 +2045,7 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
   SBCI_TRY(params_from(opt, tol, P, precision));
   SBCI_TRY(prepare(b, nroots, precision));
   // stage 1: workgroup size x residency (longest-first, tall tiles);
-  // stage 2: queue order and tile height around the winner.
+  // stage 2: queue order, tile height and queue reserve around the winner.
   std::vector<sbci_batch_config> tried;
   std::vector<double> times;
   auto trial = [&](const sbci_batch_config &c) -> int {
@@ -2065,6 +2073,9 @@ int sbci_batch_tune(sbci_batch *b, const int *nroots, double tol, const sbci_opt
     SBCI_TRY(trial(c));
     c = w;
     c.k_panel = 8;
+    SBCI_TRY(trial(c));
+    c = w;
+    c.queue_reserve = 8;
     SBCI_TRY(trial(c));
   }
   bi = std::min_element(times.begin(), times.end()) - times.begin();

@@ -162,6 +162,8 @@ def test_autotuner_picks_a_measured_candidate(small_batch):
     nroots = [t[3] for t in SMALL]
     best, cands = small_batch.tune(nroots, tol=1e-10)
     assert len(cands) >= 6
+    # the queue reserve is one of the tuned dimensions
+    assert {c["queue_reserve"] for c, _ in cands} == {0, 8}
     times = [ms for _, ms in cands]
     assert all(t > 0 for t in times)
     assert best == cands[int(np.argmin(times))][0]
@@ -182,6 +184,9 @@ def test_batch_rejects_bad_arguments():
         b.solve([5])                                  # more roots than supported
     with pytest.raises(sb.SbciError):
         b.solve([1], config=dict(threads=128, wg_per_cu=1, order=0, k_panel=16))
+    for qr in (1, 65, -2):
+        with pytest.raises(sb.SbciError, match="queue_reserve"):
+            b.solve([1], config=dict(threads=512, wg_per_cu=1, order=0, k_panel=16, queue_reserve=qr))
     with pytest.raises(sb.SbciError):
         b.solve([1], opts=dict(precision=9))
     b.close()
