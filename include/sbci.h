@@ -310,6 +310,18 @@ int sbci_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt);
 int sbci_step(sbci_ctx *ctx, sbci_step_info *info, int *done);
 int sbci_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report *rep);
 
+/* Checkpoint of a step-level solve: the current iterate x of the root being
+ * solved (root index = roots converged so far), unnormalised, as FP64 into
+ * dev_x (device [N_det]); from the running precision's copy in a
+ * low-precision phase.  At a step boundary the solver's state is x (X = H x
+ * is recomputed, Eq. S32) and the converged pairs {x_c, E_c}
+ * (sbci_finish mid-solve writes those and returns SBCI_ENOCONV; stepping
+ * can go on after it).  A new solve with opts x0 = x and nconv0 / xc0 / ec0
+ * = the pairs continues from that point.  Synchronous.  SBCI_EINVAL if no
+ * SBCI1 solve was begun on ctx (sbci_begin or sbci_solve), after
+ * sbci_solve2 or sbci_davidson, or once every root has converged. */
+int sbci_iterate(sbci_ctx *ctx, double *dev_x);
+
 /* Per-step trace of the last solve (tracing on by default): copies up to
  * max records into out (host) and returns the number copied (>= 0). */
 int sbci_set_trace(sbci_ctx *ctx, int on);

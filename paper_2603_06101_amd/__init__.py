@@ -139,6 +139,7 @@ SIGNATURES = [
     ("sbci_begin", _I, [_P, _I, _D, ctypes.POINTER(Opts)]),
     ("sbci_step", _I, [_P, ctypes.POINTER(StepInfo), ctypes.POINTER(_I)]),
     ("sbci_finish", _I, [_P, _P, _P, ctypes.POINTER(Report)]),
+    ("sbci_iterate", _I, [_P, _P]),
     ("sbci_set_trace", _I, [_P, _I]),
     ("sbci_trace", _I, [_P, ctypes.POINTER(StepInfo), _I]),
     ("sbci_davidson", _I, [_P, _I, _D, ctypes.POINTER(Opts), _P, _P, ctypes.POINTER(Report)]),
@@ -410,6 +411,13 @@ class Context:
                                ctypes.byref(rep))
         _check(rc, allow=(SBCI_ENOCONV,))
         return SolveResult(e, vec, _report_dict(rep, self._nroots), self.trace(), rc)
+
+    def iterate(self):
+        """Current iterate x of the root being solved (FP64, unnormalised) on cuda."""
+        torch = _torch()
+        x = torch.empty(self.ndet, dtype=torch.float64, device="cuda")
+        _check(lib().sbci_iterate(self.h, ctypes.c_void_p(x.data_ptr())))
+        return x
 
     def trace(self):
         n = lib().sbci_trace(self.h, None, 0)

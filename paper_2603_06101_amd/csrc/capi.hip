@@ -8,6 +8,7 @@
 namespace sbci {
 
 int solver_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt);
+int solver_iterate(sbci_ctx *ctx, double *dev_x);
 int solver_step(sbci_ctx *ctx, sbci_step_info *info, int *done);
 int solver_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report *rep);
 void solver_free(sbci_ctx *ctx);
@@ -332,6 +333,11 @@ int sbci_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report *
   return solver_finish(ctx, energies, dev_vecs, rep);
 }
 
+int sbci_iterate(sbci_ctx *ctx, double *dev_x) {
+  if (!ctx || !dev_x) return set_error(SBCI_EINVAL, "NULL argument");
+  return solver_iterate(ctx, dev_x);
+}
+
 int sbci_solve(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
                double *dev_vecs, sbci_report *rep) {
   if (!ctx || !energies) return set_error(SBCI_EINVAL, "NULL argument");
@@ -365,6 +371,7 @@ int sbci_trace(sbci_ctx *ctx, sbci_step_info *out, int max) {
 int sbci_davidson(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt, double *energies,
                   double *dev_vecs, sbci_report *rep) {
   if (!ctx || !energies) return set_error(SBCI_EINVAL, "NULL argument");
+  solver_free(ctx);  // an earlier step-level solve ends here (its state is not Davidson's)
   return davidson(ctx, nroots, tol, opt, energies, dev_vecs, rep);
 }
 

@@ -76,6 +76,7 @@ struct Solver {
   double last_dz = 0;     // |z'| of the latest step (the residual of a converged root)
   bool done = false;
   bool any_noconv = false;
+  bool stepwise = false;  // begun by solver_begin (SBCI1, one step per call)
   // report
   sbci_report rep{};
   double t0 = 0;
@@ -898,6 +899,7 @@ int solver_begin(sbci_ctx *ctx, int nroots, double tol, const sbci_opts *opt) {
       S->alloc_bytes += sizeof(float) * S->n;
     }
   }
+  S->stepwise = true;
   SBCI_TRY(resume_roots(ctx, *S));
   SBCI_TRY(initial_vector(ctx, *S));
   if (S->o.precision != SBCI_F64) {
@@ -938,6 +940,21 @@ int solver_finish(sbci_ctx *ctx, double *energies, double *dev_vecs, sbci_report
   if (rep) *rep = S->rep;
   if (!S->done) return set_error(SBCI_ENOCONV, "not all roots converged");
   if (S->any_noconv) return set_error(SBCI_ENOCONV, "a root reached max_steps");
+  return SBCI_OK;
+}
+
+// The current iterate x of the root being solved, in FP64.  Between steps
+// it is held unnormalised (the pending scale is positive), so its direction
+// is exact; with {x_c, E_c} it is the whole state at a step boundary.
+int solver_iterate(sbci_ctx *ctx, double *dev_x) {
+  Solver *S = ctx->solver;
+  if (!S || !S->stepwise) return set_error(SBCI_EINVAL, "sbci_iterate needs an SBCI1 solve begun by sbci_begin or sbci_solve");
+  if (S->done) return set_error(SBCI_EINVAL, "sbci_iterate: every root has converged");
+  if (S->phase == SBCI_F64)
+    SBCI_TRY((convert<double, double>(ctx, S->n, dev_x, S->v64[X_], 1.0)));
+  else
+    SBCI_TRY((convert<double, float>(ctx, S->n, dev_x, S->v32[X_], 1.0)));
+  SBCI_HIP(hipStreamSynchronize(ctx->stream));
   return SBCI_OK;
 }
 

@@ -63,8 +63,11 @@ static void run_ctx(sbci_ctx *ctx, int nroots) {
   CHECK(sbci_begin(ctx, nroots, 1e-10, &o));
   int done = 0, guard = 0;
   sbci_step_info info;
+  for (int k = 0; k < 2 && !done; ++k) CHECK(sbci_step(ctx, &info, &done));
+  if (!done) CHECK(sbci_iterate(ctx, c));   // checkpoint of the running root
   while (!done && guard++ < 5000) CHECK(sbci_step(ctx, &info, &done));
   CHECK(sbci_finish(ctx, e.data(), vec, &rep));
+  if (sbci_iterate(ctx, c) == 0) { std::printf("FAIL iterate after the last root\n"); std::exit(1); }
   if (nroots >= 2) {
     // resume after nroots - 1 converged roots, with and without their energies,
     // in FP64 and FP32 (host Gram-Schmidt and the root pools)

@@ -147,3 +147,62 @@ def test_bad_resumes_are_refused():
     r = ctx.solve(2, tol=1e-10, xc=v)
     assert r.status == 0 and r.report["nroots_converged"] == 2
     ctx.close()
+
+
+def test_checkpoint_between_steps_and_continue():
+    """A 3-root solve stopped a few steps into root 1: the converged pair
+    (sbci_finish mid-solve, SBCI_ENOCONV) and the iterate (sbci_iterate) are
+    the whole state, and a new context resumed from them reaches the roots of
+    the uninterrupted solve.  The stopped solve itself also steps on after
+    its finish call to the same roots."""
+    import paper_2603_06101_amd as sb
+    n, na, nb = 7, 4, 3
+    ctx, I = _ctx(n, na, nb, 14, 0)
+    w = np.linalg.eigvalsh(H.dense_h_slater_condon(n, na, nb, I.h1, I.eri))
+    full = ctx.solve(3, tol=1e-10)
+    assert full.status == 0
+    with pytest.raises(sb.SbciError, match="converged"):
+        ctx.iterate()                      # every root of that solve converged
+    ctx.begin(3, tol=1e-10)
+    done = False
+    while not done:
+        info, done = ctx.step()
+        if info["root"] == 1 and info["t"] >= 2:
+            break
+    assert not done
+    part = ctx.finish()
+    assert part.status == sb.SBCI_ENOCONV and part.report["nroots_converged"] == 1
+    xc = part.vectors[:1].cpu().numpy()
+    ec = np.array(part.energies[:1])
+    x = ctx.iterate().cpu().numpy()
+    assert np.isfinite(x).all() and np.linalg.norm(x) > 0
+    ctx2, _ = _ctx(n, na, nb, 14, 0)
+    r = ctx2.solve(3, tol=1e-10, x0=x, xc=xc, ec=ec)
+    assert r.status == 0
+    assert np.abs(np.asarray(r.energies) - np.asarray(full.energies)).max() < 1e-8
+    assert np.abs(np.asarray(r.energies) - w[:3]).max() < 1e-8
+    _eigenpairs(n, na, nb, I, r.energies, r.vectors.cpu().numpy())
+    ctx2.close()
+    while not done:
+        _, done = ctx.step()
+    rest = ctx.finish()
+    assert rest.status == 0
+    assert np.abs(np.asarray(rest.energies) - np.asarray(full.energies)).max() < 1e-8
+    ctx.close()
+
+
+def test_iterate_is_refused_without_a_step_level_solve():
+    import paper_2603_06101_amd as sb
+    ctx, _ = _ctx(6, 3, 2, 12, 0)
+    with pytest.raises(sb.SbciError):
+        ctx.iterate()                      # nothing begun
+    ctx.begin(2, tol=1e-10)
+    ctx.step()
+    assert np.isfinite(ctx.iterate().cpu().numpy()).all()
+    ctx.davidson(2, tol=1e-10)             # ends the step-level solve
+    with pytest.raises(sb.SbciError):
+        ctx.iterate()
+    ctx.solve2(2, tol=1e-10)
+    with pytest.raises(sb.SbciError):
+        ctx.iterate()
+    ctx.close()
