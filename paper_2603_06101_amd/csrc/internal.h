@@ -93,8 +93,9 @@ struct SpinTables {
 constexpr int64_t kSameLdsMinRows = 1024;
 constexpr int64_t kSameLdsMaxRows = 3840;
 // LDS-blocked same-spin kernel above that range: source rows pass through
-// LDS in blocks of kSameBlkRows rows x 64 bytes (8 FP64 or 16 FP32 columns,
-// 128 KB); up to kSameBlkMaxBlocks blocks (block-local columns fit 16 bits).
+// LDS in blocks of kSameBlkRows rows x 64 bytes (8 FP64 or 16 FP32 columns;
+// rows padded to 80 bytes, 160 KB); up to kSameBlkMaxBlocks blocks
+// (block-local columns fit 16 bits).
 constexpr int kSameBlkRows = 2048;
 constexpr int kSameBlkMaxBlocks = 64;
 // Dense same-spin form: chosen automatically above the LDS range when the

@@ -1242,8 +1242,12 @@ int launch_same_lds(sbci_ctx *ctx, const SpinTables &S, const V *fvalT, int64_t 
 // blocks.  For each block the workgroup stages the block's stripe, then each
 // wave walks its groups' block-binned lists: one 2-byte block-local column
 // and one value per lane per slot, coalesced, and four 16-byte LDS reads.
-// The 16-byte chunks of row j sit at chunk ^ ((j >> 2) & 3), so the reads of
-// 16 random rows spread over all LDS banks.  Work items are numbered
+// Rows sit 80 bytes apart (four 16-byte chunks and one of padding), so the
+// chunks that 16 lanes read from random rows spread over all LDS banks, and
+// the four reads of a row take one address with immediate offsets.  An XOR
+// swizzle of the chunks spread the banks as well but cost about 10 VALU
+// instructions per slot in address arithmetic (25 % of the FP64 kernel).
+// Work items are numbered
 // row-panel-major and dealt to the XCDs in contiguous ranges: the workgroups
 // of one XCD sweep the same panel's lists together.
 template <typename T, typename V, int RPT>
@@ -1256,7 +1260,7 @@ __global__ __launch_bounds__(1024) void k_same_blk(
   constexpr int NW = 16;               // waves per workgroup
   using T16 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  T16 *L = reinterpret_cast<T16 *>(smem);  // [rb][4] chunks, swizzled
+  T16 *L = reinterpret_cast<T16 *>(smem);  // [rb][5] chunks (the fifth is padding)
   const int64_t b = blockIdx.x;
   const int64_t w = (b & 7) * per_xcd + (b >> 3);
   if (w >= total) return;
@@ -1288,7 +1292,7 @@ __global__ __launch_bounds__(1024) void k_same_blk(
 #pragma unroll
         for (int u = 0; u < CE; ++u) pv[u] = c0 + q * CE + u < C ? g[u] : (T)0;
       }
-      L[j * 4 + (q ^ ((j >> 2) & 3))] = v;
+      L[j * 5 + q] = v;
     }
     __syncthreads();
 #pragma unroll
@@ -1297,10 +1301,10 @@ __global__ __launch_bounds__(1024) void k_same_blk(
       if (grp < ngrp) {
         const int s0 = boff[grp * nblk + blk], s1 = boff[grp * nblk + blk + 1];
         auto apply = [&](int j, T v) {
-          const int sw = (j >> 2) & 3;
+          const T16 *Lj = L + j * 5;  // one address; the chunks are immediate offsets
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const T16 x = L[j * 4 + (q ^ sw)];
+            const T16 x = Lj[q];
             const T *px = reinterpret_cast<const T *>(&x);
 #pragma unroll
             for (int u = 0; u < CE; ++u) acc[k][q * CE + u] += v * px[u];
@@ -1339,7 +1343,7 @@ template <typename T, typename V>
 int launch_same_blk(sbci_ctx *ctx, const SpinTables &S, const V *bval, int64_t R, int64_t C,
                     const T *src, T *dst, int nvec) {
   constexpr int RPT = 4, NW = 16, WC = 64 / sizeof(T);
-  const size_t lds = (size_t)kSameBlkRows * 64;
+  const size_t lds = (size_t)kSameBlkRows * 80;
   static bool attr = false;
   if (!attr) {
     SBCI_HIP(hipFuncSetAttribute((const void *)k_same_blk<T, V, RPT>,
