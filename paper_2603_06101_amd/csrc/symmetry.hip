@@ -119,25 +119,49 @@ __global__ void k_sym_gather(SymArgs g, const int32_t *__restrict__ idxA,
 }
 
 // Beta same-spin part (with the beta one-electron terms), plain write; the
-// alpha part follows block by block with the list kernel of the unblocked sigma.
+// alpha part follows block by block with the list kernel of the unblocked
+// sigma.  In-row gathers over the transposed lists: the list
+// of column q (beta string Ib) is the same for every row of the block, so a
+// thread takes one column and kSymSameRows rows: each list entry is loaded
+// once for the group (coalesced over q) and gathered from each row.  Work
+// items: block a holds ceil(rows_a / kSymSameRows) x ncol[a] of them, from
+// rg.off[a] on.
+constexpr int kSymSameRows = 8;
+struct RowGroups {
+  int64_t off[9];
+};
+
 template <typename T, typename V>
 __global__ __launch_bounds__(256) void k_sym_same(
-    SymArgs g, const int32_t *__restrict__ colBT, const V *__restrict__ valBT, int nfB, int64_t nsb,
-    const T *__restrict__ c, T *__restrict__ out) {
-  const int64_t nd = g.off[8];
+    SymArgs g, RowGroups rg, const int32_t *__restrict__ colBT, const V *__restrict__ valBT,
+    int nfB, int64_t nsb, const T *__restrict__ c, T *__restrict__ out) {
   const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (d >= nd) return;
-  const int64_t vo = (int64_t)blockIdx.y * nd;
-  const int a = find_block(g, d);
-  const int64_t nc = g.ncol[a], rel = d - g.off[a];
-  const int64_t r = rel / nc, q = rel - r * nc;
+  if (d >= rg.off[8]) return;
+  int a = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (rg.off[k] <= d) a = k;
+  const int64_t vo = (int64_t)blockIdx.y * g.off[8];
+  const int64_t nc = g.ncol[a], rel = d - rg.off[a];
+  const int64_t grp = rel / nc, q = rel - grp * nc;
+  const int64_t r0 = grp * kSymSameRows;
+  const int nr = (int)(g.rowsA[a] - r0 < kSymSameRows ? g.rowsA[a] - r0 : kSymSameRows);
   const int64_t qs = g.startBc[a] + q;
-  const T *__restrict__ blk = c + vo + g.off[a];
-  T acc = 0;
-  // in-row gather over the transposed lists (coalesced over q)
-  for (int e = 0; e < nfB; ++e)
-    acc += (T)valBT[(int64_t)e * nsb + qs] * blk[r * nc + colBT[(int64_t)e * nsb + qs]];
-  out[vo + d] = acc;
+  const T *__restrict__ blk = c + vo + g.off[a] + r0 * nc;
+  T acc[kSymSameRows];
+#pragma unroll
+  for (int i = 0; i < kSymSameRows; ++i) acc[i] = 0;
+  for (int e = 0; e < nfB; ++e) {
+    const T v = (T)valBT[(int64_t)e * nsb + qs];
+    const int64_t col = colBT[(int64_t)e * nsb + qs];
+#pragma unroll
+    for (int i = 0; i < kSymSameRows; ++i)
+      if (i < nr) acc[i] += v * blk[i * nc + col];
+  }
+  T *__restrict__ o = out + vo + g.off[a] + r0 * nc + q;
+#pragma unroll
+  for (int i = 0; i < kSymSameRows; ++i)
+    if (i < nr) o[i * nc] = acc[i];
 }
 
 // Opposite-spin part in gather form (used where the pair form below does not
@@ -849,14 +873,19 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, boo
   const int64_t nd = S.off[8];
   constexpr bool dbl = std::is_same<T, double>::value;
   if (ev) SBCI_HIP(hipEventRecord(ev[0], ctx->stream));
-  const int64_t nblk = (nd + 255) / 256;
+  RowGroups rg{};
+  for (int a = 0; a < 8; ++a)
+    rg.off[a + 1] = rg.off[a] + (g.rowsA[a] + kSymSameRows - 1) / kSymSameRows * g.ncol[a];
+  const int64_t nblk = (rg.off[8] + 255) / 256;
   if (nblk >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "blocked space too large");
-  if constexpr (dbl)
-    k_sym_same<double, double><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
-  else
-    k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
-        g, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
+  if (nblk > 0) {
+    if constexpr (dbl)
+      k_sym_same<double, double><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
+          g, rg, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
+    else
+      k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
+          g, rg, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
+  }
   SBCI_CHECK_LAUNCH();
   // alpha same-spin part, block by block (rows of irrep a, lists in sorted order)
   for (int v = 0; v < nvec; ++v)
