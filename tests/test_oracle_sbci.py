@@ -154,3 +154,27 @@ def test_stored_cas14_roots_are_the_lowest_lanczos_values():
     assert len(lan) == 6 and ref["sbci1_converged"]
     assert np.abs(e - lan[:5]).max() < 1e-9
     assert lan[5] - e[-1] > 1e-3
+
+
+@pytest.mark.parametrize("n,na,nb,seed", [(6, 3, 2, 0), (7, 4, 3, 1), (6, 2, 3, 2)])
+def test_sbci1_continued_after_given_roots_reaches_the_next_eigenvalues(n, na, nb, seed):
+    """The continuation path (prev = converged pairs and a start): with the
+    exact lowest eigenpair of the dense H given as converged and a start that
+    still overlaps it strongly, the projection of the root start (Eqs. S4-S5)
+    and the deflated steps (Eq. S31) lead to the next two eigenvalues, with
+    vectors orthogonal to the given one."""
+    I, op = _problem(n, na, nb, 2 * n, seed)
+    Hs = H.dense_h_slater_condon(n, na, nb, I.h1, I.eri)
+    w, V = np.linalg.eigh(Hs)
+    rng = np.random.default_rng(seed)
+    x0 = V[:, 0] + 0.3 * V[:, 1] + 0.05 * rng.standard_normal(Hs.shape[0])
+    X0 = op(x0)
+    r = sbci.sbci1(op, op.diag(), 3, prev=([V[:, 0]], [w[0]], x0, X0, float(x0 @ X0 / (x0 @ x0))))
+    assert r.converged and len(r.energies) == 3
+    assert r.energies[0] == w[0]
+    assert np.abs(r.energies[1:] - w[1:3]).max() < 1e-8
+    for a in (1, 2):
+        x = r.vectors[a]
+        assert abs(x @ V[:, 0]) < 1e-8
+        assert np.linalg.norm(Hs @ x - r.energies[a] * x) < 2e-5
+    assert {s.root for s in r.steps} == {1, 2}
