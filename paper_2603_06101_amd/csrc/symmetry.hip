@@ -130,6 +130,9 @@ constexpr int kSymSameRows = 8;
 struct RowGroups {
   int64_t off[9];
 };
+// LDS form of the beta gathers: rows per workgroup and the LDS it may take
+constexpr int kSymSameLdsRows = 4;
+constexpr size_t kSymSameLdsMax = 160 * 1024 / 3;  // three workgroups per CU
 
 template <typename T, typename V>
 __global__ __launch_bounds__(256) void k_sym_same(
@@ -162,6 +165,49 @@ __global__ __launch_bounds__(256) void k_sym_same(
 #pragma unroll
   for (int i = 0; i < kSymSameRows; ++i)
     if (i < nr) o[i * nc] = acc[i];
+}
+
+// The same beta gathers with the rows in LDS: one workgroup per group of
+// RG rows of a block (the groups of block a start at rg.off[a]); the group's
+// rows (contiguous in the block, RG x ncol[a] elements) are staged once, and
+// each thread walks the lists of its columns, gathering from LDS.  Random
+// columns of a global row touch up to 64 cache lines per wave instruction;
+// from LDS they cost bank cycles only.
+template <typename T, typename V, int RG>
+__global__ __launch_bounds__(256) void k_sym_same_lds(
+    SymArgs g, RowGroups rg, const int32_t *__restrict__ colBT, const V *__restrict__ valBT,
+    int nfB, int64_t nsb, const T *__restrict__ c, T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *L = reinterpret_cast<T *>(smem);  // [RG][nc]
+  const int64_t k = blockIdx.x;
+  int a = 0;
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (rg.off[t] <= k) a = t;
+  const int64_t nc = g.ncol[a];
+  const int64_t r0 = (k - rg.off[a]) * RG;
+  const int nr = (int)(g.rowsA[a] - r0 < RG ? g.rowsA[a] - r0 : RG);
+  const int64_t vo = (int64_t)blockIdx.y * g.off[8];
+  const T *__restrict__ blk = c + vo + g.off[a] + r0 * nc;
+  for (int64_t i = threadIdx.x; i < nr * nc; i += 256) L[i] = blk[i];
+  __syncthreads();
+  T *__restrict__ o = out + vo + g.off[a] + r0 * nc;
+  for (int64_t q = threadIdx.x; q < nc; q += 256) {
+    const int64_t qs = g.startBc[a] + q;
+    T acc[RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) acc[i] = 0;
+    for (int e = 0; e < nfB; ++e) {
+      const T v = (T)valBT[(int64_t)e * nsb + qs];
+      const int col = colBT[(int64_t)e * nsb + qs];
+#pragma unroll
+      for (int i = 0; i < RG; ++i)
+        if (i < nr) acc[i] += v * L[i * nc + col];
+    }
+#pragma unroll
+    for (int i = 0; i < RG; ++i)
+      if (i < nr) o[i * nc + q] = acc[i];
+  }
 }
 
 // Opposite-spin part in gather form (used where the pair form below does not
@@ -873,6 +919,26 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, boo
   const int64_t nd = S.off[8];
   constexpr bool dbl = std::is_same<T, double>::value;
   if (ev) SBCI_HIP(hipEventRecord(ev[0], ctx->stream));
+  // beta part: rows staged in LDS in groups of kSymSameLdsRows when a group
+  // of the longest rows fits in a third of a CU's LDS (three workgroups per
+  // CU), otherwise gathered from global memory
+  const size_t lds_same = (size_t)kSymSameLdsRows * (size_t)S.maxcol * sizeof(T);
+  if (S.maxcol > 0 && lds_same <= kSymSameLdsMax) {
+    RowGroups rl{};
+    for (int a = 0; a < 8; ++a)
+      rl.off[a + 1] = rl.off[a] + (g.ncol[a] > 0 ? (g.rowsA[a] + kSymSameLdsRows - 1) / kSymSameLdsRows : 0);
+    if (rl.off[8] >= ((int64_t)1 << 31)) return set_error(SBCI_EINVAL, "blocked space too large");
+    if (rl.off[8] > 0) {
+      if constexpr (dbl)
+        k_sym_same_lds<double, double, kSymSameLdsRows>
+            <<<dim3((unsigned)rl.off[8], (unsigned)nvec), 256, lds_same, ctx->stream>>>(
+                g, rl, S.colBT, S.valBT64, S.nfB, ctx->B.ns, c, out);
+      else
+        k_sym_same_lds<float, float, kSymSameLdsRows>
+            <<<dim3((unsigned)rl.off[8], (unsigned)nvec), 256, lds_same, ctx->stream>>>(
+                g, rl, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
+    }
+  } else {
   RowGroups rg{};
   for (int a = 0; a < 8; ++a)
     rg.off[a + 1] = rg.off[a] + (g.rowsA[a] + kSymSameRows - 1) / kSymSameRows * g.ncol[a];
@@ -885,6 +951,7 @@ int sigma_sym_t(sbci_ctx *ctx, const T *c, T *out, int nvec, hipEvent_t *ev, boo
     else
       k_sym_same<float, float><<<dim3((unsigned)nblk, (unsigned)nvec), 256, 0, ctx->stream>>>(
           g, rg, S.colBT, S.valBT32, S.nfB, ctx->B.ns, c, out);
+  }
   }
   SBCI_CHECK_LAUNCH();
   // alpha same-spin part, block by block (rows of irrep a, lists in sorted order)
