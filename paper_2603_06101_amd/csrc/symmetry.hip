@@ -23,8 +23,9 @@
 //              cls(E_pq) = orbsym[p] ^ orbsym[q]; the integral vanishes when
 //              the classes differ, and when they agree the source
 //              determinant lies in block a ^ cls.
-// Kernels: the beta same-spin part is an in-row gather (k_sym_same) over
-// transposed lists; the alpha same-spin part runs block by block through the
+// Kernels: the beta same-spin part is an in-row gather over transposed lists,
+// from rows staged in LDS (k_sym_same_lds; k_sym_same gathers from global
+// memory where the rows are too long); the alpha same-spin part runs block by block through the
 // list kernel of the unblocked sigma; the opposite-spin part is the pair form
 // (k_sym_opp_pair: one alpha string per workgroup, the row of sigma and the
 // class blocks of integrals in LDS), or the gather form (k_sym_opp) where that
